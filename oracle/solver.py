@@ -1,0 +1,219 @@
+"""Multilevel time stepping, plain and slow (Sec. 2.1-2.3).
+
+State: the pre-collision pdfs f of every element of every level.  One step
+of level L applies the BGK collision (Eq. bgk) to *every* element of the
+level and then streams: f_i(x, t+1) = f*_i(x - c_i, t).  Nothing is skipped:
+ghost elements are collided too (Sec. 3.2 feeds all element types into the
+compute kernel), and a pull source that does not exist yields NaN, so any
+use of a value that is not valid poisons the result.
+
+Schedule (Sec. 2.2, acoustic scaling with two fine steps per coarse step,
+GhostFromFiner before GhostFromCoarser, two GhostFromCoarser layers and no
+temporal interpolation); reading taken for the order:
+
+    advance(L): step(L); if L < Lmax: advance(L+1); advance(L+1);
+                fill GhostFromFiner(L); fill GhostFromCoarser(L+1)
+
+Initialisation (reading taken; the paper is silent about ghosts at t=0):
+fluid pdfs are f^eq(rho, u) + f^neq(S) from the given fields, then one
+synchronous fill of all GhostFromFiner and then all GhostFromCoarser.
+
+Boundary rules for pull sources: halfway bounce-back from a solid cell or
+wall face takes f*_{opp(i)}(x); an 'eq' face supplies f^eq(rho0, u_in); a
+'copy' face takes the element's own f*_i(x).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import interp, physics
+from .mesh import BOUNCE, COPY, EQ, MISSING
+
+
+class OracleSim:
+    def __init__(self, mesh, tau0, rho0: float = 1.0, u_in=None,
+                 poison: bool = True, dtype=torch.float64):
+        self.mesh = mesh
+        self.lat = mesh.lattice
+        self.dtype = dtype
+        self.L0, self.Lmax = mesh.level0, mesh.lmax
+        self.tau0 = tau0
+        self.omega = {L: 1.0 / physics.level_tau(tau0, L, self.L0)
+                      for L in range(self.L0, self.Lmax + 1)}
+        self.rho0 = rho0
+        d = self.lat.d
+        if u_in is None:
+            u_in = torch.zeros(d, dtype=dtype)
+        self.u_in = torch.as_tensor(u_in, dtype=dtype)
+        self.poison = poison
+        self.f = {}
+        self._stream_tables = {L: self._tables(L) for L in range(self.L0, self.Lmax + 1)}
+        self.time = 0  # coarse steps
+
+    # ------------------------------------------------------------------
+    def _tables(self, L):
+        t = self.mesh.lev(L)
+        q, N = self.lat.q, t.n
+        nbr = t.nbr
+        x = np.arange(N)[None, :].repeat(q, 0)
+        dirs = np.arange(q)[:, None].repeat(N, 1)
+        src_dir = dirs.copy()
+        src_elem = np.where(nbr >= 0, nbr, 0)
+        bb = nbr == BOUNCE
+        src_dir[bb] = self.lat.opp[dirs[bb]]
+        src_elem[bb] = x[bb]
+        cp = nbr == COPY
+        src_elem[cp] = x[cp]
+        flat = torch.from_numpy(src_dir * N + src_elem)
+        return dict(flat=flat, eq=torch.from_numpy(nbr == EQ),
+                    miss=torch.from_numpy(nbr == MISSING))
+
+    def _filler(self, n):
+        if self.poison:
+            return torch.full((self.lat.q, n), float("nan"), dtype=self.dtype)
+        return self.lat.w_t(self.dtype)[:, None].expand(self.lat.q, n).clone()
+
+    # ------------------------------------------------------------------
+    def init(self, rho, u, S):
+        """rho[L] (n_fluid,), u[L] (n_fluid, d), S[L] (n_fluid, d, d) in
+        level-L lattice units, for every level L."""
+        for L in range(self.L0, self.Lmax + 1):
+            t = self.mesh.lev(L)
+            r = torch.as_tensor(rho[L], dtype=self.dtype)
+            uu = torch.as_tensor(u[L], dtype=self.dtype).t()
+            SS = torch.as_tensor(S[L], dtype=self.dtype).permute(1, 2, 0)
+            f_fluid = physics.equilibrium(r, uu, self.lat) + \
+                physics.fneq_from_strain(r, SS, self.omega[L], self.lat)
+            self.f[L] = torch.cat([f_fluid, self._filler(t.n - t.n_fluid)], 1)
+        self.fill_all()
+
+    def fill_all(self):
+        for L in range(self.L0, self.Lmax):
+            self.fill_gff(L)
+        for L in range(self.L0 + 1, self.Lmax + 1):
+            self.fill_gfc(L)
+
+    def fill_gff(self, L):
+        """GhostFromFiner of level L from fluid sources on level L+1."""
+        t = self.mesh.lev(L)
+        if t.n_gff == 0:
+            return
+        d = self.lat.d
+        if d == 3:
+            pos = [(0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+        else:
+            pos = [(0, 0), (1, 0), (0, 1), (1, 1)]
+        target = (0.5,) * d
+        fs = self.f[L + 1]
+        src = torch.from_numpy(t.gff_src)
+        f_src = torch.stack([fs[:, src[:, k]] for k in range(4)], 0)
+        vals = interp.fill(f_src, pos, target, self.omega[L + 1], self.omega[L],
+                           2.0, self.lat)
+        idx = torch.arange(t.gff_begin, t.n)
+        self.f[L] = self.f[L].index_copy(1, idx, vals)
+
+    def fill_gfc(self, L):
+        """GhostFromCoarser (both layers) of level L from level L-1."""
+        t = self.mesh.lev(L)
+        ng = t.n_inner + t.n_outer
+        if ng == 0:
+            return
+        d = self.lat.d
+        fc = self.f[L - 1]
+        signs = t.gfc_sign
+        codes = ((signs + 1) // 2) @ (1 << np.arange(d))
+        out = self.f[L]
+        for oc in np.unique(codes):
+            m = np.where(codes == oc)[0]
+            s = signs[m[0]]
+            if d == 3:
+                pos = [(0, 0, 0), (s[0], s[1], 0), (s[0], 0, s[2]), (0, s[1], s[2])]
+            else:
+                pos = [(0, 0), (s[0], 0), (0, s[1]), (s[0], s[1])]
+            target = tuple(0.25 * v for v in s)
+            src = torch.from_numpy(t.gfc_src[m])
+            f_src = torch.stack([fc[:, src[:, k]] for k in range(4)], 0)
+            vals = interp.fill(f_src, pos, target, self.omega[L - 1],
+                               self.omega[L], 0.5, self.lat)
+            out = out.index_copy(1, torch.from_numpy(t.gfc_begin + m), vals)
+        self.f[L] = out
+
+    # ------------------------------------------------------------------
+    def feq_inflow(self):
+        rho = torch.full((1,), self.rho0, dtype=self.dtype)
+        return physics.equilibrium(rho, self.u_in[:, None], self.lat)[:, 0]
+
+    def stream(self, L, fstar):
+        tb = self._stream_tables[L]
+        f = fstar.reshape(-1)[tb["flat"]]
+        f = torch.where(tb["eq"], self.feq_inflow()[:, None].expand_as(f), f)
+        return torch.where(tb["miss"], self._filler(f.shape[1]), f)
+
+    def stream_collide(self, L):
+        fstar = physics.collide(self.f[L], self.omega[L], self.lat)
+        self.f[L] = self.stream(L, fstar)
+
+    def advance(self, L):
+        self.stream_collide(L)
+        if L < self.Lmax:
+            self.advance(L + 1)
+            self.advance(L + 1)
+            self.fill_gff(L)
+            self.fill_gfc(L + 1)
+
+    def step(self, n: int = 1):
+        for _ in range(n):
+            self.advance(self.L0)
+            self.time += 1
+
+    # ------------------------------------------------------------------
+    def post_collision(self, L):
+        return physics.collide(self.f[L], self.omega[L], self.lat)
+
+    def fluid_moments(self, L):
+        t = self.mesh.lev(L)
+        rho, u, S, _ = physics.strain_rate(self.f[L][:, :t.n_fluid],
+                                           self.omega[L], self.lat)
+        return rho, u, S
+
+    def volume(self, L):
+        return 2.0 ** (-self.lat.d * (L - self.L0))
+
+    def mass(self):
+        tot = 0.0
+        for L in range(self.L0, self.Lmax + 1):
+            rho, _, _ = self.fluid_moments(L)
+            tot = tot + self.volume(L) * rho.sum()
+        return tot
+
+    def kinetic_energy(self):
+        """E = 1/2 sum_L V_L sum_fluid rho |u|^2 (V_L in level0 cells)."""
+        tot = 0.0
+        for L in range(self.L0, self.Lmax + 1):
+            rho, u, _ = self.fluid_moments(L)
+            tot = tot + self.volume(L) * 0.5 * (rho * (u * u).sum(0)).sum()
+        return tot
+
+    def force(self):
+        """Momentum exchange (Sec. 2.3): F = sum_{x_b} sum_{i in V}
+        c_i [f*_i(x_b, t) + f_opp(i)(x_b, t + dt)] over fluid elements x_b
+        next to the solid and the directions i pointing into it.  Each level's
+        sum is in its own lattice units; they are added in finest-level units
+        (force scales with dx^(d-1) under acoustic scaling)."""
+        d = self.lat.d
+        c = self.lat.c_t(self.dtype)
+        total = torch.zeros(d, dtype=self.dtype)
+        for L in range(self.L0, self.Lmax + 1):
+            t = self.mesh.lev(L)
+            fstar = self.post_collision(L)
+            fnew = self.stream(L, fstar)
+            nb = t.nbr[:, :t.n_fluid]
+            ibar, x = np.where(nb == BOUNCE)   # pull source x - c_ibar is solid
+            if len(x) == 0:
+                continue
+            i = self.lat.opp[ibar]             # c_i points into the solid
+            vals = fstar[i, x] + fnew[ibar, x]
+            FL = (c[i] * vals[:, None]).sum(0)
+            total = total + FL * float(2 ** ((d - 1) * (self.Lmax - L)))
+        return total

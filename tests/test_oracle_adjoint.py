@@ -1,0 +1,60 @@
+"""Pins of the oracle's reverse pass against central finite differences of
+the forward oracle (independent of automatic differentiation)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint, mesh
+
+
+def _fields(m, n0, fn):
+    rho, u, S = {}, {}, {}
+    for L in range(m.level0, m.lmax + 1):
+        t = m.lev(L)
+        pos = m.positions(L)[:t.n_fluid]
+        r, uu, SS = fn(pos)
+        rho[L], u[L], S[L] = r, uu, SS * 2.0 ** -(L - m.level0)
+    return rho, u, S
+
+
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19"])
+def test_ke_gradient_matches_central_differences(stencil):
+    spec = (W.refined_box_mesh("D3Q19", 3, 2, 6) if stencil == "D3Q19"
+            else W.refined_box_mesh("D2Q9", 4, 4, 12))
+    m = mesh.build(spec)
+    n0 = spec.box_extent[0]
+    rho, u, S = _fields(m, n0, lambda p: W.tgv_perturbed_fields(p, n0, 0.03))
+    J, g_tau, g_u, _ = adjoint.gradient(m, 0.57, rho, u, S, 4)
+    rng = np.random.default_rng(1)
+    for _ in range(2):
+        du = {L: rng.normal(size=u[L].shape) for L in u}
+        fd = adjoint.central_difference(m, 0.57, rho, u, S, 4, du=du, eps=1e-5)
+        ad = sum((g_u[L] * du[L]).sum() for L in u)
+        assert abs(fd - ad) <= 1e-7 * abs(ad)
+    # single components on both levels
+    for L in u:
+        du = {K: np.zeros_like(u[K]) for K in u}
+        du[L][3, 0] = 1.0
+        fd = adjoint.central_difference(m, 0.57, rho, u, S, 4, du=du, eps=1e-5)
+        assert abs(fd - g_u[L][3, 0]) <= 1e-7 * max(abs(fd), 1e-6)
+    fd = adjoint.central_difference(m, 0.57, rho, u, S, 4, dtau=1.0, eps=1e-6)
+    assert abs(fd - g_tau) <= 1e-7 * abs(g_tau)
+
+
+def test_drag_gradient_wrt_inflow_and_tau():
+    spec = W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0),
+                                 half_width=2.0, boxes_in_d=((-1.0, 1.5, 1.0),))
+    m = mesh.build(spec)
+    uin = np.array([0.04, 0.0, 0.0])
+    rho, u, S = {}, {}, {}
+    for L in range(m.level0, m.lmax + 1):
+        rho[L], u[L], S[L] = W.uniform_fields(m.lev(L).n_fluid, 3, uin)
+    J, g_tau, g_u, g_in = adjoint.gradient(m, 0.6, rho, u, S, 3,
+                                           objective="drag_x", u_in=uin)
+    assert J > 0
+    fd = adjoint.central_difference(m, 0.6, rho, u, S, 3, objective="drag_x",
+                                    duin=np.array([1.0, 0, 0]), u_in=uin, eps=1e-6)
+    assert abs(fd - g_in[0]) <= 1e-6 * abs(fd)
+    fd = adjoint.central_difference(m, 0.6, rho, u, S, 3, objective="drag_x",
+                                    dtau=1.0, u_in=uin, eps=1e-6)
+    assert abs(fd - g_tau) <= 1e-6 * abs(fd)
