@@ -1,0 +1,217 @@
+/*
+ * mlbm.h -- C ABI of the MI355X multilevel lattice Boltzmann hot path.
+ *
+ * The method is the octree lattice Boltzmann scheme with the four-source
+ * compact interpolation of Qi, Klimach and Roller ("Implementation of the
+ * compact interpolation within the octree based Lattice Boltzmann solver
+ * Musubi"): level-wise BGK pull stream-collide over sparse element arrays
+ * (Sec. 2.1, Eq. bgk; Sec. 3.2), GhostFromFiner / GhostFromCoarser ghost
+ * elements filled by the compact interpolation (Sec. 2.2, Eqs. compact_3D_u,
+ * compact_3D_s, Steps 1-5), and acoustic time stepping in which level L+1
+ * takes two steps per step of level L (Sec. 2.2).
+ *
+ * Conventions for every entry point:
+ *   - return 0 (MLBM_OK) on success, a negative MLBM_E_* code on failure;
+ *     mlbm_last_error() then describes the failure (per calling thread);
+ *   - nothing is thrown across the ABI; a NULL handle gives MLBM_E_ARG;
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the device that was current at mlbm_sim_create;
+ *   - all device work is enqueued on the HIP stream given to
+ *     mlbm_sim_create and is asynchronous unless stated otherwise;
+ *   - the library never allocates device memory: the caller provides one
+ *     workspace for the simulation (and one for the adjoint) and owns it.
+ *
+ * Element layout (per level L, Sec. 3.2 stores fluid, then ghosts, each
+ * along the space-filling curve): [fluid | GhostFromCoarser inner |
+ * GhostFromCoarser outer | GhostFromFiner], every segment ascending by
+ * treeID.  Per-element arrays are structure-of-arrays: component k of
+ * element x is at k * n_level + x.
+ */
+#ifndef MLBM_H
+#define MLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- enumerations --------------------------------------------------- */
+enum { MLBM_D2Q9 = 0, MLBM_D3Q19 = 1 };
+
+/* Storage precision of the pdfs.  F64: double, FP64 collision.  F32: float,
+ * FP32 collision.  F16S: half holding s_L * (f_i - w_i rho0) with a
+ * power-of-two scale s_L per level; collision in FP32. */
+enum { MLBM_F64 = 0, MLBM_F32 = 1, MLBM_F16S = 2 };
+
+/* Face kinds, faces ordered x-, x+, y-, y+, z-, z+.  A periodic face must
+ * be paired with a periodic opposite face.  EQ supplies the equilibrium
+ * f^eq(rho0, u_in) for pdfs entering through the face; COPY makes the
+ * element pull its own post-collision value; WALL is halfway bounce-back.
+ * When a link crosses several faces EQ wins over COPY, COPY over WALL. */
+enum { MLBM_FACE_PERIODIC = 0, MLBM_FACE_EQ = 1, MLBM_FACE_COPY = 2,
+       MLBM_FACE_WALL = 3 };
+
+/* Neighbour-table codes (values < 0 in the NBR table). */
+enum { MLBM_NBR_MISSING = -1, MLBM_NBR_BOUNCE = -2, MLBM_NBR_EQ = -3,
+       MLBM_NBR_COPY = -4 };
+
+/* Error codes. */
+enum {
+  MLBM_OK = 0,
+  MLBM_E_ARG = -1,    /* bad argument, size or handle */
+  MLBM_E_MESH = -2,   /* invalid mesh: tiling, 2:1 jumps, ghost sources */
+  MLBM_E_STATE = -3,  /* call out of order (e.g. step before init) */
+  MLBM_E_HIP = -4,    /* a HIP runtime call failed */
+  MLBM_E_OOM = -5     /* host allocation failed */
+};
+
+/* Diagnostics mask bits and status flags. */
+enum { MLBM_DIAG_MASS = 1, MLBM_DIAG_KE = 2, MLBM_DIAG_FORCE = 4 };
+enum { MLBM_STATUS_NONFINITE = 1, MLBM_STATUS_F16_OVERFLOW = 2 };
+
+/* Exportable plan tables (mlbm_plan_export). */
+enum {
+  MLBM_TABLE_TREEID = 0,   /* uint64 [n]: treeIDs in layout order          */
+  MLBM_TABLE_COORDS = 1,   /* int32 [d][n]: integer coords on the level     */
+  MLBM_TABLE_NBR = 2,      /* int32 [q-1][n]: pull source of direction i>=1 */
+  MLBM_TABLE_GFC_SRC = 3,  /* int32 [4][n_gfc]: H,K,M,N (3D) or P,Px,Py,Pxy
+                              (2D) element indices on level L-1             */
+  MLBM_TABLE_GFF_SRC = 4,  /* int32 [4][n_gff]: source element indices on
+                              level L+1                                      */
+  MLBM_TABLE_CAPTURE = 5,  /* int32 [n_cap_fluid]: fluid elements whose
+                              pre-collision moments are captured            */
+  MLBM_TABLE_BOUNCE = 6    /* int32 [2][n_bounce]: (element, direction i)
+                              fluid links whose pull source is solid        */
+};
+
+/* Fields of mlbm_plan_level_info, in this order (int64 each). */
+enum {
+  MLBM_INFO_LEVEL = 0, MLBM_INFO_N = 1, MLBM_INFO_N_FLUID = 2,
+  MLBM_INFO_N_GFC_INNER = 3, MLBM_INFO_N_GFC_OUTER = 4, MLBM_INFO_N_GFF = 5,
+  MLBM_INFO_N_CAP_FLUID = 6, MLBM_INFO_N_CAP = 7, MLBM_INFO_N_GFC_GROUPS = 8,
+  MLBM_INFO_N_BOUNCE = 9, MLBM_INFO_FIELDS = 10
+};
+
+/* State selectors for mlbm_get_state / mlbm_set_state. */
+enum {
+  MLBM_STATE_PDF_POST = 0, /* post-collision pdfs f*, all elements, FP64
+                              [q][n]                                          */
+  MLBM_STATE_MOMENTS = 1   /* rho, u of fluid elements, FP64 [1+d][n_fluid] */
+};
+
+typedef struct mlbm_plan mlbm_plan;
+typedef struct mlbm_sim mlbm_sim;
+
+/* ---- errors --------------------------------------------------------- */
+/* Human-readable name of an error code (static string). */
+const char* mlbm_error_string(int32_t code);
+/* Message of the last failure on the calling thread ("" if none). */
+const char* mlbm_last_error(void);
+
+/* ---- lattice -------------------------------------------------------- */
+/* Velocity set used by the library for `stencil` (Sec. 2.1): writes q,
+ * then c (int32 [q][d], host) and w (double [q], host) if non-NULL.
+ * Direction 0 is the rest velocity.  Host only. */
+int32_t mlbm_lattice(int32_t stencil, int32_t* q, int32_t* c, double* w);
+
+/* ---- plan: host-only mesh analysis (Sec. 3.1, 3.2; Sec. 2.2 ghosts) --- */
+/* Build all level-wise tables from the leaf treeIDs of the fluid elements
+ * (any order) and the treeIDs of solid cells.  treeID numbering: root id 0
+ * at level 0, children of t are 2^d t + 1 ... 2^d t + 2^d with the Morton
+ * bit order x, y, z.  box_origin / box_extent (d entries each) give the
+ * domain in cells of level `level0`, the coarsest level present.  face_bc
+ * has 2d entries.  Host arrays are copied; the plan owns its memory until
+ * mlbm_plan_destroy.  Errors: MLBM_E_ARG (bad sizes/enums), MLBM_E_MESH
+ * (elements outside the box, holes or overlaps, a ghost source that is not
+ * fluid / GhostFromFiner, or an updated element missing a neighbour).
+ * Needs no GPU. */
+int32_t mlbm_plan_create(int32_t stencil, int32_t level0,
+                         const int32_t* box_origin, const int32_t* box_extent,
+                         const int32_t* face_bc,
+                         const uint64_t* leaf_ids, int64_t n_leaves,
+                         const uint64_t* solid_ids, int64_t n_solids,
+                         mlbm_plan** out);
+void mlbm_plan_destroy(mlbm_plan* plan);
+/* Number of levels (Lmax - L0 + 1) and L0. */
+int32_t mlbm_plan_levels(const mlbm_plan* plan, int32_t* n_levels,
+                         int32_t* level0);
+/* MLBM_INFO_FIELDS int64 values describing level index k (0 = coarsest). */
+int32_t mlbm_plan_level_info(const mlbm_plan* plan, int32_t k, int64_t* out);
+/* Copy table `table` of level index k into host memory; `bytes` must equal
+ * the table's size exactly (query it with dst = NULL, which stores the
+ * size in *bytes). */
+int32_t mlbm_plan_export(const mlbm_plan* plan, int32_t k, int32_t table,
+                         void* host_dst, size_t* bytes);
+
+/* ---- simulation ------------------------------------------------------ */
+/* Device workspace bytes a simulation of `plan` at `precision` needs. */
+int32_t mlbm_sim_workspace_bytes(const mlbm_plan* plan, int32_t precision,
+                                 size_t* bytes);
+/* Create a simulation bound to `hip_stream` (a hipStream_t, may be NULL for
+ * the null stream) using the caller's device `workspace` (256-byte aligned,
+ * at least mlbm_sim_workspace_bytes).  tau0 is the BGK relaxation time of
+ * level L0; finer levels follow Eq. fneq_scale with m = 2.  rho0 is the
+ * reference density (shift of F16S storage and density of EQ faces),
+ * u_in (d doubles, host, may be NULL = 0) the EQ-face velocity.  f16_exp
+ * (n_levels ints, host) sets s_L = 2^f16_exp[k] for F16S; NULL picks it at
+ * mlbm_init from the initial state.  Uploads the index tables (enqueued on
+ * the stream).  The workspace must outlive the simulation. */
+int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0,
+                        double rho0, const double* u_in, const int32_t* f16_exp,
+                        void* hip_stream, void* workspace,
+                        size_t workspace_bytes, mlbm_sim** out);
+void mlbm_sim_destroy(mlbm_sim* sim);
+
+/* Initial state of level index k (Sec. 4.1 initialisation): for every fluid
+ * element f = f^eq(rho, u) + f^neq(S), f^neq_i = -(w_i rho/(cs^2 omega_L))
+ * Q_i:S.  Device FP64 arrays over the level's fluid elements in layout
+ * order: rho [n_fluid], u [d][n_fluid], S [d(d+1)/2][n_fluid] with
+ * components xx, yy, zz, xy, yz, xz (2D: xx, yy, xy) in level-L lattice
+ * units; S may be NULL (zero).  Call for every level, then
+ * mlbm_fill_ghosts. */
+int32_t mlbm_init(mlbm_sim* sim, int32_t k, const double* rho, const double* u,
+                  const double* S);
+/* Synchronous ghost fill (Sec. 2.2): all GhostFromFiner, then all
+ * GhostFromCoarser, from the pre-collision moments captured at the last
+ * synchronous time. */
+int32_t mlbm_fill_ghosts(mlbm_sim* sim);
+/* Advance n coarse steps with the recursive schedule: advance(L) = one
+ * stream-collide of L; if L < Lmax: advance(L+1) twice, fill
+ * GhostFromFiner(L), fill GhostFromCoarser(L+1).  Asynchronous. */
+int32_t mlbm_step(mlbm_sim* sim, int64_t n_coarse);
+/* FP64 reductions written to device memory `dev_out` (deterministic, no
+ * atomics): for each bit set in `mask` in the order MASS (1 value),
+ * KE (1), FORCE (d).  MASS = sum_L V_L sum_fluid rho; KE = 1/2 sum_L V_L
+ * sum_fluid rho |u|^2 with V_L = 2^(-d (L - L0)); FORCE = momentum exchange
+ * (Sec. 2.3) over bounce-back links, each level scaled to finest-level
+ * units by 2^((d-1)(Lmax - L)). */
+int32_t mlbm_diagnostics(mlbm_sim* sim, uint32_t mask, double* dev_out);
+/* Copy state of level index k to device memory (see MLBM_STATE_*). */
+int32_t mlbm_get_state(mlbm_sim* sim, int32_t k, int32_t what, double* dev_dst);
+/* Overwrite the post-collision pdfs of level index k (all elements) from
+ * device FP64 [q][n]; used to inject test states. */
+int32_t mlbm_set_state(mlbm_sim* sim, int32_t k, const double* dev_src);
+/* Sticky device status flags (MLBM_STATUS_*); synchronises the stream.
+ * The flags are cleared after reading. */
+int32_t mlbm_status(mlbm_sim* sim, uint32_t* flags);
+/* Number of coarse steps taken since mlbm_init. */
+int32_t mlbm_time(const mlbm_sim* sim, int64_t* coarse_steps);
+
+/* Checkpoint: raw per-level pdf arrays, capture buffers, parities and the
+ * step counter.  Device-to-device copies on the stream; `bytes` must be at
+ * least mlbm_checkpoint_bytes.  A run restored by load_checkpoint continues
+ * bit-identically. */
+int32_t mlbm_checkpoint_bytes(const mlbm_sim* sim, size_t* bytes);
+int32_t mlbm_save_checkpoint(mlbm_sim* sim, void* dev_dst, size_t bytes);
+int32_t mlbm_load_checkpoint(mlbm_sim* sim, const void* dev_src, size_t bytes);
+
+/* Per-launch timing hook: the number of kernel launches one coarse step
+ * enqueues (for profiling). */
+int32_t mlbm_launches_per_step(const mlbm_sim* sim, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLBM_H */

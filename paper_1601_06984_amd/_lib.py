@@ -1,0 +1,91 @@
+"""ctypes declarations of the C ABI in include/mlbm.h.
+
+Loading fails loudly if the in-tree library has not been built; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libmlbm.so")
+
+# enums mirrored from include/mlbm.h
+D2Q9, D3Q19 = 0, 1
+F64, F32, F16S = 0, 1, 2
+FACE = {"periodic": 0, "eq": 1, "copy": 2, "wall": 3}
+NBR_MISSING, NBR_BOUNCE, NBR_EQ, NBR_COPY = -1, -2, -3, -4
+E_ARG, E_MESH, E_STATE, E_HIP, E_OOM = -1, -2, -3, -4, -5
+DIAG_MASS, DIAG_KE, DIAG_FORCE = 1, 2, 4
+STATUS_NONFINITE, STATUS_F16_OVERFLOW = 1, 2
+TABLE_TREEID, TABLE_COORDS, TABLE_NBR, TABLE_GFC_SRC, TABLE_GFF_SRC, \
+    TABLE_CAPTURE, TABLE_BOUNCE = range(7)
+STATE_PDF_POST, STATE_MOMENTS = 0, 1
+INFO_FIELDS = ("level", "n", "n_fluid", "n_gfc_inner", "n_gfc_outer", "n_gff",
+               "n_cap_fluid", "n_cap", "n_gfc_groups", "n_bounce")
+
+_p = C.c_void_p
+_i32, _i64, _u32, _sz = C.c_int32, C.c_int64, C.c_uint32, C.c_size_t
+_pi32, _pi64, _pu64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_uint64)
+_pd, _pu32, _psz = C.POINTER(C.c_double), C.POINTER(C.c_uint32), C.POINTER(C.c_size_t)
+
+# name: (restype, argtypes)
+SIGNATURES = {
+    "mlbm_error_string": (C.c_char_p, [_i32]),
+    "mlbm_last_error": (C.c_char_p, []),
+    "mlbm_lattice": (_i32, [_i32, _pi32, _pi32, _pd]),
+    "mlbm_plan_create": (_i32, [_i32, _i32, _pi32, _pi32, _pi32, _pu64, _i64, _pu64, _i64,
+                                C.POINTER(_p)]),
+    "mlbm_plan_destroy": (None, [_p]),
+    "mlbm_plan_levels": (_i32, [_p, _pi32, _pi32]),
+    "mlbm_plan_level_info": (_i32, [_p, _i32, _pi64]),
+    "mlbm_plan_export": (_i32, [_p, _i32, _i32, _p, _psz]),
+    "mlbm_sim_workspace_bytes": (_i32, [_p, _i32, _psz]),
+    "mlbm_sim_create": (_i32, [_p, _i32, C.c_double, C.c_double, _pd, _pi32, _p, _p, _sz,
+                               C.POINTER(_p)]),
+    "mlbm_sim_destroy": (None, [_p]),
+    "mlbm_init": (_i32, [_p, _i32, _p, _p, _p]),
+    "mlbm_fill_ghosts": (_i32, [_p]),
+    "mlbm_step": (_i32, [_p, _i64]),
+    "mlbm_diagnostics": (_i32, [_p, _u32, _p]),
+    "mlbm_get_state": (_i32, [_p, _i32, _i32, _p]),
+    "mlbm_set_state": (_i32, [_p, _i32, _p]),
+    "mlbm_status": (_i32, [_p, _pu32]),
+    "mlbm_time": (_i32, [_p, _pi64]),
+    "mlbm_checkpoint_bytes": (_i32, [_p, _psz]),
+    "mlbm_save_checkpoint": (_i32, [_p, _p, _sz]),
+    "mlbm_load_checkpoint": (_i32, [_p, _p, _sz]),
+    "mlbm_launches_per_step": (_i32, [_p, _pi64]),
+}
+
+_LIB = None
+
+
+class MLBMError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{message} (code {code})")
+        self.code = code
+
+
+def lib():
+    """The loaded library; raises if it is missing (never falls back)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "paper_1601_06984_amd/build.py first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def check(code: int):
+    if code != 0:
+        msg = lib().mlbm_last_error().decode(errors="replace")
+        raise MLBMError(code, msg or lib().mlbm_error_string(code).decode())
+    return code

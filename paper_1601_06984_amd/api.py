@@ -1,0 +1,223 @@
+"""Plan and Sim: thin wrappers over the C ABI (include/mlbm.h)."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, lib
+
+_STENCILS = {"D2Q9": _lib.D2Q9, "D3Q19": _lib.D3Q19}
+_PRECISIONS = {"f64": _lib.F64, "f32": _lib.F32, "f16s": _lib.F16S}
+
+
+def lattice(stencil: str):
+    """(c (q, d) int, w (q,) float64) of the library's velocity set."""
+    s = _STENCILS[stencil]
+    q = C.c_int32()
+    check(lib().mlbm_lattice(s, C.byref(q), None, None))
+    d = 2 if s == _lib.D2Q9 else 3
+    c = np.zeros((q.value, d), dtype=np.int32)
+    w = np.zeros(q.value, dtype=np.float64)
+    check(lib().mlbm_lattice(s, None, c.ctypes.data_as(_lib._pi32), w.ctypes.data_as(_lib._pd)))
+    return c, w
+
+
+def _i32arr(v):
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.int32))
+    return a, a.ctypes.data_as(_lib._pi32)
+
+
+class Plan:
+    """Host-only mesh analysis: level-wise element lists and index tables."""
+
+    def __init__(self, stencil: str, level0: int, box_origin, box_extent, face_bc,
+                 leaf_ids, solid_ids=()):
+        self.stencil = stencil
+        self.d = 2 if stencil == "D2Q9" else 3
+        self.q = 9 if stencil == "D2Q9" else 19
+        self._h = C.c_void_p()
+        o, po = _i32arr(box_origin)
+        e, pe = _i32arr(box_extent)
+        f, pf = _i32arr([_lib.FACE[k] if isinstance(k, str) else int(k) for k in face_bc])
+        leaves = np.ascontiguousarray(np.asarray(leaf_ids, dtype=np.uint64))
+        solids = np.ascontiguousarray(np.asarray(solid_ids, dtype=np.uint64))
+        check(lib().mlbm_plan_create(
+            _STENCILS[stencil], int(level0), po, pe, pf,
+            leaves.ctypes.data_as(_lib._pu64), len(leaves),
+            solids.ctypes.data_as(_lib._pu64) if len(solids) else None, len(solids),
+            C.byref(self._h)))
+        n = C.c_int32()
+        l0 = C.c_int32()
+        check(lib().mlbm_plan_levels(self._h, C.byref(n), C.byref(l0)))
+        self.n_levels, self.level0 = n.value, l0.value
+        self.info = []
+        for k in range(self.n_levels):
+            buf = np.zeros(len(_lib.INFO_FIELDS), dtype=np.int64)
+            check(lib().mlbm_plan_level_info(self._h, k, buf.ctypes.data_as(_lib._pi64)))
+            self.info.append(dict(zip(_lib.INFO_FIELDS, (int(v) for v in buf))))
+
+    @classmethod
+    def from_spec(cls, spec):
+        return cls(spec.stencil, spec.level0, spec.box_origin, spec.box_extent,
+                   spec.face_bc, spec.leaf_ids, spec.solid_ids)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self, k: int, table: str) -> np.ndarray:
+        tid = {"treeid": _lib.TABLE_TREEID, "coords": _lib.TABLE_COORDS,
+               "nbr": _lib.TABLE_NBR, "gfc_src": _lib.TABLE_GFC_SRC,
+               "gff_src": _lib.TABLE_GFF_SRC, "capture": _lib.TABLE_CAPTURE,
+               "bounce": _lib.TABLE_BOUNCE}[table]
+        nbytes = C.c_size_t()
+        check(lib().mlbm_plan_export(self._h, k, tid, None, C.byref(nbytes)))
+        dtype = np.uint64 if table == "treeid" else np.int32
+        out = np.zeros(nbytes.value // np.dtype(dtype).itemsize, dtype=dtype)
+        check(lib().mlbm_plan_export(self._h, k, tid, out.ctypes.data_as(C.c_void_p),
+                                     C.byref(nbytes)))
+        n = self.info[k]["n"]
+        rows = {"coords": self.d, "nbr": self.q - 1, "gfc_src": 4, "gff_src": 4, "bounce": 2}
+        if table in rows:
+            out = out.reshape(rows[table], -1)
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().mlbm_plan_destroy(h)
+            self._h = C.c_void_p()
+
+
+class Sim:
+    """A simulation on the current HIP device; memory from torch."""
+
+    def __init__(self, plan: Plan, precision: str = "f32", tau0: float = 0.8,
+                 rho0: float = 1.0, u_in=None, f16_exp=None, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("mlbm.Sim needs a HIP device")
+        self.torch = torch
+        self.plan = plan
+        self.precision = precision
+        self.device = torch.device(device or "cuda")
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        need = C.c_size_t()
+        check(lib().mlbm_sim_workspace_bytes(plan.handle, _PRECISIONS[precision],
+                                             C.byref(need)))
+        ws = torch.empty(need.value + 256, dtype=torch.uint8, device=self.device)
+        shift = (-ws.data_ptr()) % 256
+        self.workspace = ws
+        self._ws_ptr = ws.data_ptr() + shift
+        self.workspace_bytes = need.value
+        uin = None
+        if u_in is not None:
+            self._uin = np.ascontiguousarray(np.asarray(u_in, dtype=np.float64))
+            uin = self._uin.ctypes.data_as(_lib._pd)
+        f16 = None
+        if f16_exp is not None:
+            self._f16 = np.ascontiguousarray(np.asarray(f16_exp, dtype=np.int32))
+            f16 = self._f16.ctypes.data_as(_lib._pi32)
+        self._h = C.c_void_p()
+        check(lib().mlbm_sim_create(plan.handle, _PRECISIONS[precision], float(tau0),
+                                    float(rho0), uin, f16, C.c_void_p(self.stream.cuda_stream),
+                                    C.c_void_p(self._ws_ptr), need.value, C.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _ptr(self, t, dtype=None):
+        if t is None:
+            return None
+        torch = self.torch
+        assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous"
+        if dtype is not None:
+            assert t.dtype == dtype, f"expected {dtype}, got {t.dtype}"
+        return C.c_void_p(t.data_ptr())
+
+    def init(self, k: int, rho, u, S=None):
+        """rho (n_fluid,), u (d, n_fluid), S (d(d+1)/2, n_fluid): float64
+        device tensors in layout order, S in level-k lattice units."""
+        f64 = self.torch.float64
+        nf = self.plan.info[k]["n_fluid"]
+        ns = 6 if self.plan.d == 3 else 3
+        if not 0 <= k < self.plan.n_levels:
+            raise ValueError("level index out of range")
+        if rho.numel() != nf or u.numel() != self.plan.d * nf or \
+                (S is not None and S.numel() != ns * nf):
+            raise ValueError(f"level {k}: expected rho[{nf}], u[{self.plan.d}][{nf}], "
+                             f"S[{ns}][{nf}]")
+        self._init_keep = (rho, u, S)
+        check(lib().mlbm_init(self._h, k, self._ptr(rho, f64), self._ptr(u, f64),
+                              self._ptr(S, f64)))
+
+    def fill_ghosts(self):
+        check(lib().mlbm_fill_ghosts(self._h))
+
+    def step(self, n: int = 1):
+        check(lib().mlbm_step(self._h, int(n)))
+
+    def diagnostics(self, mask: int = _lib.DIAG_MASS | _lib.DIAG_KE, out=None):
+        n = (1 if mask & 1 else 0) + (1 if mask & 2 else 0) + (self.plan.d if mask & 4 else 0)
+        if out is None:
+            out = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+        if out.numel() < n:
+            raise ValueError("diagnostics output too small")
+        check(lib().mlbm_diagnostics(self._h, mask, self._ptr(out, self.torch.float64)))
+        return out
+
+    def get_pdf(self, k: int):
+        n = self.plan.info[k]["n"]
+        out = self.torch.empty((self.plan.q, n), dtype=self.torch.float64, device=self.device)
+        check(lib().mlbm_get_state(self._h, k, _lib.STATE_PDF_POST, self._ptr(out)))
+        return out
+
+    def get_moments(self, k: int):
+        nf = self.plan.info[k]["n_fluid"]
+        out = self.torch.empty((1 + self.plan.d, nf), dtype=self.torch.float64, device=self.device)
+        check(lib().mlbm_get_state(self._h, k, _lib.STATE_MOMENTS, self._ptr(out)))
+        return out
+
+    def set_pdf(self, k: int, pdf):
+        if pdf.numel() != self.plan.q * self.plan.info[k]["n"]:
+            raise ValueError("set_pdf expects [q][n] float64")
+        check(lib().mlbm_set_state(self._h, k, self._ptr(pdf, self.torch.float64)))
+
+    def status(self) -> int:
+        f = C.c_uint32()
+        check(lib().mlbm_status(self._h, C.byref(f)))
+        return f.value
+
+    def time(self) -> int:
+        t = C.c_int64()
+        check(lib().mlbm_time(self._h, C.byref(t)))
+        return t.value
+
+    def checkpoint_bytes(self) -> int:
+        b = C.c_size_t()
+        check(lib().mlbm_checkpoint_bytes(self._h, C.byref(b)))
+        return b.value
+
+    def save_checkpoint(self, buf=None):
+        n = self.checkpoint_bytes()
+        if buf is None:
+            buf = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        check(lib().mlbm_save_checkpoint(self._h, self._ptr(buf), buf.numel()))
+        return buf
+
+    def load_checkpoint(self, buf):
+        check(lib().mlbm_load_checkpoint(self._h, self._ptr(buf), buf.numel()))
+
+    def launches_per_step(self) -> int:
+        n = C.c_int64()
+        check(lib().mlbm_launches_per_step(self._h, C.byref(n)))
+        return n.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().mlbm_sim_destroy(h)
+            self._h = C.c_void_p()

@@ -1,0 +1,95 @@
+// Internal definitions shared by the host plan builder and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/mlbm.h"
+
+#if defined(__HIPCC__)
+#define MLBM_HD __host__ __device__
+#else
+#define MLBM_HD
+#endif
+
+namespace mlbm {
+
+// Velocity sets (Sec. 2.1).  Direction 0 is at rest; directions 2k-1 and 2k
+// are opposite, so opp(i) = i + 1 for odd i and i - 1 for even i > 0.
+// cs^2 = 1/3; weights give an isotropic fourth moment.
+struct D2Q9 {
+  static constexpr int D = 2, Q = 9, STENCIL = MLBM_D2Q9;
+  static constexpr int NS = 3;  // strain components xx, yy, xy
+  MLBM_HD static constexpr int c(int i, int a) {
+    constexpr int t[9][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1},
+                             {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
+    return t[i][a];
+  }
+  MLBM_HD static constexpr double w(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+  MLBM_HD static constexpr int opp(int i) {
+    return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
+  }
+};
+
+struct D3Q19 {
+  static constexpr int D = 3, Q = 19, STENCIL = MLBM_D3Q19;
+  static constexpr int NS = 6;  // strain components xx, yy, zz, xy, yz, xz
+  MLBM_HD static constexpr int c(int i, int a) {
+    constexpr int t[19][3] = {
+        {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+        {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+        {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+        {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    return t[i][a];
+  }
+  MLBM_HD static constexpr double w(int i) {
+    return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+  MLBM_HD static constexpr int opp(int i) {
+    return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
+  }
+};
+
+// Strain component order (a, b) for NS components.
+MLBM_HD constexpr int strain_a(int d, int k) {
+  return d == 3 ? (k == 0 ? 0 : k == 1 ? 1 : k == 2 ? 2 : k == 3 ? 0 : k == 4 ? 1 : 0)
+                : (k == 0 ? 0 : k == 1 ? 1 : 0);
+}
+MLBM_HD constexpr int strain_b(int d, int k) {
+  return d == 3 ? (k == 0 ? 0 : k == 1 ? 1 : k == 2 ? 2 : k == 3 ? 1 : k == 4 ? 2 : 2)
+                : (k == 0 ? 0 : k == 1 ? 1 : 1);
+}
+
+inline int stencil_q(int stencil) { return stencil == MLBM_D2Q9 ? 9 : 19; }
+inline int stencil_d(int stencil) { return stencil == MLBM_D2Q9 ? 2 : 3; }
+
+// Capture record: rho, u (d), S (NS), f^neq (q), padded to a power of two.
+MLBM_HD constexpr int cap_stride(int d) { return d == 3 ? 32 : 16; }
+MLBM_HD constexpr int cap_u(int) { return 1; }
+MLBM_HD constexpr int cap_s(int d) { return 1 + d; }
+MLBM_HD constexpr int cap_fneq(int d) { return d == 3 ? 10 : 6; }
+
+// Neighbourhood slots of a GhostFromCoarser parent group: 3D uses the
+// parent and its 12 edge neighbours, 2D the parent and its 8 neighbours.
+MLBM_HD constexpr int group_slots(int d) { return d == 3 ? 13 : 9; }
+MLBM_HD constexpr int group_children(int d) { return d == 3 ? 8 : 4; }
+// slot index of offset (ox, oy[, oz]) in {-1,0,1}; -1 if not a slot.
+MLBM_HD constexpr int group_slot_of(int d, int ox, int oy, int oz) {
+  if (d == 2) return (ox + 1) + 3 * (oy + 1);  // 0..8, parent = 4
+  // 3D: parent = 0; edges (two non-zero components) = 1..12
+  if (ox == 0 && oy == 0 && oz == 0) return 0;
+  if (oz == 0 && ox != 0 && oy != 0) return 1 + ((ox > 0) ? 0 : 2) + ((oy > 0) ? 0 : 1);
+  if (oy == 0 && ox != 0 && oz != 0) return 5 + ((ox > 0) ? 0 : 2) + ((oz > 0) ? 0 : 1);
+  if (ox == 0 && oy != 0 && oz != 0) return 9 + ((oy > 0) ? 0 : 2) + ((oz > 0) ? 0 : 1);
+  return -1;
+}
+MLBM_HD constexpr int group_parent_slot(int d) { return d == 3 ? 0 : 4; }
+
+// thread-local error reporting
+void set_error(const char* fmt, ...);
+int32_t fail(int32_t code, const char* fmt, ...);
+
+}  // namespace mlbm

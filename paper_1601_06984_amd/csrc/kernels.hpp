@@ -1,0 +1,648 @@
+// Forward device kernels: fused pull stream-collide, source capture, the
+// GhostFromFiner / GhostFromCoarser compact-interpolation fills, init,
+// state conversion and FP64 diagnostics.
+//
+// All arithmetic works on deviations g_i = f_i - w_i rho0 (exact for the
+// F64/F32 stored values by Sterbenz' lemma, and the native form of F16S),
+// which keeps FP32 rounding relative to the small deviations instead of
+// to the O(1) pdfs.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace mlbm {
+
+// ---------------------------------------------------------------- storage --
+template <int P> struct Prec;
+template <> struct Prec<MLBM_F64> { using S = double; using C = double; };
+template <> struct Prec<MLBM_F32> { using S = float; using C = float; };
+template <> struct Prec<MLBM_F16S> { using S = __half; using C = float; };
+
+template <int P>
+__device__ __forceinline__ typename Prec<P>::C load_g(const typename Prec<P>::S* __restrict__ p,
+                                                     int64_t idx, typename Prec<P>::C wr,
+                                                     typename Prec<P>::C inv_scale) {
+  if constexpr (P == MLBM_F16S) {
+    (void)wr;
+    return __half2float(p[idx]) * inv_scale;
+  } else {
+    (void)inv_scale;
+    return (typename Prec<P>::C)p[idx] - wr;
+  }
+}
+
+template <int P>
+__device__ __forceinline__ bool store_g(typename Prec<P>::S* __restrict__ p, int64_t idx,
+                                        typename Prec<P>::C g, typename Prec<P>::C wr,
+                                        typename Prec<P>::C scale) {
+  if constexpr (P == MLBM_F16S) {
+    (void)wr;
+    const float h = g * scale;
+    p[idx] = __float2half_rn(h);
+    return fabsf(h) <= 65504.0f;
+  } else {
+    (void)scale;
+    p[idx] = (typename Prec<P>::S)(wr + g);
+    return true;
+  }
+}
+
+// Per-level parameters passed by value.
+template <class C, int Q>
+struct LevelArgs {
+  int64_t n;          // elements (row stride of the pdf arrays)
+  int64_t ld_nbr;     // row stride of the neighbour table
+  C omega;            // BGK relaxation rate of the level
+  C rho0;
+  C scale, inv_scale; // F16S scale s_L and 1/s_L
+  C wr[Q];            // w_i rho0
+  C geq[Q];           // f^eq_i(rho0, u_in) - w_i rho0 for EQ faces
+};
+
+// -------------------------------------------------------- BGK in g-form ---
+// rho = rho0 + sum g; rho u = sum c g; g_eq = w (drho + rho (3 cu + 4.5 cu^2 - 1.5 uu))
+template <class Lat, class C>
+__device__ __forceinline__ void macro_g(const C* g, C rho0, C& drho, C& rho, C* u) {
+  C s = 0, j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    s += g[i];
+#pragma unroll
+    for (int a = 0; a < Lat::D; ++a) {
+      const int ci = Lat::c(i, a);
+      if (ci > 0) j[a] += g[i];
+      if (ci < 0) j[a] -= g[i];
+    }
+  }
+  drho = s;
+  rho = rho0 + s;
+  const C inv = C(1) / rho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = a < Lat::D ? j[a] * inv : C(0);
+}
+
+template <class Lat, class C>
+__device__ __forceinline__ C geq_i(int i, C drho, C rho, const C* u, C uu) {
+  C cu = 0;
+#pragma unroll
+  for (int a = 0; a < Lat::D; ++a) {
+    const int ci = Lat::c(i, a);
+    if (ci > 0) cu += u[a];
+    if (ci < 0) cu -= u[a];
+  }
+  const C w = (C)Lat::w(i);
+  return w * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu));
+}
+
+template <class Lat, class C>
+__device__ __forceinline__ C dot_uu(const C* u) {
+  C s = 0;
+#pragma unroll
+  for (int a = 0; a < Lat::D; ++a) s += u[a] * u[a];
+  return s;
+}
+
+// ------------------------------------------------------ pull gather ------
+// g_i(x) = g*_i(nbr_i(x)) with boundary codes: BOUNCE -> g*_opp(i)(x),
+// COPY -> g*_i(x), EQ -> f^eq(rho0, u_in); MISSING gives NaN.
+template <class Lat, int P>
+__device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__ src,
+                                         const int32_t* __restrict__ nbr, int64_t x,
+                                         const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
+                                         typename Prec<P>::C* g) {
+  using C = typename Prec<P>::C;
+  int32_t j[Lat::Q];
+#pragma unroll
+  for (int i = 1; i < Lat::Q; ++i) j[i] = nbr[(int64_t)(i - 1) * a.ld_nbr + x];
+  g[0] = load_g<P>(src, x, a.wr[0], a.inv_scale);
+#pragma unroll
+  for (int i = 1; i < Lat::Q; ++i) {
+    const int32_t v = j[i];
+    const int row = (v == MLBM_NBR_BOUNCE) ? Lat::opp(i) : i;
+    const int64_t e = v >= 0 ? (int64_t)v : x;
+    C val = load_g<P>(src, (int64_t)row * a.n + e, a.wr[row], a.inv_scale);
+    if (v == MLBM_NBR_EQ) val = a.geq[i];
+    if (v == MLBM_NBR_MISSING) val = C(__builtin_nan(""));
+    g[i] = val;
+  }
+}
+
+// --------------------------------------------------- stream-collide -------
+// One thread per active element x in [0, n_act); Eq. bgk in g-form, result
+// stored coalesced in the destination array.  Blocks are remapped so that
+// each of the 8 XCDs streams a contiguous slice of the element range.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb >> 3, r = nb & 7, xcd = b & 7, k = b >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+template <class Lat, int P, int BS>
+__global__ __launch_bounds__(BS) void k_stream_collide(
+    const typename Prec<P>::S* __restrict__ src, typename Prec<P>::S* __restrict__ dst,
+    const int32_t* __restrict__ nbr, int64_t n_act,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a, uint32_t* __restrict__ status) {
+  using C = typename Prec<P>::C;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t x = blk * BS + threadIdx.x;
+  if (x >= n_act) return;
+  C g[Lat::Q];
+  gather_g<Lat, P>(src, nbr, x, a, g);
+  C drho, rho, u[3];
+  macro_g<Lat, C>(g, a.rho0, drho, rho, u);
+  const C uu = dot_uu<Lat, C>(u);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
+    ok &= store_g<P>(dst, (int64_t)i * a.n + x, gs, a.wr[i], a.scale);
+  }
+  const bool finite = (rho == rho) && (rho - rho == C(0));
+  if (!finite || !ok)
+    atomicOr(status, (finite ? 0u : (uint32_t)MLBM_STATUS_NONFINITE) |
+                         (ok ? 0u : (uint32_t)MLBM_STATUS_F16_OVERFLOW));
+}
+
+// Pre-collision moments of a g-vector into a capture record:
+// drho, u, S_ab = -(3 omega / (2 rho)) sum_i c_ia c_ib g^neq_i, g^neq.
+template <class Lat, class C, class R>
+__device__ __forceinline__ void write_record(R* __restrict__ rec, const C* g, C rho0, C omega) {
+  C drho, rho, u[3];
+  macro_g<Lat, C>(g, rho0, drho, rho, u);
+  const C uu = dot_uu<Lat, C>(u);
+  C fneq[Lat::Q];
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) fneq[i] = g[i] - geq_i<Lat, C>(i, drho, rho, u, uu);
+  rec[0] = (R)drho;
+#pragma unroll
+  for (int a = 0; a < Lat::D; ++a) rec[cap_u(Lat::D) + a] = (R)u[a];
+  const C pref = -C(1.5) * omega / rho;
+#pragma unroll
+  for (int k = 0; k < Lat::NS; ++k) {
+    const int aa = strain_a(Lat::D, k), bb = strain_b(Lat::D, k);
+    C s = 0;
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i) {
+      const int cc = Lat::c(i, aa) * Lat::c(i, bb);
+      if (cc > 0) s += fneq[i];
+      if (cc < 0) s -= fneq[i];
+    }
+    rec[cap_s(Lat::D) + k] = (R)(pref * s);
+  }
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) rec[cap_fneq(Lat::D) + i] = (R)fneq[i];
+}
+
+// Capture: pre-collision moments of the fluid source elements, gathered
+// from the same (old) array the stream-collide read.
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_capture(
+    const typename Prec<P>::S* __restrict__ src, const int32_t* __restrict__ nbr,
+    const int32_t* __restrict__ cap_elem, int64_t n_cap, typename Prec<P>::C* __restrict__ cap,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a) {
+  using C = typename Prec<P>::C;
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n_cap) return;
+  const int64_t x = cap_elem[s];
+  C g[Lat::Q];
+  gather_g<Lat, P>(src, nbr, x, a, g);
+  write_record<Lat, C>(cap + s * cap_stride(Lat::D), g, a.rho0, a.omega);
+}
+
+// --------------------------------------------------- interpolation --------
+// A record view: drho, u, S, g^neq.
+template <class Lat, class C>
+struct Rec {
+  const C* p;
+  __device__ C drho() const { return p[0]; }
+  __device__ C u(int a) const { return p[cap_u(Lat::D) + a]; }
+  __device__ C S(int k) const { return p[cap_s(Lat::D) + k]; }
+  __device__ C fneq(int i) const { return p[cap_fneq(Lat::D) + i]; }
+};
+
+// Writes the interpolated ghost: g* = g_eq(rho, u) + (1 - omega_t) g^neq
+// into the pdf array; optionally its pre-collision record.
+template <class Lat, int P>
+__device__ __forceinline__ bool emit_ghost(typename Prec<P>::S* __restrict__ pdf, int64_t x,
+                                           const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
+                                           typename Prec<P>::C drho, const typename Prec<P>::C* u,
+                                           const typename Prec<P>::C* fneq) {
+  using C = typename Prec<P>::C;
+  const C rho = a.rho0 + drho;
+  const C uu = dot_uu<Lat, C>(u);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    const C gs = geq_i<Lat, C>(i, drho, rho, u, uu) + (C(1) - a.omega) * fneq[i];
+    ok &= store_g<P>(pdf, (int64_t)i * a.n + x, gs, a.wr[i], a.scale);
+  }
+  return ok;
+}
+
+// GhostFromFiner (Sec. 2.2, Steps 1-5) of coarse level: sources are the four
+// fine children (0,0,0), (1,1,0), (1,0,1), (0,1,1) (2D: all four) read from
+// the fine capture buffer; target is the parent's centre.  Closed form of
+// the compact interpolation at the tetrahedron's centroid:
+// u = mean(u_k) - 1/4 (a_xx + a_yy + a_zz) per component.
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_fill_gff(
+    typename Prec<P>::S* __restrict__ pdf, int64_t gff_begin, int64_t n_gff,
+    const int32_t* __restrict__ slots, const typename Prec<P>::C* __restrict__ cap_fine,
+    typename Prec<P>::C* __restrict__ cap_coarse, int64_t cap_gff_begin,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C fneq_scale,
+    uint32_t* __restrict__ status) {
+  using C = typename Prec<P>::C;
+  constexpr int D = Lat::D;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n_gff) return;
+  Rec<Lat, C> r[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k].p = cap_fine + (int64_t)slots[k * n_gff + j] * cap_stride(D);
+  C u[3] = {0, 0, 0};
+  C drho = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    drho += r[k].drho();
+#pragma unroll
+    for (int b = 0; b < D; ++b) u[b] += r[k].u(b);
+  }
+  drho *= C(0.25);
+#pragma unroll
+  for (int b = 0; b < D; ++b) u[b] *= C(0.25);
+  if constexpr (D == 3) {
+    // D_x = (-H + K + M - N)/2, D_y = (-H + K - M + N)/2, D_z = (-H - K + M + N)/2
+    auto Dx = [&](int k) { return C(0.5) * (-r[0].S(k) + r[1].S(k) + r[2].S(k) - r[3].S(k)); };
+    auto Dy = [&](int k) { return C(0.5) * (-r[0].S(k) + r[1].S(k) - r[2].S(k) + r[3].S(k)); };
+    auto Dz = [&](int k) { return C(0.5) * (-r[0].S(k) - r[1].S(k) + r[2].S(k) + r[3].S(k)); };
+    // S order: xx, yy, zz, xy, yz, xz
+    const C axx = C(0.5) * Dx(0), axy = Dy(0), axz = Dz(0);
+    const C bxy = Dx(1), byy = C(0.5) * Dy(1), byz = Dz(1);
+    const C cxz = Dx(2), cyz = Dy(2), czz = C(0.5) * Dz(2);
+    const C bxx = Dx(3) - C(0.5) * axy, ayy = Dy(3) - C(0.5) * bxy;
+    const C cyy = Dy(4) - C(0.5) * byz, bzz = Dz(4) - C(0.5) * cyz;
+    const C cxx = Dx(5) - C(0.5) * axz, azz = Dz(5) - C(0.5) * cxz;
+    u[0] -= C(0.25) * (axx + ayy + azz);
+    u[1] -= C(0.25) * (bxx + byy + bzz);
+    u[2] -= C(0.25) * (cxx + cyy + czz);
+  } else {
+    // children (0,0), (1,0), (0,1), (1,1): D_x = (-P00 + P10 - P01 + P11)/2
+    auto Dx = [&](int k) { return C(0.5) * (-r[0].S(k) + r[1].S(k) - r[2].S(k) + r[3].S(k)); };
+    auto Dy = [&](int k) { return C(0.5) * (-r[0].S(k) - r[1].S(k) + r[2].S(k) + r[3].S(k)); };
+    // S order: xx, yy, xy
+    const C axx = C(0.5) * Dx(0), axy = Dy(0);
+    const C bxy = Dx(1), byy = C(0.5) * Dy(1);
+    const C bxx = Dx(2) - C(0.5) * axy, ayy = Dy(2) - C(0.5) * bxy;
+    u[0] -= C(0.25) * (axx + ayy);
+    u[1] -= C(0.25) * (bxx + byy);
+  }
+  C fneq[Lat::Q];
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i)
+    fneq[i] = C(0.25) * (r[0].fneq(i) + r[1].fneq(i) + r[2].fneq(i) + r[3].fneq(i)) * fneq_scale;
+  const bool ok = emit_ghost<Lat, P>(pdf, gff_begin + j, a, drho, u, fneq);
+  // pre-collision record of the ghost: it is a GhostFromCoarser source
+  C* rec = cap_coarse + (cap_gff_begin + j) * cap_stride(D);
+  const C rho = a.rho0 + drho;
+  rec[0] = drho;
+#pragma unroll
+  for (int b = 0; b < D; ++b) rec[cap_u(D) + b] = u[b];
+  const C pref = -C(1.5) * a.omega / rho;
+#pragma unroll
+  for (int k = 0; k < Lat::NS; ++k) {
+    const int aa = strain_a(D, k), bb = strain_b(D, k);
+    C s = 0;
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i) {
+      const int cc = Lat::c(i, aa) * Lat::c(i, bb);
+      if (cc > 0) s += fneq[i];
+      if (cc < 0) s -= fneq[i];
+    }
+    rec[cap_s(D) + k] = pref * s;
+  }
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) rec[cap_fneq(D) + i] = fneq[i];
+  if (!ok) atomicOr(status, (uint32_t)MLBM_STATUS_F16_OVERFLOW);
+}
+
+// GhostFromCoarser (Sec. 2.2) of fine level, both layers.  One work-group
+// takes GPB parent groups; the capture records of each parent's
+// neighbourhood (13 cells in 3D, 9 in 2D) are staged in LDS and shared by
+// the parent's children.  For child octant s the sources are
+// H = P, K = P + (s_x, s_y, 0), M = P + (s_x, 0, s_z), N = P + (0, s_y, s_z)
+// (2D: P, P + s_x, P + s_y, P + s_x + s_y); target at s/4.
+template <class Lat, int P>
+__global__ __launch_bounds__(64) void k_fill_gfc(
+    typename Prec<P>::S* __restrict__ pdf, int64_t n_groups,
+    const int32_t* __restrict__ grp_src, const int32_t* __restrict__ grp_child,
+    const typename Prec<P>::C* __restrict__ cap_coarse,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C fneq_scale,
+    uint32_t* __restrict__ status) {
+  using C = typename Prec<P>::C;
+  constexpr int D = Lat::D;
+  constexpr int NB = group_slots(D), NC = group_children(D);
+  constexpr int GPB = 64 / NC;
+  constexpr int ST = cap_stride(D);
+  __shared__ C sh[GPB * NB * ST];
+  const int64_t g0 = (int64_t)blockIdx.x * GPB;
+  for (int t = threadIdx.x; t < GPB * NB * ST; t += 64) {
+    const int comp = t % ST, sl = (t / ST) % NB, gl = t / (ST * NB);
+    const int64_t g = g0 + gl;
+    C v = 0;
+    if (g < n_groups) {
+      const int32_t slot = grp_src[(int64_t)sl * n_groups + g];
+      if (slot >= 0) v = cap_coarse[(int64_t)slot * ST + comp];
+    }
+    sh[t] = v;
+  }
+  __syncthreads();
+  const int gl = threadIdx.x / NC, c = threadIdx.x % NC;
+  const int64_t g = g0 + gl;
+  if (g >= n_groups) return;
+  const int32_t target = grp_child[(int64_t)c * n_groups + g];
+  if (target < 0) return;
+  const int sx = (c & 1) ? 1 : -1, sy = (c & 2) ? 1 : -1, sz = (c & 4) ? 1 : -1;
+  const C* base = sh + gl * NB * ST;
+  C u[3] = {0, 0, 0}, drho, fneq[Lat::Q];
+  if constexpr (D == 3) {
+    const Rec<Lat, C> H{base + group_slot_of(3, 0, 0, 0) * ST};
+    const Rec<Lat, C> K{base + group_slot_of(3, sx, sy, 0) * ST};
+    const Rec<Lat, C> M{base + group_slot_of(3, sx, 0, sz) * ST};
+    const Rec<Lat, C> N{base + group_slot_of(3, 0, sy, sz) * ST};
+    const C hx = C(0.5) * sx, hy = C(0.5) * sy, hz = C(0.5) * sz;
+    auto Dx = [&](int k) { return hx * (-H.S(k) + K.S(k) + M.S(k) - N.S(k)); };
+    auto Dy = [&](int k) { return hy * (-H.S(k) + K.S(k) - M.S(k) + N.S(k)); };
+    auto Dz = [&](int k) { return hz * (-H.S(k) - K.S(k) + M.S(k) + N.S(k)); };
+    const C axx = C(0.5) * Dx(0), axy = Dy(0), axz = Dz(0);
+    const C bxy = Dx(1), byy = C(0.5) * Dy(1), byz = Dz(1);
+    const C cxz = Dx(2), cyz = Dy(2), czz = C(0.5) * Dz(2);
+    const C bxx = Dx(3) - C(0.5) * axy, ayy = Dy(3) - C(0.5) * bxy;
+    const C cyy = Dy(4) - C(0.5) * byz, bzz = Dz(4) - C(0.5) * cyz;
+    const C cxx = Dx(5) - C(0.5) * axz, azz = Dz(5) - C(0.5) * cxz;
+    const C T = Dz(3) + Dx(4) + Dy(5);
+    const C ayz = T - C(2) * Dx(4), bxz = T - C(2) * Dy(5), cxy = T - C(2) * Dz(3);
+    const C sxy = C(sx * sy), syz = C(sy * sz), sxz = C(sx * sz);
+    const C w5 = C(0.625), w1 = C(0.125);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u[b] = w5 * H.u(b) + w1 * (K.u(b) + M.u(b) + N.u(b));
+    u[0] -= C(3.0 / 16.0) * (axx + ayy + azz) + C(1.0 / 16.0) * (sxy * axy + syz * ayz + sxz * axz);
+    u[1] -= C(3.0 / 16.0) * (bxx + byy + bzz) + C(1.0 / 16.0) * (sxy * bxy + syz * byz + sxz * bxz);
+    u[2] -= C(3.0 / 16.0) * (cxx + cyy + czz) + C(1.0 / 16.0) * (sxy * cxy + syz * cyz + sxz * cxz);
+    drho = w5 * H.drho() + w1 * (K.drho() + M.drho() + N.drho());
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i)
+      fneq[i] = (w5 * H.fneq(i) + w1 * (K.fneq(i) + M.fneq(i) + N.fneq(i))) * fneq_scale;
+  } else {
+    const Rec<Lat, C> R0{base + group_slot_of(2, 0, 0, 0) * ST};
+    const Rec<Lat, C> Rx{base + group_slot_of(2, sx, 0, 0) * ST};
+    const Rec<Lat, C> Ry{base + group_slot_of(2, 0, sy, 0) * ST};
+    const Rec<Lat, C> Rxy{base + group_slot_of(2, sx, sy, 0) * ST};
+    const C hx = C(0.5) * sx, hy = C(0.5) * sy;
+    auto Dx = [&](int k) { return hx * (-R0.S(k) + Rx.S(k) - Ry.S(k) + Rxy.S(k)); };
+    auto Dy = [&](int k) { return hy * (-R0.S(k) - Rx.S(k) + Ry.S(k) + Rxy.S(k)); };
+    const C axx = C(0.5) * Dx(0), axy = Dy(0);
+    const C bxy = Dx(1), byy = C(0.5) * Dy(1);
+    const C bxx = Dx(2) - C(0.5) * axy, ayy = Dy(2) - C(0.5) * bxy;
+    const C w9 = C(9.0 / 16.0), w3 = C(3.0 / 16.0), w1 = C(1.0 / 16.0);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) u[b] = w9 * R0.u(b) + w3 * (Rx.u(b) + Ry.u(b)) + w1 * Rxy.u(b);
+    u[0] -= C(3.0 / 16.0) * (axx + ayy);
+    u[1] -= C(3.0 / 16.0) * (bxx + byy);
+    drho = w9 * R0.drho() + w3 * (Rx.drho() + Ry.drho()) + w1 * Rxy.drho();
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i)
+      fneq[i] = (w9 * R0.fneq(i) + w3 * (Rx.fneq(i) + Ry.fneq(i)) + w1 * Rxy.fneq(i)) * fneq_scale;
+  }
+  if (!emit_ghost<Lat, P>(pdf, target, a, drho, u, fneq))
+    atomicOr(status, (uint32_t)MLBM_STATUS_F16_OVERFLOW);
+}
+
+// -------------------------------------------------------------- init ------
+// f = f^eq(rho, u) + f^neq(S) with f^neq_i = -(w_i rho/(cs^2 omega)) Q_i:S,
+// computed in FP64 and returned as g = f - w rho0.
+template <class Lat>
+__device__ __forceinline__ void init_g(const double* __restrict__ rho_in,
+                                       const double* __restrict__ u_in,
+                                       const double* __restrict__ S_in, int64_t nf, int64_t x,
+                                       double rho0, double omega, double* g) {
+  const double rho = rho_in[x];
+  double u[3] = {0, 0, 0}, S[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < Lat::D; ++a) u[a] = u_in[(int64_t)a * nf + x];
+  if (S_in) {
+#pragma unroll
+    for (int k = 0; k < Lat::NS; ++k) S[k] = S_in[(int64_t)k * nf + x];
+  }
+  const double uu = dot_uu<Lat, double>(u);
+  double trS = 0;
+#pragma unroll
+  for (int a = 0; a < Lat::D; ++a) trS += S[a];
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    double cu = 0, cSc = 0;
+#pragma unroll
+    for (int a = 0; a < Lat::D; ++a) cu += Lat::c(i, a) * u[a];
+#pragma unroll
+    for (int k = 0; k < Lat::NS; ++k) {
+      const int aa = strain_a(Lat::D, k), bb = strain_b(Lat::D, k);
+      cSc += (aa == bb ? 1.0 : 2.0) * Lat::c(i, aa) * Lat::c(i, bb) * S[k];
+    }
+    const double w = Lat::w(i);
+    const double feq = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    const double QS = cSc - trS / 3.0;
+    const double fneq = -(w * rho / (omega / 3.0)) * QS;
+    g[i] = feq + fneq - w * rho0;
+  }
+}
+
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho_in,
+                                              const double* __restrict__ u_in,
+                                              const double* __restrict__ S_in, int64_t nf,
+                                              typename Prec<P>::S* __restrict__ pdf,
+                                              const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+                                              double rho0, double omega) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= nf) return;
+  double g[Lat::Q];
+  init_g<Lat>(rho_in, u_in, S_in, nf, x, rho0, omega, g);
+  double drho, rho, u[3];
+  macro_g<Lat, double>(g, rho0, drho, rho, u);
+  const double uu = dot_uu<Lat, double>(u);
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    const double gs = g[i] + omega * (geq_i<Lat, double>(i, drho, rho, u, uu) - g[i]);
+    store_g<P>(pdf, (int64_t)i * a.n + x, (typename Prec<P>::C)gs, a.wr[i], a.scale);
+  }
+}
+
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_init_capture(
+    const double* __restrict__ rho_in, const double* __restrict__ u_in,
+    const double* __restrict__ S_in, int64_t nf, const int32_t* __restrict__ cap_elem,
+    int64_t n_cap, typename Prec<P>::C* __restrict__ cap, double rho0, double omega) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n_cap) return;
+  double g[Lat::Q];
+  init_g<Lat>(rho_in, u_in, S_in, nf, cap_elem[s], rho0, omega, g);
+  write_record<Lat, double>(cap + s * cap_stride(Lat::D), g, rho0, omega);
+}
+
+// Max |f - w rho0| over the initial state of a level (FP16 scale choice).
+template <class Lat>
+__global__ __launch_bounds__(256) void k_init_maxdev(const double* __restrict__ rho_in,
+                                                     const double* __restrict__ u_in,
+                                                     const double* __restrict__ S_in, int64_t nf,
+                                                     double rho0, double omega,
+                                                     double* __restrict__ partial) {
+  __shared__ double sm[256];
+  double m = 0;
+  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < nf;
+       x += (int64_t)gridDim.x * 256) {
+    double g[Lat::Q];
+    init_g<Lat>(rho_in, u_in, S_in, nf, x, rho0, omega, g);
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i) m = fmax(m, fabs(g[i]));
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
+// --------------------------------------------------------- state I/O ------
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_get_pdf(const typename Prec<P>::S* __restrict__ pdf,
+                                                 int64_t n, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+                                                 double* __restrict__ out) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= n) return;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i)
+    out[(int64_t)i * n + x] = (double)a.wr[i] + (double)load_g<P>(pdf, (int64_t)i * n + x, a.wr[i], a.inv_scale);
+}
+
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_set_pdf(typename Prec<P>::S* __restrict__ pdf, int64_t n,
+                                                 const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+                                                 const double* __restrict__ in) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= n) return;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i)
+    store_g<P>(pdf, (int64_t)i * n + x, (typename Prec<P>::C)(in[(int64_t)i * n + x] - (double)a.wr[i]),
+               a.wr[i], a.scale);
+}
+
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_get_moments(const typename Prec<P>::S* __restrict__ pdf,
+                                                     int64_t nf,
+                                                     const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+                                                     double* __restrict__ out) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= nf) return;
+  double g[Lat::Q];
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) g[i] = (double)load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[i], a.inv_scale);
+  double drho, rho, u[3];
+  macro_g<Lat, double>(g, (double)a.rho0, drho, rho, u);
+  out[x] = rho;
+#pragma unroll
+  for (int b = 0; b < Lat::D; ++b) out[(int64_t)(1 + b) * nf + x] = u[b];
+}
+
+// ------------------------------------------------------- diagnostics ------
+// Per-block FP64 partial sums (deterministic tree in LDS).  Mass is summed
+// as deviations drho; the host-side constant rho0 * n_fluid is added in the
+// final pass.
+constexpr int DIAG_BLOCKS = 512;
+constexpr int DIAG_VALS = 5;  // drho, ke, fx, fy, fz
+
+__device__ __forceinline__ void block_sum(double* sm, double v, double* out) {
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+  __syncthreads();
+}
+
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_diag_partial(
+    const typename Prec<P>::S* __restrict__ pdf, int64_t nf, const int32_t* __restrict__ bounce,
+    int64_t n_bounce, const LevelArgs<typename Prec<P>::C, Lat::Q> a, double* __restrict__ partial) {
+  __shared__ double sm[256];
+  double m = 0, ke = 0, F[3] = {0, 0, 0};
+  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < nf;
+       x += (int64_t)gridDim.x * 256) {
+    double g[Lat::Q];
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i) g[i] = (double)load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[i], a.inv_scale);
+    double drho, rho, u[3];
+    macro_g<Lat, double>(g, (double)a.rho0, drho, rho, u);
+    m += drho;
+    ke += 0.5 * rho * dot_uu<Lat, double>(u);
+  }
+  // momentum exchange with halfway bounce-back: 2 c_i f*_i(x) for each link
+  // whose pull source x - c_j is solid, i = opp(j) pointing into the solid
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n_bounce;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t x = bounce[t];
+    const int j = bounce[n_bounce + t];
+    const int i = Lat::opp(j);
+    const double f = (double)a.wr[i] + (double)load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[i], a.inv_scale);
+#pragma unroll
+    for (int b = 0; b < Lat::D; ++b) F[b] += 2.0 * Lat::c(i, b) * f;
+  }
+  double* out = partial + (int64_t)blockIdx.x * DIAG_VALS;
+  block_sum(sm, m, out + 0);
+  block_sum(sm, ke, out + 1);
+  block_sum(sm, F[0], out + 2);
+  block_sum(sm, F[1], out + 3);
+  block_sum(sm, F[2], out + 4);
+}
+
+struct DiagLevel {
+  double vol, force_scale, rho0_nf;
+};
+
+// Final pass: one block; levels summed coarse to fine in fixed order.
+__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partial, int nlev,
+                                                     const DiagLevel* __restrict__ lv, uint32_t mask,
+                                                     int d, double* __restrict__ out) {
+  __shared__ double sm[256];
+  __shared__ double tot[DIAG_VALS];
+  if (threadIdx.x < DIAG_VALS) tot[threadIdx.x] = 0;
+  __syncthreads();
+  for (int k = 0; k < nlev; ++k) {
+    for (int v = 0; v < DIAG_VALS; ++v) {
+      double s = 0;
+      for (int b = threadIdx.x; b < DIAG_BLOCKS; b += 256)
+        s += partial[((int64_t)k * DIAG_BLOCKS + b) * DIAG_VALS + v];
+      double r;
+      block_sum(sm, s, &sm[0]);
+      if (threadIdx.x == 0) {
+        r = sm[0];
+        if (v == 0) tot[0] += lv[k].vol * (lv[k].rho0_nf + r);
+        else if (v == 1) tot[1] += lv[k].vol * r;
+        else tot[v] += lv[k].force_scale * r;
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    int o = 0;
+    if (mask & MLBM_DIAG_MASS) out[o++] = tot[0];
+    if (mask & MLBM_DIAG_KE) out[o++] = tot[1];
+    if (mask & MLBM_DIAG_FORCE)
+      for (int b = 0; b < d; ++b) out[o++] = tot[2 + b];
+  }
+}
+
+}  // namespace mlbm

@@ -1,0 +1,722 @@
+// Host plan builder: decodes leaf treeIDs (Sec. 3.1), classifies ghost
+// elements (Sec. 2.2), lays out the level-wise element lists (Sec. 3.2) and
+// builds the neighbour, interpolation-source and capture tables that the
+// device kernels consume.
+#include <algorithm>
+#include <cstdarg>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace mlbm {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+int32_t fail(int32_t code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+namespace {
+
+constexpr int32_t V_EMPTY = -1, V_SOLID = -2, V_REFINED = -3, V_GFF = -4,
+                  V_GFC_IN = -5, V_GFC_OUT = -6;
+
+struct MeshError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+uint64_t level_first_id(int L, int d) {
+  uint64_t s = 0;
+  for (int k = 0; k < L; ++k) s += (uint64_t)1 << (d * k);
+  return s;
+}
+
+uint64_t morton(const int64_t* c, int d, int L) {
+  uint64_t m = 0;
+  for (int b = 0; b < L; ++b)
+    for (int a = 0; a < d; ++a) m |= (uint64_t)((c[a] >> b) & 1) << (d * b + a);
+  return m;
+}
+
+struct Geom {
+  int d = 3, level0 = 0;
+  int64_t o[3] = {0, 0, 0}, e[3] = {1, 1, 1};
+  bool per[3] = {false, false, false};
+  int faces[6] = {0, 0, 0, 0, 0, 0};
+  int64_t lo(int a, int L) const { return o[a] << (L - level0); }
+  int64_t hi(int a, int L) const { return (o[a] + e[a]) << (L - level0); }
+  // wraps periodic axes in place; returns a bit mask of crossed faces
+  int wrap(int64_t* c, int L) const {
+    int out = 0;
+    for (int a = 0; a < d; ++a) {
+      const int64_t l = lo(a, L), h = hi(a, L);
+      if (per[a]) {
+        const int64_t ext = h - l;
+        int64_t r = (c[a] - l) % ext;
+        if (r < 0) r += ext;
+        c[a] = l + r;
+      } else if (c[a] < l) {
+        out |= 1 << (2 * a);
+      } else if (c[a] >= h) {
+        out |= 1 << (2 * a + 1);
+      }
+    }
+    return out;
+  }
+  int32_t face_code(int crossed) const {
+    bool eq = false, cp = false;
+    for (int f = 0; f < 2 * d; ++f) {
+      if (!(crossed & (1 << f))) continue;
+      eq |= faces[f] == MLBM_FACE_EQ;
+      cp |= faces[f] == MLBM_FACE_COPY;
+    }
+    return eq ? MLBM_NBR_EQ : (cp ? MLBM_NBR_COPY : MLBM_NBR_BOUNCE);
+  }
+};
+
+// Position -> value map of one level: a dense grid over the level's
+// bounding region when that is compact, a hash map otherwise.
+struct CellMap {
+  int d = 3, L = 0;
+  int64_t lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+  bool dense = true;
+  std::vector<int32_t> grid;
+  std::unordered_map<int64_t, int32_t> hm;
+
+  bool in_box(const int64_t* c) const {
+    for (int a = 0; a < d; ++a)
+      if (c[a] < lo[a] || c[a] >= lo[a] + ext[a]) return false;
+    return true;
+  }
+  int64_t dkey(const int64_t* c) const {
+    int64_t k = 0;
+    for (int a = d - 1; a >= 0; --a) k = k * ext[a] + (c[a] - lo[a]);
+    return k;
+  }
+  int64_t skey(const int64_t* c) const {
+    int64_t k = 0;
+    for (int a = d - 1; a >= 0; --a) k = (k << L) | c[a];
+    return k;
+  }
+  int32_t get(const int64_t* c) const {
+    if (dense) return in_box(c) ? grid[dkey(c)] : V_EMPTY;
+    auto it = hm.find(skey(c));
+    return it == hm.end() ? V_EMPTY : it->second;
+  }
+  void set(const int64_t* c, int32_t v) {
+    if (dense) {
+      if (!in_box(c)) throw MeshError("internal: position outside level map");
+      grid[dkey(c)] = v;
+    } else {
+      hm[skey(c)] = v;
+    }
+  }
+};
+
+struct LevelWork {
+  std::vector<int64_t> fluid, solid;  // [count*d]
+  int64_t bb_lo[3], bb_hi[3];
+  bool bb_set = false;
+  CellMap map;
+  std::vector<int64_t> gff, gfc;      // provisional ghost coords
+  int64_t deeper = 0;
+};
+
+void extend_bb(LevelWork& w, const int64_t* c, int d) {
+  if (!w.bb_set) {
+    for (int a = 0; a < d; ++a) w.bb_lo[a] = w.bb_hi[a] = c[a];
+    w.bb_set = true;
+    return;
+  }
+  for (int a = 0; a < d; ++a) {
+    w.bb_lo[a] = std::min(w.bb_lo[a], c[a]);
+    w.bb_hi[a] = std::max(w.bb_hi[a], c[a]);
+  }
+}
+
+template <class F>
+void for_offsets(int d, int r, F&& fn) {
+  int64_t o[3] = {0, 0, 0};
+  const int side = 2 * r + 1;
+  int total = 1;
+  for (int a = 0; a < d; ++a) total *= side;
+  for (int k = 0; k < total; ++k) {
+    int t = k, dist = 0;
+    for (int a = 0; a < d; ++a) {
+      o[a] = (t % side) - r;
+      t /= side;
+      dist = std::max(dist, (int)std::llabs(o[a]));
+    }
+    if (dist) fn(o, dist);
+  }
+}
+
+template <class Lat>
+void velocity(int i, int64_t* v) {
+  for (int a = 0; a < Lat::D; ++a) v[a] = Lat::c(i, a);
+}
+
+void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
+                const uint64_t* solid_ids, int64_t n_solids) {
+  const int d = P.d, q = P.q;
+  Geom g;
+  g.d = d;
+  g.level0 = P.level0;
+  for (int a = 0; a < d; ++a) {
+    g.o[a] = P.origin[a];
+    g.e[a] = P.extent[a];
+    g.per[a] = P.faces[2 * a] == MLBM_FACE_PERIODIC;
+  }
+  for (int f = 0; f < 2 * d; ++f) g.faces[f] = P.faces[f];
+  const int max_level = d == 3 ? 20 : 30;
+
+  // ---- decode ------------------------------------------------------
+  auto decode = [&](uint64_t t, int& L, int64_t* c) {
+    L = 0;
+    while (L < max_level && level_first_id(L + 1, d) <= t) ++L;
+    if (L >= max_level) throw MeshError("treeID beyond the supported depth");
+    uint64_t off = t - level_first_id(L, d);
+    for (int a = 0; a < d; ++a) c[a] = 0;
+    for (int b = 0; b < L; ++b)
+      for (int a = 0; a < d; ++a) c[a] |= (int64_t)((off >> (d * b + a)) & 1) << b;
+  };
+  std::vector<int> lvl_leaf(n_leaves), lvl_solid(n_solids);
+  std::vector<int64_t> c_leaf(n_leaves * d), c_solid(n_solids * d);
+  int lmax = P.level0;
+  for (int64_t i = 0; i < n_leaves; ++i) {
+    decode(leaf_ids[i], lvl_leaf[i], &c_leaf[i * d]);
+    lmax = std::max(lmax, lvl_leaf[i]);
+  }
+  for (int64_t i = 0; i < n_solids; ++i) {
+    decode(solid_ids[i], lvl_solid[i], &c_solid[i * d]);
+    lmax = std::max(lmax, lvl_solid[i]);
+  }
+  const int L0 = P.level0, nlev = lmax - L0 + 1;
+  std::vector<LevelWork> W(nlev);
+  unsigned __int128 volume = 0;
+  auto place = [&](int L, const int64_t* c, bool solid) {
+    if (L < L0) throw MeshError("element coarser than level0");
+    for (int a = 0; a < d; ++a)
+      if (c[a] < g.lo(a, L) || c[a] >= g.hi(a, L))
+        throw MeshError("element outside the domain box");
+    auto& w = W[L - L0];
+    auto& vec = solid ? w.solid : w.fluid;
+    for (int a = 0; a < d; ++a) vec.push_back(c[a]);
+    volume += (unsigned __int128)1 << (d * (lmax - L));
+    // bounding boxes of this level and all coarser ones (ancestors)
+    for (int K = L0; K <= L; ++K) {
+      int64_t anc[3];
+      for (int a = 0; a < d; ++a) anc[a] = c[a] >> (L - K);
+      extend_bb(W[K - L0], anc, d);
+      if (K < L) W[K - L0].deeper++;
+    }
+  };
+  for (int64_t i = 0; i < n_leaves; ++i) place(lvl_leaf[i], &c_leaf[i * d], false);
+  for (int64_t i = 0; i < n_solids; ++i) place(lvl_solid[i], &c_solid[i * d], true);
+  unsigned __int128 box = 1;
+  for (int a = 0; a < d; ++a) box *= (unsigned __int128)g.e[a];
+  box <<= d * (lmax - L0);
+  if (volume != box) throw MeshError("leaves and solids do not tile the domain box");
+
+  // ---- level maps ---------------------------------------------------
+  for (int k = 0; k < nlev; ++k) {
+    const int L = L0 + k;
+    auto& w = W[k];
+    auto& m = w.map;
+    m.d = d;
+    m.L = L;
+    unsigned __int128 vol = 1;
+    for (int a = 0; a < d; ++a) {
+      if (g.per[a] || !w.bb_set) {
+        m.lo[a] = g.lo(a, L);
+        m.ext[a] = g.hi(a, L) - g.lo(a, L);
+      } else {
+        const int64_t lo = std::max(g.lo(a, L), w.bb_lo[a] - 2);
+        const int64_t hi = std::min(g.hi(a, L), w.bb_hi[a] + 3);
+        m.lo[a] = lo;
+        m.ext[a] = hi - lo;
+      }
+      vol *= (unsigned __int128)m.ext[a];
+    }
+    const int64_t count = (int64_t)(w.fluid.size() + w.solid.size()) / d + w.deeper;
+    m.dense = vol <= (unsigned __int128)(16 * count + (1 << 24));
+    if (m.dense) m.grid.assign((size_t)vol, V_EMPTY);
+  }
+  for (int k = 0; k < nlev; ++k) {
+    auto& w = W[k];
+    const int64_t nf = (int64_t)w.fluid.size() / d;
+    for (int64_t i = 0; i < nf; ++i) {
+      if (w.map.get(&w.fluid[i * d]) != V_EMPTY) throw MeshError("duplicate leaf");
+      w.map.set(&w.fluid[i * d], (int32_t)i);
+    }
+    for (size_t i = 0; i < w.solid.size() / d; ++i) {
+      if (w.map.get(&w.solid[i * d]) != V_EMPTY) throw MeshError("overlapping elements");
+      w.map.set(&w.solid[i * d], V_SOLID);
+    }
+  }
+  // refined positions: ancestors of every deeper leaf or solid
+  auto mark_ancestors = [&](int L, const int64_t* c) {
+    for (int K = L - 1; K >= L0; --K) {
+      int64_t anc[3];
+      for (int a = 0; a < d; ++a) anc[a] = c[a] >> (L - K);
+      auto& m = W[K - L0].map;
+      const int32_t v = m.get(anc);
+      if (v == V_REFINED) return;  // coarser ancestors already marked
+      if (v != V_EMPTY) throw MeshError("overlapping elements");
+      m.set(anc, V_REFINED);
+    }
+  };
+  for (int64_t i = 0; i < n_leaves; ++i) mark_ancestors(lvl_leaf[i], &c_leaf[i * d]);
+  for (int64_t i = 0; i < n_solids; ++i) mark_ancestors(lvl_solid[i], &c_solid[i * d]);
+  std::vector<int>().swap(lvl_leaf);
+  std::vector<int64_t>().swap(c_leaf);
+
+  // ---- ghost classification -------------------------------------------
+  for (int k = 0; k < nlev; ++k) {
+    const int L = L0 + k;
+    auto& w = W[k];
+    auto& m = w.map;
+    const int64_t nf = (int64_t)w.fluid.size() / d;
+    for (int64_t i = 0; i < nf; ++i) {
+      const int64_t* x = &w.fluid[i * d];
+      if (L < lmax) {
+        for_offsets(d, 1, [&](const int64_t* o, int) {
+          int64_t y[3];
+          for (int a = 0; a < d; ++a) y[a] = x[a] + o[a];
+          if (g.wrap(y, L)) return;
+          if (m.get(y) == V_REFINED) {
+            m.set(y, V_GFF);
+            for (int a = 0; a < d; ++a) w.gff.push_back(y[a]);
+          }
+        });
+      }
+      if (L > L0) {
+        for_offsets(d, 2, [&](const int64_t* o, int dist) {
+          int64_t y[3];
+          for (int a = 0; a < d; ++a) y[a] = x[a] + o[a];
+          if (g.wrap(y, L)) return;
+          const int32_t v = m.get(y);
+          if (v == V_EMPTY) {
+            m.set(y, dist == 1 ? V_GFC_IN : V_GFC_OUT);
+            for (int a = 0; a < d; ++a) w.gfc.push_back(y[a]);
+          } else if (v == V_GFC_OUT && dist == 1) {
+            m.set(y, V_GFC_IN);
+          }
+        });
+      }
+    }
+  }
+
+  // ---- layout -------------------------------------------------------
+  P.lv.assign(nlev, LevelPlan());
+  for (int k = 0; k < nlev; ++k) {
+    const int L = L0 + k;
+    auto& w = W[k];
+    auto& lp = P.lv[k];
+    lp.level = L;
+    std::vector<int64_t> inner, outer;
+    for (size_t i = 0; i < w.gfc.size() / d; ++i) {
+      const int64_t* y = &w.gfc[i * d];
+      auto& dst = (w.map.get(y) == V_GFC_IN) ? inner : outer;
+      for (int a = 0; a < d; ++a) dst.push_back(y[a]);
+    }
+    std::vector<int64_t> all;
+    const std::vector<int64_t>* parts[4] = {&w.fluid, &inner, &outer, &w.gff};
+    int64_t counts[4];
+    lp.tid.clear();
+    for (int p = 0; p < 4; ++p) {
+      const auto& v = *parts[p];
+      const int64_t n = (int64_t)v.size() / d;
+      counts[p] = n;
+      std::vector<uint64_t> key(n);
+      for (int64_t i = 0; i < n; ++i) key[i] = morton(&v[i * d], d, L);
+      std::vector<int64_t> ord(n);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+      const uint64_t first = level_first_id(L, d);
+      for (int64_t i = 0; i < n; ++i) {
+        lp.tid.push_back(first + key[ord[i]]);
+        for (int a = 0; a < d; ++a) all.push_back(v[ord[i] * d + a]);
+      }
+    }
+    lp.n_fluid = counts[0];
+    lp.n_inner = counts[1];
+    lp.n_outer = counts[2];
+    lp.n_gff = counts[3];
+    lp.n = counts[0] + counts[1] + counts[2] + counts[3];
+    if (lp.n >= INT32_MAX) throw MeshError("level has too many elements for int32 indices");
+    lp.coords.resize((size_t)d * lp.n);
+    for (int64_t i = 0; i < lp.n; ++i) {
+      for (int a = 0; a < d; ++a) lp.coords[(size_t)a * lp.n + i] = (int32_t)all[i * d + a];
+      w.map.set(&all[i * d], (int32_t)i);
+    }
+    std::vector<int64_t>().swap(w.gfc);
+    std::vector<int64_t>().swap(w.gff);
+    std::vector<int64_t>().swap(w.fluid);
+    w.fluid.swap(all);  // keep layout-ordered coords
+  }
+
+  // ---- neighbours ----------------------------------------------------
+  for (int k = 0; k < nlev; ++k) {
+    const int L = L0 + k;
+    auto& w = W[k];
+    auto& lp = P.lv[k];
+    const int64_t n = lp.n;
+    lp.nbr.assign((size_t)(q - 1) * n, MLBM_NBR_MISSING);
+    for (int64_t x = 0; x < n; ++x) {
+      const int64_t* cx = &w.fluid[x * d];
+      for (int i = 1; i < q; ++i) {
+        int64_t y[3], v[3];
+        if (d == 3) velocity<D3Q19>(i, v); else velocity<D2Q9>(i, v);
+        for (int a = 0; a < d; ++a) y[a] = cx[a] - v[a];
+        const int crossed = g.wrap(y, L);
+        int32_t code;
+        if (crossed) {
+          code = g.face_code(crossed);
+        } else {
+          const int32_t val = w.map.get(y);
+          code = val >= 0 ? val : (val == V_SOLID ? MLBM_NBR_BOUNCE : MLBM_NBR_MISSING);
+        }
+        lp.nbr[(size_t)(i - 1) * n + x] = code;
+      }
+    }
+    const int64_t act = lp.n_active_max();
+    for (int i = 1; i < q; ++i)
+      for (int64_t x = 0; x < act; ++x)
+        if (lp.nbr[(size_t)(i - 1) * n + x] == MLBM_NBR_MISSING) {
+          char msg[160];
+          snprintf(msg, sizeof msg, "level %d: updated element %llu lacks a neighbour", L,
+                   (unsigned long long)lp.tid[x]);
+          throw MeshError(msg);
+        }
+    for (int i = 1; i < q; ++i)
+      for (int64_t x = 0; x < lp.n_fluid; ++x)
+        if (lp.nbr[(size_t)(i - 1) * n + x] == MLBM_NBR_BOUNCE) {
+          lp.bounce.push_back((int32_t)x);
+          lp.bounce.push_back(i);
+        }
+    // reorder bounce pairs into [2][n] (element ascending within direction)
+    std::vector<int32_t> b((size_t)lp.bounce.size());
+    const int64_t nb = (int64_t)lp.bounce.size() / 2;
+    for (int64_t j = 0; j < nb; ++j) {
+      b[j] = lp.bounce[2 * j];
+      b[nb + j] = lp.bounce[2 * j + 1];
+    }
+    lp.bounce.swap(b);
+  }
+
+  // ---- interpolation sources -------------------------------------------
+  static const int gff3[4][3] = {{0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+  static const int gff2[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+  for (int k = 0; k < nlev; ++k) {
+    const int L = L0 + k;
+    auto& lp = P.lv[k];
+    const int64_t n = lp.n;
+    // GhostFromFiner: four fluid children on L+1
+    lp.gff_src.assign((size_t)4 * lp.n_gff, -1);
+    for (int64_t j = 0; j < lp.n_gff; ++j) {
+      const int64_t x = lp.n_fluid + lp.n_gfc() + j;
+      for (int s = 0; s < 4; ++s) {
+        int64_t ch[3];
+        for (int a = 0; a < d; ++a)
+          ch[a] = 2 * (int64_t)lp.coords[(size_t)a * n + x] + (d == 3 ? gff3[s][a] : gff2[s][a]);
+        const int32_t v = W[k + 1].map.get(ch);
+        if (v < 0 || v >= P.lv[k + 1].n_fluid)
+          throw MeshError("GhostFromFiner source is not fluid");
+        lp.gff_src[(size_t)s * lp.n_gff + j] = v;
+      }
+    }
+    // GhostFromCoarser: parent H and K, M, N (3D) or the square (2D)
+    const int64_t ng = lp.n_gfc();
+    lp.gfc_src.assign((size_t)4 * ng, -1);
+    if (ng) {
+      const auto& cp = P.lv[k - 1];
+      const int64_t cgff = cp.n_fluid + cp.n_gfc();
+      for (int64_t j = 0; j < ng; ++j) {
+        const int64_t x = lp.n_fluid + j;
+        int64_t par[3], s[3];
+        for (int a = 0; a < d; ++a) {
+          const int64_t c = lp.coords[(size_t)a * n + x];
+          par[a] = c >> 1;
+          s[a] = (c & 1) ? 1 : -1;
+        }
+        int64_t off[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        if (d == 3) {
+          off[1][0] = s[0]; off[1][1] = s[1];
+          off[2][0] = s[0]; off[2][2] = s[2];
+          off[3][1] = s[1]; off[3][2] = s[2];
+        } else {
+          off[1][0] = s[0];
+          off[2][1] = s[1];
+          off[3][0] = s[0]; off[3][1] = s[1];
+        }
+        for (int t = 0; t < 4; ++t) {
+          int64_t y[3];
+          for (int a = 0; a < d; ++a) y[a] = par[a] + off[t][a];
+          if (g.wrap(y, L - 1)) throw MeshError("GhostFromCoarser source outside the domain");
+          const int32_t v = W[k - 1].map.get(y);
+          const bool fluid = v >= 0 && v < cp.n_fluid;
+          const bool ghost_ff = v >= cgff;
+          if (t == 0 ? !fluid : !(fluid || ghost_ff))
+            throw MeshError("GhostFromCoarser source is not fluid or GhostFromFiner");
+          lp.gfc_src[(size_t)t * ng + j] = v;
+        }
+      }
+    }
+  }
+
+  // ---- capture sets, slots, parent groups -------------------------------
+  std::vector<std::vector<int32_t>> slot_of(nlev);
+  for (int k = 0; k < nlev; ++k) {
+    auto& lp = P.lv[k];
+    std::vector<char> mark((size_t)lp.n_fluid, 0);
+    if (k + 1 < nlev) {
+      const auto& fp = P.lv[k + 1];
+      for (int32_t v : fp.gfc_src)
+        if (v >= 0 && v < lp.n_fluid) mark[v] = 1;
+    }
+    if (k > 0) {
+      const auto& cpl = P.lv[k - 1];
+      for (int32_t v : cpl.gff_src)
+        if (v >= 0 && v < lp.n_fluid) mark[v] = 1;
+    }
+    slot_of[k].assign((size_t)lp.n, -1);
+    lp.cap_elem.clear();
+    for (int64_t x = 0; x < lp.n_fluid; ++x)
+      if (mark[x]) {
+        slot_of[k][x] = (int32_t)lp.cap_elem.size();
+        lp.cap_elem.push_back((int32_t)x);
+      }
+    const int64_t gb = lp.n_fluid + lp.n_gfc();
+    for (int64_t j = 0; j < lp.n_gff; ++j)
+      slot_of[k][gb + j] = (int32_t)(lp.n_cap_fluid() + j);
+  }
+  for (int k = 0; k < nlev; ++k) {
+    auto& lp = P.lv[k];
+    lp.gff_slot.assign((size_t)4 * lp.n_gff, -1);
+    for (size_t t = 0; t < lp.gff_src.size(); ++t) {
+      lp.gff_slot[t] = slot_of[k + 1][lp.gff_src[t]];
+      if (lp.gff_slot[t] < 0) throw MeshError("internal: GhostFromFiner source not captured");
+    }
+    const int64_t ng = lp.n_gfc();
+    if (!ng) continue;
+    const int L = L0 + k;
+    const int64_t n = lp.n;
+    // parents in ascending element order of the coarse level
+    std::vector<std::pair<int32_t, int64_t>> par;  // (parent elem, ghost j)
+    par.reserve(ng);
+    for (int64_t j = 0; j < ng; ++j) par.emplace_back(lp.gfc_src[j], j);
+    std::sort(par.begin(), par.end());
+    const int NB = group_slots(d), NC = group_children(d);
+    std::vector<int32_t> parents;
+    for (size_t t = 0; t < par.size(); ++t)
+      if (t == 0 || par[t].first != par[t - 1].first) parents.push_back(par[t].first);
+    lp.n_groups = (int64_t)parents.size();
+    lp.grp_src.assign((size_t)NB * lp.n_groups, -1);
+    lp.grp_child.assign((size_t)NC * lp.n_groups, -1);
+    const auto& cp = P.lv[k - 1];
+    for (int64_t gi = 0; gi < lp.n_groups; ++gi) {
+      const int32_t pe = parents[gi];
+      int64_t pc[3];
+      for (int a = 0; a < d; ++a) pc[a] = cp.coords[(size_t)a * cp.n + pe];
+      for_offsets(d, 1, [&](const int64_t* o, int) {
+        const int sl = group_slot_of(d, (int)o[0], (int)o[1], d == 3 ? (int)o[2] : 0);
+        if (sl < 0) return;
+        int64_t y[3];
+        for (int a = 0; a < d; ++a) y[a] = pc[a] + o[a];
+        if (g.wrap(y, L - 1)) return;
+        const int32_t v = W[k - 1].map.get(y);
+        if (v >= 0) lp.grp_src[(size_t)sl * lp.n_groups + gi] = slot_of[k - 1][v];
+      });
+      lp.grp_src[(size_t)group_parent_slot(d) * lp.n_groups + gi] = slot_of[k - 1][pe];
+      // every source a present child uses must have a capture slot
+      for (int c = 0; c < NC; ++c) {
+        int64_t ch[3];
+        for (int a = 0; a < d; ++a) ch[a] = 2 * pc[a] + ((c >> a) & 1);
+        const int32_t v = W[k].map.get(ch);
+        if (!(v >= lp.n_fluid && v < lp.n_fluid + ng)) continue;
+        const int j = (int)(v - lp.n_fluid);
+        for (int t = 0; t < 4; ++t) {
+          const int32_t e = lp.gfc_src[(size_t)t * ng + j];
+          int64_t o3[3] = {0, 0, 0};
+          for (int a = 0; a < d; ++a) o3[a] = (int64_t)cp.coords[(size_t)a * cp.n + e] - pc[a];
+          // undo the periodic wrap of the offset
+          for (int a = 0; a < d; ++a) {
+            const int64_t ext = g.hi(a, L - 1) - g.lo(a, L - 1);
+            if (o3[a] > 1) o3[a] -= ext;
+            if (o3[a] < -1) o3[a] += ext;
+          }
+          const int sl = group_slot_of(d, (int)o3[0], (int)o3[1], (int)o3[2]);
+          if (sl < 0 || lp.grp_src[(size_t)sl * lp.n_groups + gi] != slot_of[k - 1][e] ||
+              slot_of[k - 1][e] < 0)
+            throw MeshError("internal: GhostFromCoarser source slot mismatch");
+        }
+      }
+      for (int c = 0; c < NC; ++c) {
+        int64_t ch[3];
+        for (int a = 0; a < d; ++a) ch[a] = 2 * pc[a] + ((c >> a) & 1);
+        const int32_t v = W[k].map.get(ch);
+        if (v >= lp.n_fluid && v < lp.n_fluid + ng)
+          lp.grp_child[(size_t)c * lp.n_groups + gi] = v;
+      }
+    }
+    (void)n;
+    (void)L;
+  }
+}
+
+}  // namespace
+}  // namespace mlbm
+
+using namespace mlbm;
+
+extern "C" {
+
+const char* mlbm_error_string(int32_t code) {
+  switch (code) {
+    case MLBM_OK: return "ok";
+    case MLBM_E_ARG: return "invalid argument";
+    case MLBM_E_MESH: return "invalid mesh";
+    case MLBM_E_STATE: return "call out of order";
+    case MLBM_E_HIP: return "HIP runtime error";
+    case MLBM_E_OOM: return "host out of memory";
+    default: return "unknown error";
+  }
+}
+
+const char* mlbm_last_error(void) { return g_last_error.c_str(); }
+
+int32_t mlbm_lattice(int32_t stencil, int32_t* q, int32_t* c, double* w) {
+  if (stencil != MLBM_D2Q9 && stencil != MLBM_D3Q19)
+    return fail(MLBM_E_ARG, "unknown stencil %d", stencil);
+  const int Q = stencil_q(stencil), D = stencil_d(stencil);
+  if (q) *q = Q;
+  for (int i = 0; i < Q; ++i) {
+    for (int a = 0; a < D; ++a)
+      if (c) c[i * D + a] = stencil == MLBM_D2Q9 ? D2Q9::c(i, a) : D3Q19::c(i, a);
+    if (w) w[i] = stencil == MLBM_D2Q9 ? D2Q9::w(i) : D3Q19::w(i);
+  }
+  return MLBM_OK;
+}
+
+int32_t mlbm_plan_create(int32_t stencil, int32_t level0, const int32_t* box_origin,
+                         const int32_t* box_extent, const int32_t* face_bc,
+                         const uint64_t* leaf_ids, int64_t n_leaves,
+                         const uint64_t* solid_ids, int64_t n_solids, mlbm_plan** out) {
+  if (!out) return fail(MLBM_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (stencil != MLBM_D2Q9 && stencil != MLBM_D3Q19)
+    return fail(MLBM_E_ARG, "unknown stencil %d", stencil);
+  if (!box_origin || !box_extent || !face_bc || (!leaf_ids && n_leaves) ||
+      (!solid_ids && n_solids) || n_leaves <= 0 || n_solids < 0)
+    return fail(MLBM_E_ARG, "bad mesh arrays");
+  const int d = stencil_d(stencil);
+  if (level0 < 0 || level0 > (d == 3 ? 20 : 30)) return fail(MLBM_E_ARG, "bad level0");
+  for (int a = 0; a < d; ++a) {
+    if (box_extent[a] <= 0 || box_origin[a] < 0 ||
+        (int64_t)box_origin[a] + box_extent[a] > ((int64_t)1 << level0))
+      return fail(MLBM_E_ARG, "domain box outside the root cube");
+    if (face_bc[2 * a] < 0 || face_bc[2 * a] > 3 || face_bc[2 * a + 1] < 0 || face_bc[2 * a + 1] > 3)
+      return fail(MLBM_E_ARG, "bad face kind");
+    if ((face_bc[2 * a] == MLBM_FACE_PERIODIC) != (face_bc[2 * a + 1] == MLBM_FACE_PERIODIC))
+      return fail(MLBM_E_ARG, "periodic faces must come in pairs");
+  }
+  std::unique_ptr<mlbm_plan> P;
+  try {
+    P.reset(new mlbm_plan());
+    P->stencil = stencil;
+    P->d = d;
+    P->q = stencil_q(stencil);
+    P->level0 = level0;
+    for (int a = 0; a < d; ++a) {
+      P->origin[a] = box_origin[a];
+      P->extent[a] = box_extent[a];
+    }
+    for (int f = 0; f < 2 * d; ++f) P->faces[f] = face_bc[f];
+    build_plan(*P, leaf_ids, n_leaves, solid_ids, n_solids);
+  } catch (const MeshError& e) {
+    return fail(MLBM_E_MESH, "%s", e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(MLBM_E_OOM, "host allocation failed while building the plan");
+  } catch (const std::exception& e) {
+    return fail(MLBM_E_ARG, "%s", e.what());
+  }
+  *out = P.release();
+  return MLBM_OK;
+}
+
+void mlbm_plan_destroy(mlbm_plan* plan) { delete plan; }
+
+int32_t mlbm_plan_levels(const mlbm_plan* plan, int32_t* n_levels, int32_t* level0) {
+  if (!plan) return fail(MLBM_E_ARG, "plan is NULL");
+  if (n_levels) *n_levels = plan->nlev();
+  if (level0) *level0 = plan->level0;
+  return MLBM_OK;
+}
+
+int32_t mlbm_plan_level_info(const mlbm_plan* plan, int32_t k, int64_t* out) {
+  if (!plan || !out) return fail(MLBM_E_ARG, "NULL argument");
+  if (k < 0 || k >= plan->nlev()) return fail(MLBM_E_ARG, "level index %d out of range", k);
+  const auto& lp = plan->lv[k];
+  out[MLBM_INFO_LEVEL] = lp.level;
+  out[MLBM_INFO_N] = lp.n;
+  out[MLBM_INFO_N_FLUID] = lp.n_fluid;
+  out[MLBM_INFO_N_GFC_INNER] = lp.n_inner;
+  out[MLBM_INFO_N_GFC_OUTER] = lp.n_outer;
+  out[MLBM_INFO_N_GFF] = lp.n_gff;
+  out[MLBM_INFO_N_CAP_FLUID] = lp.n_cap_fluid();
+  out[MLBM_INFO_N_CAP] = lp.n_cap();
+  out[MLBM_INFO_N_GFC_GROUPS] = lp.n_groups;
+  out[MLBM_INFO_N_BOUNCE] = lp.n_bounce();
+  return MLBM_OK;
+}
+
+int32_t mlbm_plan_export(const mlbm_plan* plan, int32_t k, int32_t table, void* host_dst,
+                         size_t* bytes) {
+  if (!plan || !bytes) return fail(MLBM_E_ARG, "NULL argument");
+  if (k < 0 || k >= plan->nlev()) return fail(MLBM_E_ARG, "level index %d out of range", k);
+  const auto& lp = plan->lv[k];
+  const void* src = nullptr;
+  size_t n = 0;
+  switch (table) {
+    case MLBM_TABLE_TREEID: src = lp.tid.data(); n = lp.tid.size() * 8; break;
+    case MLBM_TABLE_COORDS: src = lp.coords.data(); n = lp.coords.size() * 4; break;
+    case MLBM_TABLE_NBR: src = lp.nbr.data(); n = lp.nbr.size() * 4; break;
+    case MLBM_TABLE_GFC_SRC: src = lp.gfc_src.data(); n = lp.gfc_src.size() * 4; break;
+    case MLBM_TABLE_GFF_SRC: src = lp.gff_src.data(); n = lp.gff_src.size() * 4; break;
+    case MLBM_TABLE_CAPTURE: src = lp.cap_elem.data(); n = lp.cap_elem.size() * 4; break;
+    case MLBM_TABLE_BOUNCE: src = lp.bounce.data(); n = lp.bounce.size() * 4; break;
+    default: return fail(MLBM_E_ARG, "unknown table %d", table);
+  }
+  if (!host_dst) {
+    *bytes = n;
+    return MLBM_OK;
+  }
+  if (*bytes != n) return fail(MLBM_E_ARG, "table size is %zu bytes, got %zu", n, *bytes);
+  if (n) memcpy(host_dst, src, n);
+  return MLBM_OK;
+}
+
+}  // extern "C"

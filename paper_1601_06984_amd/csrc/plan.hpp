@@ -1,0 +1,41 @@
+// Host-side plan: level-wise element lists and index tables.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+namespace mlbm {
+
+struct LevelPlan {
+  int level = 0;
+  int64_t n = 0, n_fluid = 0, n_inner = 0, n_outer = 0, n_gff = 0;
+  std::vector<uint64_t> tid;       // [n]
+  std::vector<int32_t> coords;     // [d][n]
+  std::vector<int32_t> nbr;        // [q-1][n]
+  std::vector<int32_t> gfc_src;    // [4][n_gfc] element indices on L-1
+  std::vector<int32_t> gff_src;    // [4][n_gff] element indices on L+1
+  std::vector<int32_t> cap_elem;   // [n_cap_fluid] capture sources (fluid)
+  std::vector<int32_t> gff_slot;   // [4][n_gff] capture slots on L+1
+  int64_t n_groups = 0;            // GhostFromCoarser parent groups
+  std::vector<int32_t> grp_src;    // [slots][n_groups] capture slots on L-1
+  std::vector<int32_t> grp_child;  // [children][n_groups] element idx on L
+  std::vector<int32_t> bounce;     // [2][n_bounce] (element, direction)
+
+  int64_t n_gfc() const { return n_inner + n_outer; }
+  int64_t n_active_max() const { return n_fluid + n_inner; }
+  int64_t n_cap_fluid() const { return (int64_t)cap_elem.size(); }
+  int64_t n_cap() const { return n_cap_fluid() + n_gff; }
+  int64_t n_bounce() const { return (int64_t)bounce.size() / 2; }
+};
+
+}  // namespace mlbm
+
+struct mlbm_plan {
+  int stencil = 0, d = 0, q = 0, level0 = 0;
+  int32_t origin[3] = {0, 0, 0}, extent[3] = {1, 1, 1};
+  int32_t faces[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<mlbm::LevelPlan> lv;
+  int nlev() const { return (int)lv.size(); }
+};

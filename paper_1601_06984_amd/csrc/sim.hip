@@ -1,0 +1,531 @@
+// Simulation object: device workspace layout, table upload, the recursive
+// multilevel schedule (Sec. 2.2) and the C ABI of the forward path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "sim.hpp"
+
+namespace mlbm {
+
+namespace {
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t storage_bytes(int precision) {
+  return precision == MLBM_F64 ? 8 : (precision == MLBM_F32 ? 4 : 2);
+}
+size_t compute_bytes(int precision) { return precision == MLBM_F64 ? 8 : 4; }
+
+}  // namespace
+
+// Carves the workspace; with base == nullptr only the size is computed.
+size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState* s) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  const int d = P.d, q = P.q;
+  const size_t sb = storage_bytes(precision), cb = compute_bytes(precision);
+  const int NB = group_slots(d), NC = group_children(d);
+  for (int k = 0; k < P.nlev(); ++k) {
+    const auto& lp = P.lv[k];
+    DevLevel* L = s ? &s->lv[k] : nullptr;
+    char* p0 = take((size_t)q * lp.n * sb);
+    char* p1 = take((size_t)q * lp.n * sb);
+    char* nb = take((size_t)(q - 1) * lp.n_active_max() * 4);
+    char* ce = take((size_t)lp.n_cap_fluid() * 4);
+    char* cap = take((size_t)lp.n_cap() * cap_stride(d) * cb);
+    char* gs = take((size_t)4 * lp.n_gff * 4);
+    char* grs = take((size_t)NB * lp.n_groups * 4);
+    char* grc = take((size_t)NC * lp.n_groups * 4);
+    char* bb = take((size_t)2 * lp.n_bounce() * 4);
+    if (L) {
+      L->pdf[0] = p0;
+      L->pdf[1] = p1;
+      L->nbr = (int32_t*)nb;
+      L->cap_elem = (int32_t*)ce;
+      L->cap = cap;
+      L->gff_slot = (int32_t*)gs;
+      L->grp_src = (int32_t*)grs;
+      L->grp_child = (int32_t*)grc;
+      L->bounce = (int32_t*)bb;
+    }
+  }
+  char* st = take(256);
+  char* part = take((size_t)P.nlev() * DIAG_BLOCKS * DIAG_VALS * 8);
+  char* dl = take((size_t)P.nlev() * sizeof(DiagLevel));
+  char* md = take(256 * 8);
+  if (s) {
+    s->status = (uint32_t*)st;
+    s->partial = (double*)part;
+    s->diag_levels = dl;
+    s->maxdev = (double*)md;
+  }
+  return off;
+}
+
+template <class C, int Q>
+LevelArgs<C, Q> level_args(const SimState& s, int k) {
+  const DevLevel& L = s.lv[k];
+  LevelArgs<C, Q> a;
+  a.n = L.n;
+  a.ld_nbr = L.n_act_max;
+  a.omega = (C)L.omega;
+  a.rho0 = (C)s.rho0;
+  a.scale = (C)std::ldexp(1.0, L.f16_exp);
+  a.inv_scale = (C)std::ldexp(1.0, -L.f16_exp);
+  for (int i = 0; i < Q; ++i) {
+    a.wr[i] = (C)s.wr[i];
+    a.geq[i] = (C)s.geq[i];
+  }
+  return a;
+}
+
+// ---- per (lattice, precision) launchers ------------------------------------
+template <class Lat, int P>
+struct Impl {
+  using S = typename Prec<P>::S;
+  using C = typename Prec<P>::C;
+  static constexpr int BS = 256;
+
+  static void stream_collide(SimState& s, int k, int64_t n_act) {
+    DevLevel& L = s.lv[k];
+    if (n_act <= 0) return;
+    auto a = level_args<C, Lat::Q>(s, k);
+    const S* src = (const S*)L.pdf[L.parity];
+    S* dst = (S*)L.pdf[L.parity ^ 1];
+    const unsigned grid = (unsigned)((n_act + BS - 1) / BS);
+    hipLaunchKernelGGL((k_stream_collide<Lat, P, BS>), dim3(grid), dim3(BS), 0, s.stream, src, dst,
+                       L.nbr, n_act, a, s.status);
+    if (L.n_cap_fluid) {
+      const unsigned gc = (unsigned)((L.n_cap_fluid + 255) / 256);
+      hipLaunchKernelGGL((k_capture<Lat, P>), dim3(gc), dim3(256), 0, s.stream, src, L.nbr,
+                         L.cap_elem, L.n_cap_fluid, (C*)L.cap, a);
+    }
+  }
+
+  static void fill_gff(SimState& s, int k) {
+    DevLevel& L = s.lv[k];
+    if (!L.n_gff) return;
+    const DevLevel& F = s.lv[k + 1];
+    auto a = level_args<C, Lat::Q>(s, k);
+    const C scale = (C)(2.0 * F.omega / L.omega);
+    const unsigned grid = (unsigned)((L.n_gff + 255) / 256);
+    hipLaunchKernelGGL((k_fill_gff<Lat, P>), dim3(grid), dim3(256), 0, s.stream,
+                       (S*)L.pdf[L.parity], L.n_fluid + L.n_inner + L.n_outer, L.n_gff,
+                       L.gff_slot, (const C*)F.cap, (C*)L.cap, L.n_cap_fluid, a, scale, s.status);
+  }
+
+  static void fill_gfc(SimState& s, int k) {
+    DevLevel& L = s.lv[k];
+    if (!L.n_groups) return;
+    const DevLevel& Cl = s.lv[k - 1];
+    auto a = level_args<C, Lat::Q>(s, k);
+    const C scale = (C)(Cl.omega / (2.0 * L.omega));
+    constexpr int GPB = 64 / group_children(Lat::D);
+    const unsigned grid = (unsigned)((L.n_groups + GPB - 1) / GPB);
+    hipLaunchKernelGGL((k_fill_gfc<Lat, P>), dim3(grid), dim3(64), 0, s.stream,
+                       (S*)L.pdf[L.parity], L.n_groups, L.grp_src, L.grp_child,
+                       (const C*)Cl.cap, a, scale, s.status);
+  }
+
+  static double init_maxdev(SimState& s, int k, const double* rho, const double* u,
+                             const double* S_) {
+    DevLevel& L = s.lv[k];
+    if (!L.n_fluid) return 0.0;
+    hipLaunchKernelGGL((k_init_maxdev<Lat>), dim3(256), dim3(256), 0, s.stream, rho, u, S_,
+                       L.n_fluid, s.rho0, L.omega, s.maxdev);
+    double host[256];
+    if (hipMemcpyAsync(host, s.maxdev, sizeof host, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+        hipStreamSynchronize(s.stream) != hipSuccess)
+      return -1.0;
+    double m = 0;
+    for (double v : host) m = std::max(m, v);
+    return m;
+  }
+
+  static void init(SimState& s, int k, const double* rho, const double* u, const double* S_) {
+    DevLevel& L = s.lv[k];
+    auto a = level_args<C, Lat::Q>(s, k);
+    if (L.n_fluid) {
+      const unsigned grid = (unsigned)((L.n_fluid + 255) / 256);
+      hipLaunchKernelGGL((k_init<Lat, P>), dim3(grid), dim3(256), 0, s.stream, rho, u, S_,
+                         L.n_fluid, (S*)L.pdf[L.parity], a, s.rho0, L.omega);
+    }
+    if (L.n_cap_fluid) {
+      const unsigned gc = (unsigned)((L.n_cap_fluid + 255) / 256);
+      hipLaunchKernelGGL((k_init_capture<Lat, P>), dim3(gc), dim3(256), 0, s.stream, rho, u, S_,
+                         L.n_fluid, L.cap_elem, L.n_cap_fluid, (C*)L.cap, s.rho0, L.omega);
+    }
+  }
+
+  static void get_pdf(SimState& s, int k, double* out) {
+    DevLevel& L = s.lv[k];
+    if (!L.n) return;
+    auto a = level_args<C, Lat::Q>(s, k);
+    hipLaunchKernelGGL((k_get_pdf<Lat, P>), dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0,
+                       s.stream, (const S*)L.pdf[L.parity], L.n, a, out);
+  }
+  static void set_pdf(SimState& s, int k, const double* in) {
+    DevLevel& L = s.lv[k];
+    if (!L.n) return;
+    auto a = level_args<C, Lat::Q>(s, k);
+    hipLaunchKernelGGL((k_set_pdf<Lat, P>), dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0,
+                       s.stream, (S*)L.pdf[L.parity], L.n, a, in);
+  }
+  static void get_moments(SimState& s, int k, double* out) {
+    DevLevel& L = s.lv[k];
+    if (!L.n_fluid) return;
+    auto a = level_args<C, Lat::Q>(s, k);
+    hipLaunchKernelGGL((k_get_moments<Lat, P>), dim3((unsigned)((L.n_fluid + 255) / 256)),
+                       dim3(256), 0, s.stream, (const S*)L.pdf[L.parity], L.n_fluid, a, out);
+  }
+  static void diag_partial(SimState& s, int k) {
+    DevLevel& L = s.lv[k];
+    auto a = level_args<C, Lat::Q>(s, k);
+    hipLaunchKernelGGL((k_diag_partial<Lat, P>), dim3(DIAG_BLOCKS), dim3(256), 0, s.stream,
+                       (const S*)L.pdf[L.parity], L.n_fluid, L.bounce, L.n_bounce, a,
+                       s.partial + (int64_t)k * DIAG_BLOCKS * DIAG_VALS);
+  }
+};
+
+// ---- dispatch -------------------------------------------------------------
+#define MLBM_DISPATCH(s, CALL)                                              \
+  do {                                                                      \
+    if ((s).d == 3) {                                                       \
+      if ((s).precision == MLBM_F64) { using I = Impl<D3Q19, MLBM_F64>; CALL; } \
+      else if ((s).precision == MLBM_F32) { using I = Impl<D3Q19, MLBM_F32>; CALL; } \
+      else { using I = Impl<D3Q19, MLBM_F16S>; CALL; }                      \
+    } else {                                                                \
+      if ((s).precision == MLBM_F64) { using I = Impl<D2Q9, MLBM_F64>; CALL; } \
+      else if ((s).precision == MLBM_F32) { using I = Impl<D2Q9, MLBM_F32>; CALL; } \
+      else { using I = Impl<D2Q9, MLBM_F16S>; CALL; }                       \
+    }                                                                       \
+  } while (0)
+
+void sc_level(SimState& s, int k) {
+  DevLevel& L = s.lv[k];
+  const bool first = (k > 0) && (L.substep == 0);
+  const int64_t n_act = L.n_fluid + (first ? L.n_inner : 0);
+  MLBM_DISPATCH(s, I::stream_collide(s, k, n_act));
+  L.parity ^= 1;
+  if (k > 0) L.substep ^= 1;
+}
+
+void fill_gff(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_gff(s, k)); }
+void fill_gfc(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_gfc(s, k)); }
+
+void advance(SimState& s, int k) {
+  sc_level(s, k);
+  if (k + 1 < (int)s.lv.size()) {
+    advance(s, k + 1);
+    advance(s, k + 1);
+    fill_gff(s, k);
+    fill_gfc(s, k + 1);
+  }
+}
+
+int32_t check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MLBM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+  return MLBM_OK;
+}
+
+}  // namespace mlbm
+
+using namespace mlbm;
+
+extern "C" {
+
+int32_t mlbm_sim_workspace_bytes(const mlbm_plan* plan, int32_t precision, size_t* bytes) {
+  if (!plan || !bytes) return fail(MLBM_E_ARG, "NULL argument");
+  if (precision < MLBM_F64 || precision > MLBM_F16S) return fail(MLBM_E_ARG, "bad precision");
+  *bytes = layout_workspace(*plan, precision, nullptr, nullptr);
+  return MLBM_OK;
+}
+
+int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, double rho0,
+                        const double* u_in, const int32_t* f16_exp, void* hip_stream,
+                        void* workspace, size_t workspace_bytes, mlbm_sim** out) {
+  if (!out) return fail(MLBM_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!plan || !workspace) return fail(MLBM_E_ARG, "NULL plan or workspace");
+  if (precision < MLBM_F64 || precision > MLBM_F16S) return fail(MLBM_E_ARG, "bad precision");
+  if (!(tau0 > 0.5)) return fail(MLBM_E_ARG, "tau0 must exceed 1/2");
+  if (!(rho0 > 0.0)) return fail(MLBM_E_ARG, "rho0 must be positive");
+  if (((uintptr_t)workspace) & 255) return fail(MLBM_E_ARG, "workspace must be 256-byte aligned");
+  const size_t need = layout_workspace(*plan, precision, nullptr, nullptr);
+  if (workspace_bytes < need)
+    return fail(MLBM_E_ARG, "workspace too small: need %zu bytes, got %zu", need, workspace_bytes);
+  mlbm_sim* sim = new (std::nothrow) mlbm_sim();
+  if (!sim) return fail(MLBM_E_OOM, "host allocation failed");
+  SimState& s = sim->s;
+  s.stencil = plan->stencil;
+  s.d = plan->d;
+  s.q = plan->q;
+  s.precision = precision;
+  s.level0 = plan->level0;
+  s.tau0 = tau0;
+  s.rho0 = rho0;
+  s.stream = (hipStream_t)hip_stream;
+  s.ws = (char*)workspace;
+  s.ws_bytes = workspace_bytes;
+  for (int a = 0; a < 3; ++a) s.u_in[a] = (u_in && a < s.d) ? u_in[a] : 0.0;
+  s.lv.resize(plan->nlev());
+  for (int k = 0; k < plan->nlev(); ++k) {
+    const auto& lp = plan->lv[k];
+    DevLevel& L = s.lv[k];
+    L.level = lp.level;
+    L.n = lp.n;
+    L.n_fluid = lp.n_fluid;
+    L.n_inner = lp.n_inner;
+    L.n_outer = lp.n_outer;
+    L.n_gff = lp.n_gff;
+    L.n_act_max = lp.n_active_max();
+    L.n_cap_fluid = lp.n_cap_fluid();
+    L.n_cap = lp.n_cap();
+    L.n_groups = lp.n_groups;
+    L.n_bounce = lp.n_bounce();
+    const double tau = 0.5 + std::ldexp(tau0 - 0.5, lp.level - plan->level0);
+    L.omega = 1.0 / tau;
+    L.f16_exp = f16_exp ? f16_exp[k] : 0;
+    L.f16_auto = (f16_exp == nullptr) && precision == MLBM_F16S;
+  }
+  // lattice constants: w_i rho0 and the EQ-face equilibrium deviation
+  for (int i = 0; i < s.q; ++i) {
+    double w, cu = 0, uu = 0;
+    if (s.d == 3) {
+      w = D3Q19::w(i);
+      for (int a = 0; a < 3; ++a) cu += D3Q19::c(i, a) * s.u_in[a];
+    } else {
+      w = D2Q9::w(i);
+      for (int a = 0; a < 2; ++a) cu += D2Q9::c(i, a) * s.u_in[a];
+    }
+    for (int a = 0; a < s.d; ++a) uu += s.u_in[a] * s.u_in[a];
+    s.wr[i] = w * rho0;
+    s.geq[i] = w * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+  }
+  layout_workspace(*plan, precision, s.ws, &s);
+  // upload tables
+  hipError_t e = hipSuccess;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (bytes && e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s.stream);
+  };
+  for (int k = 0; k < plan->nlev() && e == hipSuccess; ++k) {
+    const auto& lp = plan->lv[k];
+    DevLevel& L = s.lv[k];
+    if (L.n_act_max && e == hipSuccess)
+      e = hipMemcpy2DAsync(L.nbr, L.n_act_max * 4, lp.nbr.data(), lp.n * 4, L.n_act_max * 4,
+                           s.q - 1, hipMemcpyHostToDevice, s.stream);
+    up(L.cap_elem, lp.cap_elem.data(), lp.cap_elem.size() * 4);
+    up(L.gff_slot, lp.gff_slot.data(), lp.gff_slot.size() * 4);
+    up(L.grp_src, lp.grp_src.data(), lp.grp_src.size() * 4);
+    up(L.grp_child, lp.grp_child.data(), lp.grp_child.size() * 4);
+    up(L.bounce, lp.bounce.data(), lp.bounce.size() * 4);
+  }
+  std::vector<DiagLevel> dl(plan->nlev());
+  for (int k = 0; k < plan->nlev(); ++k) {
+    const int L = plan->lv[k].level;
+    dl[k].vol = std::ldexp(1.0, -s.d * (L - plan->level0));
+    dl[k].force_scale = std::ldexp(1.0, (s.d - 1) * (plan->level0 + plan->nlev() - 1 - L));
+    dl[k].rho0_nf = rho0 * (double)plan->lv[k].n_fluid;
+  }
+  up(s.diag_levels, dl.data(), dl.size() * sizeof(DiagLevel));
+  if (e == hipSuccess) e = hipMemsetAsync(s.status, 0, 256, s.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+  if (e != hipSuccess) {
+    delete sim;
+    return fail(MLBM_E_HIP, "table upload: %s", hipGetErrorString(e));
+  }
+  s.inited.assign(plan->nlev(), false);
+  *out = sim;
+  return MLBM_OK;
+}
+
+void mlbm_sim_destroy(mlbm_sim* sim) { delete sim; }
+
+int32_t mlbm_init(mlbm_sim* sim, int32_t k, const double* rho, const double* u, const double* S) {
+  if (!sim) return fail(MLBM_E_ARG, "sim is NULL");
+  SimState& s = sim->s;
+  if (k < 0 || k >= (int)s.lv.size()) return fail(MLBM_E_ARG, "level index %d out of range", k);
+  DevLevel& L = s.lv[k];
+  if (L.n_fluid && (!rho || !u)) return fail(MLBM_E_ARG, "rho and u are required");
+  if (L.f16_auto) {
+    double m = 0;
+    MLBM_DISPATCH(s, m = I::init_maxdev(s, k, rho, u, S));
+    if (m < 0) return fail(MLBM_E_HIP, "FP16 scale reduction failed");
+    // largest power of two with max|f - w rho0| * s_L <= 2^12
+    int ex = m > 0 ? (int)std::floor(std::log2(4096.0 / m)) : 24;
+    L.f16_exp = std::min(24, std::max(0, ex));
+  }
+  MLBM_DISPATCH(s, I::init(s, k, rho, u, S));
+  L.parity = 0;
+  L.substep = 0;
+  s.inited[k] = true;
+  s.time = 0;
+  return check_launch("mlbm_init");
+}
+
+int32_t mlbm_fill_ghosts(mlbm_sim* sim) {
+  if (!sim) return fail(MLBM_E_ARG, "sim is NULL");
+  SimState& s = sim->s;
+  for (bool b : s.inited)
+    if (!b) return fail(MLBM_E_STATE, "mlbm_init must be called for every level first");
+  for (int k = 0; k + 1 < (int)s.lv.size(); ++k) fill_gff(s, k);
+  for (int k = 1; k < (int)s.lv.size(); ++k) fill_gfc(s, k);
+  s.filled = true;
+  return check_launch("mlbm_fill_ghosts");
+}
+
+int32_t mlbm_step(mlbm_sim* sim, int64_t n_coarse) {
+  if (!sim) return fail(MLBM_E_ARG, "sim is NULL");
+  if (n_coarse < 0) return fail(MLBM_E_ARG, "negative step count");
+  SimState& s = sim->s;
+  if (!s.filled) return fail(MLBM_E_STATE, "mlbm_fill_ghosts must follow mlbm_init");
+  for (int64_t t = 0; t < n_coarse; ++t) {
+    advance(s, 0);
+    s.time++;
+  }
+  return check_launch("mlbm_step");
+}
+
+int32_t mlbm_diagnostics(mlbm_sim* sim, uint32_t mask, double* dev_out) {
+  if (!sim || !dev_out) return fail(MLBM_E_ARG, "NULL argument");
+  SimState& s = sim->s;
+  if (!s.filled) return fail(MLBM_E_STATE, "no state yet");
+  if (mask & ~7u) return fail(MLBM_E_ARG, "bad diagnostics mask");
+  for (int k = 0; k < (int)s.lv.size(); ++k) MLBM_DISPATCH(s, I::diag_partial(s, k));
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s.stream, s.partial, (int)s.lv.size(),
+                     (const DiagLevel*)s.diag_levels, mask, s.d, dev_out);
+  return check_launch("mlbm_diagnostics");
+}
+
+int32_t mlbm_get_state(mlbm_sim* sim, int32_t k, int32_t what, double* dev_dst) {
+  if (!sim || !dev_dst) return fail(MLBM_E_ARG, "NULL argument");
+  SimState& s = sim->s;
+  if (k < 0 || k >= (int)s.lv.size()) return fail(MLBM_E_ARG, "level index %d out of range", k);
+  if (what == MLBM_STATE_PDF_POST) MLBM_DISPATCH(s, I::get_pdf(s, k, dev_dst));
+  else if (what == MLBM_STATE_MOMENTS) MLBM_DISPATCH(s, I::get_moments(s, k, dev_dst));
+  else return fail(MLBM_E_ARG, "unknown state selector %d", what);
+  return check_launch("mlbm_get_state");
+}
+
+int32_t mlbm_set_state(mlbm_sim* sim, int32_t k, const double* dev_src) {
+  if (!sim || !dev_src) return fail(MLBM_E_ARG, "NULL argument");
+  SimState& s = sim->s;
+  if (k < 0 || k >= (int)s.lv.size()) return fail(MLBM_E_ARG, "level index %d out of range", k);
+  MLBM_DISPATCH(s, I::set_pdf(s, k, dev_src));
+  return check_launch("mlbm_set_state");
+}
+
+int32_t mlbm_status(mlbm_sim* sim, uint32_t* flags) {
+  if (!sim || !flags) return fail(MLBM_E_ARG, "NULL argument");
+  SimState& s = sim->s;
+  uint32_t h = 0;
+  hipError_t e = hipMemcpyAsync(&h, s.status, 4, hipMemcpyDeviceToHost, s.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s.status, 0, 4, s.stream);
+  if (e != hipSuccess) return fail(MLBM_E_HIP, "status: %s", hipGetErrorString(e));
+  *flags = h;
+  return MLBM_OK;
+}
+
+int32_t mlbm_time(const mlbm_sim* sim, int64_t* coarse_steps) {
+  if (!sim || !coarse_steps) return fail(MLBM_E_ARG, "NULL argument");
+  *coarse_steps = sim->s.time;
+  return MLBM_OK;
+}
+
+int32_t mlbm_checkpoint_bytes(const mlbm_sim* sim, size_t* bytes) {
+  if (!sim || !bytes) return fail(MLBM_E_ARG, "NULL argument");
+  const SimState& s = sim->s;
+  size_t b = 256;
+  for (const auto& L : s.lv) b += align_up((size_t)s.q * L.n * storage_bytes(s.precision));
+  *bytes = b;
+  return MLBM_OK;
+}
+
+int32_t mlbm_save_checkpoint(mlbm_sim* sim, void* dev_dst, size_t bytes) {
+  if (!sim || !dev_dst) return fail(MLBM_E_ARG, "NULL argument");
+  SimState& s = sim->s;
+  size_t need = 0;
+  mlbm_checkpoint_bytes(sim, &need);
+  if (bytes < need) return fail(MLBM_E_ARG, "checkpoint buffer too small (%zu < %zu)", bytes, need);
+  if (!s.filled) return fail(MLBM_E_STATE, "no state to save");
+  CheckpointHeader h{};
+  h.magic = 0x4d4c424d43505431ull;
+  h.time = s.time;
+  h.nlev = (int32_t)s.lv.size();
+  h.precision = s.precision;
+  for (size_t k = 0; k < s.lv.size() && k < 16; ++k) h.f16_exp[k] = s.lv[k].f16_exp;
+  char* p = (char*)dev_dst;
+  hipError_t e = hipMemcpyAsync(p, &h, sizeof h, hipMemcpyHostToDevice, s.stream);
+  size_t off = 256;
+  for (auto& L : s.lv) {
+    const size_t b = (size_t)s.q * L.n * storage_bytes(s.precision);
+    if (e == hipSuccess && b)
+      e = hipMemcpyAsync(p + off, L.pdf[L.parity], b, hipMemcpyDeviceToDevice, s.stream);
+    off += align_up(b);
+  }
+  // the header lives on the host stack: make sure it has been consumed
+  if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+  if (e != hipSuccess) return fail(MLBM_E_HIP, "save_checkpoint: %s", hipGetErrorString(e));
+  return MLBM_OK;
+}
+
+int32_t mlbm_load_checkpoint(mlbm_sim* sim, const void* dev_src, size_t bytes) {
+  if (!sim || !dev_src) return fail(MLBM_E_ARG, "NULL argument");
+  SimState& s = sim->s;
+  size_t need = 0;
+  mlbm_checkpoint_bytes(sim, &need);
+  if (bytes < need) return fail(MLBM_E_ARG, "checkpoint buffer too small (%zu < %zu)", bytes, need);
+  CheckpointHeader h{};
+  hipError_t e = hipMemcpyAsync(&h, dev_src, sizeof h, hipMemcpyDeviceToHost, s.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+  if (e != hipSuccess) return fail(MLBM_E_HIP, "load_checkpoint: %s", hipGetErrorString(e));
+  if (h.magic != 0x4d4c424d43505431ull || h.nlev != (int32_t)s.lv.size() ||
+      h.precision != s.precision)
+    return fail(MLBM_E_ARG, "checkpoint does not belong to this simulation");
+  const char* p = (const char*)dev_src;
+  size_t off = 256;
+  for (size_t k = 0; k < s.lv.size(); ++k) {
+    DevLevel& L = s.lv[k];
+    const size_t b = (size_t)s.q * L.n * storage_bytes(s.precision);
+    L.parity = 0;
+    L.substep = 0;
+    if (k < 16) L.f16_exp = h.f16_exp[k];
+    if (e == hipSuccess && b)
+      e = hipMemcpyAsync(L.pdf[0], p + off, b, hipMemcpyDeviceToDevice, s.stream);
+    off += align_up(b);
+  }
+  if (e != hipSuccess) return fail(MLBM_E_HIP, "load_checkpoint: %s", hipGetErrorString(e));
+  s.time = h.time;
+  std::fill(s.inited.begin(), s.inited.end(), true);
+  s.filled = true;
+  return MLBM_OK;
+}
+
+int32_t mlbm_launches_per_step(const mlbm_sim* sim, int64_t* launches) {
+  if (!sim || !launches) return fail(MLBM_E_ARG, "NULL argument");
+  const SimState& s = sim->s;
+  int64_t total = 0;
+  for (size_t k = 0; k < s.lv.size(); ++k) {
+    const auto& L = s.lv[k];
+    const int64_t reps = (int64_t)1 << k;
+    total += reps * (1 + (L.n_cap_fluid ? 1 : 0));
+    if (k + 1 < s.lv.size()) total += reps * ((L.n_gff ? 1 : 0) + (s.lv[k + 1].n_groups ? 1 : 0));
+  }
+  *launches = total;
+  return MLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Host-side simulation state shared by the forward and adjoint translation
+// units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+struct mlbm_plan;
+
+namespace mlbm {
+
+struct DevLevel {
+  int level = 0;
+  int64_t n = 0, n_fluid = 0, n_inner = 0, n_outer = 0, n_gff = 0, n_act_max = 0;
+  int64_t n_cap_fluid = 0, n_cap = 0, n_groups = 0, n_bounce = 0;
+  void* pdf[2] = {nullptr, nullptr};  // storage arrays [q][n]
+  int32_t* nbr = nullptr;             // [q-1][n_act_max]
+  int32_t* cap_elem = nullptr;        // [n_cap_fluid]
+  void* cap = nullptr;                // [n_cap][cap_stride] compute type
+  int32_t* gff_slot = nullptr;        // [4][n_gff] capture slots on level+1
+  int32_t* grp_src = nullptr;         // [slots][n_groups] capture slots on level-1
+  int32_t* grp_child = nullptr;       // [children][n_groups] element indices
+  int32_t* bounce = nullptr;          // [2][n_bounce]
+  int parity = 0;                     // index of the current pdf array
+  int substep = 0;                    // 0: next step is the first after a sync
+  double omega = 1.0;
+  int f16_exp = 0;
+  bool f16_auto = false;
+};
+
+struct SimState {
+  int stencil = 0, d = 3, q = 19, precision = 0, level0 = 0;
+  double tau0 = 1.0, rho0 = 1.0, u_in[3] = {0, 0, 0};
+  double wr[19], geq[19];
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<DevLevel> lv;
+  uint32_t* status = nullptr;
+  double* partial = nullptr;
+  void* diag_levels = nullptr;
+  double* maxdev = nullptr;
+  std::vector<bool> inited;
+  bool filled = false;
+  int64_t time = 0;
+};
+
+struct CheckpointHeader {
+  uint64_t magic;
+  int64_t time;
+  int32_t nlev, precision;
+  int32_t f16_exp[16];
+};
+
+size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState* s);
+
+}  // namespace mlbm
+
+struct mlbm_sim {
+  mlbm::SimState s;
+};

@@ -1,0 +1,229 @@
+"""GPU parity of the forward hot path against the FP64 oracle.
+
+Every case prints its name, mesh and precision before touching the GPU.
+Tolerances: F64 runs are compared at 1e-12 relative pdf error (rounding
+order only); F32 runs at the stated bound of 1e-5 after 100 coarse steps;
+F16S runs at 2e-3 (half precision keeps 11 significant bits of the shifted
+deviation, about 5e-5 of a pdf per rounding, accumulated over the run).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import mesh as omesh
+from oracle import physics as ophys
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1601_06984_amd  # noqa: F401  (fails loudly if not built)
+
+
+def test_config1_d2q9_f64_tgv_200_steps():
+    """D2Q9 TGV, 32x32 coarse with the centre 16x16 refined, u0 = 0.01,
+    tau0 = 0.8, 200 coarse steps, FP64 on the GPU against the oracle."""
+    spec = W.refined_box_mesh("D2Q9", 5, 8, 24)
+    _say("config1 D2Q9 f64 200 steps")
+    osim = H.oracle_run(spec, 0.8, H.tgv(32, 0.01), 200)
+    sim = H.gpu_sim(spec, "f64", 0.8, H.tgv(32, 0.01))
+    sim.step(200)
+    assert H.compare_post(sim, osim) < 1e-12
+    assert sim.status() == 0
+
+
+@pytest.mark.parametrize("base,lo,hi", [(5, 8, 24), (6, 16, 48)])
+def test_config2_d3q19_f32_100_steps(base, lo, hi):
+    """D3Q19 TGV with the central cube refined, u0 = 0.02, Re = 100
+    (tau0 = 0.5 + 3 u0 N/(2 pi Re)), FP32 storage and collision: max
+    relative pdf error <= 1e-5 after 100 coarse steps (64^3 is the full
+    configuration)."""
+    n0 = 1 << base
+    tau0 = 0.5 + 3 * 0.02 * n0 / (2 * np.pi * 100)
+    spec = W.refined_box_mesh("D3Q19", base, lo, hi)
+    _say("config2 D3Q19 f32", n0)
+    osim = H.oracle_run(spec, tau0, H.tgv(n0, 0.02), 100)
+    sim = H.gpu_sim(spec, "f32", tau0, H.tgv(n0, 0.02))
+    sim.step(100)
+    err = H.compare_post(sim, osim)
+    print("max rel pdf err", err)
+    assert err < 1e-5
+    assert sim.status() == 0
+
+
+def test_config2_d3q19_f16s_100_steps():
+    n0 = 32
+    tau0 = 0.5 + 3 * 0.02 * n0 / (2 * np.pi * 100)
+    spec = W.refined_box_mesh("D3Q19", 5, 8, 24)
+    _say("config2 D3Q19 f16s 32")
+    osim = H.oracle_run(spec, tau0, H.tgv(n0, 0.02), 100)
+    sim = H.gpu_sim(spec, "f16s", tau0, H.tgv(n0, 0.02))
+    sim.step(100)
+    err = H.compare_post(sim, osim)
+    print("max rel pdf err f16s", err)
+    assert err < 2e-3
+    assert sim.status() == 0
+
+
+@pytest.mark.parametrize("name,spec_fn,n0,steps", [
+    ("d2q9_3lev", lambda: W.refined_box_mesh("D2Q9", 5, 8, 24, extra_levels=[(20, 44)]), 32, 20),
+    ("d3q19_3lev", lambda: W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)]), 16, 6),
+    ("d2q9_half", lambda: W.half_refined_2d(5), 32, 40),
+])
+def test_multilevel_f64_against_oracle(name, spec_fn, n0, steps):
+    spec = spec_fn()
+    _say(name, "f64", steps)
+    osim = H.oracle_run(spec, 0.7, H.tgv(n0, 0.03), steps)
+    sim = H.gpu_sim(spec, "f64", 0.7, H.tgv(n0, 0.03))
+    sim.step(steps)
+    assert H.compare_post(sim, osim) < 1e-12
+
+
+def _sphere_small():
+    return W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0), half_width=2.0,
+                                 boxes_in_d=((-1.0, 1.5, 1.0),))
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_sphere_boundaries_and_drag(precision, tol):
+    """Bounce-back, equilibrium inflow/lateral faces, copy outlet on a small
+    two-level sphere channel; drag (momentum exchange) against the oracle's
+    literal Sec. 2.3 sum."""
+    spec = _sphere_small()
+    uin = np.array([0.04, 0.0, 0.0])
+    fields = lambda pos: W.uniform_fields(len(pos), 3, uin)
+    _say("sphere small", precision)
+    osim = H.oracle_run(spec, 0.6, fields, 30, u_in=uin)
+    sim = H.gpu_sim(spec, precision, 0.6, fields, u_in=uin)
+    sim.step(30)
+    assert H.compare_post(sim, osim) < tol
+    import paper_1601_06984_amd as M
+    d = sim.diagnostics(M.DIAG_MASS | M.DIAG_KE | M.DIAG_FORCE).cpu().numpy()
+    F = osim.force().numpy()
+    assert abs(d[0] - float(osim.mass())) <= tol * abs(float(osim.mass())) * 10
+    assert abs(d[1] - float(osim.kinetic_energy())) <= tol * 100 * abs(float(osim.kinetic_energy()))
+    assert np.allclose(d[2:], F, rtol=tol * 100, atol=tol * 10)
+    assert F[0] > 0
+
+
+@pytest.mark.parametrize("stencil,base,lo,hi", [("D2Q9", 5, 8, 24), ("D3Q19", 4, 4, 12)])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-14), ("f32", 2e-7)])
+def test_fill_exact_on_quadratic_fields(stencil, base, lo, hi, precision, tol):
+    """Eqs. compact_3D_u / compact_3D_s on the GPU: initialise a quadratic
+    velocity field with constant density and its exact strain rate; after
+    the synchronous fill every ghost holds the analytic post-collision pdfs
+    (absolute tolerance: F64 roundoff; F32 ~ 2^-23 of the pdfs)."""
+    spec = W.refined_box_mesh(stencil, base, lo, hi)
+    d = 2 if stencil == "D2Q9" else 3
+    rng = np.random.default_rng(4)
+    a = rng.normal(size=d) * 0.02
+    B = rng.normal(size=(d, d)) * 0.002
+    Cq = rng.normal(size=(d, d, d)) * 2e-4
+    Cq = 0.5 * (Cq + Cq.transpose(0, 2, 1))
+
+    def fields(pos):
+        x = pos - (1 << base) / 2
+        u = a + x @ B.T + np.einsum("mab,na,nb->nm", Cq, x, x)
+        grad = B[None] + 2 * np.einsum("mab,nb->nma", Cq, x)
+        S = 0.5 * (grad + grad.transpose(0, 2, 1))
+        return np.full(len(pos), 1.01), u, S
+    _say("quadratic fill", stencil, precision)
+    import paper_1601_06984_amd as M
+    sim = H.gpu_sim(spec, precision, 0.62, fields)
+    om = omesh.build(spec)
+    lat = om.lattice
+    perm = H.direction_perm(stencil, lat)
+    for k in range(sim.plan.n_levels):
+        L = sim.plan.level0 + k
+        t = om.lev(L)
+        pos = om.positions(L)
+        rho, u, S = fields(pos)
+        S = S * 2.0 ** -(L - om.level0)
+        omega = 1.0 / ophys.level_tau(0.62, L, om.level0)
+        rt = torch.tensor(rho)
+        f = ophys.equilibrium(rt, torch.tensor(u).t(), lat) + \
+            ophys.fneq_from_strain(rt, torch.tensor(S).permute(1, 2, 0), omega, lat)
+        fstar = ophys.collide(f, omega, lat).numpy()[perm]
+        g = sim.get_pdf(k).cpu().numpy()
+        assert np.abs(g[:, t.n_fluid:] - fstar[:, t.n_fluid:]).max() < tol, (k, precision)
+
+
+def test_uniform_flow_and_single_level_mass():
+    import paper_1601_06984_amd as M
+    spec = W.refined_box_mesh("D3Q19", 4, 4, 12)
+    uc = np.array([0.03, -0.02, 0.01])
+    _say("uniform flow f64")
+    sim = H.gpu_sim(spec, "f64", 0.6, lambda p: W.uniform_fields(len(p), 3, uc))
+    sim.step(10)
+    lat_c, lat_w = M.lattice("D3Q19")
+    cu = lat_c @ uc
+    feq = lat_w * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * (uc @ uc))
+    for k in range(sim.plan.n_levels):
+        g = sim.get_pdf(k).cpu().numpy()
+        assert np.abs(g - feq[:, None]).max() < 1e-15
+    _say("single-level mass f64")
+    sim = H.gpu_sim(W.uniform_box_mesh("D2Q9", 5), "f64", 0.8, H.tgv(32, 0.02))
+    m0 = float(sim.diagnostics(M.DIAG_MASS)[0])
+    sim.step(1000)
+    m1 = float(sim.diagnostics(M.DIAG_MASS)[0])
+    assert abs(m1 - m0) / m0 < 1e-12
+
+
+def test_checkpoint_roundtrip_is_bitwise():
+    spec = W.refined_box_mesh("D3Q19", 4, 4, 12)
+    n0 = 16
+    _say("checkpoint f32")
+    a = H.gpu_sim(spec, "f32", 0.56, H.tgv(n0, 0.03))
+    a.step(7)
+    ck = a.save_checkpoint()
+    a.step(9)
+    b = H.gpu_sim(spec, "f32", 0.56, H.tgv(n0, 0.05))
+    b.load_checkpoint(ck)
+    b.step(9)
+    assert b.time() == a.time() == 16
+    for k in range(a.plan.n_levels):
+        assert torch.equal(a.get_pdf(k), b.get_pdf(k))
+
+
+def test_status_flags_from_injected_state():
+    """Failure detection: a NaN injected through set_state raises the
+    non-finite flag after a step; an oversized FP16 scale raises the
+    overflow flag.  No kernel faults; the conditions come from the host."""
+    import paper_1601_06984_amd as M
+    spec = W.refined_box_mesh("D2Q9", 4, 4, 12)
+    _say("status flags")
+    sim = H.gpu_sim(spec, "f32", 0.7, H.tgv(16, 0.02))
+    assert sim.status() == 0
+    p = sim.get_pdf(0)
+    p[3, 5] = float("nan")
+    sim.set_pdf(0, p)
+    sim.step(1)
+    assert sim.status() & M.STATUS_NONFINITE
+    sim2 = H.gpu_sim(spec, "f16s", 0.7, H.tgv(16, 0.02), f16_exp=[24, 24])
+    sim2.step(1)
+    assert sim2.status() & M.STATUS_F16_OVERFLOW
+
+
+def test_call_order_errors():
+    import paper_1601_06984_amd as M
+    spec = W.refined_box_mesh("D2Q9", 4, 4, 12)
+    plan = M.Plan.from_spec(spec)
+    sim = M.Sim(plan, "f32", 0.7)
+    with pytest.raises(M.MLBMError):
+        sim.step(1)
+    with pytest.raises(M.MLBMError):
+        sim.fill_ghosts()
+    with pytest.raises(M.MLBMError):
+        M.Sim(plan, "f32", 0.4)

