@@ -1,0 +1,247 @@
+"""Benchmark of the multilevel lattice Boltzmann hot path on one MI355X.
+
+One step = one coarse time step of the whole multilevel method (every
+level's stream-collide with captures, both interpolation fills) over the
+workload's mesh.  Throughput is reported in MLUPS with the paper's
+workload weight: each fluid element of level L counts 2^(L-L0) updates per
+coarse step.
+
+Prints ONE JSON line.  `roofline` is measured live for the dominant kernel
+(the finest level's stream-collide) with HIP events recorded on the stream
+the kernels run on; `cpu_baseline` times the FP64 oracle on the host for a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+METRIC = "MLUPS & %HBM peak, fwd and adjoint step, FP32 vs FP16-shift at fixed error"
+HBM_PEAK_GBS = 8000.0
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
+
+
+def tgv_tau(n0, u0=0.02, re=100.0):
+    # Re = u0 N0 / (2 pi nu) in coarse lattice units; nu = (tau - 1/2)/3
+    return 0.5 + 3.0 * u0 * n0 / (2.0 * math.pi * re)
+
+
+def workload(name):
+    if name == "tgv64":
+        n0, u0 = 64, 0.02
+        spec = W.refined_box_mesh("D3Q19", 6, 16, 48)
+        desc = ("D3Q19 periodic Taylor-Green vortex, 64^3 coarse with the central "
+                "32^3 coarse cells refined once (2 levels), u0=0.02, Re=100")
+        return dict(spec=spec, tau0=tgv_tau(n0, u0), fields=lambda p: W.tgv_fields(p, n0, u0),
+                    u_in=None, desc=desc, n0=n0, u0=u0, tgv=True)
+    if name == "tgv32":
+        n0, u0 = 32, 0.02
+        spec = W.refined_box_mesh("D3Q19", 5, 8, 24)
+        desc = "D3Q19 periodic Taylor-Green vortex, 32^3 coarse, central 16^3 refined"
+        return dict(spec=spec, tau0=tgv_tau(n0, u0), fields=lambda p: W.tgv_fields(p, n0, u0),
+                    u_in=None, desc=desc, n0=n0, u0=u0, tgv=True)
+    if name == "tgv128":
+        n0, u0 = 128, 0.01
+        spec = W.refined_box_mesh("D3Q19", 7, 32, 96)
+        desc = "D3Q19 periodic Taylor-Green vortex, 128^3 coarse, central 64^3 refined"
+        return dict(spec=spec, tau0=tgv_tau(64, 0.02), fields=lambda p: W.tgv_fields(p, n0, u0),
+                    u_in=None, desc=desc, n0=n0, u0=u0, tgv=True)
+    if name == "sphere3":
+        uin = 0.04
+        spec = W.sphere_channel_mesh(24, 3)
+        tau_f = 0.5 + 3.0 * uin * 24 / 100.0     # Re = u D / nu on the finest level
+        tau0 = 0.5 + (tau_f - 0.5) / 4.0
+        desc = ("D3Q19 channel [-15D,49D]x[-15D,15D]^2 with a sphere of D=24 finest "
+                "cells, 3 nested levels, Re=100, equilibrium inflow u=0.04")
+        return dict(spec=spec, tau0=tau0, u_in=[uin, 0.0, 0.0],
+                    fields=lambda p: W.uniform_fields(len(p), 3, [uin, 0.0, 0.0]),
+                    desc=desc, tgv=False)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def weighted_updates(plan):
+    return sum(plan.info[k]["n_fluid"] << k for k in range(plan.n_levels))
+
+
+def make_sim(M, torch, wl, plan, precision):
+    sim = M.Sim(plan, precision, wl["tau0"], u_in=wl["u_in"])
+    dev = sim.device
+    for k in range(plan.n_levels):
+        L = plan.level0 + k
+        nf = plan.info[k]["n_fluid"]
+        coords = plan.export(k, "coords")[:, :nf]
+        pos = (coords.T.astype(np.float64) + 0.5) / float(1 << k)
+        r, u, S = wl["fields"](pos)
+        S = S * 2.0 ** -k
+        idx = [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)]
+        Sc = np.stack([S[:, a, b] for a, b in idx], 0)
+        sim.init(k, torch.tensor(r, device=dev), torch.tensor(np.ascontiguousarray(u.T), device=dev),
+                 torch.tensor(np.ascontiguousarray(Sc), device=dev))
+    sim.fill_ghosts()
+    return sim
+
+
+def tgv_velocity_error(sim, plan, wl, t):
+    """eps_u of u_x against the decayed closed form (Sec. 4.1 norm)."""
+    nu0 = (wl["tau0"] - 0.5) / 3.0
+    num = den = 0.0
+    for k in range(plan.n_levels):
+        nf = plan.info[k]["n_fluid"]
+        coords = plan.export(k, "coords")[:, :nf]
+        pos = (coords.T.astype(np.float64) + 0.5) / float(1 << k)
+        _, ua, _ = W.tgv_fields(pos, wl["n0"], wl["u0"], nu0=nu0, t=t)
+        us = sim.get_moments(k).cpu().numpy()[1]
+        num += float(((us - ua[:, 0]) ** 2).sum())
+        den += float((ua[:, 0] ** 2).sum())
+    return math.sqrt(num / den)
+
+
+def timed_steps(torch, sim, steps):
+    s = sim.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    sim.step(steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def cpu_baseline(wl, steps):
+    """The FP64 oracle as it stands, on the host, for `steps` coarse steps."""
+    import torch
+    from oracle import mesh as omesh
+    from oracle import solver as osolver
+    om = omesh.build(wl["spec"])
+    sim = osolver.OracleSim(om, wl["tau0"], u_in=None if wl["u_in"] is None
+                            else torch.tensor(wl["u_in"], dtype=torch.float64))
+    rho, u, S = {}, {}, {}
+    for L in range(om.level0, om.lmax + 1):
+        pos = om.positions(L)[:om.lev(L).n_fluid]
+        r, uu, SS = wl["fields"](pos)
+        rho[L], u[L], S[L] = r, uu, SS * 2.0 ** -(L - om.level0)
+    sim.init(rho, u, S)
+    sim.step(1)  # warm
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    upd = sum(om.lev(L).n_fluid << (L - om.level0) for L in range(om.level0, om.lmax + 1))
+    return dict(value=upd * steps / dt / 1e6, unit="MLUPS", cores=torch.get_num_threads(),
+                kind="oracle",
+                sample=f"{steps} coarse steps of the same mesh and initial state after one "
+                       f"warm-up step ({dt:.1f} s wall, FP64, torch CPU ops, "
+                       f"{platform.processor() or platform.machine()})")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="tgv64")
+    ap.add_argument("--precision", default="f32", choices=["f64", "f32", "f16s"])
+    ap.add_argument("--variants", type=int, default=1,
+                    help="also time F64/F16S and report the fixed-error study")
+    ap.add_argument("--cpu-steps", type=int, default=15)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        raise SystemExit(2)
+
+    import torch
+    import paper_1601_06984_amd as M
+    torch.cuda.set_device(0)
+    wl = workload(args.workload)
+    print(f"[bench] workload {args.workload}: planning", file=sys.stderr, flush=True)
+    plan = M.Plan.from_spec(wl["spec"])
+    upd = weighted_updates(plan)
+    prec = args.precision
+    sim = make_sim(M, torch, wl, plan, prec)
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    sim.profile(True)
+    print(f"[bench] timed {args.steps} coarse steps", file=sys.stderr, flush=True)
+    ms = timed_steps(torch, sim, args.steps)
+    sim.profile(False)
+    status = sim.status()
+    value = upd * args.steps / (ms / 1e3) / 1e6
+    # dominant kernel: the stream-collide with the largest total time
+    q = plan.q
+    bpe = 2 * q * STORAGE_BYTES[prec] + 4 * (q - 1)
+    prof = []
+    for k in range(plan.n_levels):
+        kms, n, el = sim.profile_read(k)
+        prof.append(dict(level=plan.level0 + k, launches=n, ms_total=kms,
+                         us_per_launch=1e3 * kms / max(n, 1),
+                         elements_per_launch=el / max(n, 1),
+                         gbs=(el * bpe / 1e9) / (kms / 1e3) if kms else 0.0))
+    dom = max(prof, key=lambda p: p["ms_total"])
+    achieved = dom["gbs"]
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": wl["desc"], "precision": prec,
+                   "elements": int(sum(i["n"] for i in plan.info)),
+                   "weighted_updates_per_step": int(upd),
+                   "levels": plan.n_levels},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "kernel": f"k_stream_collide level {dom['level']} ({prec})",
+                     "algorithmic_bytes_per_update": bpe,
+                     "us_per_launch": round(dom["us_per_launch"], 2),
+                     "elements_per_launch": round(dom["elements_per_launch"], 1)},
+        "kernels": prof,
+        "status_flags": status,
+    }
+    if args.variants and wl.get("tgv"):
+        # precision study at a fixed run length: MLUPS and eps_u for each
+        study = {}
+        n_fix = 1000
+        for p in ("f64", "f32", "f16s"):
+            print(f"[bench] precision study {p}", file=sys.stderr, flush=True)
+            s2 = make_sim(M, torch, wl, plan, p)
+            s2.step(20)
+            t_ms = timed_steps(torch, s2, n_fix - 20)
+            study[p] = dict(mlups=round(upd * (n_fix - 20) / (t_ms / 1e3) / 1e6, 1),
+                            eps_u=tgv_velocity_error(s2, plan, wl, n_fix),
+                            status=s2.status())
+            del s2
+        ref = study["f64"]["eps_u"]
+        for p in study:
+            study[p]["fixed_error_pass"] = bool(study[p]["eps_u"] <= 1.05 * ref)
+        out["precision_study"] = {"coarse_steps": n_fix, "results": study}
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = n
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

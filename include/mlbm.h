@@ -207,9 +207,17 @@ int32_t mlbm_checkpoint_bytes(const mlbm_sim* sim, size_t* bytes);
 int32_t mlbm_save_checkpoint(mlbm_sim* sim, void* dev_dst, size_t bytes);
 int32_t mlbm_load_checkpoint(mlbm_sim* sim, const void* dev_src, size_t bytes);
 
-/* Per-launch timing hook: the number of kernel launches one coarse step
- * enqueues (for profiling). */
+/* The number of kernel launches one coarse step enqueues. */
 int32_t mlbm_launches_per_step(const mlbm_sim* sim, int64_t* launches);
+
+/* Kernel timing.  While enabled, every stream-collide launch is bracketed
+ * by HIP events recorded on the bound stream; enabling synchronises the
+ * stream and clears earlier records.  mlbm_profile_read (synchronises)
+ * returns, for level index k, the summed bracketed time in milliseconds,
+ * the number of launches and the summed number of elements updated. */
+int32_t mlbm_profile(mlbm_sim* sim, int32_t enable);
+int32_t mlbm_profile_read(mlbm_sim* sim, int32_t k, double* ms, int64_t* launches,
+                          int64_t* elements);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,8 @@ SIGNATURES = {
     "mlbm_save_checkpoint": (_i32, [_p, _p, _sz]),
     "mlbm_load_checkpoint": (_i32, [_p, _p, _sz]),
     "mlbm_launches_per_step": (_i32, [_p, _pi64]),
+    "mlbm_profile": (_i32, [_p, _i32]),
+    "mlbm_profile_read": (_i32, [_p, _i32, _pd, _pi64, _pi64]),
 }
 
 _LIB = None

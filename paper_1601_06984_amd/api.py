@@ -211,6 +211,15 @@ class Sim:
     def load_checkpoint(self, buf):
         check(lib().mlbm_load_checkpoint(self._h, self._ptr(buf), buf.numel()))
 
+    def profile(self, enable: bool):
+        check(lib().mlbm_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self, k: int):
+        """(ms, launches, elements) of level k's stream-collide launches."""
+        ms, n, el = C.c_double(), C.c_int64(), C.c_int64()
+        check(lib().mlbm_profile_read(self._h, k, C.byref(ms), C.byref(n), C.byref(el)))
+        return ms.value, n.value, el.value
+
     def launches_per_step(self) -> int:
         n = C.c_int64()
         check(lib().mlbm_launches_per_step(self._h, C.byref(n)))

@@ -37,7 +37,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", src, "-o", obj])
+        _run(["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-c", src, "-o", obj])
         objs.append(obj)
     for src in HIP_SOURCES:
         if not os.path.exists(os.path.join(CSRC, src)):
@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
         _run([hipcc] + HIPCC_FLAGS + ["-c", src, "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs)
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

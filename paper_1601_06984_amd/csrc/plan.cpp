@@ -3,6 +3,8 @@
 // builds the neighbour, interpolation-source and capture tables that the
 // device kernels consume.
 #include <algorithm>
+#include <chrono>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstring>
 #include <memory>
@@ -10,6 +12,7 @@
 #include <numeric>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -141,6 +144,8 @@ struct LevelWork {
   bool bb_set = false;
   CellMap map;
   std::vector<int64_t> gff, gfc;      // provisional ghost coords
+  std::vector<int64_t> refined;       // refined positions (coords)
+  std::vector<int64_t> ring;          // fluid positions touching refined ones
   int64_t deeper = 0;
 };
 
@@ -173,14 +178,44 @@ void for_offsets(int d, int r, F&& fn) {
   }
 }
 
+// Splits [0, n) into contiguous chunks over the hardware threads.
+template <class F>
+void parallel_for(int64_t n, F&& fn) {
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = std::max(1u, std::min(nt, 16u));
+  if (n < (1 << 16) || nt == 1) {
+    fn((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const int64_t a = (int64_t)t * chunk, b = std::min(n, a + chunk);
+    if (a < b) th.emplace_back([&fn, a, b] { fn(a, b); });
+  }
+  for (auto& t : th) t.join();
+}
+
 template <class Lat>
 void velocity(int i, int64_t* v) {
   for (int a = 0; a < Lat::D; ++a) v[a] = Lat::c(i, a);
 }
 
+struct PhaseTimer {
+  bool on = std::getenv("MLBM_PLAN_TIMING") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char* what) {
+    if (!on) return;
+    auto n = std::chrono::steady_clock::now();
+    fprintf(stderr, "[plan] %-28s %8.3f s\n", what, std::chrono::duration<double>(n - t).count());
+    t = n;
+  }
+};
+
 void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
                 const uint64_t* solid_ids, int64_t n_solids) {
   const int d = P.d, q = P.q;
+  PhaseTimer T;
   Geom g;
   g.d = d;
   g.level0 = P.level0;
@@ -240,6 +275,7 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
   box <<= d * (lmax - L0);
   if (volume != box) throw MeshError("leaves and solids do not tile the domain box");
 
+  T.mark("decode");
   // ---- level maps ---------------------------------------------------
   for (int k = 0; k < nlev; ++k) {
     const int L = L0 + k;
@@ -276,6 +312,7 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
       w.map.set(&w.solid[i * d], V_SOLID);
     }
   }
+  T.mark("insert");
   // refined positions: ancestors of every deeper leaf or solid
   auto mark_ancestors = [&](int L, const int64_t* c) {
     for (int K = L - 1; K >= L0; --K) {
@@ -286,6 +323,7 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
       if (v == V_REFINED) return;  // coarser ancestors already marked
       if (v != V_EMPTY) throw MeshError("overlapping elements");
       m.set(anc, V_REFINED);
+      for (int a = 0; a < d; ++a) W[K - L0].refined.push_back(anc[a]);
     }
   };
   for (int64_t i = 0; i < n_leaves; ++i) mark_ancestors(lvl_leaf[i], &c_leaf[i * d]);
@@ -293,42 +331,73 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
   std::vector<int>().swap(lvl_leaf);
   std::vector<int64_t>().swap(c_leaf);
 
+  T.mark("refined");
   // ---- ghost classification -------------------------------------------
+  // GhostFromFiner(L): refined cells within L-infinity distance 1 of level-L
+  // fluid.  The fluid cells they touch are the ring whose children are the
+  // only candidates for GhostFromCoarser(L+1): a level-(L+1) position within
+  // distance 2 of level-(L+1) fluid has its parent within distance 1 of a
+  // refined level-L cell.
   for (int k = 0; k < nlev; ++k) {
     const int L = L0 + k;
     auto& w = W[k];
     auto& m = w.map;
     const int64_t nf = (int64_t)w.fluid.size() / d;
-    for (int64_t i = 0; i < nf; ++i) {
-      const int64_t* x = &w.fluid[i * d];
-      if (L < lmax) {
-        for_offsets(d, 1, [&](const int64_t* o, int) {
-          int64_t y[3];
-          for (int a = 0; a < d; ++a) y[a] = x[a] + o[a];
-          if (g.wrap(y, L)) return;
-          if (m.get(y) == V_REFINED) {
-            m.set(y, V_GFF);
-            for (int a = 0; a < d; ++a) w.gff.push_back(y[a]);
+    std::vector<char> ring_mark((size_t)nf, 0);
+    const int64_t nr = (int64_t)w.refined.size() / d;
+    for (int64_t r = 0; r < nr; ++r) {
+      const int64_t* x = &w.refined[r * d];
+      bool touches = false;
+      for_offsets(d, 1, [&](const int64_t* o, int) {
+        int64_t y[3];
+        for (int a = 0; a < d; ++a) y[a] = x[a] + o[a];
+        if (g.wrap(y, L)) return;
+        const int32_t v = m.get(y);
+        if (v >= 0) {
+          touches = true;
+          if (!ring_mark[v]) {
+            ring_mark[v] = 1;
+            for (int a = 0; a < d; ++a) w.ring.push_back(y[a]);
           }
-        });
-      }
-      if (L > L0) {
-        for_offsets(d, 2, [&](const int64_t* o, int dist) {
-          int64_t y[3];
-          for (int a = 0; a < d; ++a) y[a] = x[a] + o[a];
-          if (g.wrap(y, L)) return;
-          const int32_t v = m.get(y);
-          if (v == V_EMPTY) {
-            m.set(y, dist == 1 ? V_GFC_IN : V_GFC_OUT);
-            for (int a = 0; a < d; ++a) w.gfc.push_back(y[a]);
-          } else if (v == V_GFC_OUT && dist == 1) {
-            m.set(y, V_GFC_IN);
-          }
-        });
+        }
+      });
+      if (touches) {
+        m.set(x, V_GFF);
+        for (int a = 0; a < d; ++a) w.gff.push_back(x[a]);
       }
     }
   }
+  for (int k = 1; k < nlev; ++k) {
+    const int L = L0 + k;
+    auto& w = W[k];
+    auto& m = w.map;
+    const auto& ring = W[k - 1].ring;
+    const int nch = 1 << d;
+    for (size_t r = 0; r < ring.size() / d; ++r) {
+      for (int c = 0; c < nch; ++c) {
+        int64_t y[3];
+        for (int a = 0; a < d; ++a) y[a] = 2 * ring[r * d + a] + ((c >> a) & 1);
+        if (m.get(y) != V_EMPTY) continue;
+        int best = 3;
+        for_offsets(d, 2, [&](const int64_t* o, int dist) {
+          if (dist >= best) return;
+          int64_t z[3];
+          for (int a = 0; a < d; ++a) z[a] = y[a] + o[a];
+          if (g.wrap(z, L)) return;
+          if (m.get(z) >= 0) best = dist;
+        });
+        if (best <= 2) {
+          m.set(y, best == 1 ? V_GFC_IN : V_GFC_OUT);
+          for (int a = 0; a < d; ++a) w.gfc.push_back(y[a]);
+        }
+      }
+    }
+  }
+  for (auto& w : W) {
+    std::vector<int64_t>().swap(w.refined);
+  }
 
+  T.mark("classify");
   // ---- layout -------------------------------------------------------
   P.lv.assign(nlev, LevelPlan());
   for (int k = 0; k < nlev; ++k) {
@@ -378,6 +447,7 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
     w.fluid.swap(all);  // keep layout-ordered coords
   }
 
+  T.mark("layout");
   // ---- neighbours ----------------------------------------------------
   for (int k = 0; k < nlev; ++k) {
     const int L = L0 + k;
@@ -385,23 +455,51 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
     auto& lp = P.lv[k];
     const int64_t n = lp.n;
     lp.nbr.assign((size_t)(q - 1) * n, MLBM_NBR_MISSING);
-    for (int64_t x = 0; x < n; ++x) {
-      const int64_t* cx = &w.fluid[x * d];
-      for (int i = 1; i < q; ++i) {
-        int64_t y[3], v[3];
-        if (d == 3) velocity<D3Q19>(i, v); else velocity<D2Q9>(i, v);
-        for (int a = 0; a < d; ++a) y[a] = cx[a] - v[a];
-        const int crossed = g.wrap(y, L);
-        int32_t code;
-        if (crossed) {
-          code = g.face_code(crossed);
-        } else {
-          const int32_t val = w.map.get(y);
-          code = val >= 0 ? val : (val == V_SOLID ? MLBM_NBR_BOUNCE : MLBM_NBR_MISSING);
-        }
-        lp.nbr[(size_t)(i - 1) * n + x] = code;
+    const CellMap& m = w.map;
+    int64_t vel[19][3];
+    int64_t delta[19];
+    for (int i = 0; i < q; ++i) {
+      int64_t v[3] = {0, 0, 0};
+      if (d == 3) velocity<D3Q19>(i, v); else velocity<D2Q9>(i, v);
+      int64_t stride = 1;
+      delta[i] = 0;
+      for (int a = 0; a < d; ++a) {
+        vel[i][a] = v[a];
+        delta[i] += -v[a] * stride;
+        stride *= m.ext[a];
       }
     }
+    auto work = [&](int64_t x0, int64_t x1) {
+      for (int64_t x = x0; x < x1; ++x) {
+        const int64_t* cx = &w.fluid[x * d];
+        bool interior = m.dense;
+        for (int a = 0; a < d && interior; ++a)
+          interior = cx[a] >= m.lo[a] + 1 && cx[a] < m.lo[a] + m.ext[a] - 1;
+        if (interior) {
+          const int64_t base = m.dkey(cx);
+          for (int i = 1; i < q; ++i) {
+            const int32_t val = m.grid[base + delta[i]];
+            lp.nbr[(size_t)(i - 1) * n + x] =
+                val >= 0 ? val : (val == V_SOLID ? MLBM_NBR_BOUNCE : MLBM_NBR_MISSING);
+          }
+          continue;
+        }
+        for (int i = 1; i < q; ++i) {
+          int64_t y[3];
+          for (int a = 0; a < d; ++a) y[a] = cx[a] - vel[i][a];
+          const int crossed = g.wrap(y, L);
+          int32_t code;
+          if (crossed) {
+            code = g.face_code(crossed);
+          } else {
+            const int32_t val = m.get(y);
+            code = val >= 0 ? val : (val == V_SOLID ? MLBM_NBR_BOUNCE : MLBM_NBR_MISSING);
+          }
+          lp.nbr[(size_t)(i - 1) * n + x] = code;
+        }
+      }
+    };
+    parallel_for(n, work);
     const int64_t act = lp.n_active_max();
     for (int i = 1; i < q; ++i)
       for (int64_t x = 0; x < act; ++x)
@@ -427,6 +525,7 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
     lp.bounce.swap(b);
   }
 
+  T.mark("neighbours");
   // ---- interpolation sources -------------------------------------------
   static const int gff3[4][3] = {{0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
   static const int gff2[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
@@ -487,6 +586,7 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
     }
   }
 
+  T.mark("sources");
   // ---- capture sets, slots, parent groups -------------------------------
   std::vector<std::vector<int32_t>> slot_of(nlev);
   for (int k = 0; k < nlev; ++k) {

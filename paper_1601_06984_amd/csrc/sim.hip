@@ -106,6 +106,12 @@ struct Impl {
     const unsigned grid = (unsigned)((n_act + BS - 1) / BS);
     hipLaunchKernelGGL((k_stream_collide<Lat, P, BS>), dim3(grid), dim3(BS), 0, s.stream, src, dst,
                        L.nbr, n_act, a, s.status);
+  }
+
+  static void capture(SimState& s, int k) {
+    DevLevel& L = s.lv[k];
+    auto a = level_args<C, Lat::Q>(s, k);
+    const S* src = (const S*)L.pdf[L.parity];
     if (L.n_cap_fluid) {
       const unsigned gc = (unsigned)((L.n_cap_fluid + 255) / 256);
       hipLaunchKernelGGL((k_capture<Lat, P>), dim3(gc), dim3(256), 0, s.stream, src, L.nbr,
@@ -212,11 +218,35 @@ struct Impl {
     }                                                                       \
   } while (0)
 
+SimState::~SimState() {
+  for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+}
+
+static hipEvent_t prof_event(SimState& s) {
+  if (s.prof.used == s.prof.pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    s.prof.pool.push_back(e);
+  }
+  return s.prof.pool[s.prof.used++];
+}
+
 void sc_level(SimState& s, int k) {
   DevLevel& L = s.lv[k];
   const bool first = (k > 0) && (L.substep == 0);
   const int64_t n_act = L.n_fluid + (first ? L.n_inner : 0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (s.prof.on) {
+    e0 = prof_event(s);
+    e1 = prof_event(s);
+    if (e0 && e1) (void)hipEventRecord(e0, s.stream);
+  }
   MLBM_DISPATCH(s, I::stream_collide(s, k, n_act));
+  if (s.prof.on && e0 && e1) {
+    (void)hipEventRecord(e1, s.stream);
+    s.prof.rec.push_back({k, n_act, e0, e1});
+  }
+  MLBM_DISPATCH(s, I::capture(s, k));
   L.parity ^= 1;
   if (k > 0) L.substep ^= 1;
 }
@@ -511,6 +541,41 @@ int32_t mlbm_load_checkpoint(mlbm_sim* sim, const void* dev_src, size_t bytes) {
   s.time = h.time;
   std::fill(s.inited.begin(), s.inited.end(), true);
   s.filled = true;
+  return MLBM_OK;
+}
+
+int32_t mlbm_profile(mlbm_sim* sim, int32_t enable) {
+  if (!sim) return fail(MLBM_E_ARG, "sim is NULL");
+  SimState& s = sim->s;
+  if (enable) {
+    if (hipStreamSynchronize(s.stream) != hipSuccess) return fail(MLBM_E_HIP, "profile: sync failed");
+    s.prof.rec.clear();
+    s.prof.used = 0;
+  }
+  s.prof.on = enable != 0;
+  return MLBM_OK;
+}
+
+int32_t mlbm_profile_read(mlbm_sim* sim, int32_t k, double* ms, int64_t* launches,
+                          int64_t* elements) {
+  if (!sim || !ms || !launches || !elements) return fail(MLBM_E_ARG, "NULL argument");
+  SimState& s = sim->s;
+  if (k < 0 || k >= (int)s.lv.size()) return fail(MLBM_E_ARG, "level index %d out of range", k);
+  if (hipStreamSynchronize(s.stream) != hipSuccess) return fail(MLBM_E_HIP, "profile: sync failed");
+  double t = 0;
+  int64_t n = 0, el = 0;
+  for (const auto& r : s.prof.rec) {
+    if (r.level != k) continue;
+    float dt = 0;
+    if (hipEventElapsedTime(&dt, r.start, r.stop) != hipSuccess)
+      return fail(MLBM_E_HIP, "profile: elapsed time failed");
+    t += dt;
+    n++;
+    el += r.n_act;
+  }
+  *ms = t;
+  *launches = n;
+  *elements = el;
   return MLBM_OK;
 }
 

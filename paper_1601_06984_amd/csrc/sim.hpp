@@ -32,6 +32,19 @@ struct DevLevel {
   bool f16_auto = false;
 };
 
+// Event-bracketed timing of stream-collide launches.
+struct ProfRecord {
+  int level;
+  int64_t n_act;
+  hipEvent_t start, stop;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<ProfRecord> rec;
+};
+
 struct SimState {
   int stencil = 0, d = 3, q = 19, precision = 0, level0 = 0;
   double tau0 = 1.0, rho0 = 1.0, u_in[3] = {0, 0, 0};
@@ -47,6 +60,8 @@ struct SimState {
   std::vector<bool> inited;
   bool filled = false;
   int64_t time = 0;
+  Profiler prof;
+  ~SimState();
 };
 
 struct CheckpointHeader {

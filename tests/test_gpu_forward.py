@@ -44,6 +44,7 @@ def test_config1_d2q9_f64_tgv_200_steps():
     assert sim.status() == 0
 
 
+@pytest.mark.timeout(400)
 @pytest.mark.parametrize("base,lo,hi", [(5, 8, 24), (6, 16, 48)])
 def test_config2_d3q19_f32_100_steps(base, lo, hi):
     """D3Q19 TGV with the central cube refined, u0 = 0.02, Re = 100
