@@ -175,9 +175,13 @@ def main():
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     sim.step(args.warmup)
     torch.cuda.synchronize()
-    sim.profile(True)
     print(f"[bench] timed {args.steps} coarse steps", file=sys.stderr, flush=True)
     ms = timed_steps(torch, sim, args.steps)
+    # per-kernel durations: the same number of steps launched directly, each
+    # stream-collide bracketed by HIP events on the stream it runs on
+    print(f"[bench] kernel timing over {args.steps} coarse steps", file=sys.stderr, flush=True)
+    sim.profile(True)
+    ms_direct = timed_steps(torch, sim, args.steps)
     sim.profile(False)
     status = sim.status()
     value = upd * args.steps / (ms / 1e3) / 1e6
@@ -210,6 +214,7 @@ def main():
                      "us_per_launch": round(dom["us_per_launch"], 2),
                      "elements_per_launch": round(dom["elements_per_launch"], 1)},
         "kernels": prof,
+        "ms_per_step_direct_launches": ms_direct / args.steps,
         "status_flags": status,
     }
     if args.variants and wl.get("tgv"):

@@ -23,8 +23,9 @@
  *
  * Element layout (per level L, Sec. 3.2 stores fluid, then ghosts, each
  * along the space-filling curve): [fluid | GhostFromCoarser inner |
- * GhostFromCoarser outer | GhostFromFiner], every segment ascending by
- * treeID.  Per-element arrays are structure-of-arrays: component k of
+ * GhostFromCoarser outer | GhostFromFiner].  The fluid segment is itself
+ * [fluid read by no interpolation | interpolation-source fluid]; every
+ * part is ascending by treeID.  Per-element arrays are structure-of-arrays: component k of
  * element x is at k * n_level + x.
  */
 #ifndef MLBM_H
@@ -81,7 +82,8 @@ enum {
   MLBM_TABLE_GFF_SRC = 4,  /* int32 [4][n_gff]: source element indices on
                               level L+1                                      */
   MLBM_TABLE_CAPTURE = 5,  /* int32 [n_cap_fluid]: fluid elements whose
-                              pre-collision moments are captured            */
+                              pre-collision moments are captured (the tail
+                              of the fluid segment)                         */
   MLBM_TABLE_BOUNCE = 6    /* int32 [2][n_bounce]: (element, direction i)
                               fluid links whose pull source is solid        */
 };
@@ -179,8 +181,13 @@ int32_t mlbm_init(mlbm_sim* sim, int32_t k, const double* rho, const double* u,
 int32_t mlbm_fill_ghosts(mlbm_sim* sim);
 /* Advance n coarse steps with the recursive schedule: advance(L) = one
  * stream-collide of L; if L < Lmax: advance(L+1) twice, fill
- * GhostFromFiner(L), fill GhostFromCoarser(L+1).  Asynchronous. */
+ * GhostFromFiner(L), fill GhostFromCoarser(L+1).  Asynchronous.  Pairs of
+ * coarse steps are replayed from an instantiated HIP graph (recorded once
+ * per parity state on an internal stream, launched on the bound stream);
+ * the results are identical to direct launches. */
 int32_t mlbm_step(mlbm_sim* sim, int64_t n_coarse);
+/* Enable (default) or disable graph replay in mlbm_step. */
+int32_t mlbm_use_graphs(mlbm_sim* sim, int32_t enable);
 /* FP64 reductions written to device memory `dev_out` (deterministic, no
  * atomics): for each bit set in `mask` in the order MASS (1 value),
  * KE (1), FORCE (d).  MASS = sum_L V_L sum_fluid rho; KE = 1/2 sum_L V_L

@@ -58,6 +58,7 @@ SIGNATURES = {
     "mlbm_load_checkpoint": (_i32, [_p, _p, _sz]),
     "mlbm_launches_per_step": (_i32, [_p, _pi64]),
     "mlbm_profile": (_i32, [_p, _i32]),
+    "mlbm_use_graphs": (_i32, [_p, _i32]),
     "mlbm_profile_read": (_i32, [_p, _i32, _pd, _pi64, _pi64]),
 }
 

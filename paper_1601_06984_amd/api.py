@@ -211,6 +211,9 @@ class Sim:
     def load_checkpoint(self, buf):
         check(lib().mlbm_load_checkpoint(self._h, self._ptr(buf), buf.numel()))
 
+    def use_graphs(self, enable: bool):
+        check(lib().mlbm_use_graphs(self._h, 1 if enable else 0))
+
     def profile(self, enable: bool):
         check(lib().mlbm_profile(self._h, 1 if enable else 0))
 

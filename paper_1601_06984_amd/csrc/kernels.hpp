@@ -55,6 +55,8 @@ template <class C, int Q>
 struct LevelArgs {
   int64_t n;          // elements (row stride of the pdf arrays)
   int64_t ld_nbr;     // row stride of the neighbour table
+  int64_t cap_begin;  // fluid elements [cap_begin, n_fluid) are sources
+  int64_t n_fluid;
   C omega;            // BGK relaxation rate of the level
   C rho0;
   C scale, inv_scale; // F16S scale s_L and 1/s_L
@@ -130,48 +132,11 @@ __device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__
   }
 }
 
-// --------------------------------------------------- stream-collide -------
-// One thread per active element x in [0, n_act); Eq. bgk in g-form, result
-// stored coalesced in the destination array.  Blocks are remapped so that
-// each of the 8 XCDs streams a contiguous slice of the element range.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
-  const int64_t q = nb >> 3, r = nb & 7, xcd = b & 7, k = b >> 3;
-  return xcd * q + (xcd < r ? xcd : r) + k;
-}
-
-template <class Lat, int P, int BS>
-__global__ __launch_bounds__(BS) void k_stream_collide(
-    const typename Prec<P>::S* __restrict__ src, typename Prec<P>::S* __restrict__ dst,
-    const int32_t* __restrict__ nbr, int64_t n_act,
-    const LevelArgs<typename Prec<P>::C, Lat::Q> a, uint32_t* __restrict__ status) {
-  using C = typename Prec<P>::C;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t x = blk * BS + threadIdx.x;
-  if (x >= n_act) return;
-  C g[Lat::Q];
-  gather_g<Lat, P>(src, nbr, x, a, g);
-  C drho, rho, u[3];
-  macro_g<Lat, C>(g, a.rho0, drho, rho, u);
-  const C uu = dot_uu<Lat, C>(u);
-  bool ok = true;
-#pragma unroll
-  for (int i = 0; i < Lat::Q; ++i) {
-    const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
-    ok &= store_g<P>(dst, (int64_t)i * a.n + x, gs, a.wr[i], a.scale);
-  }
-  const bool finite = (rho == rho) && (rho - rho == C(0));
-  if (!finite || !ok)
-    atomicOr(status, (finite ? 0u : (uint32_t)MLBM_STATUS_NONFINITE) |
-                         (ok ? 0u : (uint32_t)MLBM_STATUS_F16_OVERFLOW));
-}
-
 // Pre-collision moments of a g-vector into a capture record:
 // drho, u, S_ab = -(3 omega / (2 rho)) sum_i c_ia c_ib g^neq_i, g^neq.
 template <class Lat, class C, class R>
-__device__ __forceinline__ void write_record(R* __restrict__ rec, const C* g, C rho0, C omega) {
-  C drho, rho, u[3];
-  macro_g<Lat, C>(g, rho0, drho, rho, u);
-  const C uu = dot_uu<Lat, C>(u);
+__device__ __forceinline__ void write_record_m(R* __restrict__ rec, const C* g, C drho, C rho,
+                                               const C* u, C uu, C omega) {
   C fneq[Lat::Q];
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) fneq[i] = g[i] - geq_i<Lat, C>(i, drho, rho, u, uu);
@@ -195,20 +160,52 @@ __device__ __forceinline__ void write_record(R* __restrict__ rec, const C* g, C 
   for (int i = 0; i < Lat::Q; ++i) rec[cap_fneq(Lat::D) + i] = (R)fneq[i];
 }
 
-// Capture: pre-collision moments of the fluid source elements, gathered
-// from the same (old) array the stream-collide read.
-template <class Lat, int P>
-__global__ __launch_bounds__(256) void k_capture(
-    const typename Prec<P>::S* __restrict__ src, const int32_t* __restrict__ nbr,
-    const int32_t* __restrict__ cap_elem, int64_t n_cap, typename Prec<P>::C* __restrict__ cap,
-    const LevelArgs<typename Prec<P>::C, Lat::Q> a) {
+template <class Lat, class C, class R>
+__device__ __forceinline__ void write_record(R* __restrict__ rec, const C* g, C rho0, C omega) {
+  C drho, rho, u[3];
+  macro_g<Lat, C>(g, rho0, drho, rho, u);
+  write_record_m<Lat, C, R>(rec, g, drho, rho, u, dot_uu<Lat, C>(u), omega);
+}
+
+// --------------------------------------------------- stream-collide -------
+// One thread per active element x in [0, n_act); Eq. bgk in g-form, result
+// stored coalesced in the destination array.  Elements of the capture
+// segment also write their pre-collision moments (the interpolation input).  Blocks are remapped so that
+// each of the 8 XCDs streams a contiguous slice of the element range.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb >> 3, r = nb & 7, xcd = b & 7, k = b >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+template <class Lat, int P, int BS>
+__global__ __launch_bounds__(BS) void k_stream_collide(
+    const typename Prec<P>::S* __restrict__ src, typename Prec<P>::S* __restrict__ dst,
+    const int32_t* __restrict__ nbr, int64_t n_act,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C* __restrict__ cap,
+    uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
-  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (s >= n_cap) return;
-  const int64_t x = cap_elem[s];
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t x = blk * BS + threadIdx.x;
+  if (x >= n_act) return;
   C g[Lat::Q];
   gather_g<Lat, P>(src, nbr, x, a, g);
-  write_record<Lat, C>(cap + s * cap_stride(Lat::D), g, a.rho0, a.omega);
+  C drho, rho, u[3];
+  macro_g<Lat, C>(g, a.rho0, drho, rho, u);
+  const C uu = dot_uu<Lat, C>(u);
+  // interpolation sources keep their pre-collision moments
+  if (x >= a.cap_begin && x < a.n_fluid)
+    write_record_m<Lat, C, C>(cap + (x - a.cap_begin) * cap_stride(Lat::D), g, drho, rho, u, uu,
+                              a.omega);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
+    ok &= store_g<P>(dst, (int64_t)i * a.n + x, gs, a.wr[i], a.scale);
+  }
+  const bool finite = (rho == rho) && (rho - rho == C(0));
+  if (!finite || !ok)
+    atomicOr(status, (finite ? 0u : (uint32_t)MLBM_STATUS_NONFINITE) |
+                         (ok ? 0u : (uint32_t)MLBM_STATUS_F16_OVERFLOW));
 }
 
 // --------------------------------------------------- interpolation --------
@@ -247,7 +244,7 @@ __device__ __forceinline__ bool emit_ghost(typename Prec<P>::S* __restrict__ pdf
 // the compact interpolation at the tetrahedron's centroid:
 // u = mean(u_k) - 1/4 (a_xx + a_yy + a_zz) per component.
 template <class Lat, int P>
-__global__ __launch_bounds__(256) void k_fill_gff(
+__global__ __launch_bounds__(64) void k_fill_gff(
     typename Prec<P>::S* __restrict__ pdf, int64_t gff_begin, int64_t n_gff,
     const int32_t* __restrict__ slots, const typename Prec<P>::C* __restrict__ cap_fine,
     typename Prec<P>::C* __restrict__ cap_coarse, int64_t cap_gff_begin,
@@ -255,7 +252,7 @@ __global__ __launch_bounds__(256) void k_fill_gff(
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (j >= n_gff) return;
   Rec<Lat, C> r[4];
 #pragma unroll
@@ -344,17 +341,24 @@ __global__ __launch_bounds__(64) void k_fill_gfc(
   constexpr int NB = group_slots(D), NC = group_children(D);
   constexpr int GPB = 64 / NC;
   constexpr int ST = cap_stride(D);
-  __shared__ C sh[GPB * NB * ST];
+  constexpr int USED = cap_fneq(D) + Lat::Q;   // components actually read
+  constexpr int LST = USED | 1;                // odd LDS stride: no bank conflicts
+  __shared__ C sh[GPB * NB * LST];
   const int64_t g0 = (int64_t)blockIdx.x * GPB;
-  for (int t = threadIdx.x; t < GPB * NB * ST; t += 64) {
-    const int comp = t % ST, sl = (t / ST) % NB, gl = t / (ST * NB);
+  // one record per thread and pass: a single slot lookup, contiguous reads
+  for (int r = threadIdx.x; r < GPB * NB; r += 64) {
+    const int gl = r / NB, sl = r % NB;
     const int64_t g = g0 + gl;
-    C v = 0;
-    if (g < n_groups) {
-      const int32_t slot = grp_src[(int64_t)sl * n_groups + g];
-      if (slot >= 0) v = cap_coarse[(int64_t)slot * ST + comp];
+    const int32_t slot = g < n_groups ? grp_src[(int64_t)sl * n_groups + g] : -1;
+    C* dst = sh + r * LST;
+    if (slot >= 0) {
+      const C* src = cap_coarse + (int64_t)slot * ST;
+#pragma unroll
+      for (int c = 0; c < USED; ++c) dst[c] = src[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < USED; ++c) dst[c] = C(0);
     }
-    sh[t] = v;
   }
   __syncthreads();
   const int gl = threadIdx.x / NC, c = threadIdx.x % NC;
@@ -363,13 +367,13 @@ __global__ __launch_bounds__(64) void k_fill_gfc(
   const int32_t target = grp_child[(int64_t)c * n_groups + g];
   if (target < 0) return;
   const int sx = (c & 1) ? 1 : -1, sy = (c & 2) ? 1 : -1, sz = (c & 4) ? 1 : -1;
-  const C* base = sh + gl * NB * ST;
+  const C* base = sh + gl * NB * LST;
   C u[3] = {0, 0, 0}, drho, fneq[Lat::Q];
   if constexpr (D == 3) {
-    const Rec<Lat, C> H{base + group_slot_of(3, 0, 0, 0) * ST};
-    const Rec<Lat, C> K{base + group_slot_of(3, sx, sy, 0) * ST};
-    const Rec<Lat, C> M{base + group_slot_of(3, sx, 0, sz) * ST};
-    const Rec<Lat, C> N{base + group_slot_of(3, 0, sy, sz) * ST};
+    const Rec<Lat, C> H{base + group_slot_of(3, 0, 0, 0) * LST};
+    const Rec<Lat, C> K{base + group_slot_of(3, sx, sy, 0) * LST};
+    const Rec<Lat, C> M{base + group_slot_of(3, sx, 0, sz) * LST};
+    const Rec<Lat, C> N{base + group_slot_of(3, 0, sy, sz) * LST};
     const C hx = C(0.5) * sx, hy = C(0.5) * sy, hz = C(0.5) * sz;
     auto Dx = [&](int k) { return hx * (-H.S(k) + K.S(k) + M.S(k) - N.S(k)); };
     auto Dy = [&](int k) { return hy * (-H.S(k) + K.S(k) - M.S(k) + N.S(k)); };
@@ -394,10 +398,10 @@ __global__ __launch_bounds__(64) void k_fill_gfc(
     for (int i = 0; i < Lat::Q; ++i)
       fneq[i] = (w5 * H.fneq(i) + w1 * (K.fneq(i) + M.fneq(i) + N.fneq(i))) * fneq_scale;
   } else {
-    const Rec<Lat, C> R0{base + group_slot_of(2, 0, 0, 0) * ST};
-    const Rec<Lat, C> Rx{base + group_slot_of(2, sx, 0, 0) * ST};
-    const Rec<Lat, C> Ry{base + group_slot_of(2, 0, sy, 0) * ST};
-    const Rec<Lat, C> Rxy{base + group_slot_of(2, sx, sy, 0) * ST};
+    const Rec<Lat, C> R0{base + group_slot_of(2, 0, 0, 0) * LST};
+    const Rec<Lat, C> Rx{base + group_slot_of(2, sx, 0, 0) * LST};
+    const Rec<Lat, C> Ry{base + group_slot_of(2, 0, sy, 0) * LST};
+    const Rec<Lat, C> Rxy{base + group_slot_of(2, sx, sy, 0) * LST};
     const C hx = C(0.5) * sx, hy = C(0.5) * sy;
     auto Dx = [&](int k) { return hx * (-R0.S(k) + Rx.S(k) - Ry.S(k) + Rxy.S(k)); };
     auto Dy = [&](int k) { return hy * (-R0.S(k) - Rx.S(k) + Ry.S(k) + Rxy.S(k)); };

@@ -398,6 +398,54 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
   }
 
   T.mark("classify");
+  // ---- capture sources ----------------------------------------------
+  // Fluid elements read by an interpolation (the parent H and K, M, N of a
+  // GhostFromCoarser one level up, the four children of a GhostFromFiner one
+  // level down) are laid out as the tail of the fluid segment, so the
+  // stream-collide kernel knows from the index alone that it must record the
+  // pre-collision moments of an element.
+  std::vector<std::vector<char>> src_mark(nlev);
+  for (int k = 0; k < nlev; ++k) src_mark[k].assign(W[k].fluid.size() / d, 0);
+  for (int k = 1; k < nlev; ++k) {
+    const auto& gl = W[k].gfc;
+    for (size_t j = 0; j < gl.size() / d; ++j) {
+      int64_t par[3], s[3];
+      for (int a = 0; a < d; ++a) {
+        par[a] = gl[j * d + a] >> 1;
+        s[a] = (gl[j * d + a] & 1) ? 1 : -1;
+      }
+      int64_t off[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      if (d == 3) {
+        off[1][0] = s[0]; off[1][1] = s[1];
+        off[2][0] = s[0]; off[2][2] = s[2];
+        off[3][1] = s[1]; off[3][2] = s[2];
+      } else {
+        off[1][0] = s[0];
+        off[2][1] = s[1];
+        off[3][0] = s[0]; off[3][1] = s[1];
+      }
+      for (int t = 0; t < 4; ++t) {
+        int64_t y[3];
+        for (int a = 0; a < d; ++a) y[a] = par[a] + off[t][a];
+        if (g.wrap(y, L0 + k - 1)) continue;  // rejected with the source check
+        const int32_t v = W[k - 1].map.get(y);
+        if (v >= 0) src_mark[k - 1][v] = 1;
+      }
+    }
+  }
+  for (int k = 0; k + 1 < nlev; ++k) {
+    const auto& gl = W[k].gff;
+    static const int ch3[4][3] = {{0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+    static const int ch2[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+    for (size_t j = 0; j < gl.size() / d; ++j)
+      for (int t = 0; t < 4; ++t) {
+        int64_t y[3];
+        for (int a = 0; a < d; ++a) y[a] = 2 * gl[j * d + a] + (d == 3 ? ch3[t][a] : ch2[t][a]);
+        const int32_t v = W[k + 1].map.get(y);
+        if (v >= 0) src_mark[k + 1][v] = 1;
+      }
+  }
+
   // ---- layout -------------------------------------------------------
   P.lv.assign(nlev, LevelPlan());
   for (int k = 0; k < nlev; ++k) {
@@ -405,17 +453,22 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
     auto& w = W[k];
     auto& lp = P.lv[k];
     lp.level = L;
-    std::vector<int64_t> inner, outer;
+    std::vector<int64_t> inner, outer, plain, capt;
     for (size_t i = 0; i < w.gfc.size() / d; ++i) {
       const int64_t* y = &w.gfc[i * d];
       auto& dst = (w.map.get(y) == V_GFC_IN) ? inner : outer;
       for (int a = 0; a < d; ++a) dst.push_back(y[a]);
     }
+    for (size_t i = 0; i < w.fluid.size() / d; ++i) {
+      auto& dst = src_mark[k][i] ? capt : plain;
+      for (int a = 0; a < d; ++a) dst.push_back(w.fluid[i * d + a]);
+    }
+    std::vector<char>().swap(src_mark[k]);
     std::vector<int64_t> all;
-    const std::vector<int64_t>* parts[4] = {&w.fluid, &inner, &outer, &w.gff};
-    int64_t counts[4];
+    const std::vector<int64_t>* parts[5] = {&plain, &capt, &inner, &outer, &w.gff};
+    int64_t counts[5];
     lp.tid.clear();
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < 5; ++p) {
       const auto& v = *parts[p];
       const int64_t n = (int64_t)v.size() / d;
       counts[p] = n;
@@ -430,11 +483,12 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
         for (int a = 0; a < d; ++a) all.push_back(v[ord[i] * d + a]);
       }
     }
-    lp.n_fluid = counts[0];
-    lp.n_inner = counts[1];
-    lp.n_outer = counts[2];
-    lp.n_gff = counts[3];
-    lp.n = counts[0] + counts[1] + counts[2] + counts[3];
+    lp.cap_begin = counts[0];
+    lp.n_fluid = counts[0] + counts[1];
+    lp.n_inner = counts[2];
+    lp.n_outer = counts[3];
+    lp.n_gff = counts[4];
+    lp.n = lp.n_fluid + lp.n_inner + lp.n_outer + lp.n_gff;
     if (lp.n >= INT32_MAX) throw MeshError("level has too many elements for int32 indices");
     lp.coords.resize((size_t)d * lp.n);
     for (int64_t i = 0; i < lp.n; ++i) {
@@ -602,13 +656,16 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
       for (int32_t v : cpl.gff_src)
         if (v >= 0 && v < lp.n_fluid) mark[v] = 1;
     }
+    // the sources found in the tables are exactly the laid-out tail
+    for (int64_t x = 0; x < lp.n_fluid; ++x)
+      if ((bool)mark[x] != (x >= lp.cap_begin))
+        throw MeshError("internal: capture segment does not match the source tables");
     slot_of[k].assign((size_t)lp.n, -1);
     lp.cap_elem.clear();
-    for (int64_t x = 0; x < lp.n_fluid; ++x)
-      if (mark[x]) {
-        slot_of[k][x] = (int32_t)lp.cap_elem.size();
-        lp.cap_elem.push_back((int32_t)x);
-      }
+    for (int64_t x = lp.cap_begin; x < lp.n_fluid; ++x) {
+      slot_of[k][x] = (int32_t)lp.cap_elem.size();
+      lp.cap_elem.push_back((int32_t)x);
+    }
     const int64_t gb = lp.n_fluid + lp.n_gfc();
     for (int64_t j = 0; j < lp.n_gff; ++j)
       slot_of[k][gb + j] = (int32_t)(lp.n_cap_fluid() + j);

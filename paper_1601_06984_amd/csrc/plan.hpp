@@ -11,6 +11,7 @@ namespace mlbm {
 struct LevelPlan {
   int level = 0;
   int64_t n = 0, n_fluid = 0, n_inner = 0, n_outer = 0, n_gff = 0;
+  int64_t cap_begin = 0;           // fluid [cap_begin, n_fluid) are sources
   std::vector<uint64_t> tid;       // [n]
   std::vector<int32_t> coords;     // [d][n]
   std::vector<int32_t> nbr;        // [q-1][n]

@@ -79,6 +79,8 @@ LevelArgs<C, Q> level_args(const SimState& s, int k) {
   LevelArgs<C, Q> a;
   a.n = L.n;
   a.ld_nbr = L.n_act_max;
+  a.cap_begin = L.n_fluid - L.n_cap_fluid;
+  a.n_fluid = L.n_fluid;
   a.omega = (C)L.omega;
   a.rho0 = (C)s.rho0;
   a.scale = (C)std::ldexp(1.0, L.f16_exp);
@@ -105,18 +107,7 @@ struct Impl {
     S* dst = (S*)L.pdf[L.parity ^ 1];
     const unsigned grid = (unsigned)((n_act + BS - 1) / BS);
     hipLaunchKernelGGL((k_stream_collide<Lat, P, BS>), dim3(grid), dim3(BS), 0, s.stream, src, dst,
-                       L.nbr, n_act, a, s.status);
-  }
-
-  static void capture(SimState& s, int k) {
-    DevLevel& L = s.lv[k];
-    auto a = level_args<C, Lat::Q>(s, k);
-    const S* src = (const S*)L.pdf[L.parity];
-    if (L.n_cap_fluid) {
-      const unsigned gc = (unsigned)((L.n_cap_fluid + 255) / 256);
-      hipLaunchKernelGGL((k_capture<Lat, P>), dim3(gc), dim3(256), 0, s.stream, src, L.nbr,
-                         L.cap_elem, L.n_cap_fluid, (C*)L.cap, a);
-    }
+                       L.nbr, n_act, a, (C*)L.cap, s.status);
   }
 
   static void fill_gff(SimState& s, int k) {
@@ -125,8 +116,8 @@ struct Impl {
     const DevLevel& F = s.lv[k + 1];
     auto a = level_args<C, Lat::Q>(s, k);
     const C scale = (C)(2.0 * F.omega / L.omega);
-    const unsigned grid = (unsigned)((L.n_gff + 255) / 256);
-    hipLaunchKernelGGL((k_fill_gff<Lat, P>), dim3(grid), dim3(256), 0, s.stream,
+    const unsigned grid = (unsigned)((L.n_gff + 63) / 64);
+    hipLaunchKernelGGL((k_fill_gff<Lat, P>), dim3(grid), dim3(64), 0, s.stream,
                        (S*)L.pdf[L.parity], L.n_fluid + L.n_inner + L.n_outer, L.n_gff,
                        L.gff_slot, (const C*)F.cap, (C*)L.cap, L.n_cap_fluid, a, scale, s.status);
   }
@@ -218,8 +209,15 @@ struct Impl {
     }                                                                       \
   } while (0)
 
+void SimState::drop_graphs() {
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  graphs.clear();
+}
+
 SimState::~SimState() {
+  drop_graphs();
   for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }
 
 static hipEvent_t prof_event(SimState& s) {
@@ -246,7 +244,6 @@ void sc_level(SimState& s, int k) {
     (void)hipEventRecord(e1, s.stream);
     s.prof.rec.push_back({k, n_act, e0, e1});
   }
-  MLBM_DISPATCH(s, I::capture(s, k));
   L.parity ^= 1;
   if (k > 0) L.substep ^= 1;
 }
@@ -262,6 +259,41 @@ void advance(SimState& s, int k) {
     fill_gff(s, k);
     fill_gfc(s, k + 1);
   }
+}
+
+static uint64_t parity_key(const SimState& s) {
+  uint64_t key = 0;
+  for (size_t k = 0; k < s.lv.size() && k < 32; ++k)
+    key |= (uint64_t)(s.lv[k].parity & 1) << (2 * k) | (uint64_t)(s.lv[k].substep & 1) << (2 * k + 1);
+  return key;
+}
+
+// Records two coarse steps into a graph on the capture stream.  Every level
+// takes an even number of stream-collides in two coarse steps, so the
+// parity state after the graph equals the state it was captured from.
+static hipError_t two_step_graph(SimState& s, hipGraphExec_t* exec) {
+  hipError_t e = hipSuccess;
+  if (!s.capture_stream) e = hipStreamCreateWithFlags(&s.capture_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  const hipStream_t user = s.stream;
+  std::vector<std::pair<int, int>> saved;
+  for (auto& L : s.lv) saved.emplace_back(L.parity, L.substep);
+  s.stream = s.capture_stream;
+  e = hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    advance(s, 0);
+    advance(s, 0);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s.stream, &graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  s.stream = user;
+  for (size_t k = 0; k < s.lv.size(); ++k) {
+    s.lv[k].parity = saved[k].first;
+    s.lv[k].substep = saved[k].second;
+  }
+  return e;
 }
 
 int32_t check_launch(const char* what) {
@@ -397,6 +429,7 @@ int32_t mlbm_init(mlbm_sim* sim, int32_t k, const double* rho, const double* u, 
     int ex = m > 0 ? (int)std::floor(std::log2(4096.0 / m)) : 24;
     L.f16_exp = std::min(24, std::max(0, ex));
   }
+  s.drop_graphs();
   MLBM_DISPATCH(s, I::init(s, k, rho, u, S));
   L.parity = 0;
   L.substep = 0;
@@ -421,7 +454,29 @@ int32_t mlbm_step(mlbm_sim* sim, int64_t n_coarse) {
   if (n_coarse < 0) return fail(MLBM_E_ARG, "negative step count");
   SimState& s = sim->s;
   if (!s.filled) return fail(MLBM_E_STATE, "mlbm_fill_ghosts must follow mlbm_init");
-  for (int64_t t = 0; t < n_coarse; ++t) {
+  int64_t left = n_coarse;
+  if (s.use_graphs && !s.prof.on) {
+    while (left >= 2) {
+      const uint64_t key = parity_key(s);
+      hipGraphExec_t exec = nullptr;
+      for (auto& g : s.graphs)
+        if (g.first == key) exec = g.second;
+      if (!exec) {
+        const hipError_t e = two_step_graph(s, &exec);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          s.use_graphs = false;  // fall back to direct launches
+          break;
+        }
+        s.graphs.emplace_back(key, exec);
+      }
+      const hipError_t e = hipGraphLaunch(exec, s.stream);
+      if (e != hipSuccess) return fail(MLBM_E_HIP, "graph launch: %s", hipGetErrorString(e));
+      left -= 2;
+      s.time += 2;
+    }
+  }
+  for (; left > 0; --left) {
     advance(s, 0);
     s.time++;
   }
@@ -527,6 +582,7 @@ int32_t mlbm_load_checkpoint(mlbm_sim* sim, const void* dev_src, size_t bytes) {
     return fail(MLBM_E_ARG, "checkpoint does not belong to this simulation");
   const char* p = (const char*)dev_src;
   size_t off = 256;
+  s.drop_graphs();
   for (size_t k = 0; k < s.lv.size(); ++k) {
     DevLevel& L = s.lv[k];
     const size_t b = (size_t)s.q * L.n * storage_bytes(s.precision);
@@ -541,6 +597,13 @@ int32_t mlbm_load_checkpoint(mlbm_sim* sim, const void* dev_src, size_t bytes) {
   s.time = h.time;
   std::fill(s.inited.begin(), s.inited.end(), true);
   s.filled = true;
+  return MLBM_OK;
+}
+
+int32_t mlbm_use_graphs(mlbm_sim* sim, int32_t enable) {
+  if (!sim) return fail(MLBM_E_ARG, "sim is NULL");
+  sim->s.use_graphs = enable != 0;
+  if (!enable) sim->s.drop_graphs();
   return MLBM_OK;
 }
 
@@ -586,7 +649,7 @@ int32_t mlbm_launches_per_step(const mlbm_sim* sim, int64_t* launches) {
   for (size_t k = 0; k < s.lv.size(); ++k) {
     const auto& L = s.lv[k];
     const int64_t reps = (int64_t)1 << k;
-    total += reps * (1 + (L.n_cap_fluid ? 1 : 0));
+    total += reps;
     if (k + 1 < s.lv.size()) total += reps * ((L.n_gff ? 1 : 0) + (s.lv[k + 1].n_groups ? 1 : 0));
   }
   *launches = total;

@@ -61,6 +61,11 @@ struct SimState {
   bool filled = false;
   int64_t time = 0;
   Profiler prof;
+  // graphs of two coarse steps, keyed by the parity state they start from
+  hipStream_t capture_stream = nullptr;
+  bool use_graphs = true;
+  std::vector<std::pair<uint64_t, hipGraphExec_t>> graphs;
+  void drop_graphs();
   ~SimState();
 };
 

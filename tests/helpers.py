@@ -69,6 +69,18 @@ def direction_perm(stencil, olat):
     return [int(np.where((olat.c == c[i]).all(1))[0][0]) for i in range(len(c))]
 
 
+def gpu_to_oracle(plan, om, k):
+    """Index map: element g of the library's level k -> oracle index (the
+    two layouts hold the same treeIDs; only the fluid order may differ)."""
+    gt = plan.export(k, "treeid")
+    ot = om.lev(om.level0 + k).tid
+    order = np.argsort(ot)
+    pos = np.searchsorted(ot[order], gt)
+    g2o = order[np.minimum(pos, len(ot) - 1)]
+    assert np.array_equal(ot[g2o], gt), "element sets differ"
+    return g2o
+
+
 def compare_post(sim, osim, fluid_only=False):
     """Max relative difference of post-collision pdfs over all levels."""
     perm = direction_perm(sim.plan.stencil, osim.lat)
@@ -76,7 +88,8 @@ def compare_post(sim, osim, fluid_only=False):
     for k in range(sim.plan.n_levels):
         L = sim.plan.level0 + k
         g = sim.get_pdf(k).cpu().numpy()
-        o = osim.post_collision(L).detach().numpy()[perm]
+        g2o = gpu_to_oracle(sim.plan, osim.mesh, k)
+        o = osim.post_collision(L).detach().numpy()[perm][:, g2o]
         n = sim.plan.info[k]["n_fluid"] if fluid_only else g.shape[1]
         rel = np.abs(g[:, :n] - o[:, :n]) / np.abs(o[:, :n])
         assert np.isfinite(o[:, :n]).all()

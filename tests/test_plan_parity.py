@@ -44,33 +44,60 @@ def _dir_perm(stencil, olat):
     return perm
 
 
+def _g2o(gt, ot):
+    order = np.argsort(ot)
+    pos = np.searchsorted(ot[order], gt)
+    g2o = order[np.minimum(pos, len(ot) - 1)]
+    assert np.array_equal(ot[g2o], gt)
+    return g2o
+
+
 @pytest.mark.parametrize("name", sorted(MESHES))
 def test_plan_tables_bit_exact(name):
+    """Every table equals the oracle's after mapping element indices through
+    treeIDs.  Layout rule: [fluid | GFC inner | GFC outer | GFF] with the
+    fluid part split into [not an interpolation source | source], each part
+    ascending by treeID; the ghost parts coincide with the oracle's."""
     spec = MESHES[name]()
     om = omesh.build(spec)
     plan = M.Plan.from_spec(spec)
     assert plan.n_levels == len(om.levels) and plan.level0 == om.level0
     perm = _dir_perm(spec.stencil, om.lattice)
+    g2o = [_g2o(plan.export(k, "treeid"), ot.tid) for k, ot in enumerate(om.levels)]
     for k, ot in enumerate(om.levels):
         info = plan.info[k]
         assert (info["n"], info["n_fluid"], info["n_gfc_inner"], info["n_gfc_outer"],
                 info["n_gff"]) == (ot.n, ot.n_fluid, ot.n_inner, ot.n_outer, ot.n_gff)
-        assert np.array_equal(plan.export(k, "treeid"), ot.tid)
-        assert np.array_equal(plan.export(k, "coords"), ot.coords.T)
+        tid = plan.export(k, "treeid")
+        nf, cb = ot.n_fluid, ot.n_fluid - info["n_cap_fluid"]
+        # segment order and contents
+        for a, b in ((0, cb), (cb, nf)):
+            assert np.all(np.diff(tid[a:b].astype(np.int64)) > 0)
+        assert np.array_equal(tid[nf:], ot.tid[nf:])
+        src = om.source_sets(ot.level)
+        src = src[src < nf]
+        assert np.array_equal(np.sort(tid[cb:nf]), np.sort(ot.tid[src]))
+        assert np.array_equal(plan.export(k, "capture"), np.arange(cb, nf))
+        m = g2o[k]
+        assert np.array_equal(plan.export(k, "coords"), ot.coords[m].T)
         nbr = plan.export(k, "nbr")
         for i in range(1, plan.q):
-            o = ot.nbr[perm[i]]
-            want = np.where(o >= 0, o, 0)
+            o = ot.nbr[perm[i]][m]
+            got = nbr[i - 1]
+            mapped = np.where(got >= 0, m[np.maximum(got, 0)], got)
+            want = o.copy()
             for oc, gc in CODE_MAP.items():
                 want = np.where(o == oc, gc, want)
-            assert np.array_equal(nbr[i - 1], want), (k, i)
+            assert np.array_equal(mapped, want), (k, i)
         ng = ot.n_inner + ot.n_outer
-        assert np.array_equal(plan.export(k, "gfc_src").reshape(4, ng), ot.gfc_src.T)
-        assert np.array_equal(plan.export(k, "gff_src").reshape(4, ot.n_gff), ot.gff_src.T)
-        src = om.source_sets(ot.level)
-        assert np.array_equal(plan.export(k, "capture"), src[src < ot.n_fluid])
+        if ng:
+            gs = plan.export(k, "gfc_src").reshape(4, ng)
+            assert np.array_equal(g2o[k - 1][gs], ot.gfc_src.T)
+        if ot.n_gff:
+            gs = plan.export(k, "gff_src").reshape(4, ot.n_gff)
+            assert np.array_equal(g2o[k + 1][gs], ot.gff_src.T)
         b = plan.export(k, "bounce").reshape(2, -1)
-        got = set(zip(b[0].tolist(), b[1].tolist()))
+        got = set(zip(m[b[0]].tolist(), b[1].tolist()))
         ob = set()
         for i in range(1, plan.q):
             xs = np.where(ot.nbr[perm[i], :ot.n_fluid] == omesh.BOUNCE)[0]
