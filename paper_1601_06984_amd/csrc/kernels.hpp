@@ -137,27 +137,28 @@ __device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__
 template <class Lat, class C, class R>
 __device__ __forceinline__ void write_record_m(R* __restrict__ rec, const C* g, C drho, C rho,
                                                const C* u, C uu, C omega) {
-  C fneq[Lat::Q];
+  // streamed: each g^neq_i is written and folded into the second moments
+  // as it is formed, so no per-direction array stays live
+  C pi[Lat::NS];
 #pragma unroll
-  for (int i = 0; i < Lat::Q; ++i) fneq[i] = g[i] - geq_i<Lat, C>(i, drho, rho, u, uu);
+  for (int k = 0; k < Lat::NS; ++k) pi[k] = C(0);
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    const C fneq = g[i] - geq_i<Lat, C>(i, drho, rho, u, uu);
+    rec[cap_fneq(Lat::D) + i] = (R)fneq;
+#pragma unroll
+    for (int k = 0; k < Lat::NS; ++k) {
+      const int cc = Lat::c(i, strain_a(Lat::D, k)) * Lat::c(i, strain_b(Lat::D, k));
+      if (cc > 0) pi[k] += fneq;
+      if (cc < 0) pi[k] -= fneq;
+    }
+  }
   rec[0] = (R)drho;
 #pragma unroll
   for (int a = 0; a < Lat::D; ++a) rec[cap_u(Lat::D) + a] = (R)u[a];
   const C pref = -C(1.5) * omega / rho;
 #pragma unroll
-  for (int k = 0; k < Lat::NS; ++k) {
-    const int aa = strain_a(Lat::D, k), bb = strain_b(Lat::D, k);
-    C s = 0;
-#pragma unroll
-    for (int i = 0; i < Lat::Q; ++i) {
-      const int cc = Lat::c(i, aa) * Lat::c(i, bb);
-      if (cc > 0) s += fneq[i];
-      if (cc < 0) s -= fneq[i];
-    }
-    rec[cap_s(Lat::D) + k] = (R)(pref * s);
-  }
-#pragma unroll
-  for (int i = 0; i < Lat::Q; ++i) rec[cap_fneq(Lat::D) + i] = (R)fneq[i];
+  for (int k = 0; k < Lat::NS; ++k) rec[cap_s(Lat::D) + k] = (R)(pref * pi[k]);
 }
 
 template <class Lat, class C, class R>
@@ -177,6 +178,18 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
   return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
+// Two-range variant: logical blocks [0, nb1) (plain fluid) and [nb1, nb)
+// (capture sources and ghosts, which do more work per element) are each
+// split into 8 contiguous slices, one per XCD, so every XCD gets the same
+// share of both ranges; within an XCD the plain slice is dispatched first.
+__device__ __forceinline__ int64_t xcd_block2(int64_t b, int64_t nb, int64_t nb1) {
+  const int64_t x = b & 7, k = b >> 3;
+  const int64_t q = nb >> 3, r = nb & 7, q1 = nb1 >> 3, r1 = nb1 & 7;
+  const int64_t cnt1 = q1 + (x < r1 ? 1 : 0);
+  if (k < cnt1) return x * q1 + (x < r1 ? x : r1) + k;
+  return nb1 + x * (q - q1) + (x < r ? x : r) - (x < r1 ? x : r1) + (k - cnt1);
+}
+
 template <class Lat, int P, int BS>
 __global__ __launch_bounds__(BS) void k_stream_collide(
     const typename Prec<P>::S* __restrict__ src, typename Prec<P>::S* __restrict__ dst,
@@ -184,7 +197,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
     const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C* __restrict__ cap,
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t blk = xcd_block2(blockIdx.x, gridDim.x, a.cap_begin / BS);
   const int64_t x = blk * BS + threadIdx.x;
   if (x >= n_act) return;
   C g[Lat::Q];
