@@ -226,6 +226,52 @@ int32_t mlbm_profile(mlbm_sim* sim, int32_t enable);
 int32_t mlbm_profile_read(mlbm_sim* sim, int32_t k, double* ms, int64_t* launches,
                           int64_t* elements);
 
+/* ---- adjoint ----------------------------------------------------------
+ * Hand-written reverse of the multilevel step (adjoints of Eq. bgk, of the
+ * pull streaming and of both compact-interpolation fills, Steps 1-5), for
+ * gradients of an objective of the final state with respect to the
+ * initial fields, tau0 and the EQ-face velocity.  lambda arrays hold
+ * dJ/d(f*) per level in the simulation's compute precision; the FP16
+ * storage rounding is treated as the identity.  Usage: attach a workspace;
+ * run the forward to time T; seed; call mlbm_adjoint_step with the
+ * checkpoint of the start of each coarse step, last step first; finish
+ * with mlbm_adjoint_init; read the parameter gradients. */
+enum { MLBM_OBJ_KE = 0, MLBM_OBJ_DRAG_X = 1 };
+
+/* Device workspace bytes for the adjoint of `sim`, which was created from
+ * `plan` (the plan must still exist; its transposed tables are used). */
+int32_t mlbm_adjoint_workspace_bytes(const mlbm_sim* sim, const mlbm_plan* plan,
+                                     size_t* bytes);
+/* Attach a caller-owned, 256-byte aligned device workspace (the tape of one
+ * coarse step, lambda arrays and transposed tables).  Synchronises. */
+int32_t mlbm_adjoint_attach(mlbm_sim* sim, const mlbm_plan* plan, void* workspace,
+                            size_t bytes);
+/* lambda := dJ/df* of the simulation's current state for objective
+ * MLBM_OBJ_KE (kinetic energy, as MLBM_DIAG_KE) or MLBM_OBJ_DRAG_X (x force,
+ * as MLBM_DIAG_FORCE); clears the parameter accumulators. */
+int32_t mlbm_adjoint_seed(mlbm_sim* sim, int32_t objective);
+/* Reverse one coarse step.  `dev_ckpt` (device, `bytes` >= checkpoint size)
+ * is the mlbm_save_checkpoint image of the state at the START of the coarse
+ * step whose end-state adjoint lambda holds; afterwards lambda refers to
+ * that start state.  The simulation's own arrays are not modified. */
+int32_t mlbm_adjoint_step(mlbm_sim* sim, const void* dev_ckpt, size_t bytes);
+/* Reverse the initialisation and the initial synchronous fill.  rho, u, S
+ * are host arrays of n_levels device pointers to the inputs given to
+ * mlbm_init (S may be NULL or hold NULL entries); dJ_du (required) and
+ * dJ_drho, dJ_dS (optional, NULL) are host arrays of n_levels device
+ * pointers receiving FP64 gradients laid out like the inputs. */
+int32_t mlbm_adjoint_init(mlbm_sim* sim, const double* const* rho,
+                          const double* const* u, const double* const* S,
+                          double* const* dJ_du, double* const* dJ_drho,
+                          double* const* dJ_dS);
+/* Accumulated parameter gradients (synchronises): dJ/dtau0 through all
+ * levels' omega_L (Eq. fneq_scale), dJ/domega_L per level (n_levels
+ * doubles, may be NULL) and dJ/du_in (3 doubles, may be NULL). */
+int32_t mlbm_adjoint_params(mlbm_sim* sim, double* dJ_dtau0, double* dJ_domega,
+                            double* dJ_duin);
+/* Copy lambda of level index k to device FP64 [q][n]. */
+int32_t mlbm_adjoint_get_lambda(mlbm_sim* sim, int32_t k, double* dev_dst);
+
 #ifdef __cplusplus
 }
 #endif

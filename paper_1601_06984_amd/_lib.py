@@ -60,7 +60,16 @@ SIGNATURES = {
     "mlbm_profile": (_i32, [_p, _i32]),
     "mlbm_use_graphs": (_i32, [_p, _i32]),
     "mlbm_profile_read": (_i32, [_p, _i32, _pd, _pi64, _pi64]),
+    "mlbm_adjoint_workspace_bytes": (_i32, [_p, _p, _psz]),
+    "mlbm_adjoint_attach": (_i32, [_p, _p, _p, _sz]),
+    "mlbm_adjoint_seed": (_i32, [_p, _i32]),
+    "mlbm_adjoint_step": (_i32, [_p, _p, _sz]),
+    "mlbm_adjoint_init": (_i32, [_p, C.POINTER(_p), C.POINTER(_p), C.POINTER(_p),
+                                 C.POINTER(_p), C.POINTER(_p), C.POINTER(_p)]),
+    "mlbm_adjoint_params": (_i32, [_p, _pd, _pd, _pd]),
+    "mlbm_adjoint_get_lambda": (_i32, [_p, _i32, _p]),
 }
+OBJ_KE, OBJ_DRAG_X = 0, 1
 
 _LIB = None
 

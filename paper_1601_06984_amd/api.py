@@ -150,7 +150,9 @@ class Sim:
                 (S is not None and S.numel() != ns * nf):
             raise ValueError(f"level {k}: expected rho[{nf}], u[{self.plan.d}][{nf}], "
                              f"S[{ns}][{nf}]")
-        self._init_keep = (rho, u, S)
+        if not hasattr(self, "inputs"):
+            self.inputs = {}
+        self.inputs[k] = (rho, u, S)
         check(lib().mlbm_init(self._h, k, self._ptr(rho, f64), self._ptr(u, f64),
                               self._ptr(S, f64)))
 
@@ -222,6 +224,66 @@ class Sim:
         ms, n, el = C.c_double(), C.c_int64(), C.c_int64()
         check(lib().mlbm_profile_read(self._h, k, C.byref(ms), C.byref(n), C.byref(el)))
         return ms.value, n.value, el.value
+
+    # ---- adjoint --------------------------------------------------------
+    def adjoint_attach(self):
+        need = C.c_size_t()
+        check(lib().mlbm_adjoint_workspace_bytes(self._h, self.plan.handle, C.byref(need)))
+        ws = self.torch.empty(need.value + 256, dtype=self.torch.uint8, device=self.device)
+        shift = (-ws.data_ptr()) % 256
+        self.adj_workspace = ws
+        check(lib().mlbm_adjoint_attach(self._h, self.plan.handle,
+                                        C.c_void_p(ws.data_ptr() + shift), need.value))
+
+    def adjoint_seed(self, objective: str = "ke"):
+        check(lib().mlbm_adjoint_seed(self._h, {"ke": _lib.OBJ_KE,
+                                                "drag_x": _lib.OBJ_DRAG_X}[objective]))
+
+    def adjoint_step(self, ckpt):
+        check(lib().mlbm_adjoint_step(self._h, self._ptr(ckpt), ckpt.numel()))
+
+    def adjoint_init(self, rho, u, S=None, want_rho=False, want_S=False):
+        """rho, u, S: per-level lists of the tensors given to init.  Returns
+        per-level dJ/du (d, n_fluid) [and dJ/drho, dJ/dS]."""
+        torch = self.torch
+        n = self.plan.n_levels
+        arr = C.c_void_p * n
+        def ptrs(ts):
+            return arr(*[C.c_void_p(t.data_ptr()) if t is not None else None for t in ts])
+        du = [torch.empty((self.plan.d, self.plan.info[k]["n_fluid"]), dtype=torch.float64,
+                          device=self.device) for k in range(n)]
+        dr = [torch.empty(self.plan.info[k]["n_fluid"], dtype=torch.float64, device=self.device)
+              for k in range(n)] if want_rho else None
+        ns = 6 if self.plan.d == 3 else 3
+        dS = [torch.empty((ns, self.plan.info[k]["n_fluid"]), dtype=torch.float64,
+                          device=self.device) for k in range(n)] if want_S else None
+        for k in range(n):
+            nf = self.plan.info[k]["n_fluid"]
+            assert rho[k].numel() == nf and u[k].numel() == self.plan.d * nf
+            assert S is None or S[k] is None or S[k].numel() == ns * nf
+        check(lib().mlbm_adjoint_init(self._h, ptrs(rho), ptrs(u),
+                                      ptrs(S) if S is not None else None, ptrs(du),
+                                      ptrs(dr) if dr else None, ptrs(dS) if dS else None))
+        out = [du]
+        if want_rho:
+            out.append(dr)
+        if want_S:
+            out.append(dS)
+        return out[0] if len(out) == 1 else tuple(out)
+
+    def adjoint_params(self):
+        """(dJ/dtau0, [dJ/domega_L], dJ/du_in (3,))."""
+        t = C.c_double()
+        w = (C.c_double * self.plan.n_levels)()
+        u = (C.c_double * 3)()
+        check(lib().mlbm_adjoint_params(self._h, C.byref(t), w, u))
+        return t.value, list(w), np.array(list(u))
+
+    def adjoint_lambda(self, k: int):
+        out = self.torch.empty((self.plan.q, self.plan.info[k]["n"]), dtype=self.torch.float64,
+                               device=self.device)
+        check(lib().mlbm_adjoint_get_lambda(self._h, k, self._ptr(out)))
+        return out
 
     def launches_per_step(self) -> int:
         n = C.c_int64()

@@ -1,0 +1,709 @@
+// Hand-written adjoint kernels of one multilevel time step: the transposed
+// BGK collision and capture record, the pull streaming as a scatter (each
+// (element, direction) entry is read by at most one pull, so the scatter is
+// race-free), and the transposes of both compact-interpolation fills.
+//
+// Conventions: lambda arrays hold dJ/dg for the g-form pdfs, in the compute
+// precision of the simulation; the storage codec is treated as identity.
+// Every kernel that touches a relaxation rate adds its FP64 partials per
+// block to `part` (DPART doubles per block): d/d omega of the kernel's own
+// level, d/d omega of the other level it couples to, and d/d u_in.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace mlbm {
+
+constexpr int DPART = 5;
+
+__device__ __forceinline__ void block_sums(double* sm, const double* v, int nv, double* out) {
+  for (int k = 0; k < nv; ++k) {
+    sm[threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sm[0];
+    __syncthreads();
+  }
+}
+
+// d g_eq / d(drho, rho, u) transposed: adds the contributions of lgeq.
+template <class Lat, class C>
+__device__ __forceinline__ void geq_adjoint(const C* lgeq, C rho, const C* u, C uu, C& ldrho,
+                                            C& lrho, C* lu) {
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    C cu = 0;
+#pragma unroll
+    for (int a = 0; a < Lat::D; ++a) cu += C(Lat::c(i, a)) * u[a];
+    const C w = (C)Lat::w(i);
+    const C P = C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu;
+    const C wl = w * lgeq[i];
+    ldrho += wl;
+    lrho += wl * P;
+#pragma unroll
+    for (int a = 0; a < Lat::D; ++a)
+      lu[a] += wl * rho * (C(3) * C(Lat::c(i, a)) + C(9) * cu * C(Lat::c(i, a)) - C(3) * u[a]);
+  }
+}
+
+// mu = (d g*/d g)^T lam_star + (d rec/d g)^T lam_rec for one element with
+// pre-collision g; rec is the capture record (drho, u, S, g^neq).
+template <class Lat, class C>
+__device__ __forceinline__ void collide_adjoint(const C* g, const C* ls, const C* lrec, C rho0,
+                                                C omega, C* mu, double& d_omega) {
+  constexpr int D = Lat::D, Q = Lat::Q;
+  C drho, rho, u[3];
+  macro_g<Lat, C>(g, rho0, drho, rho, u);
+  const C uu = dot_uu<Lat, C>(u);
+  C geq[Q], lg[Q], lgeq[Q];
+  double dw = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    geq[i] = geq_i<Lat, C>(i, drho, rho, u, uu);
+    lg[i] = (C(1) - omega) * ls[i];
+    lgeq[i] = omega * ls[i];
+    dw += (double)ls[i] * (double)(geq[i] - g[i]);
+  }
+  C ldrho = 0, lrho = 0, lu[3] = {0, 0, 0};
+  if (lrec) {
+    const C pref = -C(1.5) * omega / rho;
+    C S[Lat::NS];
+#pragma unroll
+    for (int k = 0; k < Lat::NS; ++k) {
+      C pi = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) pi += C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * (g[i] - geq[i]);
+      S[k] = pref * pi;
+      const C lS = lrec[cap_s(D) + k];
+      lrho -= lS * S[k] / rho;
+      dw += (double)lS * (double)S[k] / (double)omega;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      C lf = lrec[cap_fneq(D) + i];
+#pragma unroll
+      for (int k = 0; k < Lat::NS; ++k)
+        lf += pref * C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * lrec[cap_s(D) + k];
+      lg[i] += lf;
+      lgeq[i] -= lf;
+    }
+    ldrho += lrec[0];
+#pragma unroll
+    for (int a = 0; a < D; ++a) lu[a] += lrec[cap_u(D) + a];
+  }
+  geq_adjoint<Lat, C>(lgeq, rho, u, uu, ldrho, lrho, lu);
+  C lj[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lj[a] = lu[a] / rho;
+    lrho -= lu[a] * u[a] / rho;
+  }
+  ldrho += lrho;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    C v = lg[i] + ldrho;
+#pragma unroll
+    for (int a = 0; a < D; ++a) v += C(Lat::c(i, a)) * lj[a];
+    mu[i] = v;
+  }
+  d_omega += dw;
+}
+
+// ---------------------------------------------------------------- seeds ----
+// Kinetic energy E = 1/2 V sum rho |u|^2 of the post-collision state:
+// dE/dg*_i = V (c_i . u - u.u/2) on fluid elements, zero elsewhere.
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_seed_ke(const typename Prec<P>::S* __restrict__ pdf,
+                                                 const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+                                                 double vol, typename Prec<P>::C* __restrict__ lam) {
+  using C = typename Prec<P>::C;
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= a.n) return;
+  if (x >= a.n_fluid) {
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i) lam[(int64_t)i * a.n + x] = C(0);
+    return;
+  }
+  C g[Lat::Q];
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) g[i] = load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[i], a.inv_scale);
+  C drho, rho, u[3];
+  macro_g<Lat, C>(g, a.rho0, drho, rho, u);
+  const C uu = dot_uu<Lat, C>(u);
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    C cu = 0;
+#pragma unroll
+    for (int b = 0; b < Lat::D; ++b) cu += C(Lat::c(i, b)) * u[b];
+    lam[(int64_t)i * a.n + x] = (C)vol * (cu - C(0.5) * uu);
+  }
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void k_fill_value(C* __restrict__ p, int64_t n, C v) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+// Drag along x: d/dg*_i of sum over links 2 c_i f*_i scaled to finest units.
+template <class Lat, class C>
+__global__ __launch_bounds__(256) void k_seed_drag(const int32_t* __restrict__ bounce,
+                                                   int64_t n_bounce, int64_t n, double scale,
+                                                   C* __restrict__ lam) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_bounce) return;
+  const int64_t x = bounce[t];
+  const int i = Lat::opp(bounce[n_bounce + t]);
+  lam[(int64_t)i * n + x] = (C)(2.0 * Lat::c(i, 0) * scale);
+}
+
+// ------------------------------------------------- stream-collide reverse --
+// Gathers the tape state, forms mu, and scatters mu_i to the entry the pull
+// read.  COPY links are added by k_adj_copy afterwards.
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_adj_sc(
+    const typename Prec<P>::S* __restrict__ X, const int32_t* __restrict__ nbr, int64_t n_act,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a, const typename Prec<P>::C* __restrict__ lam_new,
+    typename Prec<P>::C* __restrict__ lam_cap, typename Prec<P>::C* __restrict__ lam_old,
+    double* __restrict__ part) {
+  using C = typename Prec<P>::C;
+  constexpr int Q = Lat::Q, D = Lat::D;
+  __shared__ double sm[256];
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double acc[DPART] = {0, 0, 0, 0, 0};
+  if (x < n_act) {
+    C g[Q], ls[Q], mu[Q];
+    gather_g<Lat, P>(X, nbr, x, a, g);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) ls[i] = lam_new[(int64_t)i * a.n + x];
+    const bool src = x >= a.cap_begin && x < a.n_fluid;
+    C lrec[cap_fneq(D) + Q];
+    if (src) {
+      C* r = lam_cap + (x - a.cap_begin) * cap_stride(D);
+#pragma unroll
+      for (int c = 0; c < cap_fneq(D) + Q; ++c) {
+        lrec[c] = r[c];
+        r[c] = C(0);  // consumed
+      }
+    }
+    collide_adjoint<Lat, C>(g, ls, src ? lrec : nullptr, a.rho0, a.omega, mu, acc[0]);
+    lam_old[x] = mu[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int32_t v = nbr[(int64_t)(i - 1) * a.ld_nbr + x];
+      if (v >= 0) {
+        lam_old[(int64_t)i * a.n + v] = mu[i];
+      } else if (v == MLBM_NBR_BOUNCE) {
+        lam_old[(int64_t)Lat::opp(i) * a.n + x] = mu[i];
+      } else if (v == MLBM_NBR_EQ) {
+        // f_i = f^eq_i(rho0, u_in): d/du_in = w rho0 (3 c + 9 (c.u_in) c - 3 u_in)
+        const double w = Lat::w(i);
+        double cu = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) cu += Lat::c(i, b) * a.u_in[b];
+#pragma unroll
+        for (int b = 0; b < D; ++b)
+          acc[2 + b] += (double)mu[i] * w * (double)a.rho0 *
+                        (3.0 * Lat::c(i, b) + 9.0 * cu * Lat::c(i, b) - 3.0 * a.u_in[b]);
+      }
+    }
+  }
+  block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
+}
+
+// COPY links, part 1 (before k_adj_sc consumes the record adjoints):
+// tmp[t][i] = mu_i(x) for the copied directions of element x = elems[t].
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_adj_copy_pre(
+    const typename Prec<P>::S* __restrict__ X, const int32_t* __restrict__ nbr,
+    const int32_t* __restrict__ elems, int64_t n_el, int64_t n_act,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a, const typename Prec<P>::C* __restrict__ lam_new,
+    const typename Prec<P>::C* __restrict__ lam_cap, typename Prec<P>::C* __restrict__ tmp) {
+  using C = typename Prec<P>::C;
+  constexpr int Q = Lat::Q, D = Lat::D;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_el) return;
+  const int64_t x = elems[t];
+  if (x >= n_act) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) tmp[t * Q + i] = C(0);
+    return;
+  }
+  C g[Q], ls[Q], mu[Q];
+  gather_g<Lat, P>(X, nbr, x, a, g);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ls[i] = lam_new[(int64_t)i * a.n + x];
+  const bool src = x >= a.cap_begin && x < a.n_fluid;
+  double dummy = 0;
+  collide_adjoint<Lat, C>(g, ls, src ? lam_cap + (x - a.cap_begin) * cap_stride(D) : nullptr,
+                          a.rho0, a.omega, mu, dummy);
+  tmp[t * Q] = C(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i)
+    tmp[t * Q + i] = nbr[(int64_t)(i - 1) * a.ld_nbr + x] == MLBM_NBR_COPY ? mu[i] : C(0);
+}
+
+// COPY links, part 2 (after k_adj_sc): lam_old[i][x] += tmp[t][i].
+template <int Q, class C>
+__global__ __launch_bounds__(256) void k_adj_copy_add(const int32_t* __restrict__ elems,
+                                                      int64_t n_el, int64_t n,
+                                                      const C* __restrict__ tmp,
+                                                      C* __restrict__ lam_old) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_el) return;
+  const int64_t x = elems[t];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const C v = tmp[t * Q + i];
+    if (v != C(0)) lam_old[(int64_t)i * n + x] += v;
+  }
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void k_zero_entries(C* __restrict__ lam, int64_t n,
+                                                      const int32_t* __restrict__ list, int64_t cnt) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < cnt) lam[(int64_t)list[cnt + t] * n + list[t]] = C(0);
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void k_zero_ghost_rows(C* __restrict__ lam, int64_t n,
+                                                         int64_t begin, int q) {
+  const int64_t w = n - begin;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= w * q) return;
+  lam[(t / w) * n + begin + t % w] = C(0);
+}
+
+// --------------------------------------------- interpolation transposes ----
+// Adjoint of the strain-rate part of the closed-form velocity: given the
+// velocity adjoint lu, adds d/dS of the four sources to lS[4][NS].
+// wd, wc: weights of the diagonal and (3D) cross coefficients in
+// u -= wd (a_xx + a_yy + a_zz) + wc (s_x s_y a_xy + s_y s_z a_yz + s_x s_z a_xz).
+template <int D, class C>
+__device__ __forceinline__ void strain_terms_adjoint(const C* lu, int sx, int sy, int sz, C wd,
+                                                     C wc, C (*lS)[6]) {
+  if constexpr (D == 3) {
+    const C sxy = C(sx * sy), syz = C(sy * sz), sxz = C(sx * sz);
+    C laxx = -wd * lu[0], layy = -wd * lu[0], lazz = -wd * lu[0];
+    C laxy = -wc * sxy * lu[0], layz = -wc * syz * lu[0], laxz = -wc * sxz * lu[0];
+    C lbxx = -wd * lu[1], lbyy = -wd * lu[1], lbzz = -wd * lu[1];
+    C lbxy = -wc * sxy * lu[1], lbyz = -wc * syz * lu[1], lbxz = -wc * sxz * lu[1];
+    C lcxx = -wd * lu[2], lcyy = -wd * lu[2], lczz = -wd * lu[2];
+    C lcxy = -wc * sxy * lu[2], lcyz = -wc * syz * lu[2], lcxz = -wc * sxz * lu[2];
+    C lDx[6] = {0, 0, 0, 0, 0, 0}, lDy[6] = {0, 0, 0, 0, 0, 0}, lDz[6] = {0, 0, 0, 0, 0, 0};
+    // a_yz = T - 2 Dx(yz), b_xz = T - 2 Dy(xz), c_xy = T - 2 Dz(xy),
+    // T = Dz(xy) + Dx(yz) + Dy(xz)
+    const C lT = layz + lbxz + lcxy;
+    lDx[4] += lT - C(2) * layz;
+    lDy[5] += lT - C(2) * lbxz;
+    lDz[3] += lT - C(2) * lcxy;
+    lDz[5] += lazz; lcxz -= C(0.5) * lazz;   // a_zz = Dz(xz) - c_xz/2
+    lDx[5] += lcxx; laxz -= C(0.5) * lcxx;   // c_xx = Dx(xz) - a_xz/2
+    lDz[4] += lbzz; lcyz -= C(0.5) * lbzz;   // b_zz = Dz(yz) - c_yz/2
+    lDy[4] += lcyy; lbyz -= C(0.5) * lcyy;   // c_yy = Dy(yz) - b_yz/2
+    lDy[3] += layy; lbxy -= C(0.5) * layy;   // a_yy = Dy(xy) - b_xy/2
+    lDx[3] += lbxx; laxy -= C(0.5) * lbxx;   // b_xx = Dx(xy) - a_xy/2
+    lDx[0] += C(0.5) * laxx; lDy[0] += laxy; lDz[0] += laxz;
+    lDx[1] += lbxy; lDy[1] += C(0.5) * lbyy; lDz[1] += lbyz;
+    lDx[2] += lcxz; lDy[2] += lcyz; lDz[2] += C(0.5) * lczz;
+    const C hx = C(0.5) * sx, hy = C(0.5) * sy, hz = C(0.5) * sz;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const C ex = hx * lDx[c], ey = hy * lDy[c], ez = hz * lDz[c];
+      lS[0][c] += -ex - ey - ez;   // H
+      lS[1][c] += ex + ey - ez;    // K
+      lS[2][c] += ex - ey + ez;    // M
+      lS[3][c] += -ex + ey + ez;   // N
+    }
+  } else {
+    (void)sz;
+    (void)wc;
+    const C laxx = -wd * lu[0], layy = -wd * lu[0];
+    const C lbxx = -wd * lu[1], lbyy = -wd * lu[1];
+    C lDx[3] = {0, 0, 0}, lDy[3] = {0, 0, 0};
+    lDx[2] += lbxx;                     // b_xx = Dx(xy) - a_xy/2
+    const C laxy = -C(0.5) * lbxx;
+    lDy[2] += layy;                     // a_yy = Dy(xy) - b_xy/2
+    const C lbxy = -C(0.5) * layy;
+    lDx[0] += C(0.5) * laxx;
+    lDy[0] += laxy;
+    lDx[1] += lbxy;
+    lDy[1] += C(0.5) * lbyy;
+    const C hx = C(0.5) * sx, hy = C(0.5) * sy;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const C ex = hx * lDx[c], ey = hy * lDy[c];
+      lS[0][c] += -ex - ey;   // P
+      lS[1][c] += ex - ey;    // P + s_x
+      lS[2][c] += -ex + ey;   // P + s_y
+      lS[3][c] += ex + ey;    // P + s_x + s_y
+    }
+  }
+}
+
+// Forward closed form of the strain part (same as the fill kernels), used to
+// recompute the interpolated velocity in the reverse kernels.
+template <int D, class C>
+__device__ __forceinline__ void strain_terms(const C* const* S, int sx, int sy, int sz, C wd, C wc,
+                                             C* u) {
+  if constexpr (D == 3) {
+    const C hx = C(0.5) * sx, hy = C(0.5) * sy, hz = C(0.5) * sz;
+    auto Dx = [&](int k) { return hx * (-S[0][k] + S[1][k] + S[2][k] - S[3][k]); };
+    auto Dy = [&](int k) { return hy * (-S[0][k] + S[1][k] - S[2][k] + S[3][k]); };
+    auto Dz = [&](int k) { return hz * (-S[0][k] - S[1][k] + S[2][k] + S[3][k]); };
+    const C axx = C(0.5) * Dx(0), axy = Dy(0), axz = Dz(0);
+    const C bxy = Dx(1), byy = C(0.5) * Dy(1), byz = Dz(1);
+    const C cxz = Dx(2), cyz = Dy(2), czz = C(0.5) * Dz(2);
+    const C bxx = Dx(3) - C(0.5) * axy, ayy = Dy(3) - C(0.5) * bxy;
+    const C cyy = Dy(4) - C(0.5) * byz, bzz = Dz(4) - C(0.5) * cyz;
+    const C cxx = Dx(5) - C(0.5) * axz, azz = Dz(5) - C(0.5) * cxz;
+    const C T = Dz(3) + Dx(4) + Dy(5);
+    const C ayz = T - C(2) * Dx(4), bxz = T - C(2) * Dy(5), cxy = T - C(2) * Dz(3);
+    const C sxy = C(sx * sy), syz = C(sy * sz), sxz = C(sx * sz);
+    u[0] -= wd * (axx + ayy + azz) + wc * (sxy * axy + syz * ayz + sxz * axz);
+    u[1] -= wd * (bxx + byy + bzz) + wc * (sxy * bxy + syz * byz + sxz * bxz);
+    u[2] -= wd * (cxx + cyy + czz) + wc * (sxy * cxy + syz * cyz + sxz * cxz);
+  } else {
+    (void)sz;
+    (void)wc;
+    const C hx = C(0.5) * sx, hy = C(0.5) * sy;
+    auto Dx = [&](int k) { return hx * (-S[0][k] + S[1][k] - S[2][k] + S[3][k]); };
+    auto Dy = [&](int k) { return hy * (-S[0][k] - S[1][k] + S[2][k] + S[3][k]); };
+    const C axx = C(0.5) * Dx(0), axy = Dy(0);
+    const C bxy = Dx(1), byy = C(0.5) * Dy(1);
+    const C bxx = Dx(2) - C(0.5) * axy, ayy = Dy(2) - C(0.5) * bxy;
+    u[0] -= wd * (axx + ayy);
+    u[1] -= wd * (bxx + byy);
+  }
+}
+
+// Reverse of one interpolated ghost.  Inputs: the four source records, the
+// linear weights beta, the f^neq rescale r, the target's omega (omega_t) and
+// the adjoints of the ghost's post-collision g* (lgs) and, for
+// GhostFromFiner, of its own record (lrec, may be null).  Outputs: adjoints
+// of the four source records (lsrc[4][stride]) and the omega partials
+// (d_t for the target level, d_s for the source level).
+template <class Lat, class C>
+__device__ __forceinline__ void ghost_adjoint(const C* const* rec, const C* beta, C r, C omega_t,
+                                              C omega_s, C rho0, int sx, int sy, int sz, C wd,
+                                              C wc, const C* lgs, const C* lrec, C (*lsrc)[32],
+                                              double& d_t, double& d_s) {
+  constexpr int D = Lat::D, Q = Lat::Q, NS = Lat::NS;
+  // forward recompute
+  C drho = 0, u[3] = {0, 0, 0}, fneq[Q];
+  const C* S[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    drho += beta[k] * rec[k][0];
+#pragma unroll
+    for (int b = 0; b < D; ++b) u[b] += beta[k] * rec[k][cap_u(D) + b];
+    S[k] = rec[k] + cap_s(D);
+  }
+  strain_terms<D, C>(S, sx, sy, sz, wd, wc, u);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    C m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m += beta[k] * rec[k][cap_fneq(D) + i];
+    fneq[i] = r * m;
+  }
+  const C rho = rho0 + drho;
+  const C uu = dot_uu<Lat, C>(u);
+  // adjoint of g* = g_eq + (1 - omega_t) fneq and of the record
+  C lfneq[Q], lgeq[Q];
+  C ldrho = 0, lrho = 0, lu[3] = {0, 0, 0};
+  double dt = 0, ds = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    lgeq[i] = lgs[i];
+    lfneq[i] = (C(1) - omega_t) * lgs[i];
+    dt -= (double)lgs[i] * (double)fneq[i];
+  }
+  if (lrec) {
+    const C pref = -C(1.5) * omega_t / rho;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      C pi = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) pi += C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * fneq[i];
+      const C Sk = pref * pi;
+      const C lS = lrec[cap_s(D) + k];
+      lrho -= lS * Sk / rho;
+      dt += (double)lS * (double)Sk / (double)omega_t;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      C lf = lrec[cap_fneq(D) + i];
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        lf += pref * C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * lrec[cap_s(D) + k];
+      lfneq[i] += lf;
+    }
+    ldrho += lrec[0];
+#pragma unroll
+    for (int b = 0; b < D; ++b) lu[b] += lrec[cap_u(D) + b];
+  }
+  // rescale r = omega_s dt_t / (omega_t dt_s): d r/d omega_s = r/omega_s,
+  // d r/d omega_t = -r/omega_t
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double p = (double)lfneq[i] * (double)fneq[i];
+    ds += p / (double)omega_s;
+    dt -= p / (double)omega_t;
+  }
+  geq_adjoint<Lat, C>(lgeq, rho, u, uu, ldrho, lrho, lu);
+  ldrho += lrho;
+  // to the sources
+  C lS[4][6];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) lS[k][c] = 0;
+  strain_terms_adjoint<D, C>(lu, sx, sy, sz, wd, wc, lS);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    lsrc[k][0] = beta[k] * ldrho;
+#pragma unroll
+    for (int b = 0; b < D; ++b) lsrc[k][cap_u(D) + b] = beta[k] * lu[b];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) lsrc[k][cap_s(D) + c] = lS[k][c];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lsrc[k][cap_fneq(D) + i] = beta[k] * r * lfneq[i];
+  }
+  d_t += dt;
+  d_s += ds;
+}
+
+// GhostFromFiner reverse, one thread per ghost of the coarse level.
+template <class Lat, int P>
+__global__ __launch_bounds__(64) void k_adj_gff(
+    int64_t gff_begin, int64_t n_gff, const int32_t* __restrict__ slots,
+    const typename Prec<P>::C* __restrict__ cap_fine, const typename Prec<P>::C* __restrict__ lam,
+    int64_t n, typename Prec<P>::C* __restrict__ lam_cap_coarse, int64_t cap_gff_begin,
+    typename Prec<P>::C* __restrict__ lam_cap_fine, typename Prec<P>::C omega_c,
+    typename Prec<P>::C omega_f, typename Prec<P>::C rho0, double* __restrict__ part) {
+  using C = typename Prec<P>::C;
+  constexpr int D = Lat::D, Q = Lat::Q;
+  __shared__ double sm[64];
+  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  double acc[DPART] = {0, 0, 0, 0, 0};
+  if (j < n_gff) {
+    const C* rec[4];
+    int32_t sl[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sl[k] = slots[k * n_gff + j];
+      rec[k] = cap_fine + (int64_t)sl[k] * cap_stride(D);
+    }
+    C lgs[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lgs[i] = lam[(int64_t)i * n + gff_begin + j];
+    C* lr = lam_cap_coarse + (cap_gff_begin + j) * cap_stride(D);
+    C lrec[cap_fneq(D) + Q];
+#pragma unroll
+    for (int c = 0; c < cap_fneq(D) + Q; ++c) {
+      lrec[c] = lr[c];
+      lr[c] = C(0);
+    }
+    const C beta[4] = {C(0.25), C(0.25), C(0.25), C(0.25)};
+    C lsrc[4][32];
+    ghost_adjoint<Lat, C>(rec, beta, C(2) * omega_f / omega_c, omega_c, omega_f, rho0, 1, 1, 1,
+                          C(0.25), C(0), lgs, lrec, lsrc, acc[0], acc[1]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      C* dst = lam_cap_fine + (int64_t)sl[k] * cap_stride(D);
+#pragma unroll
+      for (int c = 0; c < cap_fneq(D) + Q; ++c) dst[c] += lsrc[k][c];
+    }
+  }
+  block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
+}
+
+// GhostFromCoarser reverse, phase 1: one thread per ghost of the fine level
+// writes the adjoints of its four source records to T[ghost][4][stride].
+template <class Lat, int P>
+__global__ __launch_bounds__(64) void k_adj_gfc(
+    int64_t n_fluid, int64_t n_gfc, const int32_t* __restrict__ slots,
+    const int8_t* __restrict__ oct, const typename Prec<P>::C* __restrict__ cap_coarse,
+    const typename Prec<P>::C* __restrict__ lam, int64_t n, typename Prec<P>::C* __restrict__ T,
+    typename Prec<P>::C omega_f, typename Prec<P>::C omega_c, typename Prec<P>::C rho0,
+    double* __restrict__ part) {
+  using C = typename Prec<P>::C;
+  constexpr int D = Lat::D, Q = Lat::Q;
+  __shared__ double sm[64];
+  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  double acc[DPART] = {0, 0, 0, 0, 0};
+  if (j < n_gfc) {
+    const C* rec[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rec[k] = cap_coarse + (int64_t)slots[k * n_gfc + j] * cap_stride(D);
+    const int o = oct[j];
+    const int sx = (o & 1) ? 1 : -1, sy = (o & 2) ? 1 : -1, sz = (o & 4) ? 1 : -1;
+    C lgs[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lgs[i] = lam[(int64_t)i * n + n_fluid + j];
+    C beta[4];
+    C wd, wc;
+    if constexpr (D == 3) {
+      beta[0] = C(0.625); beta[1] = beta[2] = beta[3] = C(0.125);
+      wd = C(3.0 / 16.0); wc = C(1.0 / 16.0);
+    } else {
+      beta[0] = C(9.0 / 16.0); beta[1] = beta[2] = C(3.0 / 16.0); beta[3] = C(1.0 / 16.0);
+      wd = C(3.0 / 16.0); wc = C(0);
+    }
+    C lsrc[4][32];
+    ghost_adjoint<Lat, C>(rec, beta, omega_c / (C(2) * omega_f), omega_f, omega_c, rho0, sx, sy,
+                          sz, wd, wc, lgs, nullptr, lsrc, acc[0], acc[1]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      C* dst = T + (j * 4 + k) * cap_stride(D);
+#pragma unroll
+      for (int c = 0; c < cap_fneq(D) + Q; ++c) dst[c] = lsrc[k][c];
+    }
+  }
+  block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
+}
+
+// Phase 2: each coarse record sums its contributions in a fixed order.
+template <class Lat, class C>
+__global__ __launch_bounds__(256) void k_adj_gfc_gather(const int32_t* __restrict__ ptr,
+                                                        const int32_t* __restrict__ ent,
+                                                        int64_t n_slots, const C* __restrict__ T,
+                                                        C* __restrict__ lam_cap) {
+  constexpr int D = Lat::D;
+  constexpr int W = cap_fneq(D) + Lat::Q;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t s = t / W, c = t % W;
+  if (s >= n_slots) return;
+  C v = 0;
+  for (int32_t e = ptr[s]; e < ptr[s + 1]; ++e) v += T[(int64_t)ent[e] * cap_stride(D) + c];
+  if (ptr[s + 1] > ptr[s]) lam_cap[s * cap_stride(D) + c] += v;
+}
+
+// Init reverse: f = f^eq(rho, u) + f^neq(S) per fluid element, collided into
+// the stored state and recorded when the element is a source.
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_adj_init(
+    const double* __restrict__ rho_in, const double* __restrict__ u_in,
+    const double* __restrict__ S_in, int64_t nf, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+    double omega_d, const typename Prec<P>::C* __restrict__ lam,
+    typename Prec<P>::C* __restrict__ lam_cap, double* __restrict__ du, double* __restrict__ drho_out,
+    double* __restrict__ dS, double* __restrict__ part) {
+  using C = typename Prec<P>::C;
+  constexpr int D = Lat::D, Q = Lat::Q, NS = Lat::NS;
+  __shared__ double sm[256];
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double acc[DPART] = {0, 0, 0, 0, 0};
+  if (x < nf) {
+    double gd[Q];
+    init_g<Lat>(rho_in, u_in, S_in, nf, x, (double)a.rho0, omega_d, gd);
+    C g[Q], ls[Q], mu[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      g[i] = (C)gd[i];
+      ls[i] = lam[(int64_t)i * a.n + x];
+    }
+    const bool src = x >= a.cap_begin;
+    C lrec[cap_fneq(D) + Q];
+    if (src) {
+      C* r = lam_cap + (x - a.cap_begin) * cap_stride(D);
+#pragma unroll
+      for (int c = 0; c < cap_fneq(D) + Q; ++c) {
+        lrec[c] = r[c];
+        r[c] = C(0);
+      }
+    }
+    collide_adjoint<Lat, C>(g, ls, src ? lrec : nullptr, a.rho0, a.omega, mu, acc[0]);
+    // f_i = w rho (1 + 3 cu + 4.5 cu^2 - 1.5 uu) - 3 w rho / omega (c c : S - tr S / 3)
+    const double rho = rho_in[x];
+    double u[3] = {0, 0, 0}, S[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < D; ++b) u[b] = u_in[(int64_t)b * nf + x];
+    if (S_in) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) S[k] = S_in[(int64_t)k * nf + x];
+    }
+    const double uu = dot_uu<Lat, double>(u);
+    double trS = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) trS += S[b];
+    double lu[3] = {0, 0, 0}, lrho = 0, lS[6] = {0, 0, 0, 0, 0, 0}, dw = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double m = (double)mu[i], w = Lat::w(i);
+      double cu = 0, cSc = 0;
+#pragma unroll
+      for (int b = 0; b < D; ++b) cu += Lat::c(i, b) * u[b];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const int aa = strain_a(D, k), bb = strain_b(D, k);
+        cSc += (aa == bb ? 1.0 : 2.0) * Lat::c(i, aa) * Lat::c(i, bb) * S[k];
+      }
+      const double QS = cSc - trS / 3.0;
+      const double feq_over_rho = w * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+      const double fneq = -3.0 * w * rho / omega_d * QS;
+      lrho += m * (feq_over_rho + fneq / rho);
+      dw += m * (-fneq / omega_d);
+#pragma unroll
+      for (int b = 0; b < D; ++b)
+        lu[b] += m * w * rho * (3.0 * Lat::c(i, b) + 9.0 * cu * Lat::c(i, b) - 3.0 * u[b]);
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const int aa = strain_a(D, k), bb = strain_b(D, k);
+        const double dq = (aa == bb) ? (Lat::c(i, aa) * Lat::c(i, aa) - 1.0 / 3.0)
+                                     : 2.0 * Lat::c(i, aa) * Lat::c(i, bb);
+        lS[k] += m * (-3.0 * w * rho / omega_d) * dq;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < D; ++b) du[(int64_t)b * nf + x] = lu[b];
+    if (drho_out) drho_out[x] = lrho;
+    if (dS) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) dS[(int64_t)k * nf + x] = lS[k];
+    }
+    acc[0] += dw;
+  }
+  block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void k_to_double(const C* __restrict__ in, int64_t n,
+                                                   double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) out[t] = (double)in[t];
+}
+
+// Deterministic reduction of all partial records, op by op in a fixed order.
+struct AdjOp {
+  int64_t offset;   // first block record
+  int64_t blocks;
+  int32_t level_self, level_other;  // -1 when unused
+};
+
+__global__ __launch_bounds__(256) void k_adj_reduce(const double* __restrict__ part,
+                                                    const AdjOp* __restrict__ ops, int n_ops,
+                                                    double* __restrict__ acc, int nlev) {
+  __shared__ double sm[256];
+  for (int o = 0; o < n_ops; ++o) {
+    const AdjOp op = ops[o];
+    double v[DPART] = {0, 0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < op.blocks; b += 256)
+#pragma unroll
+      for (int k = 0; k < DPART; ++k) v[k] += part[(op.offset + b) * DPART + k];
+    double tot[DPART];
+    block_sums(sm, v, DPART, tot);
+    if (threadIdx.x == 0) {
+      if (op.level_self >= 0) acc[op.level_self] += tot[0];
+      if (op.level_other >= 0) acc[op.level_other] += tot[1];
+      for (int k = 0; k < 3; ++k) acc[nlev + k] += tot[2 + k];
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace mlbm

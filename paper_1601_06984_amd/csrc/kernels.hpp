@@ -62,6 +62,7 @@ struct LevelArgs {
   C scale, inv_scale; // F16S scale s_L and 1/s_L
   C wr[Q];            // w_i rho0
   C geq[Q];           // f^eq_i(rho0, u_in) - w_i rho0 for EQ faces
+  double u_in[3];     // EQ-face velocity
 };
 
 // -------------------------------------------------------- BGK in g-form ---
@@ -630,7 +631,7 @@ struct DiagLevel {
 };
 
 // Final pass: one block; levels summed coarse to fine in fixed order.
-__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partial, int nlev,
+static __global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partial, int nlev,
                                                      const DiagLevel* __restrict__ lv, uint32_t mask,
                                                      int d, double* __restrict__ out) {
   __shared__ double sm[256];

@@ -742,6 +742,81 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
     (void)n;
     (void)L;
   }
+
+  // ---- adjoint tables ------------------------------------------------------
+  for (int k = 0; k < nlev; ++k) {
+    auto& lp = P.lv[k];
+    const int64_t n = lp.n, nf = lp.n_fluid;
+    for (int v = 0; v < 2; ++v) {
+      const int64_t act = v == 0 ? nf : nf + lp.n_inner;
+      std::vector<char> hit((size_t)q * nf, 0);
+      for (int64_t x = 0; x < act; ++x) {
+        if (x < nf) hit[x] = 1;  // rest direction reads the element itself
+        for (int i = 1; i < q; ++i) {
+          const int32_t y = lp.nbr[(size_t)(i - 1) * n + x];
+          if (y >= 0 && y < nf) hit[(size_t)i * nf + y] = 1;
+          if (y == MLBM_NBR_BOUNCE && x < nf) {
+            const int o = d == 3 ? D3Q19::opp(i) : D2Q9::opp(i);
+            hit[(size_t)o * nf + x] = 1;
+          }
+        }
+      }
+      auto& u = lp.unassigned[v];
+      u.clear();
+      std::vector<int32_t> dirs;
+      for (int i = 0; i < q; ++i)
+        for (int64_t x = 0; x < nf; ++x)
+          if (!hit[(size_t)i * nf + x]) {
+            u.push_back((int32_t)x);
+            dirs.push_back(i);
+          }
+      u.insert(u.end(), dirs.begin(), dirs.end());
+    }
+    lp.copy_elems.clear();
+    for (int64_t x = 0; x < lp.n_active_max(); ++x)
+      for (int i = 1; i < q; ++i)
+        if (lp.nbr[(size_t)(i - 1) * n + x] == MLBM_NBR_COPY) {
+          lp.copy_elems.push_back((int32_t)x);
+          break;
+        }
+    const int64_t ng = lp.n_gfc();
+    lp.gfc_slot.assign((size_t)4 * ng, -1);
+    lp.gfc_oct.assign((size_t)ng, 0);
+    lp.csr_ptr.clear();
+    lp.csr_ent.clear();
+    if (ng) {
+      const int64_t ncap_c = P.lv[k - 1].n_cap();
+      std::vector<int32_t> count((size_t)ncap_c + 1, 0);
+      for (int64_t j = 0; j < ng; ++j) {
+        int oct = 0;
+        for (int a = 0; a < d; ++a) oct |= (lp.coords[(size_t)a * n + nf + j] & 1) << a;
+        lp.gfc_oct[j] = (int8_t)oct;
+        for (int t = 0; t < 4; ++t) {
+          const int32_t sl = slot_of[k - 1][lp.gfc_src[(size_t)t * ng + j]];
+          if (sl < 0) throw MeshError("internal: GhostFromCoarser source without a slot");
+          lp.gfc_slot[(size_t)t * ng + j] = sl;
+          count[sl + 1]++;
+        }
+      }
+      for (int64_t s2 = 0; s2 < ncap_c; ++s2) count[s2 + 1] += count[s2];
+      lp.csr_ptr = count;
+      lp.csr_ent.assign((size_t)4 * ng, 0);
+      std::vector<int32_t> fillp(count.begin(), count.end() - 1);
+      for (int64_t j = 0; j < ng; ++j)  // ascending ghost order within each row
+        for (int t = 0; t < 4; ++t) {
+          const int32_t sl = lp.gfc_slot[(size_t)t * ng + j];
+          lp.csr_ent[fillp[sl]++] = (int32_t)(j * 4 + t);
+        }
+    }
+  }
+  // a fine source belongs to exactly one GhostFromFiner (disjoint children)
+  for (int k = 0; k + 1 < nlev; ++k) {
+    std::vector<char> used((size_t)P.lv[k + 1].n_cap(), 0);
+    for (int32_t sl : P.lv[k].gff_slot) {
+      if (used[sl]) throw MeshError("internal: shared GhostFromFiner source");
+      used[sl] = 1;
+    }
+  }
 }
 
 }  // namespace

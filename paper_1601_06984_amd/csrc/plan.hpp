@@ -24,6 +24,16 @@ struct LevelPlan {
   std::vector<int32_t> grp_child;  // [children][n_groups] element idx on L
   std::vector<int32_t> bounce;     // [2][n_bounce] (element, direction)
 
+  // adjoint tables
+  std::vector<int32_t> unassigned[2];  // [2][cnt] (element, direction) fluid-range
+                                       // entries no pull reads; variant 0: fluid
+                                       // updated, 1: fluid and inner ghosts
+  std::vector<int32_t> copy_elems;     // updated elements with a COPY link
+  std::vector<int32_t> gfc_slot;       // [4][n_gfc] source capture slots on L-1
+  std::vector<int8_t> gfc_oct;         // [n_gfc] octant bits (x, y, z) of the ghost
+  std::vector<int32_t> csr_ptr;        // [n_cap(L-1)+1] coarse slot -> contributions
+  std::vector<int32_t> csr_ent;        // ghost * 4 + source index
+
   int64_t n_gfc() const { return n_inner + n_outer; }
   int64_t n_active_max() const { return n_fluid + n_inner; }
   int64_t n_cap_fluid() const { return (int64_t)cap_elem.size(); }

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "launch.hpp"
 #include "plan.hpp"
 #include "sim.hpp"
 
@@ -72,142 +73,6 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
   }
   return off;
 }
-
-template <class C, int Q>
-LevelArgs<C, Q> level_args(const SimState& s, int k) {
-  const DevLevel& L = s.lv[k];
-  LevelArgs<C, Q> a;
-  a.n = L.n;
-  a.ld_nbr = L.n_act_max;
-  a.cap_begin = L.n_fluid - L.n_cap_fluid;
-  a.n_fluid = L.n_fluid;
-  a.omega = (C)L.omega;
-  a.rho0 = (C)s.rho0;
-  a.scale = (C)std::ldexp(1.0, L.f16_exp);
-  a.inv_scale = (C)std::ldexp(1.0, -L.f16_exp);
-  for (int i = 0; i < Q; ++i) {
-    a.wr[i] = (C)s.wr[i];
-    a.geq[i] = (C)s.geq[i];
-  }
-  return a;
-}
-
-// ---- per (lattice, precision) launchers ------------------------------------
-template <class Lat, int P>
-struct Impl {
-  using S = typename Prec<P>::S;
-  using C = typename Prec<P>::C;
-  static constexpr int BS = 256;
-
-  static void stream_collide(SimState& s, int k, int64_t n_act) {
-    DevLevel& L = s.lv[k];
-    if (n_act <= 0) return;
-    auto a = level_args<C, Lat::Q>(s, k);
-    const S* src = (const S*)L.pdf[L.parity];
-    S* dst = (S*)L.pdf[L.parity ^ 1];
-    const unsigned grid = (unsigned)((n_act + BS - 1) / BS);
-    hipLaunchKernelGGL((k_stream_collide<Lat, P, BS>), dim3(grid), dim3(BS), 0, s.stream, src, dst,
-                       L.nbr, n_act, a, (C*)L.cap, s.status);
-  }
-
-  static void fill_gff(SimState& s, int k) {
-    DevLevel& L = s.lv[k];
-    if (!L.n_gff) return;
-    const DevLevel& F = s.lv[k + 1];
-    auto a = level_args<C, Lat::Q>(s, k);
-    const C scale = (C)(2.0 * F.omega / L.omega);
-    const unsigned grid = (unsigned)((L.n_gff + 63) / 64);
-    hipLaunchKernelGGL((k_fill_gff<Lat, P>), dim3(grid), dim3(64), 0, s.stream,
-                       (S*)L.pdf[L.parity], L.n_fluid + L.n_inner + L.n_outer, L.n_gff,
-                       L.gff_slot, (const C*)F.cap, (C*)L.cap, L.n_cap_fluid, a, scale, s.status);
-  }
-
-  static void fill_gfc(SimState& s, int k) {
-    DevLevel& L = s.lv[k];
-    if (!L.n_groups) return;
-    const DevLevel& Cl = s.lv[k - 1];
-    auto a = level_args<C, Lat::Q>(s, k);
-    const C scale = (C)(Cl.omega / (2.0 * L.omega));
-    constexpr int GPB = 64 / group_children(Lat::D);
-    const unsigned grid = (unsigned)((L.n_groups + GPB - 1) / GPB);
-    hipLaunchKernelGGL((k_fill_gfc<Lat, P>), dim3(grid), dim3(64), 0, s.stream,
-                       (S*)L.pdf[L.parity], L.n_groups, L.grp_src, L.grp_child,
-                       (const C*)Cl.cap, a, scale, s.status);
-  }
-
-  static double init_maxdev(SimState& s, int k, const double* rho, const double* u,
-                             const double* S_) {
-    DevLevel& L = s.lv[k];
-    if (!L.n_fluid) return 0.0;
-    hipLaunchKernelGGL((k_init_maxdev<Lat>), dim3(256), dim3(256), 0, s.stream, rho, u, S_,
-                       L.n_fluid, s.rho0, L.omega, s.maxdev);
-    double host[256];
-    if (hipMemcpyAsync(host, s.maxdev, sizeof host, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
-        hipStreamSynchronize(s.stream) != hipSuccess)
-      return -1.0;
-    double m = 0;
-    for (double v : host) m = std::max(m, v);
-    return m;
-  }
-
-  static void init(SimState& s, int k, const double* rho, const double* u, const double* S_) {
-    DevLevel& L = s.lv[k];
-    auto a = level_args<C, Lat::Q>(s, k);
-    if (L.n_fluid) {
-      const unsigned grid = (unsigned)((L.n_fluid + 255) / 256);
-      hipLaunchKernelGGL((k_init<Lat, P>), dim3(grid), dim3(256), 0, s.stream, rho, u, S_,
-                         L.n_fluid, (S*)L.pdf[L.parity], a, s.rho0, L.omega);
-    }
-    if (L.n_cap_fluid) {
-      const unsigned gc = (unsigned)((L.n_cap_fluid + 255) / 256);
-      hipLaunchKernelGGL((k_init_capture<Lat, P>), dim3(gc), dim3(256), 0, s.stream, rho, u, S_,
-                         L.n_fluid, L.cap_elem, L.n_cap_fluid, (C*)L.cap, s.rho0, L.omega);
-    }
-  }
-
-  static void get_pdf(SimState& s, int k, double* out) {
-    DevLevel& L = s.lv[k];
-    if (!L.n) return;
-    auto a = level_args<C, Lat::Q>(s, k);
-    hipLaunchKernelGGL((k_get_pdf<Lat, P>), dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0,
-                       s.stream, (const S*)L.pdf[L.parity], L.n, a, out);
-  }
-  static void set_pdf(SimState& s, int k, const double* in) {
-    DevLevel& L = s.lv[k];
-    if (!L.n) return;
-    auto a = level_args<C, Lat::Q>(s, k);
-    hipLaunchKernelGGL((k_set_pdf<Lat, P>), dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0,
-                       s.stream, (S*)L.pdf[L.parity], L.n, a, in);
-  }
-  static void get_moments(SimState& s, int k, double* out) {
-    DevLevel& L = s.lv[k];
-    if (!L.n_fluid) return;
-    auto a = level_args<C, Lat::Q>(s, k);
-    hipLaunchKernelGGL((k_get_moments<Lat, P>), dim3((unsigned)((L.n_fluid + 255) / 256)),
-                       dim3(256), 0, s.stream, (const S*)L.pdf[L.parity], L.n_fluid, a, out);
-  }
-  static void diag_partial(SimState& s, int k) {
-    DevLevel& L = s.lv[k];
-    auto a = level_args<C, Lat::Q>(s, k);
-    hipLaunchKernelGGL((k_diag_partial<Lat, P>), dim3(DIAG_BLOCKS), dim3(256), 0, s.stream,
-                       (const S*)L.pdf[L.parity], L.n_fluid, L.bounce, L.n_bounce, a,
-                       s.partial + (int64_t)k * DIAG_BLOCKS * DIAG_VALS);
-  }
-};
-
-// ---- dispatch -------------------------------------------------------------
-#define MLBM_DISPATCH(s, CALL)                                              \
-  do {                                                                      \
-    if ((s).d == 3) {                                                       \
-      if ((s).precision == MLBM_F64) { using I = Impl<D3Q19, MLBM_F64>; CALL; } \
-      else if ((s).precision == MLBM_F32) { using I = Impl<D3Q19, MLBM_F32>; CALL; } \
-      else { using I = Impl<D3Q19, MLBM_F16S>; CALL; }                      \
-    } else {                                                                \
-      if ((s).precision == MLBM_F64) { using I = Impl<D2Q9, MLBM_F64>; CALL; } \
-      else if ((s).precision == MLBM_F32) { using I = Impl<D2Q9, MLBM_F32>; CALL; } \
-      else { using I = Impl<D2Q9, MLBM_F16S>; CALL; }                       \
-    }                                                                       \
-  } while (0)
 
 void SimState::drop_graphs() {
   for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);

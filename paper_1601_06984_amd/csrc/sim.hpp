@@ -45,6 +45,38 @@ struct Profiler {
   std::vector<ProfRecord> rec;
 };
 
+struct AdjOp;
+
+// Adjoint state: the tape of one coarse step and the lambda arrays.
+struct AdjLevel {
+  std::vector<void*> X;        // tape pdf arrays, substeps 0..2^k
+  std::vector<void*> cap;      // tape capture records, substeps 0..2^k-1
+  void* lam[2] = {nullptr, nullptr};
+  int cur = 0;                 // lam[cur] holds dJ/dg* of the current state
+  void* lam_cap = nullptr;     // record adjoints [n_cap][stride]
+  int32_t* unas[2] = {nullptr, nullptr};
+  int64_t n_unas[2] = {0, 0};
+  int32_t* copy_el = nullptr;
+  int64_t n_copy = 0;
+  void* copy_tmp = nullptr;
+  int32_t* gfc_slot = nullptr;
+  int8_t* gfc_oct = nullptr;
+  int32_t* csr_ptr = nullptr;
+  int32_t* csr_ent = nullptr;
+  void* T = nullptr;
+};
+
+struct AdjState {
+  bool attached = false;
+  std::vector<AdjLevel> lv;
+  double* part = nullptr;      // per-block partial records
+  int64_t part_records = 0;
+  AdjOp* ops_step = nullptr;   // device op lists for the reductions
+  AdjOp* ops_init = nullptr;
+  int n_ops_step = 0, n_ops_init = 0;
+  double* acc = nullptr;       // [nlev] d/d omega_L, then d/d u_in (3)
+};
+
 struct SimState {
   int stencil = 0, d = 3, q = 19, precision = 0, level0 = 0;
   double tau0 = 1.0, rho0 = 1.0, u_in[3] = {0, 0, 0};
@@ -61,6 +93,7 @@ struct SimState {
   bool filled = false;
   int64_t time = 0;
   Profiler prof;
+  AdjState adj;
   // graphs of two coarse steps, keyed by the parity state they start from
   hipStream_t capture_stream = nullptr;
   bool use_graphs = true;

@@ -1,0 +1,150 @@
+"""GPU adjoint of the multilevel step against (a) the oracle's reverse pass
+(automatic differentiation of the FP64 oracle run) and (b) central finite
+differences of the library's own FP64 forward.
+
+Tolerances: F64 gradients agree with the oracle to 1e-8 relative (max
+norm); F32 to 2e-4 (single-precision forward and reverse arithmetic over a
+few steps of O(1) pdfs).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint as oadj
+from oracle import mesh as omesh
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1601_06984_amd  # noqa: F401
+
+
+def gpu_gradient(spec, precision, tau0, fields, steps, objective="ke", u_in=None):
+    import paper_1601_06984_amd as M
+    sim = H.gpu_sim(spec, precision, tau0, fields, u_in=u_in)
+    sim.adjoint_attach()
+    ckpts = []
+    for _ in range(steps):
+        ckpts.append(sim.save_checkpoint())
+        sim.step(1)
+    mask = M.DIAG_KE if objective == "ke" else M.DIAG_FORCE
+    J = float(sim.diagnostics(mask)[0])
+    sim.adjoint_seed(objective)
+    for t in reversed(range(steps)):
+        sim.adjoint_step(ckpts[t])
+    n = sim.plan.n_levels
+    rho = [sim.inputs[k][0] for k in range(n)]
+    u = [sim.inputs[k][1] for k in range(n)]
+    S = [sim.inputs[k][2] for k in range(n)]
+    du = sim.adjoint_init(rho, u, S)
+    dtau, domega, duin = sim.adjoint_params()
+    return sim, J, [d.cpu().numpy() for d in du], dtau, duin
+
+
+def oracle_gradient(spec, tau0, fields, steps, objective="ke", u_in=None):
+    om = omesh.build(spec)
+    rho, u, S = {}, {}, {}
+    for L in range(om.level0, om.lmax + 1):
+        pos = om.positions(L)[:om.lev(L).n_fluid]
+        r, uu, SS = fields(pos)
+        rho[L], u[L], S[L] = r, uu, SS * 2.0 ** -(L - om.level0)
+    J, gt, gu, gin = oadj.gradient(om, tau0, rho, u, S, steps, objective, u_in=u_in)
+    return om, J, gt, gu, gin
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _compare(sim, om, du_gpu, gu_or):
+    worst = 0.0
+    for k in range(sim.plan.n_levels):
+        L = sim.plan.level0 + k
+        g2o = H.gpu_to_oracle(sim.plan, om, k)
+        nf = sim.plan.info[k]["n_fluid"]
+        want = gu_or[L][g2o[:nf]].T          # (d, n_fluid) in GPU order
+        worst = max(worst, _rel(du_gpu[k], want))
+    return worst
+
+
+CASES = [
+    ("d3q19_2lev_ke", lambda: W.refined_box_mesh("D3Q19", 4, 4, 12), 16, 4, 0.56),
+    ("d2q9_2lev_ke", lambda: W.refined_box_mesh("D2Q9", 5, 8, 24), 32, 6, 0.6),
+    ("d2q9_3lev_ke", lambda: W.refined_box_mesh("D2Q9", 5, 8, 24, extra_levels=[(20, 44)]), 32, 3, 0.7),
+]
+
+
+@pytest.mark.parametrize("name,spec_fn,n0,steps,tau0", CASES)
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-8), ("f32", 2e-4)])
+def test_ke_gradient_matches_oracle_reverse(name, spec_fn, n0, steps, tau0, precision, tol):
+    spec = spec_fn()
+    fields = lambda p: W.tgv_perturbed_fields(p, n0, 0.03)
+    _say(name, precision, steps)
+    sim, J, du, dtau, _ = gpu_gradient(spec, precision, tau0, fields, steps)
+    om, Jo, gto, guo, _ = oracle_gradient(spec, tau0, fields, steps)
+    assert abs(J - Jo) <= 1e-6 * abs(Jo)
+    err = _compare(sim, om, du, guo)
+    print("du rel err", err, "dtau", dtau, gto)
+    assert err < tol
+    assert abs(dtau - gto) <= tol * abs(gto)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-8), ("f32", 5e-4)])
+def test_drag_gradient_with_boundaries(precision, tol):
+    """Bounce-back, equilibrium faces (d/du_in) and copy outlet in reverse."""
+    spec = W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0), half_width=2.0,
+                                 boxes_in_d=((-1.0, 1.5, 1.0),))
+    uin = np.array([0.04, 0.0, 0.0])
+    fields = lambda p: W.uniform_fields(len(p), 3, uin)
+    _say("sphere drag", precision)
+    sim, J, du, dtau, duin = gpu_gradient(spec, precision, 0.6, fields, 3, "drag_x", u_in=uin)
+    om, Jo, gto, guo, gino = oracle_gradient(spec, 0.6, fields, 3, "drag_x", u_in=uin)
+    assert abs(J - Jo) <= 1e-5 * abs(Jo)
+    print("duin", duin, gino, "dtau", dtau, gto)
+    assert np.abs(duin - gino).max() <= tol * np.abs(gino).max()
+    assert abs(dtau - gto) <= tol * abs(gto)
+    assert _compare(sim, om, du, guo) < tol * 10
+
+
+def test_f64_adjoint_matches_central_differences_of_gpu_forward():
+    """Directional derivative along a random initial-velocity perturbation:
+    the GPU adjoint against (J(u + e d) - J(u - e d)) / 2e of the GPU FP64
+    forward itself, e = 1e-4 as in the adjoint configuration."""
+    import paper_1601_06984_amd as M
+    spec = W.refined_box_mesh("D3Q19", 4, 4, 12)
+    base = lambda p: W.tgv_perturbed_fields(p, 16, 0.02)
+    steps = 6
+    _say("fd check f64")
+    sim, J, du, dtau, _ = gpu_gradient(spec, "f64", 0.55, base, steps)
+    rng = np.random.default_rng(3)
+    plan = sim.plan
+    dirs = {}
+    for k in range(plan.n_levels):
+        dirs[k] = rng.normal(size=(plan.d, plan.info[k]["n_fluid"]))
+    ad = sum(float((du[k] * dirs[k]).sum()) for k in dirs)
+
+    def J_of(eps):
+        s2 = M.Sim(plan, "f64", 0.55)
+        for k in range(plan.n_levels):
+            r, u, S = sim.inputs[k]
+            s2.init(k, r, (u + eps * torch.tensor(dirs[k], device=u.device)).contiguous(), S)
+        s2.fill_ghosts()
+        s2.step(steps)
+        return float(s2.diagnostics(M.DIAG_KE)[0])
+    eps = 1e-4
+    fd = (J_of(eps) - J_of(-eps)) / (2 * eps)
+    print("fd", fd, "adjoint", ad)
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
