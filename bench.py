@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--variants", type=int, default=1,
                     help="also time F64/F16S and report the fixed-error study")
     ap.add_argument("--cpu-steps", type=int, default=15)
+    ap.add_argument("--adjoint", type=int, default=20,
+                    help="time this many reverse coarse steps (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size (counter calibration)")
@@ -217,6 +219,43 @@ def main():
         "ms_per_step_direct_launches": ms_direct / args.steps,
         "status_flags": status,
     }
+    if args.adjoint:
+        # reverse of one coarse step: tape rerun + transposed kernels
+        print("[bench] adjoint steps", file=sys.stderr, flush=True)
+        sim.adjoint_attach()
+        ck = sim.save_checkpoint()
+        sim.adjoint_seed("ke")
+        for _ in range(3):
+            sim.adjoint_step(ck)
+        torch.cuda.synchronize()
+        n_adj = args.adjoint
+        sim.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        for _ in range(n_adj):
+            sim.adjoint_step(ck)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        sim.profile(False)
+        adj_ms = e0.elapsed_time(e1) / n_adj
+        cb = 8 if prec == "f64" else 4
+        abpe = 2 * q * cb + q * STORAGE_BYTES[prec] + 4 * (q - 1)
+        akern = []
+        for k in range(plan.n_levels):
+            kms, n, el = sim.profile_read(k, kind=1)
+            akern.append(dict(level=plan.level0 + k, launches=n, us_per_launch=1e3 * kms / max(n, 1),
+                              gbs=(el * abpe / 1e9) / (kms / 1e3) if kms else 0.0))
+        adom = max(akern, key=lambda p: p["us_per_launch"] * p["launches"])
+        out["adjoint"] = {
+            "ms_per_step": adj_ms,
+            "mlups": round(upd / (adj_ms / 1e3) / 1e6, 1),
+            "note": "one reverse coarse step = tape rerun of the forward step + transposed kernels",
+            "kernel": f"k_adj_sc level {adom['level']} ({prec})",
+            "algorithmic_bytes_per_update": abpe,
+            "achieved_gbs": round(adom["gbs"], 1),
+            "frac": round(adom["gbs"] / HBM_PEAK_GBS, 4),
+            "kernels": akern,
+        }
     if args.variants and wl.get("tgv"):
         # precision study at a fixed run length: MLUPS and eps_u for each
         study = {}

@@ -225,6 +225,10 @@ int32_t mlbm_launches_per_step(const mlbm_sim* sim, int64_t* launches);
 int32_t mlbm_profile(mlbm_sim* sim, int32_t enable);
 int32_t mlbm_profile_read(mlbm_sim* sim, int32_t k, double* ms, int64_t* launches,
                           int64_t* elements);
+/* As mlbm_profile_read for kernel kind 0 (forward stream-collide) or 1
+ * (adjoint stream-collide, bracketed inside mlbm_adjoint_step). */
+int32_t mlbm_profile_read_kind(mlbm_sim* sim, int32_t kind, int32_t k, double* ms,
+                               int64_t* launches, int64_t* elements);
 
 /* ---- adjoint ----------------------------------------------------------
  * Hand-written reverse of the multilevel step (adjoints of Eq. bgk, of the

@@ -60,6 +60,7 @@ SIGNATURES = {
     "mlbm_profile": (_i32, [_p, _i32]),
     "mlbm_use_graphs": (_i32, [_p, _i32]),
     "mlbm_profile_read": (_i32, [_p, _i32, _pd, _pi64, _pi64]),
+    "mlbm_profile_read_kind": (_i32, [_p, _i32, _i32, _pd, _pi64, _pi64]),
     "mlbm_adjoint_workspace_bytes": (_i32, [_p, _p, _psz]),
     "mlbm_adjoint_attach": (_i32, [_p, _p, _p, _sz]),
     "mlbm_adjoint_seed": (_i32, [_p, _i32]),

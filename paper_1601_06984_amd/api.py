@@ -219,10 +219,12 @@ class Sim:
     def profile(self, enable: bool):
         check(lib().mlbm_profile(self._h, 1 if enable else 0))
 
-    def profile_read(self, k: int):
-        """(ms, launches, elements) of level k's stream-collide launches."""
+    def profile_read(self, k: int, kind: int = 0):
+        """(ms, launches, elements) of level k's stream-collide launches
+        (kind 0) or adjoint stream-collide launches (kind 1)."""
         ms, n, el = C.c_double(), C.c_int64(), C.c_int64()
-        check(lib().mlbm_profile_read(self._h, k, C.byref(ms), C.byref(n), C.byref(el)))
+        check(lib().mlbm_profile_read_kind(self._h, kind, k, C.byref(ms), C.byref(n),
+                                           C.byref(el)))
         return ms.value, n.value, el.value
 
     # ---- adjoint --------------------------------------------------------

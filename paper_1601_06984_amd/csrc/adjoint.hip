@@ -212,10 +212,20 @@ struct Adj {
                          s.stream, (const S*)X, L.nbr, A.copy_el, A.n_copy, n_act, a,
                          (const C*)lnew, (const C*)A.lam_cap, (C*)A.copy_tmp);
     const int64_t nb = blocks(n_act, 256);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s.prof.on) {
+      e0 = prof_event(s);
+      e1 = prof_event(s);
+      if (e0 && e1) (void)hipEventRecord(e0, s.stream);
+    }
     if (nb)
       hipLaunchKernelGGL((k_adj_sc<Lat, P>), dim3((unsigned)nb), dim3(256), 0, s.stream, (const S*)X,
                          L.nbr, n_act, a, (const C*)lnew, (C*)A.lam_cap, lold,
                          s.adj.part + off * DPART);
+    if (s.prof.on && e0 && e1) {
+      (void)hipEventRecord(e1, s.stream);
+      s.prof.rec.push_back({1, k, n_act, e0, e1});
+    }
     off += nb;
     if (A.n_copy)
       hipLaunchKernelGGL((k_adj_copy_add<Lat::Q, C>), dim3((unsigned)blocks(A.n_copy, 256)), dim3(256),

@@ -85,7 +85,7 @@ SimState::~SimState() {
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }
 
-static hipEvent_t prof_event(SimState& s) {
+hipEvent_t prof_event(SimState& s) {
   if (s.prof.used == s.prof.pool.size()) {
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
@@ -107,7 +107,7 @@ void sc_level(SimState& s, int k) {
   MLBM_DISPATCH(s, I::stream_collide(s, k, n_act));
   if (s.prof.on && e0 && e1) {
     (void)hipEventRecord(e1, s.stream);
-    s.prof.rec.push_back({k, n_act, e0, e1});
+    s.prof.rec.push_back({0, k, n_act, e0, e1});
   }
   L.parity ^= 1;
   if (k > 0) L.substep ^= 1;
@@ -486,6 +486,11 @@ int32_t mlbm_profile(mlbm_sim* sim, int32_t enable) {
 
 int32_t mlbm_profile_read(mlbm_sim* sim, int32_t k, double* ms, int64_t* launches,
                           int64_t* elements) {
+  return mlbm_profile_read_kind(sim, 0, k, ms, launches, elements);
+}
+
+int32_t mlbm_profile_read_kind(mlbm_sim* sim, int32_t kind, int32_t k, double* ms,
+                               int64_t* launches, int64_t* elements) {
   if (!sim || !ms || !launches || !elements) return fail(MLBM_E_ARG, "NULL argument");
   SimState& s = sim->s;
   if (k < 0 || k >= (int)s.lv.size()) return fail(MLBM_E_ARG, "level index %d out of range", k);
@@ -493,7 +498,7 @@ int32_t mlbm_profile_read(mlbm_sim* sim, int32_t k, double* ms, int64_t* launche
   double t = 0;
   int64_t n = 0, el = 0;
   for (const auto& r : s.prof.rec) {
-    if (r.level != k) continue;
+    if (r.level != k || r.kind != kind) continue;
     float dt = 0;
     if (hipEventElapsedTime(&dt, r.start, r.stop) != hipSuccess)
       return fail(MLBM_E_HIP, "profile: elapsed time failed");

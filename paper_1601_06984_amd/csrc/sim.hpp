@@ -34,6 +34,7 @@ struct DevLevel {
 
 // Event-bracketed timing of stream-collide launches.
 struct ProfRecord {
+  int kind;   // 0: forward stream-collide, 1: adjoint stream-collide
   int level;
   int64_t n_act;
   hipEvent_t start, stop;
@@ -110,6 +111,7 @@ struct CheckpointHeader {
 };
 
 size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState* s);
+hipEvent_t prof_event(SimState& s);
 
 }  // namespace mlbm
 
