@@ -102,18 +102,25 @@ def test_ke_gradient_matches_oracle_reverse(name, spec_fn, n0, steps, tau0, prec
     assert abs(dtau - gto) <= tol * abs(gto)
 
 
+def _compact_sphere():
+    return W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-1.5, 2.0), half_width=1.5,
+                                 boxes_in_d=((-0.75, 1.0, 0.75),))
+
+
+@pytest.mark.parametrize("objective,steps", [("ke", 3), ("drag_x", 6)])
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-8), ("f32", 5e-4)])
-def test_drag_gradient_with_boundaries(precision, tol):
-    """Bounce-back, equilibrium faces (d/du_in) and copy outlet in reverse."""
-    spec = W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0), half_width=2.0,
-                                 boxes_in_d=((-1.0, 1.5, 1.0),))
+def test_gradients_with_boundaries(objective, steps, precision, tol):
+    """Bounce-back, equilibrium faces (d/du_in, far from zero here) and the
+    copy outlet in reverse, against the oracle's reverse pass."""
+    spec = _compact_sphere()
     uin = np.array([0.04, 0.0, 0.0])
     fields = lambda p: W.uniform_fields(len(p), 3, uin)
-    _say("sphere drag", precision)
-    sim, J, du, dtau, duin = gpu_gradient(spec, precision, 0.6, fields, 3, "drag_x", u_in=uin)
-    om, Jo, gto, guo, gino = oracle_gradient(spec, 0.6, fields, 3, "drag_x", u_in=uin)
+    _say("sphere", objective, precision)
+    sim, J, du, dtau, duin = gpu_gradient(spec, precision, 0.6, fields, steps, objective, u_in=uin)
+    om, Jo, gto, guo, gino = oracle_gradient(spec, 0.6, fields, steps, objective, u_in=uin)
     assert abs(J - Jo) <= 1e-5 * abs(Jo)
     print("duin", duin, gino, "dtau", dtau, gto)
+    assert abs(gino[0]) > 1.0
     assert np.abs(duin - gino).max() <= tol * np.abs(gino).max()
     assert abs(dtau - gto) <= tol * abs(gto)
     assert _compare(sim, om, du, guo) < tol * 10

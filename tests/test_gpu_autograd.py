@@ -71,16 +71,17 @@ def test_checkpointed_gradient_equals_stepwise_adjoint_and_oracle():
 def test_drag_gradient_wrt_inflow_through_autograd():
     import paper_1601_06984_amd as M
     from tests.test_gpu_adjoint import gpu_gradient
-    spec = W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0), half_width=2.0,
-                                 boxes_in_d=((-1.0, 1.5, 1.0),))
+    spec = W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-1.5, 2.0), half_width=1.5,
+                                 boxes_in_d=((-0.75, 1.0, 0.75),))
     uin = [0.04, 0.0, 0.0]
     fields = lambda p: W.uniform_fields(len(p), 3, uin)
     plan = M.Plan.from_spec(spec)
     rho, u, S = _inputs(plan, fields, "cuda")
     _say("autograd drag u_in f64")
-    J, gu, gt, gin = _run(plan, "f64", rho, u, S, 0.6, 5, 2, objective="drag_x", u_in=uin)
-    _, J2, du, dtau, duin = gpu_gradient(spec, "f64", 0.6, fields, 5, "drag_x", u_in=np.array(uin))
+    J, gu, gt, gin = _run(plan, "f64", rho, u, S, 0.6, 7, 3, objective="drag_x", u_in=uin)
+    _, J2, du, dtau, duin = gpu_gradient(spec, "f64", 0.6, fields, 7, "drag_x", u_in=np.array(uin))
     assert J == J2 and gt == dtau
+    assert abs(float(gin[0])) > 1.0
     assert np.array_equal(gin.numpy(), duin)
 
 

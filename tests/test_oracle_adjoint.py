@@ -41,20 +41,26 @@ def test_ke_gradient_matches_central_differences(stencil):
     assert abs(fd - g_tau) <= 1e-7 * abs(g_tau)
 
 
-def test_drag_gradient_wrt_inflow_and_tau():
-    spec = W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0),
-                                 half_width=2.0, boxes_in_d=((-1.0, 1.5, 1.0),))
-    m = mesh.build(spec)
+def _compact_sphere():
+    return W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-1.5, 2.0), half_width=1.5,
+                                 boxes_in_d=((-0.75, 1.0, 0.75),))
+
+
+@pytest.mark.parametrize("objective,steps", [("ke", 3), ("drag_x", 6)])
+def test_gradient_wrt_inflow_and_tau(objective, steps):
+    """Compact sphere channel: both objectives feel the inflow face within
+    the run, so d/du_in is far from zero and is checked, as is d/dtau0."""
+    m = mesh.build(_compact_sphere())
     uin = np.array([0.04, 0.0, 0.0])
     rho, u, S = {}, {}, {}
     for L in range(m.level0, m.lmax + 1):
         rho[L], u[L], S[L] = W.uniform_fields(m.lev(L).n_fluid, 3, uin)
-    J, g_tau, g_u, g_in = adjoint.gradient(m, 0.6, rho, u, S, 3,
-                                           objective="drag_x", u_in=uin)
-    assert J > 0
-    fd = adjoint.central_difference(m, 0.6, rho, u, S, 3, objective="drag_x",
+    J, g_tau, g_u, g_in = adjoint.gradient(m, 0.6, rho, u, S, steps,
+                                           objective=objective, u_in=uin)
+    assert J > 0 and abs(g_in[0]) > 1.0
+    fd = adjoint.central_difference(m, 0.6, rho, u, S, steps, objective=objective,
                                     duin=np.array([1.0, 0, 0]), u_in=uin, eps=1e-6)
     assert abs(fd - g_in[0]) <= 1e-6 * abs(fd)
-    fd = adjoint.central_difference(m, 0.6, rho, u, S, 3, objective="drag_x",
+    fd = adjoint.central_difference(m, 0.6, rho, u, S, steps, objective=objective,
                                     dtau=1.0, u_in=uin, eps=1e-6)
     assert abs(fd - g_tau) <= 1e-6 * abs(fd)
