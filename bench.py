@@ -158,6 +158,8 @@ def main():
     ap.add_argument("--adjoint", type=int, default=20,
                     help="time this many reverse coarse steps (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-ceiling", type=int, default=1,
+                    help="also time a plain 2 GiB device copy (read + write)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -273,6 +275,21 @@ def main():
         for p in study:
             study[p]["fixed_error_pass"] = bool(study[p]["eps_u"] <= 1.05 * ref)
         out["precision_study"] = {"coarse_steps": n_fix, "results": study}
+    if args.copy_ceiling:
+        # practical streaming ceiling of this device: a plain 2 GiB copy
+        n = 2 << 30
+        a_ = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b_ = torch.empty_like(a_)
+        b_.copy_(a_)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(5):
+            b_.copy_(a_)
+        c1.record()
+        torch.cuda.synchronize()
+        out["copy_ceiling_gbs"] = round(2 * n * 5 / (c0.elapsed_time(c1) / 1e3) / 1e9, 1)
+        del a_, b_
     if args.calib_copy_mib:
         n = args.calib_copy_mib << 20
         a = torch.empty(n, dtype=torch.uint8, device="cuda")

@@ -51,7 +51,8 @@ void step_ops(const SimState& s, int k, int j, OpBuilder& ob) {
   }
   const auto& L = s.lv[k];
   const bool first = k > 0 && (j % 2 == 0);
-  ob.add(blocks(L.n_fluid + (first ? L.n_inner : 0), 256), k, -1);
+  const int64_t cb = L.n_fluid - L.n_cap_fluid;
+  ob.add(blocks(cb, 256) + blocks(L.n_fluid + (first ? L.n_inner : 0) - cb, 256), k, -1);
 }
 
 void init_ops(const SimState& s, OpBuilder& ob) {
@@ -211,22 +212,27 @@ struct Adj {
       hipLaunchKernelGGL((k_adj_copy_pre<Lat, P>), dim3((unsigned)blocks(A.n_copy, 256)), dim3(256), 0,
                          s.stream, (const S*)X, L.nbr, A.copy_el, A.n_copy, n_act, a,
                          (const C*)lnew, (const C*)A.lam_cap, (C*)A.copy_tmp);
-    const int64_t nb = blocks(n_act, 256);
+    const int64_t cb = L.n_fluid - L.n_cap_fluid;   // plain fluid [0, cb)
+    const int64_t nb1 = blocks(cb, 256), nb2 = blocks(n_act - cb, 256);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (s.prof.on) {
       e0 = prof_event(s);
       e1 = prof_event(s);
       if (e0 && e1) (void)hipEventRecord(e0, s.stream);
     }
-    if (nb)
-      hipLaunchKernelGGL((k_adj_sc<Lat, P>), dim3((unsigned)nb), dim3(256), 0, s.stream, (const S*)X,
-                         L.nbr, n_act, a, (const C*)lnew, (C*)A.lam_cap, lold,
+    if (nb1)
+      hipLaunchKernelGGL((k_adj_sc<Lat, P, false>), dim3((unsigned)nb1), dim3(256), 0, s.stream,
+                         (const S*)X, L.nbr, (int64_t)0, cb, a, (const C*)lnew, (C*)A.lam_cap, lold,
                          s.adj.part + off * DPART);
+    if (nb2)
+      hipLaunchKernelGGL((k_adj_sc<Lat, P, true>), dim3((unsigned)nb2), dim3(256), 0, s.stream,
+                         (const S*)X, L.nbr, cb, n_act, a, (const C*)lnew, (C*)A.lam_cap, lold,
+                         s.adj.part + (off + nb1) * DPART);
     if (s.prof.on && e0 && e1) {
       (void)hipEventRecord(e1, s.stream);
       s.prof.rec.push_back({1, k, n_act, e0, e1});
     }
-    off += nb;
+    off += nb1 + nb2;
     if (A.n_copy)
       hipLaunchKernelGGL((k_adj_copy_add<Lat::Q, C>), dim3((unsigned)blocks(A.n_copy, 256)), dim3(256),
                          0, s.stream, A.copy_el, A.n_copy, L.n, (const C*)A.copy_tmp, lold);

@@ -161,43 +161,134 @@ __global__ __launch_bounds__(256) void k_seed_drag(const int32_t* __restrict__ b
 }
 
 // ------------------------------------------------- stream-collide reverse --
-// Gathers the tape state, forms mu, and scatters mu_i to the entry the pull
-// read.  COPY links are added by k_adj_copy afterwards.
-template <class Lat, int P>
-__global__ __launch_bounds__(256) void k_adj_sc(
-    const typename Prec<P>::S* __restrict__ X, const int32_t* __restrict__ nbr, int64_t n_act,
-    const LevelArgs<typename Prec<P>::C, Lat::Q> a, const typename Prec<P>::C* __restrict__ lam_new,
-    typename Prec<P>::C* __restrict__ lam_cap, typename Prec<P>::C* __restrict__ lam_old,
-    double* __restrict__ part) {
+// Gathers the tape state, forms mu = (d g*/d g)^T lam* [+ (d rec/d g)^T
+// lam_rec] in streamed passes over the directions (no per-direction
+// temporaries beyond g and lam*), and scatters each mu_i to the entry its
+// pull read.  COPY links are added by k_adj_copy_* around this kernel.
+// REC instantiations cover the tail of the element range, where capture
+// sources (with a record adjoint) and inner ghosts live; the plain
+// instantiation carries no record code and needs fewer registers.
+template <class Lat, int P, bool REC>
+__global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc(
+    const typename Prec<P>::S* __restrict__ X, const int32_t* __restrict__ nbr, int64_t x0,
+    int64_t x1, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+    const typename Prec<P>::C* __restrict__ lam_new, typename Prec<P>::C* __restrict__ lam_cap,
+    typename Prec<P>::C* __restrict__ lam_old, double* __restrict__ part) {
   using C = typename Prec<P>::C;
-  constexpr int Q = Lat::Q, D = Lat::D;
+  constexpr int Q = Lat::Q, D = Lat::D, NS = Lat::NS;
   __shared__ double sm[256];
-  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t x = x0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
   double acc[DPART] = {0, 0, 0, 0, 0};
-  if (x < n_act) {
-    C g[Q], ls[Q], mu[Q];
+  if (x < x1) {
+    C g[Q], ls[Q];
     gather_g<Lat, P>(X, nbr, x, a, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i) ls[i] = lam_new[(int64_t)i * a.n + x];
-    const bool src = x >= a.cap_begin && x < a.n_fluid;
-    C lrec[cap_fneq(D) + Q];
-    if (src) {
-      C* r = lam_cap + (x - a.cap_begin) * cap_stride(D);
+    C drho, rho, u[3];
+    macro_g<Lat, C>(g, a.rho0, drho, rho, u);
+    const C uu = dot_uu<Lat, C>(u);
+    const C om = a.omega;
+    C ldrho = 0, lrho = 0, lu[3] = {0, 0, 0};
+    double dw = 0;
+    // record adjoint (capture sources only)
+    C lr_S[NS], lr_f[Q], pref = 0;
+    bool src = false;
+    if constexpr (REC) {
+      src = x < a.n_fluid;
+      if (src) {
+        C* r = lam_cap + (x - a.cap_begin) * cap_stride(D);
+        ldrho += r[0];
 #pragma unroll
-      for (int c = 0; c < cap_fneq(D) + Q; ++c) {
-        lrec[c] = r[c];
-        r[c] = C(0);  // consumed
+        for (int b = 0; b < D; ++b) lu[b] += r[cap_u(D) + b];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) lr_S[k] = r[cap_s(D) + k];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lr_f[i] = r[cap_fneq(D) + i];
+#pragma unroll
+        for (int c = 0; c < cap_fneq(D) + Q; ++c) r[c] = C(0);  // consumed
+        pref = -C(1.5) * om / rho;
+        // S of the record: lrho and omega contributions
+        C pi[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) pi[k] = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const C fneq = g[i] - geq_i<Lat, C>(i, drho, rho, u, uu);
+#pragma unroll
+          for (int k = 0; k < NS; ++k) {
+            const int cc = Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k));
+            if (cc > 0) pi[k] += fneq;
+            if (cc < 0) pi[k] -= fneq;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const C Sk = pref * pi[k];
+          lrho -= lr_S[k] * Sk / rho;
+          dw += (double)lr_S[k] * (double)Sk / (double)om;
+        }
       }
     }
-    collide_adjoint<Lat, C>(g, ls, src ? lrec : nullptr, a.rho0, a.omega, mu, acc[0]);
-    lam_old[x] = mu[0];
+    auto lf_of = [&](int i) -> C {   // adjoint of g^neq_i through the record
+      C lf = 0;
+      if constexpr (REC) {
+        if (src) {
+          lf = lr_f[i];
+#pragma unroll
+          for (int k = 0; k < NS; ++k) {
+            const int cc = Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k));
+            if (cc > 0) lf += pref * lr_S[k];
+            if (cc < 0) lf -= pref * lr_S[k];
+          }
+        }
+      }
+      return lf;
+    };
+    // pass 1: lambda of g^eq, pulled back to (drho, rho, u)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      C cu = 0;
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        const int ci = Lat::c(i, b);
+        if (ci > 0) cu += u[b];
+        if (ci < 0) cu -= u[b];
+      }
+      const C w = (C)Lat::w(i);
+      const C Pq = C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu;
+      const C geq = w * (drho + rho * Pq);
+      dw += (double)ls[i] * (double)(geq - g[i]);
+      const C wl = w * (om * ls[i] - lf_of(i));
+      ldrho += wl;
+      lrho += wl * Pq;
+#pragma unroll
+      for (int b = 0; b < D; ++b)
+        lu[b] += wl * rho * (C(3) * C(Lat::c(i, b)) + C(9) * cu * C(Lat::c(i, b)) - C(3) * u[b]);
+    }
+    C lj[3] = {0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      lj[b] = lu[b] / rho;
+      lrho -= lu[b] * u[b] / rho;
+    }
+    ldrho += lrho;
+    // pass 2: mu_i, scattered as formed
+    const C om1 = C(1) - om;
+    lam_old[x] = om1 * ls[0] + lf_of(0) + ldrho;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
+      C mu = om1 * ls[i] + lf_of(i) + ldrho;
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        const int ci = Lat::c(i, b);
+        if (ci > 0) mu += lj[b];
+        if (ci < 0) mu -= lj[b];
+      }
       const int32_t v = nbr[(int64_t)(i - 1) * a.ld_nbr + x];
       if (v >= 0) {
-        lam_old[(int64_t)i * a.n + v] = mu[i];
+        lam_old[(int64_t)i * a.n + v] = mu;
       } else if (v == MLBM_NBR_BOUNCE) {
-        lam_old[(int64_t)Lat::opp(i) * a.n + x] = mu[i];
+        lam_old[(int64_t)Lat::opp(i) * a.n + x] = mu;
       } else if (v == MLBM_NBR_EQ) {
         // f_i = f^eq_i(rho0, u_in): d/du_in = w rho0 (3 c + 9 (c.u_in) c - 3 u_in)
         const double w = Lat::w(i);
@@ -206,10 +297,11 @@ __global__ __launch_bounds__(256) void k_adj_sc(
         for (int b = 0; b < D; ++b) cu += Lat::c(i, b) * a.u_in[b];
 #pragma unroll
         for (int b = 0; b < D; ++b)
-          acc[2 + b] += (double)mu[i] * w * (double)a.rho0 *
+          acc[2 + b] += (double)mu * w * (double)a.rho0 *
                         (3.0 * Lat::c(i, b) + 9.0 * cu * Lat::c(i, b) - 3.0 * a.u_in[b]);
       }
     }
+    acc[0] = dw;
   }
   block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
 }

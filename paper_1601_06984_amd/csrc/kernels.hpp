@@ -170,9 +170,10 @@ __device__ __forceinline__ void write_record(R* __restrict__ rec, const C* g, C 
 }
 
 // --------------------------------------------------- stream-collide -------
-// One thread per active element x in [0, n_act); Eq. bgk in g-form, result
-// stored coalesced in the destination array.  Elements of the capture
-// segment also write their pre-collision moments (the interpolation input).  Blocks are remapped so that
+// One thread per element x in [x0, x1); Eq. bgk in g-form, result stored
+// coalesced in the destination array.  The REC instantiation runs over the
+// tail of the element range, whose fluid elements (the capture segment)
+// also write their pre-collision moments (the interpolation input).  Blocks are remapped so that
 // each of the 8 XCDs streams a contiguous slice of the element range.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
   const int64_t q = nb >> 3, r = nb & 7, xcd = b & 7, k = b >> 3;
@@ -191,25 +192,27 @@ __device__ __forceinline__ int64_t xcd_block2(int64_t b, int64_t nb, int64_t nb1
   return nb1 + x * (q - q1) + (x < r ? x : r) - (x < r1 ? x : r1) + (k - cnt1);
 }
 
-template <class Lat, int P, int BS>
+template <class Lat, int P, int BS, bool REC>
 __global__ __launch_bounds__(BS) void k_stream_collide(
     const typename Prec<P>::S* __restrict__ src, typename Prec<P>::S* __restrict__ dst,
-    const int32_t* __restrict__ nbr, int64_t n_act,
+    const int32_t* __restrict__ nbr, int64_t x0, int64_t x1,
     const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C* __restrict__ cap,
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
-  const int64_t blk = xcd_block2(blockIdx.x, gridDim.x, a.cap_begin / BS);
-  const int64_t x = blk * BS + threadIdx.x;
-  if (x >= n_act) return;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t x = x0 + blk * BS + threadIdx.x;
+  if (x >= x1) return;
   C g[Lat::Q];
   gather_g<Lat, P>(src, nbr, x, a, g);
   C drho, rho, u[3];
   macro_g<Lat, C>(g, a.rho0, drho, rho, u);
   const C uu = dot_uu<Lat, C>(u);
   // interpolation sources keep their pre-collision moments
-  if (x >= a.cap_begin && x < a.n_fluid)
-    write_record_m<Lat, C, C>(cap + (x - a.cap_begin) * cap_stride(Lat::D), g, drho, rho, u, uu,
-                              a.omega);
+  if constexpr (REC) {
+    if (x < a.n_fluid)
+      write_record_m<Lat, C, C>(cap + (x - a.cap_begin) * cap_stride(Lat::D), g, drho, rho, u, uu,
+                                a.omega);
+  }
   bool ok = true;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
