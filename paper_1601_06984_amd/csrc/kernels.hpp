@@ -171,9 +171,10 @@ __device__ __forceinline__ void write_record(R* __restrict__ rec, const C* g, C 
 
 // --------------------------------------------------- stream-collide -------
 // One thread per element x in [x0, x1); Eq. bgk in g-form, result stored
-// coalesced in the destination array.  The REC instantiation runs over the
-// tail of the element range, whose fluid elements (the capture segment)
-// also write their pre-collision moments (the interpolation input).  Blocks are remapped so that
+// coalesced in the destination array.  In the REC instantiation the fluid
+// elements of the capture segment also write their pre-collision moments
+// (the interpolation input); it maps the plain range and the tail to XCD
+// slices separately.  Blocks are remapped so that
 // each of the 8 XCDs streams a contiguous slice of the element range.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
   const int64_t q = nb >> 3, r = nb & 7, xcd = b & 7, k = b >> 3;
@@ -199,7 +200,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
     const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C* __restrict__ cap,
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t blk = REC ? xcd_block2(blockIdx.x, gridDim.x, (a.cap_begin - x0) / BS)
+                          : xcd_block(blockIdx.x, gridDim.x);
   const int64_t x = x0 + blk * BS + threadIdx.x;
   if (x >= x1) return;
   C g[Lat::Q];

@@ -45,16 +45,11 @@ struct Impl {
     DevLevel& L = s.lv[k];
     if (n_act <= 0) return;
     auto a = level_args<C, Lat::Q>(s, k);
-    // plain fluid, then the tail (capture sources, inner ghosts)
-    const int64_t cb = std::min<int64_t>(L.n_fluid - L.n_cap_fluid, n_act);
-    if (cb > 0)
-      hipLaunchKernelGGL((k_stream_collide<Lat, P, BS, false>), dim3((unsigned)((cb + BS - 1) / BS)),
-                         dim3(BS), 0, s.stream, (const S*)src, (S*)dst, L.nbr, (int64_t)0, cb, a,
-                         (C*)cap, s.status);
-    if (n_act > cb)
-      hipLaunchKernelGGL((k_stream_collide<Lat, P, BS, true>),
-                         dim3((unsigned)((n_act - cb + BS - 1) / BS)), dim3(BS), 0, s.stream,
-                         (const S*)src, (S*)dst, L.nbr, cb, n_act, a, (C*)cap, s.status);
+    // one launch; the block map balances the plain range and the tail
+    // (capture sources, inner ghosts) over the XCDs
+    hipLaunchKernelGGL((k_stream_collide<Lat, P, BS, true>), dim3((unsigned)((n_act + BS - 1) / BS)),
+                       dim3(BS), 0, s.stream, (const S*)src, (S*)dst, L.nbr, (int64_t)0, n_act, a,
+                       (C*)cap, s.status);
   }
 
   static void fill_gff_ptr(SimState& s, int k, void* pdf, const void* cap_fine, void* cap_coarse) {
