@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc
     C lr_S[NS], lr_f[Q], pref = 0;
     bool src = false;
     if constexpr (REC) {
-      src = x < a.n_fluid;
+      src = x >= a.cap_begin && x < a.n_fluid;
       if (src) {
         C* r = lam_cap + (x - a.cap_begin) * cap_stride(D);
         ldrho += r[0];

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
   const C uu = dot_uu<Lat, C>(u);
   // interpolation sources keep their pre-collision moments
   if constexpr (REC) {
-    if (x < a.n_fluid)
+    if (x >= a.cap_begin && x < a.n_fluid)
       write_record_m<Lat, C, C>(cap + (x - a.cap_begin) * cap_stride(Lat::D), g, drho, rho, u, uu,
                                 a.omega);
   }
