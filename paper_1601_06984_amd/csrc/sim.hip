@@ -82,9 +82,6 @@ void SimState::drop_graphs() {
 SimState::~SimState() {
   drop_graphs();
   for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : fork_ev) (void)hipEventDestroy(e);
-  for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
-  for (hipStream_t t : level_streams) (void)hipStreamDestroy(t);
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }
 
@@ -129,29 +126,6 @@ void advance(SimState& s, int k) {
   }
 }
 
-// Graph-capture variant of advance(): level k runs on stream st[k].  The
-// stream-collide of level k touches only level-k arrays and records, while
-// the two sub-advances of level k+1 touch only finer levels, so they are
-// forked onto st[k+1] and joined before the fills that need both.
-static void advance_forked(SimState& s, int k, const std::vector<hipStream_t>& st) {
-  const bool finer = k + 1 < (int)s.lv.size();
-  if (finer) {
-    (void)hipEventRecord(s.fork_ev[k], st[k]);
-    (void)hipStreamWaitEvent(st[k + 1], s.fork_ev[k], 0);
-  }
-  s.stream = st[k];
-  sc_level(s, k);
-  if (finer) {
-    advance_forked(s, k + 1, st);
-    advance_forked(s, k + 1, st);
-    (void)hipEventRecord(s.join_ev[k], st[k + 1]);
-    (void)hipStreamWaitEvent(st[k], s.join_ev[k], 0);
-    s.stream = st[k];
-    fill_gff(s, k);
-    fill_gfc(s, k + 1);
-  }
-}
-
 static uint64_t parity_key(const SimState& s) {
   uint64_t key = 0;
   for (size_t k = 0; k < s.lv.size() && k < 32; ++k)
@@ -165,33 +139,15 @@ static uint64_t parity_key(const SimState& s) {
 static hipError_t two_step_graph(SimState& s, hipGraphExec_t* exec) {
   hipError_t e = hipSuccess;
   if (!s.capture_stream) e = hipStreamCreateWithFlags(&s.capture_stream, hipStreamNonBlocking);
-  const size_t nlev = s.lv.size();
-  while (e == hipSuccess && s.level_streams.size() + 1 < nlev) {
-    hipStream_t t = nullptr;
-    e = hipStreamCreateWithFlags(&t, hipStreamNonBlocking);
-    if (e == hipSuccess) s.level_streams.push_back(t);
-  }
-  while (e == hipSuccess && s.fork_ev.size() + 1 < nlev) {
-    hipEvent_t a = nullptr, b = nullptr;
-    e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
-    if (e == hipSuccess) {
-      s.fork_ev.push_back(a);
-      s.join_ev.push_back(b);
-    }
-  }
   if (e != hipSuccess) return e;
-  std::vector<hipStream_t> st{s.capture_stream};
-  for (size_t k = 0; k + 1 < nlev; ++k) st.push_back(s.level_streams[k]);
   const hipStream_t user = s.stream;
   std::vector<std::pair<int, int>> saved;
   for (auto& L : s.lv) saved.emplace_back(L.parity, L.substep);
   s.stream = s.capture_stream;
   e = hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    advance_forked(s, 0, st);
-    advance_forked(s, 0, st);
-    s.stream = s.capture_stream;
+    advance(s, 0);
+    advance(s, 0);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s.stream, &graph);
     if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);

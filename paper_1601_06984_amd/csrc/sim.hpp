@@ -97,8 +97,6 @@ struct SimState {
   AdjState adj;
   // graphs of two coarse steps, keyed by the parity state they start from
   hipStream_t capture_stream = nullptr;
-  std::vector<hipStream_t> level_streams;   // fork targets during capture
-  std::vector<hipEvent_t> fork_ev, join_ev;
   bool use_graphs = true;
   std::vector<std::pair<uint64_t, hipGraphExec_t>> graphs;
   void drop_graphs();
