@@ -119,8 +119,16 @@ def timed_steps(torch, sim, steps):
     return e0.elapsed_time(e1)
 
 
-def cpu_baseline(wl, steps):
-    """The FP64 oracle as it stands, on the host, for `steps` coarse steps."""
+def _dir_perm(c_lib, c_oracle):
+    return [int(np.where((c_oracle == c_lib[i]).all(1))[0][0]) for i in range(len(c_lib))]
+
+
+def cpu_baseline(wl, steps, gpu_pdfs=None, lattice=None):
+    """The FP64 oracle as it stands, on the host, for `steps` coarse steps
+    from the workload's initial state.  With `gpu_pdfs` ({precision: list of
+    (treeids, [q][n_fluid] post-collision pdfs) per level}, taken after the
+    same number of steps), also the max relative pdf difference of each
+    precision against the oracle's FP64 result."""
     import torch
     from oracle import mesh as omesh
     from oracle import solver as osolver
@@ -133,28 +141,56 @@ def cpu_baseline(wl, steps):
         r, uu, SS = wl["fields"](pos)
         rho[L], u[L], S[L] = r, uu, SS * 2.0 ** -(L - om.level0)
     sim.init(rho, u, S)
-    sim.step(1)  # warm
     t0 = time.perf_counter()
     sim.step(steps)
     dt = time.perf_counter() - t0
     upd = sum(om.lev(L).n_fluid << (L - om.level0) for L in range(om.level0, om.lmax + 1))
-    return dict(value=upd * steps / dt / 1e6, unit="MLUPS", cores=torch.get_num_threads(),
-                kind="oracle",
-                sample=f"{steps} coarse steps of the same mesh and initial state after one "
-                       f"warm-up step ({dt:.1f} s wall, FP64, torch CPU ops, "
-                       f"{platform.processor() or platform.machine()})")
+    out = dict(value=upd * steps / dt / 1e6, unit="MLUPS", cores=torch.get_num_threads(),
+               kind="oracle",
+               sample=f"{steps} coarse steps of the same mesh from the same initial state "
+                      f"({dt:.1f} s wall, FP64, torch CPU ops, "
+                      f"{platform.processor() or platform.machine()}, "
+                      f"{os.cpu_count()} logical CPUs visible)")
+    if gpu_pdfs:
+        perm = _dir_perm(lattice, np.asarray(sim.lat.c))
+        errs = {}
+        for prec, levels in gpu_pdfs.items():
+            worst = 0.0
+            for k, (tid, g) in enumerate(levels):
+                lev = om.lev(om.level0 + k)
+                ot = np.asarray(lev.tid)
+                order = np.argsort(ot)
+                g2o = order[np.searchsorted(ot[order], tid)]
+                o = sim.post_collision(om.level0 + k).detach().numpy()[perm][:, g2o]
+                worst = max(worst, float((np.abs(g - o) / np.abs(o)).max()))
+            errs[prec] = worst
+        out["max_rel_pdf_err_vs_oracle"] = errs
+    return out
+
+
+def fluid_pdfs(sim, plan):
+    """Per level: (treeIDs, [q][n_fluid] FP64 post-collision pdfs) on the host."""
+    res = []
+    for k in range(plan.n_levels):
+        nf = plan.info[k]["n_fluid"]
+        res.append((plan.export(k, "treeid")[:nf], sim.get_pdf(k)[:, :nf].cpu().numpy()))
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--workload", default="tgv64")
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "f16s"])
     ap.add_argument("--variants", type=int, default=1,
                     help="also time F64/F16S and report the fixed-error study")
-    ap.add_argument("--cpu-steps", type=int, default=15)
+    ap.add_argument("--cpu-steps", type=int, default=100,
+                    help="coarse steps of the oracle (also the accuracy check length)")
+    ap.add_argument("--drag-steps", type=int, default=0,
+                    help="sphere workloads: run this many coarse steps in F32 and F16S "
+                         "from the initial state and report the drag coefficient")
     ap.add_argument("--adjoint", type=int, default=20,
                     help="time this many reverse coarse steps (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -258,16 +294,27 @@ def main():
             "frac": round(adom["gbs"] / HBM_PEAK_GBS, 4),
             "kernels": akern,
         }
+    gpu_pdfs = {}
     if args.variants and wl.get("tgv"):
-        # precision study at a fixed run length: MLUPS and eps_u for each
+        # precision study at a fixed run length: MLUPS and eps_u for each;
+        # the pdfs after `cpu_steps` coarse steps go to the oracle comparison
         study = {}
         n_fix = 1000
+        n_chk = args.cpu_steps if not args.no_cpu else 0
         for p in ("f64", "f32", "f16s"):
             print(f"[bench] precision study {p}", file=sys.stderr, flush=True)
             s2 = make_sim(M, torch, wl, plan, p)
-            s2.step(20)
-            t_ms = timed_steps(torch, s2, n_fix - 20)
-            study[p] = dict(mlups=round(upd * (n_fix - 20) / (t_ms / 1e3) / 1e6, 1),
+            if 0 < n_chk <= n_fix - 20:
+                s2.step(n_chk)
+                gpu_pdfs[p] = fluid_pdfs(s2, plan)
+                if n_chk < 20:
+                    s2.step(20 - n_chk)
+                done = max(n_chk, 20)
+            else:
+                s2.step(20)
+                done = 20
+            t_ms = timed_steps(torch, s2, n_fix - done)
+            study[p] = dict(mlups=round(upd * (n_fix - done) / (t_ms / 1e3) / 1e6, 1),
                             eps_u=tgv_velocity_error(s2, plan, wl, n_fix),
                             status=s2.status())
             del s2
@@ -275,6 +322,31 @@ def main():
         for p in study:
             study[p]["fixed_error_pass"] = bool(study[p]["eps_u"] <= 1.05 * ref)
         out["precision_study"] = {"coarse_steps": n_fix, "results": study}
+    if args.drag_steps and not wl.get("tgv"):
+        D = wl["spec"].meta["D"]
+        uin = wl["u_in"][0]
+        drag = {}
+        for p in ("f32", "f16s"):
+            print(f"[bench] drag run {p}: {args.drag_steps} coarse steps", file=sys.stderr,
+                  flush=True)
+            s3 = make_sim(M, torch, wl, plan, p)
+            hist = []
+            chunk = max(1, args.drag_steps // 10)
+            t_ms = 0.0
+            done = 0
+            while done < args.drag_steps:
+                m = min(chunk, args.drag_steps - done)
+                t_ms += timed_steps(torch, s3, m)
+                done += m
+                fx = float(s3.diagnostics(M.DIAG_FORCE)[0])
+                hist.append((done, round(2.0 * fx / (uin ** 2 * math.pi * D * D / 4.0), 5)))
+            drag[p] = dict(c_d=hist[-1][1], c_d_history=hist,
+                           mlups=round(upd * args.drag_steps / (t_ms / 1e3) / 1e6, 1),
+                           status=s3.status())
+            del s3
+        out["drag"] = {"coarse_steps": args.drag_steps, "D_finest": D, "u_in": uin,
+                       "definition": "c_D = 2 F_x / (rho0 u_in^2 pi D^2 / 4), finest-level units",
+                       "results": drag}
     if args.copy_ceiling:
         # practical streaming ceiling of this device: a plain 2 GiB copy
         n = 2 << 30
@@ -300,7 +372,13 @@ def main():
         out["calib_copy_bytes"] = n
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+        c, _ = M.lattice(plan.stencil)
+        cb = cpu_baseline(wl, args.cpu_steps, gpu_pdfs, np.asarray(c))
+        errs = cb.pop("max_rel_pdf_err_vs_oracle", None)
+        if errs and "precision_study" in out:
+            for p, e in errs.items():
+                out["precision_study"]["results"][p][f"max_rel_pdf_err_vs_oracle_{args.cpu_steps}"] = e
+        out["cpu_baseline"] = cb
     print(json.dumps(out))
 
 

@@ -172,7 +172,7 @@ struct Adj {
                        ng, A.gfc_slot, A.gfc_oct, (const C*)cap_coarse, lam, L.n, (C*)A.T,
                        (C)L.omega, (C)Cl.omega, (C)s.rho0, s.adj.part + off * DPART);
     off += nb;
-    constexpr int W = cap_fneq(Lat::D) + Lat::Q;
+    constexpr int W = cap_used(Lat::D);
     const int64_t work = Cl.n_cap * W;
     hipLaunchKernelGGL((k_adj_gfc_gather<Lat, C>), dim3((unsigned)blocks(work, 256)), dim3(256), 0,
                        s.stream, A.csr_ptr, A.csr_ent, Cl.n_cap, (const C*)A.T,
@@ -214,24 +214,23 @@ struct Adj {
                          (const C*)lnew, (const C*)A.lam_cap, (C*)A.copy_tmp);
     const int64_t cb = L.n_fluid - L.n_cap_fluid;   // plain fluid [0, cb)
     const int64_t nb1 = blocks(cb, 256), nb2 = blocks(n_act - cb, 256);
+    // profiling: the first launch records the start, the last the end
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (s.prof.on) {
+    if (s.prof.on && nb1 + nb2 > 0) {
       e0 = prof_event(s);
       e1 = prof_event(s);
-      if (e0 && e1) (void)hipEventRecord(e0, s.stream);
     }
+    const bool ev = e0 && e1;
     if (nb1)
-      hipLaunchKernelGGL((k_adj_sc<Lat, P, false>), dim3((unsigned)nb1), dim3(256), 0, s.stream,
-                         (const S*)X, L.nbr, (int64_t)0, cb, a, (const C*)lnew, (C*)A.lam_cap, lold,
-                         s.adj.part + off * DPART);
+      launch_timed(k_adj_sc<Lat, P, false>, dim3((unsigned)nb1), dim3(256), s.stream,
+                   ev ? e0 : nullptr, (ev && !nb2) ? e1 : nullptr, (const S*)X, (const int*)L.nbr,
+                   (int64_t)0, cb, a, (const C*)lnew, (C*)A.lam_cap, lold, s.adj.part + off * DPART);
     if (nb2)
-      hipLaunchKernelGGL((k_adj_sc<Lat, P, true>), dim3((unsigned)nb2), dim3(256), 0, s.stream,
-                         (const S*)X, L.nbr, cb, n_act, a, (const C*)lnew, (C*)A.lam_cap, lold,
-                         s.adj.part + (off + nb1) * DPART);
-    if (s.prof.on && e0 && e1) {
-      (void)hipEventRecord(e1, s.stream);
-      s.prof.rec.push_back({1, k, n_act, e0, e1});
-    }
+      launch_timed(k_adj_sc<Lat, P, true>, dim3((unsigned)nb2), dim3(256), s.stream,
+                   (ev && !nb1) ? e0 : nullptr, ev ? e1 : nullptr, (const S*)X, (const int*)L.nbr,
+                   cb, n_act, a, (const C*)lnew, (C*)A.lam_cap, lold,
+                   s.adj.part + (off + nb1) * DPART);
+    if (ev) s.prof.rec.push_back({1, k, n_act, e0, e1});
     off += nb1 + nb2;
     if (A.n_copy)
       hipLaunchKernelGGL((k_adj_copy_add<Lat::Q, C>), dim3((unsigned)blocks(A.n_copy, 256)), dim3(256),

@@ -90,7 +90,7 @@ __device__ __forceinline__ void collide_adjoint(const C* g, const C* ls, const C
       lg[i] += lf;
       lgeq[i] -= lf;
     }
-    ldrho += lrec[0];
+    ldrho += lrec[cap_rho(D)];
 #pragma unroll
     for (int a = 0; a < D; ++a) lu[a] += lrec[cap_u(D) + a];
   }
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc
       src = x >= a.cap_begin && x < a.n_fluid;
       if (src) {
         C* r = lam_cap + (x - a.cap_begin) * cap_stride(D);
-        ldrho += r[0];
+        ldrho += r[cap_rho(D)];
 #pragma unroll
         for (int b = 0; b < D; ++b) lu[b] += r[cap_u(D) + b];
 #pragma unroll
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc
 #pragma unroll
         for (int i = 0; i < Q; ++i) lr_f[i] = r[cap_fneq(D) + i];
 #pragma unroll
-        for (int c = 0; c < cap_fneq(D) + Q; ++c) r[c] = C(0);  // consumed
+        for (int c = 0; c < cap_used(D); ++c) r[c] = C(0);  // consumed
         pref = -C(1.5) * om / rho;
         // S of the record: lrho and omega contributions
         C pi[NS];
@@ -490,7 +490,7 @@ __device__ __forceinline__ void ghost_adjoint(const C* const* rec, const C* beta
   const C* S[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    drho += beta[k] * rec[k][0];
+    drho += beta[k] * rec[k][cap_rho(D)];
 #pragma unroll
     for (int b = 0; b < D; ++b) u[b] += beta[k] * rec[k][cap_u(D) + b];
     S[k] = rec[k] + cap_s(D);
@@ -535,7 +535,7 @@ __device__ __forceinline__ void ghost_adjoint(const C* const* rec, const C* beta
         lf += pref * C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * lrec[cap_s(D) + k];
       lfneq[i] += lf;
     }
-    ldrho += lrec[0];
+    ldrho += lrec[cap_rho(D)];
 #pragma unroll
     for (int b = 0; b < D; ++b) lu[b] += lrec[cap_u(D) + b];
   }
@@ -558,7 +558,7 @@ __device__ __forceinline__ void ghost_adjoint(const C* const* rec, const C* beta
   strain_terms_adjoint<D, C>(lu, sx, sy, sz, wd, wc, lS);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    lsrc[k][0] = beta[k] * ldrho;
+    lsrc[k][cap_rho(D)] = beta[k] * ldrho;
 #pragma unroll
     for (int b = 0; b < D; ++b) lsrc[k][cap_u(D) + b] = beta[k] * lu[b];
 #pragma unroll
@@ -595,9 +595,9 @@ __global__ __launch_bounds__(64) void k_adj_gff(
 #pragma unroll
     for (int i = 0; i < Q; ++i) lgs[i] = lam[(int64_t)i * n + gff_begin + j];
     C* lr = lam_cap_coarse + (cap_gff_begin + j) * cap_stride(D);
-    C lrec[cap_fneq(D) + Q];
+    C lrec[cap_used(D)];
 #pragma unroll
-    for (int c = 0; c < cap_fneq(D) + Q; ++c) {
+    for (int c = 0; c < cap_used(D); ++c) {
       lrec[c] = lr[c];
       lr[c] = C(0);
     }
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(64) void k_adj_gff(
     for (int k = 0; k < 4; ++k) {
       C* dst = lam_cap_fine + (int64_t)sl[k] * cap_stride(D);
 #pragma unroll
-      for (int c = 0; c < cap_fneq(D) + Q; ++c) dst[c] += lsrc[k][c];
+      for (int c = 0; c < cap_used(D); ++c) dst[c] += lsrc[k][c];
     }
   }
   block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(64) void k_adj_gfc(
     for (int k = 0; k < 4; ++k) {
       C* dst = T + (j * 4 + k) * cap_stride(D);
 #pragma unroll
-      for (int c = 0; c < cap_fneq(D) + Q; ++c) dst[c] = lsrc[k][c];
+      for (int c = 0; c < cap_used(D); ++c) dst[c] = lsrc[k][c];
     }
   }
   block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
@@ -667,7 +667,7 @@ __global__ __launch_bounds__(256) void k_adj_gfc_gather(const int32_t* __restric
                                                         int64_t n_slots, const C* __restrict__ T,
                                                         C* __restrict__ lam_cap) {
   constexpr int D = Lat::D;
-  constexpr int W = cap_fneq(D) + Lat::Q;
+  constexpr int W = cap_used(D);
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t s = t / W, c = t % W;
   if (s >= n_slots) return;
@@ -700,11 +700,11 @@ __global__ __launch_bounds__(256) void k_adj_init(
       ls[i] = lam[(int64_t)i * a.n + x];
     }
     const bool src = x >= a.cap_begin;
-    C lrec[cap_fneq(D) + Q];
+    C lrec[cap_used(D)];
     if (src) {
       C* r = lam_cap + (x - a.cap_begin) * cap_stride(D);
 #pragma unroll
-      for (int c = 0; c < cap_fneq(D) + Q; ++c) {
+      for (int c = 0; c < cap_used(D); ++c) {
         lrec[c] = r[c];
         r[c] = C(0);
       }

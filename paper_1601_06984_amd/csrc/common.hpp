@@ -66,11 +66,40 @@ MLBM_HD constexpr int strain_b(int d, int k) {
 inline int stencil_q(int stencil) { return stencil == MLBM_D2Q9 ? 9 : 19; }
 inline int stencil_d(int stencil) { return stencil == MLBM_D2Q9 ? 2 : 3; }
 
-// Capture record: rho, u (d), S (NS), f^neq (q), padded to a power of two.
+// Work-group order.  Consecutive work-groups of a launch go to the 8 XCDs in
+// turn (dispatch position b runs on XCD b mod 8), and each XCD has its own
+// L2.  xcd_block maps dispatch position b of nb to a logical block so that
+// every XCD streams one contiguous slice of the range.
+MLBM_HD inline int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb >> 3, r = nb & 7, xcd = b & 7, k = b >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+// Two-range variant: logical blocks [0, nb1) (plain fluid) and [nb1, nb)
+// (capture sources and ghosts, which do more work per element) are each
+// split into contiguous per-XCD slices.  Every XCD runs its share of the
+// heavier tail first, so the slow blocks overlap the streaming of the plain
+// ones instead of trailing behind them.  A bijection of [0, nb) for any
+// 0 <= nb1 <= nb.
+MLBM_HD inline int64_t xcd_block2(int64_t b, int64_t nb, int64_t nb1) {
+  const int64_t x = b & 7, k = b >> 3;
+  const int64_t q = nb >> 3, r = nb & 7, q1 = nb1 >> 3, r1 = nb1 & 7;
+  const int64_t cnt = q + (x < r ? 1 : 0);          // positions on XCD x
+  const int64_t cnt1 = q1 + (x < r1 ? 1 : 0);       // its plain blocks
+  const int64_t cnt2 = cnt - cnt1;                  // its tail blocks
+  if (k < cnt2) return nb1 + x * (q - q1) + (x < r ? x : r) - (x < r1 ? x : r1) + k;
+  return x * q1 + (x < r1 ? x : r1) + (k - cnt2);
+}
+
+// Capture record: f^neq (q), drho, u (d), S (NS), padded to a power of two
+// (3D FP32: one 128-byte line).  f^neq and drho come first so that the q+1
+// values formed in the collide loop fill whole 16-byte chunks.
 MLBM_HD constexpr int cap_stride(int d) { return d == 3 ? 32 : 16; }
-MLBM_HD constexpr int cap_u(int) { return 1; }
-MLBM_HD constexpr int cap_s(int d) { return 1 + d; }
-MLBM_HD constexpr int cap_fneq(int d) { return d == 3 ? 10 : 6; }
+MLBM_HD constexpr int cap_fneq(int) { return 0; }
+MLBM_HD constexpr int cap_rho(int d) { return d == 3 ? 19 : 9; }
+MLBM_HD constexpr int cap_u(int d) { return cap_rho(d) + 1; }
+MLBM_HD constexpr int cap_s(int d) { return cap_u(d) + d; }
+MLBM_HD constexpr int cap_used(int d) { return cap_s(d) + (d == 3 ? 6 : 3); }
 
 // Neighbourhood slots of a GhostFromCoarser parent group: 3D uses the
 // parent and its 12 edge neighbours, 2D the parent and its 8 neighbours.

@@ -10,6 +10,7 @@
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "common.hpp"
 
@@ -133,12 +134,38 @@ __device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__
   }
 }
 
-// Pre-collision moments of a g-vector into a capture record:
-// drho, u, S_ab = -(3 omega / (2 rho)) sum_i c_ia c_ib g^neq_i, g^neq.
-template <class Lat, class C, class R>
-__device__ __forceinline__ void write_record_m(R* __restrict__ rec, const C* g, C drho, C rho,
-                                               const C* u, C uu, C omega) {
-  // streamed: each g^neq_i is written and folded into the second moments
+// Writes the values of one record in slot order with 16-byte stores: each
+// put(c, v) must come in increasing c starting from 0; a chunk is stored as
+// soon as it is full, and finish() zero-pads and stores the last one.  The
+// record base is 16-byte aligned (records start at multiples of 64 bytes).
+template <class R>
+struct RecordWriter {
+  static constexpr int V = 16 / (int)sizeof(R);
+  typedef R VT __attribute__((ext_vector_type(16 / sizeof(R))));
+  R* __restrict__ p;
+  VT buf;
+  __device__ __forceinline__ void put(int c, R v) {
+    buf[c % V] = v;
+    if (c % V == V - 1) *reinterpret_cast<VT*>(p + (c - (V - 1))) = buf;
+  }
+  __device__ __forceinline__ void finish(int used) {
+    if (used % V) {
+#pragma unroll
+      for (int c = used % V; c < V; ++c) buf[c] = R(0);
+      *reinterpret_cast<VT*>(p + (used - used % V)) = buf;
+    }
+  }
+};
+
+// The values of a capture record in slot order: g^neq, drho, u,
+// S_ab = -(3 omega / (2 rho)) sum_i c_ia c_ib g^neq_i, handed to a writer
+// (RecordWriter or WaveRecordStager) one slot at a time.
+template <class Lat, class C, class Wr>
+__device__ __forceinline__ void record_values(Wr& w, const C* g, C drho, C rho, const C* u, C uu,
+                                              C omega) {
+  constexpr int D = Lat::D;
+  static_assert(cap_fneq(D) == 0 && cap_rho(D) == Lat::Q, "record layout");
+  // streamed: each g^neq_i is handed on and folded into the second moments
   // as it is formed, so no per-direction array stays live
   C pi[Lat::NS];
 #pragma unroll
@@ -146,21 +173,81 @@ __device__ __forceinline__ void write_record_m(R* __restrict__ rec, const C* g, 
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const C fneq = g[i] - geq_i<Lat, C>(i, drho, rho, u, uu);
-    rec[cap_fneq(Lat::D) + i] = (R)fneq;
+    w.put(cap_fneq(D) + i, fneq);
 #pragma unroll
     for (int k = 0; k < Lat::NS; ++k) {
-      const int cc = Lat::c(i, strain_a(Lat::D, k)) * Lat::c(i, strain_b(Lat::D, k));
+      const int cc = Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k));
       if (cc > 0) pi[k] += fneq;
       if (cc < 0) pi[k] -= fneq;
     }
   }
-  rec[0] = (R)drho;
+  w.put(cap_rho(D), drho);
 #pragma unroll
-  for (int a = 0; a < Lat::D; ++a) rec[cap_u(Lat::D) + a] = (R)u[a];
+  for (int a = 0; a < D; ++a) w.put(cap_u(D) + a, u[a]);
   const C pref = -C(1.5) * omega / rho;
 #pragma unroll
-  for (int k = 0; k < Lat::NS; ++k) rec[cap_s(Lat::D) + k] = (R)(pref * pi[k]);
+  for (int k = 0; k < Lat::NS; ++k) w.put(cap_s(D) + k, pref * pi[k]);
+  w.finish(cap_used(D));
 }
+
+template <class Lat, class C, class R>
+__device__ __forceinline__ void write_record_m(R* __restrict__ rec, const C* g, C drho, C rho,
+                                               const C* u, C uu, C omega) {
+  RecordWriter<R> w{rec, {}};   // values rounded to the record type
+  record_values<Lat, C>(w, g, drho, rho, u, uu, omega);
+}
+
+// Capture records of a whole wavefront, staged through LDS.  Each record is
+// written in phases of 64 bytes: the lanes put their values of the phase
+// into their LDS rows, then the wave stores the phase of all its source
+// records with 16-byte stores, four consecutive lanes covering one record's
+// 64 contiguous bytes (instead of every lane's stores touching 64 lines).
+// All 64 lanes call put/finish together (wave-uniform control flow); bit r
+// of `mask` marks lane r as a source, whose record is rbase + r.  LDS ops of
+// one wave complete in order; the wavefront fences keep the compiler from
+// moving them across the phase boundary.
+template <class C, int ST>
+struct WaveRecordStager {
+  static constexpr int V = 16 / (int)sizeof(C);   // values per 16-byte chunk
+  static constexpr int PH = 64 / (int)sizeof(C);  // values per phase
+  static constexpr int RS = PH + V;               // LDS row stride, 16-byte aligned
+  static constexpr int LDS_PER_WAVE = 64 * RS;    // values
+  static_assert(ST % PH == 0, "record stride");
+  typedef C VT __attribute__((ext_vector_type(16 / sizeof(C))));
+  C* __restrict__ lds;   // this wave's 64 rows
+  C* __restrict__ cap;   // record array
+  int64_t rbase;         // record index of lane 0 (only used for set bits)
+  uint64_t mask;
+  int lane;
+  VT buf;
+  __device__ __forceinline__ void put(int c, C v) {
+    buf[c % V] = v;
+    if (c % V == V - 1) {
+      *reinterpret_cast<VT*>(lds + lane * RS + (c % PH) - (V - 1)) = buf;
+      if (c % PH == PH - 1) flush(c - (PH - 1));
+    }
+  }
+  __device__ __forceinline__ void flush(int c0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {          // 64 records x 4 chunks of 16 bytes
+      const int q = t * 64 + lane, r = q >> 2, ch = q & 3;
+      if ((mask >> r) & 1ull) {
+        const VT v = *reinterpret_cast<const VT*>(lds + r * RS + ch * V);
+        *reinterpret_cast<VT*>(cap + (rbase + r) * ST + c0 + ch * V) = v;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __device__ __forceinline__ void finish(int used) {
+#pragma unroll
+    for (int c = used; c < (used + PH - 1) / PH * PH; ++c) put(c, C(0));
+  }
+};
 
 template <class Lat, class C, class R>
 __device__ __forceinline__ void write_record(R* __restrict__ rec, const C* g, C rho0, C omega) {
@@ -173,24 +260,18 @@ __device__ __forceinline__ void write_record(R* __restrict__ rec, const C* g, C 
 // One thread per element x in [x0, x1); Eq. bgk in g-form, result stored
 // coalesced in the destination array.  In the REC instantiation the fluid
 // elements of the capture segment also write their pre-collision moments
-// (the interpolation input); it maps the plain range and the tail to XCD
-// slices separately.  Blocks are remapped so that
-// each of the 8 XCDs streams a contiguous slice of the element range.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
-  const int64_t q = nb >> 3, r = nb & 7, xcd = b & 7, k = b >> 3;
-  return xcd * q + (xcd < r ? xcd : r) + k;
-}
+// (the interpolation input).  Blocks are remapped (xcd_block, xcd_block2)
+// so that each of the 8 XCDs streams contiguous slices of the element range.
 
-// Two-range variant: logical blocks [0, nb1) (plain fluid) and [nb1, nb)
-// (capture sources and ghosts, which do more work per element) are each
-// split into 8 contiguous slices, one per XCD, so every XCD gets the same
-// share of both ranges; within an XCD the plain slice is dispatched first.
-__device__ __forceinline__ int64_t xcd_block2(int64_t b, int64_t nb, int64_t nb1) {
-  const int64_t x = b & 7, k = b >> 3;
-  const int64_t q = nb >> 3, r = nb & 7, q1 = nb1 >> 3, r1 = nb1 & 7;
-  const int64_t cnt1 = q1 + (x < r1 ? 1 : 0);
-  if (k < cnt1) return x * q1 + (x < r1 ? x : r1) + k;
-  return nb1 + x * (q - q1) + (x < r ? x : r) - (x < r1 ? x : r1) + (k - cnt1);
+// Launch on `st`.  With events, they take the kernel's own dispatch start
+// and end timestamps (no extra packets between kernels).
+template <typename... KArgs, typename... Args>
+inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t st,
+                         hipEvent_t e0, hipEvent_t e1, Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0u, static_cast<KArgs>(args)...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, static_cast<KArgs>(args)...);
 }
 
 template <class Lat, int P, int BS, bool REC>
@@ -200,10 +281,18 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
     const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C* __restrict__ cap,
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
+  using Stager = WaveRecordStager<C, cap_stride(Lat::D)>;
+  static_assert(BS % 64 == 0, "whole wavefronts");
   const int64_t blk = REC ? xcd_block2(blockIdx.x, gridDim.x, (a.cap_begin - x0) / BS)
                           : xcd_block(blockIdx.x, gridDim.x);
-  const int64_t x = x0 + blk * BS + threadIdx.x;
-  if (x >= x1) return;
+  const int64_t xr = x0 + blk * BS + threadIdx.x;
+  const bool valid = xr < x1;
+  if constexpr (!REC) {
+    if (!valid) return;
+  }
+  // lanes past the end recompute the last element (in bounds) and store
+  // nothing; the record staging needs every lane of the wave
+  const int64_t x = valid ? xr : x1 - 1;
   C g[Lat::Q];
   gather_g<Lat, P>(src, nbr, x, a, g);
   C drho, rho, u[3];
@@ -211,9 +300,16 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
   const C uu = dot_uu<Lat, C>(u);
   // interpolation sources keep their pre-collision moments
   if constexpr (REC) {
-    if (x >= a.cap_begin && x < a.n_fluid)
-      write_record_m<Lat, C, C>(cap + (x - a.cap_begin) * cap_stride(Lat::D), g, drho, rho, u, uu,
-                                a.omega);
+    __shared__ C stage[(BS / 64) * Stager::LDS_PER_WAVE];
+    const bool is_src = valid && x >= a.cap_begin && x < a.n_fluid;
+    const uint64_t m = __ballot(is_src);
+    if (m) {   // wave-uniform
+      const int lane = threadIdx.x & 63;
+      Stager w{stage + (threadIdx.x >> 6) * Stager::LDS_PER_WAVE, cap,
+               (xr - lane) - a.cap_begin, m, lane, {}};
+      record_values<Lat, C>(w, g, drho, rho, u, uu, a.omega);
+    }
+    if (!valid) return;
   }
   bool ok = true;
 #pragma unroll
@@ -232,7 +328,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
 template <class Lat, class C>
 struct Rec {
   const C* p;
-  __device__ C drho() const { return p[0]; }
+  __device__ C drho() const { return p[cap_rho(Lat::D)]; }
   __device__ C u(int a) const { return p[cap_u(Lat::D) + a]; }
   __device__ C S(int k) const { return p[cap_s(Lat::D) + k]; }
   __device__ C fneq(int i) const { return p[cap_fneq(Lat::D) + i]; }
@@ -319,11 +415,13 @@ __global__ __launch_bounds__(64) void k_fill_gff(
     fneq[i] = C(0.25) * (r[0].fneq(i) + r[1].fneq(i) + r[2].fneq(i) + r[3].fneq(i)) * fneq_scale;
   const bool ok = emit_ghost<Lat, P>(pdf, gff_begin + j, a, drho, u, fneq);
   // pre-collision record of the ghost: it is a GhostFromCoarser source
-  C* rec = cap_coarse + (cap_gff_begin + j) * cap_stride(D);
+  RecordWriter<C> w{cap_coarse + (cap_gff_begin + j) * cap_stride(D), {}};
   const C rho = a.rho0 + drho;
-  rec[0] = drho;
 #pragma unroll
-  for (int b = 0; b < D; ++b) rec[cap_u(D) + b] = u[b];
+  for (int i = 0; i < Lat::Q; ++i) w.put(cap_fneq(D) + i, fneq[i]);
+  w.put(cap_rho(D), drho);
+#pragma unroll
+  for (int b = 0; b < D; ++b) w.put(cap_u(D) + b, u[b]);
   const C pref = -C(1.5) * a.omega / rho;
 #pragma unroll
   for (int k = 0; k < Lat::NS; ++k) {
@@ -335,10 +433,9 @@ __global__ __launch_bounds__(64) void k_fill_gff(
       if (cc > 0) s += fneq[i];
       if (cc < 0) s -= fneq[i];
     }
-    rec[cap_s(D) + k] = pref * s;
+    w.put(cap_s(D) + k, pref * s);
   }
-#pragma unroll
-  for (int i = 0; i < Lat::Q; ++i) rec[cap_fneq(D) + i] = fneq[i];
+  w.finish(cap_used(D));
   if (!ok) atomicOr(status, (uint32_t)MLBM_STATUS_F16_OVERFLOW);
 }
 
@@ -360,7 +457,7 @@ __global__ __launch_bounds__(64) void k_fill_gfc(
   constexpr int NB = group_slots(D), NC = group_children(D);
   constexpr int GPB = 64 / NC;
   constexpr int ST = cap_stride(D);
-  constexpr int USED = cap_fneq(D) + Lat::Q;   // components actually read
+  constexpr int USED = cap_used(D);            // components actually read
   constexpr int LST = USED | 1;                // odd LDS stride: no bank conflicts
   __shared__ C sh[GPB * NB * LST];
   const int64_t g0 = (int64_t)blockIdx.x * GPB;

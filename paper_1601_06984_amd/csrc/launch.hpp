@@ -47,9 +47,9 @@ struct Impl {
     auto a = level_args<C, Lat::Q>(s, k);
     // one launch; the block map balances the plain range and the tail
     // (capture sources, inner ghosts) over the XCDs
-    hipLaunchKernelGGL((k_stream_collide<Lat, P, BS, true>), dim3((unsigned)((n_act + BS - 1) / BS)),
-                       dim3(BS), 0, s.stream, (const S*)src, (S*)dst, L.nbr, (int64_t)0, n_act, a,
-                       (C*)cap, s.status);
+    launch_timed(k_stream_collide<Lat, P, BS, true>, dim3((unsigned)((n_act + BS - 1) / BS)),
+                 dim3(BS), s.stream, s.launch_ev[0], s.launch_ev[1], (const S*)src, (S*)dst,
+                 (const int*)L.nbr, (int64_t)0, n_act, a, (C*)cap, s.status);
   }
 
   static void fill_gff_ptr(SimState& s, int k, void* pdf, const void* cap_fine, void* cap_coarse) {

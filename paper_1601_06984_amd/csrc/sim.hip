@@ -99,16 +99,17 @@ void sc_level(SimState& s, int k) {
   const bool first = (k > 0) && (L.substep == 0);
   const int64_t n_act = L.n_fluid + (first ? L.n_inner : 0);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (s.prof.on) {
+  if (s.prof.on && n_act > 0) {
     e0 = prof_event(s);
     e1 = prof_event(s);
-    if (e0 && e1) (void)hipEventRecord(e0, s.stream);
+    if (e0 && e1) {
+      s.launch_ev[0] = e0;
+      s.launch_ev[1] = e1;
+    }
   }
   MLBM_DISPATCH(s, I::stream_collide(s, k, n_act));
-  if (s.prof.on && e0 && e1) {
-    (void)hipEventRecord(e1, s.stream);
-    s.prof.rec.push_back({0, k, n_act, e0, e1});
-  }
+  s.launch_ev[0] = s.launch_ev[1] = nullptr;
+  if (s.prof.on && e0 && e1) s.prof.rec.push_back({0, k, n_act, e0, e1});
   L.parity ^= 1;
   if (k > 0) L.substep ^= 1;
 }

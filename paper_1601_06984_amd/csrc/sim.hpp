@@ -94,6 +94,9 @@ struct SimState {
   bool filled = false;
   int64_t time = 0;
   Profiler prof;
+  // when set, the next stream-collide launch records these events with its
+  // own dispatch timestamps (start, stop)
+  hipEvent_t launch_ev[2] = {nullptr, nullptr};
   AdjState adj;
   // graphs of two coarse steps, keyed by the parity state they start from
   hipStream_t capture_stream = nullptr;
