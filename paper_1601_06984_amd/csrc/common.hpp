@@ -66,6 +66,14 @@ MLBM_HD constexpr int strain_b(int d, int k) {
 inline int stencil_q(int stencil) { return stencil == MLBM_D2Q9 ? 9 : 19; }
 inline int stencil_d(int stencil) { return stencil == MLBM_D2Q9 ? 2 : 3; }
 
+// Opposite directions carry equal weights (true of every symmetric lattice).
+template <class Lat>
+MLBM_HD constexpr bool opposite_weights_equal() {
+  for (int i = 0; i < Lat::Q; ++i)
+    if (Lat::w(i) != Lat::w(Lat::opp(i))) return false;
+  return true;
+}
+
 // Work-group order.  Consecutive work-groups of a launch go to the 8 XCDs in
 // turn (dispatch position b runs on XCD b mod 8), and each XCD has its own
 // L2.  xcd_block maps dispatch position b of nb to a logical block so that

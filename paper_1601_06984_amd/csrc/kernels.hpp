@@ -51,6 +51,78 @@ __device__ __forceinline__ bool store_g(typename Prec<P>::S* __restrict__ p, int
   }
 }
 
+// Row access through buffer instructions: a wave-uniform row start and
+// length give a scalar buffer descriptor, each lane supplies a 32-bit byte
+// offset (no 64-bit address arithmetic per lane), and the hardware drops
+// stores and zeroes loads outside the row.  Rows stay below 4 GiB (checked
+// at sim_create).  0x00020000 is the gfx9-family descriptor word 3 for
+// untyped 32-bit data.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* row, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(row), (short)0, (int)(uint32_t)bytes,
+                                           0x00020000);
+}
+
+__device__ __forceinline__ int32_t load_idx(const int32_t* row, int64_t len, uint32_t e) {
+  return __builtin_amdgcn_raw_buffer_load_b32(row_rsrc(row, len * 4), (int)(e * 4u), 0, 0);
+}
+
+template <class S>
+__device__ __forceinline__ S load_elem(const S* row, int64_t len, uint32_t e) {
+  const auto r = row_rsrc(row, len * (int64_t)sizeof(S));
+  const int off = (int)(e * (uint32_t)sizeof(S));
+  if constexpr (sizeof(S) == 8)
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else if constexpr (sizeof(S) == 4)
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+
+template <class S>
+__device__ __forceinline__ void store_elem(S* row, int64_t len, uint32_t e, S v) {
+  const auto r = row_rsrc(row, len * (int64_t)sizeof(S));
+  const int off = (int)(e * (uint32_t)sizeof(S));
+  if constexpr (sizeof(S) == 8) {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, off, 0, 0);
+  } else if constexpr (sizeof(S) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, off, 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(short, v), r, off, 0, 0);
+  }
+}
+
+template <int P>
+__device__ __forceinline__ typename Prec<P>::C load_row(const typename Prec<P>::S* __restrict__ row,
+                                                        int64_t len, uint32_t e,
+                                                        typename Prec<P>::C wr,
+                                                        typename Prec<P>::C inv_scale) {
+  if constexpr (P == MLBM_F16S) {
+    (void)wr;
+    return __half2float(load_elem(row, len, e)) * inv_scale;
+  } else {
+    (void)inv_scale;
+    return (typename Prec<P>::C)load_elem(row, len, e) - wr;
+  }
+}
+
+template <int P>
+__device__ __forceinline__ bool store_row(typename Prec<P>::S* __restrict__ row, int64_t len,
+                                          uint32_t e, typename Prec<P>::C g,
+                                          typename Prec<P>::C wr, typename Prec<P>::C scale) {
+  using S = typename Prec<P>::S;
+  if constexpr (P == MLBM_F16S) {
+    (void)wr;
+    const float h = g * scale;
+    store_elem(row, len, e, __float2half_rn(h));
+    return fabsf(h) <= 65504.0f;
+  } else {
+    (void)scale;
+    store_elem(row, len, e, (S)(wr + g));
+    return true;
+  }
+}
+
 // Per-level parameters passed by value.
 template <class C, int Q>
 struct LevelArgs {
@@ -118,16 +190,25 @@ __device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__
                                          const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
                                          typename Prec<P>::C* g) {
   using C = typename Prec<P>::C;
+  const uint32_t xo = (uint32_t)x;
   int32_t j[Lat::Q];
 #pragma unroll
-  for (int i = 1; i < Lat::Q; ++i) j[i] = nbr[(int64_t)(i - 1) * a.ld_nbr + x];
-  g[0] = load_g<P>(src, x, a.wr[0], a.inv_scale);
+  for (int i = 1; i < Lat::Q; ++i) j[i] = load_idx(nbr + (int64_t)(i - 1) * a.ld_nbr, a.ld_nbr, xo);
+  static_assert(opposite_weights_equal<Lat>(), "w(opp(i)) == w(i)");
+  g[0] = load_row<P>(src, a.n, xo, a.wr[0], a.inv_scale);
+  const uint32_t nn = (uint32_t)a.n;
 #pragma unroll
   for (int i = 1; i < Lat::Q; ++i) {
+    // rows 2k-1 and 2k hold opposite directions: one descriptor over the
+    // pair serves both the pull (row i) and halfway bounce-back (row
+    // opp(i) at x) without a per-lane choice of base address; opposite
+    // directions have equal weights, so wr[i] fits both
+    const int pair = (i & 1) ? i : i - 1;
     const int32_t v = j[i];
-    const int row = (v == MLBM_NBR_BOUNCE) ? Lat::opp(i) : i;
-    const int64_t e = v >= 0 ? (int64_t)v : x;
-    C val = load_g<P>(src, (int64_t)row * a.n + e, a.wr[row], a.inv_scale);
+    const uint32_t e = v >= 0 ? (uint32_t)v : xo;
+    const uint32_t off = v == MLBM_NBR_BOUNCE ? (uint32_t)(Lat::opp(i) - pair) * nn + xo
+                                             : (uint32_t)(i - pair) * nn + e;
+    C val = load_row<P>(src + (int64_t)pair * a.n, 2 * a.n, off, a.wr[i], a.inv_scale);
     if (v == MLBM_NBR_EQ) val = a.geq[i];
     if (v == MLBM_NBR_MISSING) val = C(__builtin_nan(""));
     g[i] = val;
@@ -315,7 +396,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
-    ok &= store_g<P>(dst, (int64_t)i * a.n + x, gs, a.wr[i], a.scale);
+    ok &= store_row<P>(dst + (int64_t)i * a.n, a.n, (uint32_t)x, gs, a.wr[i], a.scale);
   }
   const bool finite = (rho == rho) && (rho - rho == C(0));
   if (!finite || !ok)

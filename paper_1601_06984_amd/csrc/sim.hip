@@ -191,6 +191,14 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
   if (!(tau0 > 0.5)) return fail(MLBM_E_ARG, "tau0 must exceed 1/2");
   if (!(rho0 > 0.0)) return fail(MLBM_E_ARG, "rho0 must be positive");
   if (((uintptr_t)workspace) & 255) return fail(MLBM_E_ARG, "workspace must be 256-byte aligned");
+  // the stream-collide addresses a pair of pdf rows (and a neighbour row)
+  // through one buffer descriptor with 32-bit byte offsets
+  const size_t pdf_bytes = precision == MLBM_F64 ? 8 : precision == MLBM_F32 ? 4 : 2;
+  for (const auto& lp : plan->lv)
+    if ((uint64_t)lp.n * pdf_bytes * 2 >= (1ull << 32) || (uint64_t)lp.n * 4 >= (1ull << 32))
+      return fail(MLBM_E_ARG,
+                  "level %d has %lld elements: two pdf rows must stay below 4 GiB",
+                  lp.level, (long long)lp.n);
   const size_t need = layout_workspace(*plan, precision, nullptr, nullptr);
   if (workspace_bytes < need)
     return fail(MLBM_E_ARG, "workspace too small: need %zu bytes, got %zu", need, workspace_bytes);
