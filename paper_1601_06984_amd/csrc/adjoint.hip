@@ -33,9 +33,13 @@ int64_t blocks(int64_t n, int bs) { return (n + bs - 1) / bs; }
 // ---- op lists (partial-record layout), identical to the launch order ------
 struct OpBuilder {
   std::vector<AdjOp> ops;
+  std::vector<AdjChunk> chunks;
   int64_t off = 0;
   void add(int64_t nb, int self, int other) {
-    ops.push_back(AdjOp{off, nb, self, other});
+    const int32_t c0 = (int32_t)chunks.size();
+    for (int64_t b = 0; b < nb; b += REDUCE_CHUNK)
+      chunks.push_back(AdjChunk{off + b, std::min<int64_t>(REDUCE_CHUNK, nb - b)});
+    ops.push_back(AdjOp{off, nb, self, other, c0, (int32_t)chunks.size() - c0});
     off += nb;
   }
 };
@@ -121,6 +125,9 @@ size_t layout_adjoint(const SimState& s, const mlbm_plan& P, char* base, AdjStat
   char* part = take((size_t)rec * DPART * 8);
   char* ops1 = take(os.ops.size() * sizeof(AdjOp));
   char* ops2 = take(oi.ops.size() * sizeof(AdjOp));
+  char* ch1 = take(os.chunks.size() * sizeof(AdjChunk));
+  char* ch2 = take(oi.chunks.size() * sizeof(AdjChunk));
+  char* chs = take(std::max(os.chunks.size(), oi.chunks.size()) * DPART * 8);
   char* acc = take((size_t)(P.nlev() + 3) * 8);
   if (a) {
     a->part = (double*)part;
@@ -129,6 +136,11 @@ size_t layout_adjoint(const SimState& s, const mlbm_plan& P, char* base, AdjStat
     a->ops_init = (AdjOp*)ops2;
     a->n_ops_step = (int)os.ops.size();
     a->n_ops_init = (int)oi.ops.size();
+    a->chunks_step = (AdjChunk*)ch1;
+    a->chunks_init = (AdjChunk*)ch2;
+    a->n_chunks_step = (int)os.chunks.size();
+    a->n_chunks_init = (int)oi.chunks.size();
+    a->chunk_sums = (double*)chs;
     a->acc = (double*)acc;
   }
   return off;
@@ -277,12 +289,21 @@ struct Adj {
                        (int64_t)s.lv.size() + 3, 0.0);
   }
 
+  // deterministic two-stage reduction of the block partials into acc
+  static void reduce(SimState& s, const AdjOp* ops, int n_ops, const AdjChunk* chunks,
+                     int n_chunks) {
+    if (n_chunks)
+      hipLaunchKernelGGL(k_adj_reduce_chunks, dim3((unsigned)n_chunks), dim3(256), 0, s.stream,
+                         s.adj.part, chunks, s.adj.chunk_sums);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(64), 0, s.stream, s.adj.chunk_sums, ops, n_ops,
+                       s.adj.acc, (int)s.lv.size());
+  }
+
   static void step(SimState& s) {
     tape_advance(s, 0, 0);
     int64_t off = 0;
     reverse(s, 0, 0, off);
-    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s.stream, s.adj.part,
-                       s.adj.ops_step, s.adj.n_ops_step, s.adj.acc, (int)s.lv.size());
+    reduce(s, s.adj.ops_step, s.adj.n_ops_step, s.adj.chunks_step, s.adj.n_chunks_step);
     s.adj.lv[0].cur ^= 1;  // level 0 took one substep; finer levels an even count
   }
 
@@ -311,8 +332,7 @@ struct Adj {
                          drho ? drho[k] : nullptr, dS ? dS[k] : nullptr, s.adj.part + off * DPART);
       off += nb;
     }
-    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, s.stream, s.adj.part,
-                       s.adj.ops_init, s.adj.n_ops_init, s.adj.acc, nlev);
+    reduce(s, s.adj.ops_init, s.adj.n_ops_init, s.adj.chunks_init, s.adj.n_chunks_init);
   }
 
   static void get_lambda(SimState& s, int k, double* out) {
@@ -405,6 +425,8 @@ int32_t mlbm_adjoint_attach(mlbm_sim* sim, const mlbm_plan* plan, void* workspac
   }
   up(a.ops_step, os.ops.data(), os.ops.size() * sizeof(AdjOp));
   up(a.ops_init, oi.ops.data(), oi.ops.size() * sizeof(AdjOp));
+  up(a.chunks_step, os.chunks.data(), os.chunks.size() * sizeof(AdjChunk));
+  up(a.chunks_init, oi.chunks.data(), oi.chunks.size() * sizeof(AdjChunk));
   if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
   if (e != hipSuccess) return fail(MLBM_E_HIP, "adjoint attach: %s", hipGetErrorString(e));
   a.attached = true;

@@ -17,16 +17,23 @@ namespace mlbm {
 constexpr int DPART = 5;
 
 __device__ __forceinline__ void block_sums(double* sm, const double* v, int nv, double* out) {
+  // butterfly within each wavefront, then the wavefronts' sums in order:
+  // a fixed sequence of additions, so the result does not depend on timing
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int k = 0; k < nv; ++k) {
-    sm[threadIdx.x] = v[k];
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = sm[0];
-    __syncthreads();
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == 0) sm[wave * nv + k] = x;
   }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < nv; ++k) {
+      double t = 0;
+      for (int w = 0; w < nw; ++w) t += sm[w * nv + k];
+      out[k] = t;
+    }
+  __syncthreads();
 }
 
 // d g_eq / d(drho, rho, u) transposed: adds the contributions of lgeq.
@@ -169,21 +176,21 @@ __global__ __launch_bounds__(256) void k_seed_drag(const int32_t* __restrict__ b
 // sources (with a record adjoint) and inner ghosts live; the plain
 // instantiation carries no record code and needs fewer registers.
 template <class Lat, int P, bool REC>
-__global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc(
+__global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 5 : 1) void k_adj_sc(
     const typename Prec<P>::S* __restrict__ X, const int32_t* __restrict__ nbr, int64_t x0,
     int64_t x1, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
     const typename Prec<P>::C* __restrict__ lam_new, typename Prec<P>::C* __restrict__ lam_cap,
     typename Prec<P>::C* __restrict__ lam_old, double* __restrict__ part) {
   using C = typename Prec<P>::C;
   constexpr int Q = Lat::Q, D = Lat::D, NS = Lat::NS;
-  __shared__ double sm[256];
+  __shared__ double sm[4 * DPART];
   const int64_t x = x0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
   double acc[DPART] = {0, 0, 0, 0, 0};
   if (x < x1) {
     C g[Q], ls[Q];
     gather_g<Lat, P>(X, nbr, x, a, g);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) ls[i] = lam_new[(int64_t)i * a.n + x];
+    for (int i = 0; i < Q; ++i) ls[i] = load_elem(lam_new + (int64_t)i * a.n, a.n, (uint32_t)x);
     C drho, rho, u[3];
     macro_g<Lat, C>(g, a.rho0, drho, rho, u);
     const C uu = dot_uu<Lat, C>(u);
@@ -274,7 +281,8 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc
     ldrho += lrho;
     // pass 2: mu_i, scattered as formed
     const C om1 = C(1) - om;
-    lam_old[x] = om1 * ls[0] + lf_of(0) + ldrho;
+    store_elem(lam_old, a.n, (uint32_t)x, om1 * ls[0] + lf_of(0) + ldrho);
+    const uint32_t nn = (uint32_t)a.n, xo = (uint32_t)x;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       C mu = om1 * ls[i] + lf_of(i) + ldrho;
@@ -284,11 +292,14 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc
         if (ci > 0) mu += lj[b];
         if (ci < 0) mu -= lj[b];
       }
-      const int32_t v = nbr[(int64_t)(i - 1) * a.ld_nbr + x];
-      if (v >= 0) {
-        lam_old[(int64_t)i * a.n + v] = mu;
-      } else if (v == MLBM_NBR_BOUNCE) {
-        lam_old[(int64_t)Lat::opp(i) * a.n + x] = mu;
+      const int32_t v = load_idx(nbr + (int64_t)(i - 1) * a.ld_nbr, a.ld_nbr, xo);
+      // scatter to the entry the pull read: (i, v), or (opp(i), x) for
+      // bounce-back; one descriptor over the pair of opposite rows
+      const int pair = (i & 1) ? i : i - 1;
+      const uint32_t off = v >= 0 ? (uint32_t)(i - pair) * nn + (uint32_t)v
+                                  : (uint32_t)(Lat::opp(i) - pair) * nn + xo;
+      if (v >= 0 || v == MLBM_NBR_BOUNCE) {
+        store_elem(lam_old + (int64_t)pair * a.n, 2 * a.n, off, mu);
       } else if (v == MLBM_NBR_EQ) {
         // f_i = f^eq_i(rho0, u_in): d/du_in = w rho0 (3 c + 9 (c.u_in) c - 3 u_in)
         const double w = Lat::w(i);
@@ -580,7 +591,7 @@ __global__ __launch_bounds__(64) void k_adj_gff(
     typename Prec<P>::C omega_f, typename Prec<P>::C rho0, double* __restrict__ part) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D, Q = Lat::Q;
-  __shared__ double sm[64];
+  __shared__ double sm[DPART];
   const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
   double acc[DPART] = {0, 0, 0, 0, 0};
   if (j < n_gff) {
@@ -626,7 +637,7 @@ __global__ __launch_bounds__(64) void k_adj_gfc(
     double* __restrict__ part) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D, Q = Lat::Q;
-  __shared__ double sm[64];
+  __shared__ double sm[DPART];
   const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
   double acc[DPART] = {0, 0, 0, 0, 0};
   if (j < n_gfc) {
@@ -687,7 +698,7 @@ __global__ __launch_bounds__(256) void k_adj_init(
     double* __restrict__ dS, double* __restrict__ part) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D, Q = Lat::Q, NS = Lat::NS;
-  __shared__ double sm[256];
+  __shared__ double sm[4 * DPART];
   const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double acc[DPART] = {0, 0, 0, 0, 0};
   if (x < nf) {
@@ -775,26 +786,44 @@ struct AdjOp {
   int64_t offset;   // first block record
   int64_t blocks;
   int32_t level_self, level_other;  // -1 when unused
+  int32_t chunk_begin, chunk_count; // its chunks in the first reduction stage
 };
 
-__global__ __launch_bounds__(256) void k_adj_reduce(const double* __restrict__ part,
-                                                    const AdjOp* __restrict__ ops, int n_ops,
-                                                    double* __restrict__ acc, int nlev) {
-  __shared__ double sm[256];
+// A run of at most REDUCE_CHUNK consecutive block records of one op.
+constexpr int REDUCE_CHUNK = 2048;
+struct AdjChunk {
+  int64_t start;
+  int64_t count;
+};
+
+// Stage 1: one work-group per chunk sums its records in a fixed order.
+__global__ __launch_bounds__(256) void k_adj_reduce_chunks(const double* __restrict__ part,
+                                                           const AdjChunk* __restrict__ chunks,
+                                                           double* __restrict__ chunk_sums) {
+  __shared__ double sm[4 * DPART];
+  const AdjChunk c = chunks[blockIdx.x];
+  double v[DPART] = {0, 0, 0, 0, 0};
+  for (int64_t b = threadIdx.x; b < c.count; b += 256)
+#pragma unroll
+    for (int k = 0; k < DPART; ++k) v[k] += part[(c.start + b) * DPART + k];
+  block_sums(sm, v, DPART, chunk_sums + (int64_t)blockIdx.x * DPART);
+}
+
+// Stage 2: one thread adds each op's chunk sums, op by op, into the
+// parameter accumulators.
+__global__ __launch_bounds__(64) void k_adj_reduce(const double* __restrict__ chunk_sums,
+                                                   const AdjOp* __restrict__ ops, int n_ops,
+                                                   double* __restrict__ acc, int nlev) {
+  if (threadIdx.x != 0) return;
   for (int o = 0; o < n_ops; ++o) {
     const AdjOp op = ops[o];
-    double v[DPART] = {0, 0, 0, 0, 0};
-    for (int64_t b = threadIdx.x; b < op.blocks; b += 256)
+    double tot[DPART] = {0, 0, 0, 0, 0};
+    for (int c = 0; c < op.chunk_count; ++c)
 #pragma unroll
-      for (int k = 0; k < DPART; ++k) v[k] += part[(op.offset + b) * DPART + k];
-    double tot[DPART];
-    block_sums(sm, v, DPART, tot);
-    if (threadIdx.x == 0) {
-      if (op.level_self >= 0) acc[op.level_self] += tot[0];
-      if (op.level_other >= 0) acc[op.level_other] += tot[1];
-      for (int k = 0; k < 3; ++k) acc[nlev + k] += tot[2 + k];
-    }
-    __syncthreads();
+      for (int k = 0; k < DPART; ++k) tot[k] += chunk_sums[(int64_t)(op.chunk_begin + c) * DPART + k];
+    if (op.level_self >= 0) acc[op.level_self] += tot[0];
+    if (op.level_other >= 0) acc[op.level_other] += tot[1];
+    for (int k = 0; k < 3; ++k) acc[nlev + k] += tot[2 + k];
   }
 }
 

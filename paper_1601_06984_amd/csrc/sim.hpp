@@ -47,6 +47,7 @@ struct Profiler {
 };
 
 struct AdjOp;
+struct AdjChunk;
 
 // Adjoint state: the tape of one coarse step and the lambda arrays.
 struct AdjLevel {
@@ -75,6 +76,10 @@ struct AdjState {
   AdjOp* ops_step = nullptr;   // device op lists for the reductions
   AdjOp* ops_init = nullptr;
   int n_ops_step = 0, n_ops_init = 0;
+  AdjChunk* chunks_step = nullptr;  // first-stage chunks of each list
+  AdjChunk* chunks_init = nullptr;
+  int n_chunks_step = 0, n_chunks_init = 0;
+  double* chunk_sums = nullptr;
   double* acc = nullptr;       // [nlev] d/d omega_L, then d/d u_in (3)
 };
 
