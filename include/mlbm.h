@@ -257,7 +257,9 @@ int32_t mlbm_adjoint_seed(mlbm_sim* sim, int32_t objective);
 /* Reverse one coarse step.  `dev_ckpt` (device, `bytes` >= checkpoint size)
  * is the mlbm_save_checkpoint image of the state at the START of the coarse
  * step whose end-state adjoint lambda holds; afterwards lambda refers to
- * that start state.  The simulation's own arrays are not modified. */
+ * that start state.  The step's kernels read the checkpoint in place: keep
+ * it unchanged until the bound stream has passed this step.  The
+ * simulation's own arrays are not modified. */
 int32_t mlbm_adjoint_step(mlbm_sim* sim, const void* dev_ckpt, size_t bytes);
 /* Reverse the initialisation and the initial synchronous fill.  rho, u, S
  * are host arrays of n_levels device pointers to the inputs given to

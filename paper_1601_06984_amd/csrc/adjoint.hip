@@ -153,12 +153,15 @@ struct Adj {
   using C = typename Prec<P>::C;
   using I = Impl<Lat, P>;
 
+  static const void* X_of(const AdjLevel& A, int j) { return (j == 0 && A.X0) ? A.X0 : A.X[j]; }
+
   // forward rerun of one coarse step on the tape
   static void tape_advance(SimState& s, int k, int j) {
     AdjLevel& A = s.adj.lv[k];
     DevLevel& L = s.lv[k];
     const bool first = k > 0 && (j % 2 == 0);
-    I::stream_collide_ptr(s, k, L.n_fluid + (first ? L.n_inner : 0), A.X[j], A.X[j + 1], A.cap[j]);
+    I::stream_collide_ptr(s, k, L.n_fluid + (first ? L.n_inner : 0), X_of(A, j), A.X[j + 1],
+                          A.cap[j]);
     if (k + 1 < (int)s.lv.size()) {
       tape_advance(s, k + 1, 2 * j);
       tape_advance(s, k + 1, 2 * j + 1);
@@ -233,15 +236,28 @@ struct Adj {
       e1 = prof_event(s);
     }
     const bool ev = e0 && e1;
-    if (nb1)
-      launch_timed(k_adj_sc<Lat, P, false>, dim3((unsigned)nb1), dim3(256), s.stream,
-                   ev ? e0 : nullptr, (ev && !nb2) ? e1 : nullptr, (const S*)X, (const int*)L.nbr,
-                   (int64_t)0, cb, a, (const C*)lnew, (C*)A.lam_cap, lold, s.adj.part + off * DPART);
+    // the tail (sources and inner ghosts: more work per element, few
+    // blocks) runs on the side stream beside the plain range; both only
+    // read lam_new and scatter to disjoint lam_old entries.  Profiled runs
+    // keep them in order on one stream so each can be timed.
+    const bool fork = nb1 && nb2 && !s.prof.on && s.adj.side;
+    hipStream_t tail_stream = s.stream;
+    if (fork && hipEventRecord(s.adj.fork, s.stream) == hipSuccess &&
+        hipStreamWaitEvent(s.adj.side, s.adj.fork, 0) == hipSuccess)
+      tail_stream = s.adj.side;
     if (nb2)
-      launch_timed(k_adj_sc<Lat, P, true>, dim3((unsigned)nb2), dim3(256), s.stream,
-                   (ev && !nb1) ? e0 : nullptr, ev ? e1 : nullptr, (const S*)X, (const int*)L.nbr,
+      launch_timed(k_adj_sc<Lat, P, true>, dim3((unsigned)nb2), dim3(256), tail_stream,
+                   ev ? e0 : nullptr, (ev && !nb1) ? e1 : nullptr, (const S*)X, (const int*)L.nbr,
                    cb, n_act, a, (const C*)lnew, (C*)A.lam_cap, lold,
                    s.adj.part + (off + nb1) * DPART);
+    if (nb1)
+      launch_timed(k_adj_sc<Lat, P, false>, dim3((unsigned)nb1), dim3(256), s.stream,
+                   (ev && !nb2) ? e0 : nullptr, ev ? e1 : nullptr, (const S*)X, (const int*)L.nbr,
+                   (int64_t)0, cb, a, (const C*)lnew, (C*)A.lam_cap, lold, s.adj.part + off * DPART);
+    if (tail_stream != s.stream) {
+      (void)hipEventRecord(s.adj.join, tail_stream);
+      (void)hipStreamWaitEvent(s.stream, s.adj.join, 0);
+    }
     if (ev) s.prof.rec.push_back({1, k, n_act, e0, e1});
     off += nb1 + nb2;
     if (A.n_copy)
@@ -259,7 +275,7 @@ struct Adj {
       reverse(s, k + 1, 2 * j + 1, off);
       reverse(s, k + 1, 2 * j, off);
     }
-    sc_reverse(s, k, j, A.X[j], off);
+    sc_reverse(s, k, j, X_of(A, j), off);
   }
 
   static void seed(SimState& s, int objective) {
@@ -451,17 +467,22 @@ int32_t mlbm_adjoint_step(mlbm_sim* sim, const void* dev_ckpt, size_t bytes) {
   size_t need = 0;
   mlbm_checkpoint_bytes(sim, &need);
   if (bytes < need) return fail(MLBM_E_ARG, "checkpoint buffer too small");
-  // the checkpoint's per-level arrays become substep 0 of the tape
+  if (!s.adj.side) {
+    hipError_t e = hipStreamCreateWithFlags(&s.adj.side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.adj.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.adj.join, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(MLBM_E_HIP, "adjoint step: %s", hipGetErrorString(e));
+  }
+  // the checkpoint's per-level arrays are read in place as substep 0 of
+  // the tape (nothing writes substep 0)
   const char* p = (const char*)dev_ckpt;
   size_t off = 256;
-  hipError_t e = hipSuccess;
-  for (size_t k = 0; k < s.lv.size() && e == hipSuccess; ++k) {
-    const size_t b = (size_t)s.q * s.lv[k].n * sbytes(s.precision);
-    if (b) e = hipMemcpyAsync(s.adj.lv[k].X[0], p + off, b, hipMemcpyDeviceToDevice, s.stream);
-    off += al(b);
+  for (size_t k = 0; k < s.lv.size(); ++k) {
+    s.adj.lv[k].X0 = p + off;
+    off += al((size_t)s.q * s.lv[k].n * sbytes(s.precision));
   }
-  if (e != hipSuccess) return fail(MLBM_E_HIP, "adjoint step: %s", hipGetErrorString(e));
   MLBM_ADJ_DISPATCH(s, J::step(s));
+  for (auto& A : s.adj.lv) A.X0 = nullptr;
   return hip_check(hipSuccess, "mlbm_adjoint_step");
 }
 

@@ -83,6 +83,9 @@ SimState::~SimState() {
   drop_graphs();
   for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  if (adj.fork) (void)hipEventDestroy(adj.fork);
+  if (adj.join) (void)hipEventDestroy(adj.join);
+  if (adj.side) (void)hipStreamDestroy(adj.side);
 }
 
 hipEvent_t prof_event(SimState& s) {

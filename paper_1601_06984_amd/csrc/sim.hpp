@@ -52,6 +52,7 @@ struct AdjChunk;
 // Adjoint state: the tape of one coarse step and the lambda arrays.
 struct AdjLevel {
   std::vector<void*> X;        // tape pdf arrays, substeps 0..2^k
+  const void* X0 = nullptr;    // when set, substep 0 of the tape (a checkpoint's array)
   std::vector<void*> cap;      // tape capture records, substeps 0..2^k-1
   void* lam[2] = {nullptr, nullptr};
   int cur = 0;                 // lam[cur] holds dJ/dg* of the current state
@@ -81,6 +82,10 @@ struct AdjState {
   int n_chunks_step = 0, n_chunks_init = 0;
   double* chunk_sums = nullptr;
   double* acc = nullptr;       // [nlev] d/d omega_L, then d/d u_in (3)
+  // second stream for the source/ghost tail of the reverse stream-collide,
+  // which runs beside the plain range (default priority, non-blocking)
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 struct SimState {
