@@ -60,11 +60,13 @@ def workload(name):
                     u_in=None, desc=desc, n0=n0, u0=u0, tgv=True)
     if name == "sphere3":
         uin = 0.04
-        spec = W.sphere_channel_mesh(24, 3)
+        # free-stream equilibrium on every face: a zero-gradient (copy)
+        # outlet destabilises BGK at the coarse level's tau = 0.507
+        spec = W.sphere_channel_mesh(24, 3, outlet="eq")
         tau_f = 0.5 + 3.0 * uin * 24 / 100.0     # Re = u D / nu on the finest level
         tau0 = 0.5 + (tau_f - 0.5) / 4.0
         desc = ("D3Q19 channel [-15D,49D]x[-15D,15D]^2 with a sphere of D=24 finest "
-                "cells, 3 nested levels, Re=100, equilibrium inflow u=0.04")
+                "cells, 3 nested levels, Re=100, free-stream equilibrium u=0.04 on all faces")
         return dict(spec=spec, tau0=tau0, u_in=[uin, 0.0, 0.0],
                     fields=lambda p: W.uniform_fields(len(p), 3, [uin, 0.0, 0.0]),
                     desc=desc, tgv=False)
@@ -106,6 +108,68 @@ def tgv_velocity_error(sim, plan, wl, t):
         num += float(((us - ua[:, 0]) ** 2).sum())
         den += float((ua[:, 0] ** 2).sum())
     return math.sqrt(num / den)
+
+
+def tgv_level_errors(sim, plan, n0, u0, tau0, t):
+    """(eps_u, eps_S) of u_x and S_xx against the decayed closed form at
+    coarse time t (Sec. 4.1 norm: unweighted over the fluid elements of all
+    levels, S in coarsest-level units).  S comes from the stored
+    post-collision pdfs: their moments equal the pre-collision ones and
+    f* - f^eq = (1 - omega_L) f^neq, so f^neq is recovered exactly for
+    omega_L != 1."""
+    import paper_1601_06984_amd as M
+    c, w = M.lattice(plan.stencil)
+    c = np.asarray(c, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    nu0 = (tau0 - 0.5) / 3.0
+    nu_num = nu_den = s_num = s_den = 0.0
+    for k in range(plan.n_levels):
+        nf = plan.info[k]["n_fluid"]
+        coords = plan.export(k, "coords")[:, :nf]
+        pos = (coords.T.astype(np.float64) + 0.5) / float(1 << k)
+        _, ua, Sa = W.tgv_fields(pos, n0, u0, nu0=nu0, t=t)
+        f = sim.get_pdf(k)[:, :nf].cpu().numpy()
+        rho = f.sum(0)
+        u = (c.T @ f) / rho
+        cu = c @ u
+        feq = w[:, None] * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * (u * u).sum(0))
+        om = 1.0 / (0.5 + (tau0 - 0.5) * 2.0 ** k)
+        fneq = (f - feq) / (1.0 - om)
+        sxx = -(1.5 * om / rho) * ((c[:, 0] ** 2)[:, None] * fneq).sum(0) * 2.0 ** k
+        nu_num += float(((u[0] - ua[:, 0]) ** 2).sum())
+        nu_den += float((ua[:, 0] ** 2).sum())
+        s_num += float(((sxx - Sa[:, 0, 0]) ** 2).sum())
+        s_den += float((Sa[:, 0, 0] ** 2).sum())
+    return math.sqrt(nu_num / nu_den), math.sqrt(s_num / s_den)
+
+
+def convergence_sweep(M, torch, bases=(32, 64, 128), precision="f64"):
+    """Diffusive refinement of the two-level D3Q19 Taylor-Green box: coarse
+    base N with the central half refined, u0 = 0.02 * 64 / N and tau0 fixed,
+    run to t_D = 1 / (2 nu k^2) coarse steps; errors and observed orders."""
+    tau0 = tgv_tau(64, 0.02)
+    nu0 = (tau0 - 0.5) / 3.0
+    rows = []
+    for n0 in bases:
+        level0 = int(round(math.log2(n0)))
+        u0 = 0.02 * 64.0 / n0
+        spec = W.refined_box_mesh("D3Q19", level0, n0 // 4, 3 * n0 // 4)
+        plan = M.Plan.from_spec(spec)
+        wl = dict(tau0=tau0, u_in=None, fields=lambda p, n0=n0, u0=u0: W.tgv_fields(p, n0, u0))
+        sim = make_sim(M, torch, wl, plan, precision)
+        k = 2.0 * math.pi / n0
+        t_d = int(round(1.0 / (2.0 * nu0 * k * k)))
+        print(f"[bench] sweep N={n0}: {t_d} coarse steps", file=sys.stderr, flush=True)
+        ms = timed_steps(torch, sim, t_d)
+        eu, es = tgv_level_errors(sim, plan, n0, u0, tau0, t_d)
+        rows.append(dict(base=n0, u0=u0, coarse_steps=t_d, eps_u=eu, eps_S=es,
+                         seconds=round(ms / 1e3, 2), status=sim.status()))
+        del sim
+    for a, b in zip(rows, rows[1:]):
+        b["order_u"] = math.log(a["eps_u"] / b["eps_u"], 2)
+        b["order_S"] = math.log(a["eps_S"] / b["eps_S"], 2)
+    return {"precision": precision, "tau0": tau0, "refinement": "central half refined once",
+            "results": rows}
 
 
 def timed_steps(torch, sim, steps):
@@ -196,6 +260,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-ceiling", type=int, default=1,
                     help="also time a plain 2 GiB device copy (read + write)")
+    ap.add_argument("--sweep", type=int, default=0,
+                    help="also run the FP64 convergence sweep (bases 32/64/128 to t_D)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -352,6 +418,8 @@ def main():
         out["drag"] = {"coarse_steps": args.drag_steps, "D_finest": D, "u_in": uin,
                        "definition": "c_D = 2 F_x / (rho0 u_in^2 pi D^2 / 4), finest-level units",
                        "results": drag}
+    if args.sweep:
+        out["convergence"] = convergence_sweep(M, torch)
     if args.copy_ceiling:
         # practical streaming ceiling of this device: a plain 2 GiB copy
         n = 2 << 30

@@ -87,7 +87,10 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().mlbm_plan_destroy(h)
+            try:
+                lib().mlbm_plan_destroy(h)
+            except Exception:   # interpreter shutdown: modules already torn down
+                pass
             self._h = C.c_void_p()
 
 
@@ -295,5 +298,8 @@ class Sim:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().mlbm_sim_destroy(h)
+            try:
+                lib().mlbm_sim_destroy(h)
+            except Exception:   # interpreter shutdown: modules already torn down
+                pass
             self._h = C.c_void_p()

@@ -196,7 +196,7 @@ def sphere_channel_mesh(d_finest: int, n_levels: int, *,
                         length=(-15.0, 49.0), half_width=15.0,
                         boxes_in_d=((-5.0, 19.0, 5.0), (-2.5, 9.5, 2.5),
                                     (-1.25, 4.75, 1.25)),
-                        inflow_only_eq: bool = False) -> MeshSpec:
+                        inflow_only_eq: bool = False, outlet: str = "copy") -> MeshSpec:
     """Channel [-15D,49D]x[-15D,15D]^2 with a sphere of diameter D at the
     origin and nested refinement boxes around it (Sec. 4.3 geometry).
 
@@ -204,8 +204,9 @@ def sphere_channel_mesh(d_finest: int, n_levels: int, *,
     n_levels    number of levels; box k (k>=1) is
                 [xlo*D, xhi*D] x [-h*D, h*D]^2 from ``boxes_in_d``
     Faces: inflow x- and the four lateral faces carry the free-stream
-    equilibrium, the outlet x+ copies its own post-collision values.
-    The sphere centre sits on a vertex of the finest grid.
+    equilibrium; the outlet x+ copies its own post-collision values
+    (outlet="copy") or also carries the free-stream equilibrium
+    (outlet="eq").  The sphere centre sits on a vertex of the finest grid.
     """
     assert 1 <= n_levels <= 1 + len(boxes_in_d)
     ratio = 1 << (n_levels - 1)
@@ -231,9 +232,10 @@ def sphere_channel_mesh(d_finest: int, n_levels: int, *,
         p = cells.astype(np.float64) + 0.5 - centre
         return (p * p).sum(axis=1) < r2
 
-    faces = ("eq", "copy", "eq", "eq", "eq", "eq")
+    assert outlet in ("copy", "eq")
+    faces = ("eq", outlet, "eq", "eq", "eq", "eq")
     if inflow_only_eq:
-        faces = ("eq", "copy", "periodic", "periodic", "periodic", "periodic")
+        faces = ("eq", outlet, "periodic", "periodic", "periodic", "periodic")
     return nested_mesh(f"sphere_D{d_finest}_L{n_levels}", "D3Q19", level0, ext,
                        boxes, faces, solid=solid,
                        meta={"D": d_finest, "centre_finest": tuple(centre),
