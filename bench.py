@@ -33,6 +33,42 @@ HBM_PEAK_GBS = 8000.0
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
 
 
+# HBM bytes per stream-collide launch (average over the level's launches),
+# from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of this bench
+# on MI355X, each scaled by what the counter reads for a plain 1 GiB device
+# copy (fetch x 2.0, write x 1.0).  Summaries and commands:
+# profiles/stream_collide_<workload>_f32.md.  The figures belong to the
+# kernel sources they were measured on (KERNEL_SOURCES digest); with any
+# other source the bench reports traffic as null.
+PMC_TRAFFIC = {
+    "sources_sha256_16": "ac47cbb96c58738e",
+    "bytes_per_launch": {
+        "tgv64/f32/6": 57943984,
+        "tgv64/f32/7": 71208900,
+        "sphere3/f32/9": 2892928884,
+        "sphere3/f32/10": 974847491,
+        "sphere3/f32/11": 1079896740,
+    },
+}
+KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")
+
+
+def kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1601_06984_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name, precision, level):
+    if kernel_sources_digest() != PMC_TRAFFIC["sources_sha256_16"]:
+        return None
+    return PMC_TRAFFIC["bytes_per_launch"].get(f"{workload_name}/{precision}/{level}")
+
+
 def tgv_tau(n0, u0=0.02, re=100.0):
     # Re = u0 N0 / (2 pi nu) in coarse lattice units; nu = (tau - 1/2)/3
     return 0.5 + 3.0 * u0 * n0 / (2.0 * math.pi * re)
@@ -314,9 +350,12 @@ def main():
                    "levels": plan.n_levels},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic(args.workload, prec, dom["level"]),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
                      "kernel": f"k_stream_collide level {dom['level']} ({prec})",
                      "algorithmic_bytes_per_update": bpe,
+                     "algorithmic_bytes_per_launch": round(dom["elements_per_launch"] * bpe),
                      "us_per_launch": round(dom["us_per_launch"], 2),
                      "elements_per_launch": round(dom["elements_per_launch"], 1)},
         "kernels": prof,
