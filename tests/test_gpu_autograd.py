@@ -37,13 +37,13 @@ def _inputs(plan, fields, dev):
     return rho, u, S
 
 
-def _run(plan, precision, rho, u, S, tau0, n, K, objective="ke", u_in=None):
+def _run(plan, precision, rho, u, S, tau0, n, K, objective="ke", u_in=None, snapshots=None):
     from paper_1601_06984_amd import autograd as AG
     u0 = [x.clone().requires_grad_(True) for x in u]
     tau = torch.tensor(tau0, dtype=torch.float64, requires_grad=True)
     uin = None if u_in is None else torch.tensor(u_in, dtype=torch.float64, requires_grad=True)
     J = AG.objective(plan, rho, u0, tau, n, S=S, u_in=uin, precision=precision,
-                     checkpoint_every=K, objective=objective)
+                     checkpoint_every=K, objective=objective, max_snapshots=snapshots)
     J.backward()
     return float(J), [x.grad.clone() for x in u0], float(tau.grad), \
         (uin.grad.clone() if uin is not None else None)
@@ -66,6 +66,24 @@ def test_checkpointed_gradient_equals_stepwise_adjoint_and_oracle():
     om, Jo, gto, guo, _ = oracle_gradient(spec, 0.56, fields, 7)
     assert _compare(sim, om, [g.cpu().numpy() for g in gu], guo) < 1e-8
     assert abs(gt - gto) < 1e-8 * abs(gto)
+
+
+def test_bisection_checkpointing_matches_stored_states():
+    """Reversing a segment by recursive bisection with few stored states
+    recomputes the same forward states, so the gradient is bitwise the one
+    obtained by keeping every step state."""
+    import paper_1601_06984_amd as M
+    spec = W.refined_box_mesh("D3Q19", 4, 4, 12)
+    fields = lambda p: W.tgv_perturbed_fields(p, 16, 0.03)
+    plan = M.Plan.from_spec(spec)
+    rho, u, S = _inputs(plan, fields, "cuda")
+    _say("autograd snapshots None/2/0, 11 steps, K=11 and K=4, f32")
+    ref = _run(plan, "f32", rho, u, S, 0.56, 11, 11)
+    for K, snaps in ((11, 2), (11, 0), (4, 1)):
+        J, gu, gt, _ = _run(plan, "f32", rho, u, S, 0.56, 11, K, snapshots=snaps)
+        assert J == ref[0] and gt == ref[2]
+        for a, b in zip(gu, ref[1]):
+            assert torch.equal(a, b)
 
 
 def test_drag_gradient_wrt_inflow_through_autograd():
