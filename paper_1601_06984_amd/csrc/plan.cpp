@@ -3,6 +3,7 @@
 // builds the neighbour, interpolation-source and capture tables that the
 // device kernels consume.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdlib>
 #include <cstdarg>
@@ -196,6 +197,37 @@ void parallel_for(int64_t n, F&& fn) {
   for (auto& t : th) t.join();
 }
 
+// Sorts v: contiguous chunks sorted on the hardware threads, then merged
+// pairwise in parallel rounds.
+template <class T>
+void parallel_sort(std::vector<T>& v) {
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = std::max(1u, std::min(nt, 16u));
+  const int64_t n = (int64_t)v.size();
+  if (n < (1 << 20) || nt == 1) {
+    std::sort(v.begin(), v.end());
+    return;
+  }
+  std::vector<int64_t> b(nt + 1);
+  for (unsigned t = 0; t <= nt; ++t) b[t] = n * t / nt;
+  {
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+      th.emplace_back([&v, &b, t] { std::sort(v.begin() + b[t], v.begin() + b[t + 1]); });
+    for (auto& t : th) t.join();
+  }
+  for (unsigned w = 1; w < nt; w *= 2) {
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t + w < nt; t += 2 * w) {
+      const int64_t lo = b[t], mid = b[t + w], hi = b[std::min(t + 2 * w, nt)];
+      th.emplace_back([&v, lo, mid, hi] {
+        std::inplace_merge(v.begin() + lo, v.begin() + mid, v.begin() + hi);
+      });
+    }
+    for (auto& t : th) t.join();
+  }
+}
+
 template <class Lat>
 void velocity(int i, int64_t* v) {
   for (int a = 0; a < Lat::D; ++a) v[a] = Lat::c(i, a);
@@ -239,15 +271,26 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
   };
   std::vector<int> lvl_leaf(n_leaves), lvl_solid(n_solids);
   std::vector<int64_t> c_leaf(n_leaves * d), c_solid(n_solids * d);
+  // independent per id; a failure is reported after the threads join
+  std::atomic<bool> too_deep{false};
+  auto decode_range = [&](const uint64_t* ids, std::vector<int>& lv, std::vector<int64_t>& cc) {
+    return [&, ids](int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) {
+        try {
+          decode(ids[i], lv[i], &cc[i * d]);
+        } catch (const MeshError&) {
+          too_deep = true;
+          return;
+        }
+      }
+    };
+  };
+  parallel_for(n_leaves, decode_range(leaf_ids, lvl_leaf, c_leaf));
+  parallel_for(n_solids, decode_range(solid_ids, lvl_solid, c_solid));
+  if (too_deep) throw MeshError("treeID beyond the supported depth");
   int lmax = P.level0;
-  for (int64_t i = 0; i < n_leaves; ++i) {
-    decode(leaf_ids[i], lvl_leaf[i], &c_leaf[i * d]);
-    lmax = std::max(lmax, lvl_leaf[i]);
-  }
-  for (int64_t i = 0; i < n_solids; ++i) {
-    decode(solid_ids[i], lvl_solid[i], &c_solid[i * d]);
-    lmax = std::max(lmax, lvl_solid[i]);
-  }
+  for (int64_t i = 0; i < n_leaves; ++i) lmax = std::max(lmax, lvl_leaf[i]);
+  for (int64_t i = 0; i < n_solids; ++i) lmax = std::max(lmax, lvl_solid[i]);
   const int L0 = P.level0, nlev = lmax - L0 + 1;
   std::vector<LevelWork> W(nlev);
   unsigned __int128 volume = 0;
@@ -472,16 +515,21 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
       const auto& v = *parts[p];
       const int64_t n = (int64_t)v.size() / d;
       counts[p] = n;
-      std::vector<uint64_t> key(n);
-      for (int64_t i = 0; i < n; ++i) key[i] = morton(&v[i * d], d, L);
-      std::vector<int64_t> ord(n);
-      std::iota(ord.begin(), ord.end(), 0);
-      std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+      std::vector<std::pair<uint64_t, int64_t>> key(n);
+      parallel_for(n, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) key[i] = {morton(&v[i * d], d, L), i};
+      });
+      parallel_sort(key);
       const uint64_t first = level_first_id(L, d);
-      for (int64_t i = 0; i < n; ++i) {
-        lp.tid.push_back(first + key[ord[i]]);
-        for (int a = 0; a < d; ++a) all.push_back(v[ord[i] * d + a]);
-      }
+      const size_t t0 = lp.tid.size(), a0 = all.size();
+      lp.tid.resize(t0 + n);
+      all.resize(a0 + (size_t)n * d);
+      parallel_for(n, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) {
+          lp.tid[t0 + i] = first + key[i].first;
+          for (int c = 0; c < d; ++c) all[a0 + (size_t)i * d + c] = v[key[i].second * d + c];
+        }
+      });
     }
     lp.cap_begin = counts[0];
     lp.n_fluid = counts[0] + counts[1];
