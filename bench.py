@@ -94,6 +94,18 @@ def workload(name):
         desc = "D3Q19 periodic Taylor-Green vortex, 128^3 coarse, central 64^3 refined"
         return dict(spec=spec, tau0=tgv_tau(64, 0.02), fields=lambda p: W.tgv_fields(p, n0, u0),
                     u_in=None, desc=desc, n0=n0, u0=u0, tgv=True)
+    if name == "sphere4":
+        # the four-level configuration sized to one GPU's HBM: D = 128 finest
+        # cells, boxes [-5D,19D]x[-5D,5D]^2, [-2.5D,9.5D]x[-2.5D,2.5D]^2,
+        # [-1.25D,4.75D]x[-1.25D,1.25D]^2; about 449 M elements
+        uin = 0.04
+        spec = W.sphere_channel_mesh(128, 4, outlet="eq")
+        tau_f = 0.5 + 3.0 * uin * 128 / 100.0
+        tau0 = 0.5 + (tau_f - 0.5) / 8.0
+        desc = ("D3Q19 channel [-15D,49D]x[-15D,15D]^2 with a sphere of D=128 finest "
+                "cells, 4 nested levels, Re=100, free-stream equilibrium u=0.04 on all faces")
+        return dict(spec=spec, tau0=tau0, u_in=[uin, 0.0, 0.0], uniform_u=[uin, 0.0, 0.0],
+                    desc=desc, tgv=False)
     if name == "sphere3":
         uin = 0.04
         # free-stream equilibrium on every face: a zero-gradient (copy)
@@ -103,7 +115,7 @@ def workload(name):
         tau0 = 0.5 + (tau_f - 0.5) / 4.0
         desc = ("D3Q19 channel [-15D,49D]x[-15D,15D]^2 with a sphere of D=24 finest "
                 "cells, 3 nested levels, Re=100, free-stream equilibrium u=0.04 on all faces")
-        return dict(spec=spec, tau0=tau0, u_in=[uin, 0.0, 0.0],
+        return dict(spec=spec, tau0=tau0, u_in=[uin, 0.0, 0.0], uniform_u=[uin, 0.0, 0.0],
                     fields=lambda p: W.uniform_fields(len(p), 3, [uin, 0.0, 0.0]),
                     desc=desc, tgv=False)
     raise SystemExit(f"unknown workload {name}")
@@ -116,6 +128,19 @@ def weighted_updates(plan):
 def make_sim(M, torch, wl, plan, precision):
     sim = M.Sim(plan, precision, wl["tau0"], u_in=wl["u_in"])
     dev = sim.device
+    if wl.get("uniform_u") is not None:
+        # uniform initial flow built on the device (S = 0); the inputs are
+        # released after the fill to keep the HBM for the state
+        for k in range(plan.n_levels):
+            nf = plan.info[k]["n_fluid"]
+            u = torch.empty((plan.d, nf), dtype=torch.float64, device=dev)
+            for a in range(plan.d):
+                u[a].fill_(wl["uniform_u"][a])
+            sim.init(k, torch.ones(nf, dtype=torch.float64, device=dev), u, None)
+        sim.fill_ghosts()
+        torch.cuda.synchronize()
+        sim.inputs = {}
+        return sim
     for k in range(plan.n_levels):
         L = plan.level0 + k
         nf = plan.info[k]["n_fluid"]
@@ -277,6 +302,60 @@ def fluid_pdfs(sim, plan):
     return res
 
 
+def drag_inflow_gradient(M, torch, sim, uin, n_steps, K, snapshots):
+    """Gradient of the x drag after n_steps coarse steps with respect to the
+    free-stream velocity `uin`, which sets the EQ faces and the uniform
+    initial field: forward with a checkpoint every K coarse steps, each
+    segment reversed last first (recursive bisection with at most
+    `snapshots` extra states), then the initialisation reversed."""
+    from paper_1601_06984_amd import autograd as AG
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    e0, e1, e2 = ev(), ev(), ev()
+    ck = {}
+    torch.cuda.synchronize()
+    e0.record(sim.stream)
+    t = 0
+    while t < n_steps:
+        ck[t] = sim.save_checkpoint()
+        m = min(K, n_steps - t)
+        sim.step(m)
+        t += m
+    J = float(sim.diagnostics(M.DIAG_FORCE)[0])
+    e1.record(sim.stream)
+    if getattr(sim, "adj_workspace", None) is None:
+        sim.adjoint_attach()
+    sim.adjoint_seed("drag_x")
+    for start in sorted(ck, reverse=True):
+        print(f"[bench] reversing coarse steps {start}..{min(start + K, n_steps)}",
+              file=sys.stderr, flush=True)
+        AG.reverse_steps(sim, ck[start], min(K, n_steps - start), snapshots)
+        torch.cuda.synchronize()
+    # the run starts from the uniform free stream u0 = u_in: its initial
+    # field is a second path from u_in to the drag
+    rho0, u0 = [], []
+    for k in range(sim.plan.n_levels):
+        nf = sim.plan.info[k]["n_fluid"]
+        rho0.append(torch.ones(nf, dtype=torch.float64, device=sim.device))
+        u = torch.empty((sim.plan.d, nf), dtype=torch.float64, device=sim.device)
+        for a in range(sim.plan.d):
+            u[a].fill_(uin[a])
+        u0.append(u)
+    du = sim.adjoint_init(rho0, u0, None)
+    via_init = [sum(float(g[a].sum()) for g in du) for a in range(sim.plan.d)]
+    del rho0, u0, du
+    dtau, domega, duin = sim.adjoint_params()
+    e2.record(sim.stream)
+    torch.cuda.synchronize()
+    return {"coarse_steps": n_steps, "checkpoint_every": K, "max_snapshots": snapshots,
+            "drag_x": J, "dJ_du_in_faces": list(duin[:3]),
+            "dJ_du_in_via_initial_field": via_init,
+            "dJ_du_in": [duin[a] + via_init[a] for a in range(sim.plan.d)], "dJ_dtau0": dtau,
+            "forward_ms": round(e0.elapsed_time(e1), 1),
+            "backward_ms": round(e1.elapsed_time(e2), 1),
+            "backward_ms_per_coarse_step": round(e1.elapsed_time(e2) / n_steps, 2),
+            "peak_device_GB": round(torch.cuda.max_memory_allocated() / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +375,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-ceiling", type=int, default=1,
                     help="also time a plain 2 GiB device copy (read + write)")
+    ap.add_argument("--drag-adjoint", type=int, default=0,
+                    help="sphere workloads: dJ/du_in of the x drag over this many coarse steps")
+    ap.add_argument("--checkpoint-every", type=int, default=50)
+    ap.add_argument("--snapshots", type=int, default=-1,
+                    help="extra states kept while reversing a segment (-1: all)")
     ap.add_argument("--sweep", type=int, default=0,
                     help="also run the FP64 convergence sweep (bases 32/64/128 to t_D)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -405,6 +489,17 @@ def main():
             "kernels": akern,
         }
     gpu_pdfs = {}
+    if args.drag_adjoint and not wl.get("tgv"):
+        print(f"[bench] drag gradient over {args.drag_adjoint} coarse steps", file=sys.stderr,
+              flush=True)
+        sim = None   # release the timing run's state first (HBM)
+        import gc
+        gc.collect()
+        sim2 = make_sim(M, torch, wl, plan, prec)
+        out["drag_adjoint"] = drag_inflow_gradient(
+            M, torch, sim2, wl["uniform_u"], args.drag_adjoint, args.checkpoint_every,
+            None if args.snapshots < 0 else args.snapshots)
+        del sim2
     if args.variants and wl.get("tgv"):
         # precision study at a fixed run length: MLUPS and eps_u for each;
         # the pdfs after `cpu_steps` coarse steps go to the oracle comparison
