@@ -125,6 +125,17 @@ def weighted_updates(plan):
     return sum(plan.info[k]["n_fluid"] << k for k in range(plan.n_levels))
 
 
+def index_bytes_per_update(plan, k):
+    """Bytes of the pull table read per updated element of level index k, as
+    the device holds it: a 16-bit code per direction, the high halves for
+    the blocks that need int32 entries, and the block's bases (4 int32 per
+    direction per 256 elements)."""
+    q1 = plan.q - 1
+    base = plan.export(k, "nbase").reshape(-1, q1, 4)
+    wide_frac = float((base[:, 0, 0] < 0).mean()) if len(base) else 0.0
+    return 2 * q1 * (1.0 + wide_frac) + 16.0 * q1 / 256.0
+
+
 def make_sim(M, torch, wl, plan, precision):
     sim = M.Sim(plan, precision, wl["tau0"], u_in=wl["u_in"])
     dev = sim.device
@@ -413,16 +424,19 @@ def main():
     value = upd * args.steps / (ms / 1e3) / 1e6
     # dominant kernel: the stream-collide with the largest total time
     q = plan.q
-    bpe = 2 * q * STORAGE_BYTES[prec] + 4 * (q - 1)
+    idx_b = [index_bytes_per_update(plan, k) for k in range(plan.n_levels)]
     prof = []
     for k in range(plan.n_levels):
         kms, n, el = sim.profile_read(k)
+        bpe_k = 2 * q * STORAGE_BYTES[prec] + idx_b[k]
         prof.append(dict(level=plan.level0 + k, launches=n, ms_total=kms,
                          us_per_launch=1e3 * kms / max(n, 1),
                          elements_per_launch=el / max(n, 1),
-                         gbs=(el * bpe / 1e9) / (kms / 1e3) if kms else 0.0))
+                         algorithmic_bytes_per_update=round(bpe_k, 2),
+                         gbs=(el * bpe_k / 1e9) / (kms / 1e3) if kms else 0.0))
     dom = max(prof, key=lambda p: p["ms_total"])
     achieved = dom["gbs"]
+    bpe = dom["algorithmic_bytes_per_update"]
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
@@ -471,13 +485,15 @@ def main():
         torch.cuda.synchronize()
         sim.profile(False)
         cb = 8 if prec == "f64" else 4
-        abpe = 2 * q * cb + q * STORAGE_BYTES[prec] + 4 * (q - 1)
         akern = []
         for k in range(plan.n_levels):
             kms, n, el = sim.profile_read(k, kind=1)
+            abpe_k = 2 * q * cb + q * STORAGE_BYTES[prec] + idx_b[k]
             akern.append(dict(level=plan.level0 + k, launches=n, us_per_launch=1e3 * kms / max(n, 1),
-                              gbs=(el * abpe / 1e9) / (kms / 1e3) if kms else 0.0))
+                              algorithmic_bytes_per_update=round(abpe_k, 2),
+                              gbs=(el * abpe_k / 1e9) / (kms / 1e3) if kms else 0.0))
         adom = max(akern, key=lambda p: p["us_per_launch"] * p["launches"])
+        abpe = adom["algorithmic_bytes_per_update"]
         out["adjoint"] = {
             "ms_per_step": adj_ms,
             "mlups": round(upd / (adj_ms / 1e3) / 1e6, 1),

@@ -84,8 +84,17 @@ enum {
   MLBM_TABLE_CAPTURE = 5,  /* int32 [n_cap_fluid]: fluid elements whose
                               pre-collision moments are captured (the tail
                               of the fluid segment)                         */
-  MLBM_TABLE_BOUNCE = 6    /* int32 [2][n_bounce]: (element, direction i)
+  MLBM_TABLE_BOUNCE = 6,   /* int32 [2][n_bounce]: (element, direction i)
                               fluid links whose pull source is solid        */
+  /* The NBR table over the updated elements as the device holds it, in
+   * blocks of 256 elements.  For block b and direction i >= 1, code c of
+   * element x: c >= 0xFFFC is the link code c - 0x10000 (-4..-1);
+   * otherwise the source is NBASE[b][i-1][c >> 14] + (c & 0x3FFF).  A
+   * block with NBASE[b][0][0] = -1 - w < 0 is wide: its entry is the int32
+   * (NBR_WIDE[i-1][w * 256 + x - 256 b] << 16) | c. */
+  MLBM_TABLE_NBR16 = 7,    /* uint16 [q-1][n_blocks * 256]                  */
+  MLBM_TABLE_NBASE = 8,    /* int32 [n_blocks][q-1][4]                      */
+  MLBM_TABLE_NBR_WIDE = 9  /* uint16 [q-1][n_wide * 256]                    */
 };
 
 /* Fields of mlbm_plan_level_info, in this order (int64 each). */

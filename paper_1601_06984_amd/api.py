@@ -71,15 +71,17 @@ class Plan:
         tid = {"treeid": _lib.TABLE_TREEID, "coords": _lib.TABLE_COORDS,
                "nbr": _lib.TABLE_NBR, "gfc_src": _lib.TABLE_GFC_SRC,
                "gff_src": _lib.TABLE_GFF_SRC, "capture": _lib.TABLE_CAPTURE,
-               "bounce": _lib.TABLE_BOUNCE}[table]
+               "bounce": _lib.TABLE_BOUNCE, "nbr16": _lib.TABLE_NBR16,
+               "nbase": _lib.TABLE_NBASE, "nbr_wide": _lib.TABLE_NBR_WIDE}[table]
         nbytes = C.c_size_t()
         check(lib().mlbm_plan_export(self._h, k, tid, None, C.byref(nbytes)))
-        dtype = np.uint64 if table == "treeid" else np.int32
+        dtype = {"treeid": np.uint64, "nbr16": np.uint16, "nbr_wide": np.uint16}.get(table, np.int32)
         out = np.zeros(nbytes.value // np.dtype(dtype).itemsize, dtype=dtype)
         check(lib().mlbm_plan_export(self._h, k, tid, out.ctypes.data_as(C.c_void_p),
                                      C.byref(nbytes)))
         n = self.info[k]["n"]
-        rows = {"coords": self.d, "nbr": self.q - 1, "gfc_src": 4, "gff_src": 4, "bounce": 2}
+        rows = {"coords": self.d, "nbr": self.q - 1, "gfc_src": 4, "gff_src": 4, "bounce": 2,
+                "nbr16": self.q - 1, "nbr_wide": self.q - 1}
         if table in rows:
             out = out.reshape(rows[table], -1)
         return out

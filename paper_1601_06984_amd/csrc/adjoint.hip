@@ -55,7 +55,7 @@ void step_ops(const SimState& s, int k, int j, OpBuilder& ob) {
   }
   const auto& L = s.lv[k];
   const bool first = k > 0 && (j % 2 == 0);
-  const int64_t cb = L.n_fluid - L.n_cap_fluid;
+  const int64_t cb = (L.n_fluid - L.n_cap_fluid) / NBR_BLOCK * NBR_BLOCK;
   ob.add(blocks(cb, 256) + blocks(L.n_fluid + (first ? L.n_inner : 0) - cb, 256), k, -1);
 }
 
@@ -225,9 +225,11 @@ struct Adj {
                          s.stream, lold, L.n, A.unas[v], A.n_unas[v]);
     if (A.n_copy)
       hipLaunchKernelGGL((k_adj_copy_pre<Lat, P>), dim3((unsigned)blocks(A.n_copy, 256)), dim3(256), 0,
-                         s.stream, (const S*)X, L.nbr, A.copy_el, A.n_copy, n_act, a,
+                         s.stream, (const S*)X, A.copy_el, A.n_copy, n_act, a,
                          (const C*)lnew, (const C*)A.lam_cap, (C*)A.copy_tmp);
-    const int64_t cb = L.n_fluid - L.n_cap_fluid;   // plain fluid [0, cb)
+    // plain fluid [0, cb) without records; the split is rounded down to a
+    // pull-table block so each work-group covers one block
+    const int64_t cb = (L.n_fluid - L.n_cap_fluid) / NBR_BLOCK * NBR_BLOCK;
     const int64_t nb1 = blocks(cb, 256), nb2 = blocks(n_act - cb, 256);
     // profiling: the first launch records the start, the last the end
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -247,12 +249,12 @@ struct Adj {
       tail_stream = s.adj.side;
     if (nb2)
       launch_timed(k_adj_sc<Lat, P, true>, dim3((unsigned)nb2), dim3(256), tail_stream,
-                   ev ? e0 : nullptr, (ev && !nb1) ? e1 : nullptr, (const S*)X, (const int*)L.nbr,
+                   ev ? e0 : nullptr, (ev && !nb1) ? e1 : nullptr, (const S*)X,
                    cb, n_act, a, (const C*)lnew, (C*)A.lam_cap, lold,
                    s.adj.part + (off + nb1) * DPART);
     if (nb1)
       launch_timed(k_adj_sc<Lat, P, false>, dim3((unsigned)nb1), dim3(256), s.stream,
-                   (ev && !nb2) ? e0 : nullptr, ev ? e1 : nullptr, (const S*)X, (const int*)L.nbr,
+                   (ev && !nb2) ? e0 : nullptr, ev ? e1 : nullptr, (const S*)X,
                    (int64_t)0, cb, a, (const C*)lnew, (C*)A.lam_cap, lold, s.adj.part + off * DPART);
     if (tail_stream != s.stream) {
       (void)hipEventRecord(s.adj.join, tail_stream);

@@ -177,18 +177,20 @@ __global__ __launch_bounds__(256) void k_seed_drag(const int32_t* __restrict__ b
 // instantiation carries no record code and needs fewer registers.
 template <class Lat, int P, bool REC>
 __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 5 : 1) void k_adj_sc(
-    const typename Prec<P>::S* __restrict__ X, const int32_t* __restrict__ nbr, int64_t x0,
-    int64_t x1, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+    const typename Prec<P>::S* __restrict__ X, int64_t x0, int64_t x1,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a,
     const typename Prec<P>::C* __restrict__ lam_new, typename Prec<P>::C* __restrict__ lam_cap,
     typename Prec<P>::C* __restrict__ lam_old, double* __restrict__ part) {
   using C = typename Prec<P>::C;
   constexpr int Q = Lat::Q, D = Lat::D, NS = Lat::NS;
   __shared__ double sm[4 * DPART];
+  // x0 is a multiple of the pull-table block: a work-group is one block
+  const int64_t blk = (x0 >> 8) + blockIdx.x;
   const int64_t x = x0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
   double acc[DPART] = {0, 0, 0, 0, 0};
   if (x < x1) {
     C g[Q], ls[Q];
-    gather_g<Lat, P>(X, nbr, x, a, g);
+    gather_g<Lat, P>(X, blk, x, a, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i) ls[i] = load_elem(lam_new + (int64_t)i * a.n, a.n, (uint32_t)x);
     C drho, rho, u[3];
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 5 : 1) void k_adj_sc
         if (ci > 0) mu += lj[b];
         if (ci < 0) mu -= lj[b];
       }
-      const int32_t v = load_idx(nbr + (int64_t)(i - 1) * a.ld_nbr, a.ld_nbr, xo);
+      const int32_t v = pull_source<Q>(a, blk, xo, i);
       // scatter to the entry the pull read: (i, v), or (opp(i), x) for
       // bounce-back; one descriptor over the pair of opposite rows
       const int pair = (i & 1) ? i : i - 1;
@@ -321,8 +323,7 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 5 : 1) void k_adj_sc
 // tmp[t][i] = mu_i(x) for the copied directions of element x = elems[t].
 template <class Lat, int P>
 __global__ __launch_bounds__(256) void k_adj_copy_pre(
-    const typename Prec<P>::S* __restrict__ X, const int32_t* __restrict__ nbr,
-    const int32_t* __restrict__ elems, int64_t n_el, int64_t n_act,
+    const typename Prec<P>::S* __restrict__ X, const int32_t* __restrict__ elems, int64_t n_el, int64_t n_act,
     const LevelArgs<typename Prec<P>::C, Lat::Q> a, const typename Prec<P>::C* __restrict__ lam_new,
     const typename Prec<P>::C* __restrict__ lam_cap, typename Prec<P>::C* __restrict__ tmp) {
   using C = typename Prec<P>::C;
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(256) void k_adj_copy_pre(
     return;
   }
   C g[Q], ls[Q], mu[Q];
-  gather_g<Lat, P>(X, nbr, x, a, g);
+  gather_g<Lat, P>(X, x >> 8, x, a, g);
 #pragma unroll
   for (int i = 0; i < Q; ++i) ls[i] = lam_new[(int64_t)i * a.n + x];
   const bool src = x >= a.cap_begin && x < a.n_fluid;
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(256) void k_adj_copy_pre(
   tmp[t * Q] = C(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i)
-    tmp[t * Q + i] = nbr[(int64_t)(i - 1) * a.ld_nbr + x] == MLBM_NBR_COPY ? mu[i] : C(0);
+    tmp[t * Q + i] = pull_source<Q>(a, x >> 8, (uint32_t)x, i) == MLBM_NBR_COPY ? mu[i] : C(0);
 }
 
 // COPY links, part 2 (after k_adj_sc): lam_old[i][x] += tmp[t][i].

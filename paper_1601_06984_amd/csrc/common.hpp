@@ -74,6 +74,13 @@ MLBM_HD constexpr bool opposite_weights_equal() {
   return true;
 }
 
+// Compressed pull table (see LevelPlan): block size, bases per block and
+// direction, largest offset from a base, first code value.
+constexpr int NBR_BLOCK = 256;
+constexpr int NBR_BASES = 4;
+constexpr int NBR_SPAN = 16380;
+constexpr uint32_t NBR_CODE0 = 0xFFFCu;
+
 // Work-group order.  Consecutive work-groups of a launch go to the 8 XCDs in
 // turn (dispatch position b runs on XCD b mod 8), and each XCD has its own
 // L2.  xcd_block maps dispatch position b of nb to a logical block so that

@@ -127,7 +127,12 @@ __device__ __forceinline__ bool store_row(typename Prec<P>::S* __restrict__ row,
 template <class C, int Q>
 struct LevelArgs {
   int64_t n;          // elements (row stride of the pdf arrays)
-  int64_t ld_nbr;     // row stride of the neighbour table
+  // pull table, device form (see the plan's NBR16 table): 16-bit codes
+  // [q-1][ld16], bases [blocks][q-1][NBR_BASES], wide rows [q-1][ldw]
+  const uint16_t* nbr16;
+  const int32_t* nbase;
+  const uint16_t* nbr_wide;
+  int64_t ld16, ldw;
   int64_t cap_begin;  // fluid elements [cap_begin, n_fluid) are sources
   int64_t n_fluid;
   C omega;            // BGK relaxation rate of the level
@@ -184,16 +189,67 @@ __device__ __forceinline__ C dot_uu(const C* u) {
 // ------------------------------------------------------ pull gather ------
 // g_i(x) = g*_i(nbr_i(x)) with boundary codes: BOUNCE -> g*_opp(i)(x),
 // COPY -> g*_i(x), EQ -> f^eq(rho0, u_in); MISSING gives NaN.
+__device__ __forceinline__ uint32_t load_u16(const uint16_t* row, int64_t len, uint32_t e) {
+  return (uint32_t)(uint16_t)__builtin_amdgcn_raw_buffer_load_b16(row_rsrc(row, len * 2),
+                                                                  (int)(e * 2u), 0, 0);
+}
+
+// Source index (or link code) of a 16-bit pull code against the four bases
+// of its block and direction.
+__device__ __forceinline__ int32_t pull_decode(uint32_t c, int32_t b0, int32_t b1, int32_t b2,
+                                               int32_t b3) {
+  const uint32_t s = c >> 14;
+  const int32_t base = s == 0 ? b0 : (s == 1 ? b1 : (s == 2 ? b2 : b3));
+  return c >= NBR_CODE0 ? (int32_t)c - 0x10000 : base + (int32_t)(c & 0x3FFFu);
+}
+
+// Pull sources j[1..Q-1] of element x in pull-table block blk (x >> 8).
+// Kernels whose work-groups cover whole blocks pass a block index that is
+// uniform over the work-group, so the bases come through scalar loads.  The
+// code loads and the base loads are independent; the wide-block flag is the
+// first base, so no load waits for another before the decode.
+template <int Q, class LA>
+__device__ __forceinline__ void pull_sources(const LA& a, int64_t blk, uint32_t x, int32_t* j) {
+  const int32_t* __restrict__ bb = a.nbase + blk * (Q - 1) * NBR_BASES;
+  uint32_t c[Q];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    c[i] = load_u16(a.nbr16 + (int64_t)(i - 1) * a.ld16, a.ld16, x);
+    const int32_t* b = bb + (i - 1) * NBR_BASES;
+    j[i] = pull_decode(c[i], b[0], b[1], b[2], b[3]);
+  }
+  const int32_t flag = bb[0];
+  if (flag < 0) {   // wide block: codes are the low halves of int32 entries
+    const uint32_t e = (uint32_t)(-1 - flag) * NBR_BLOCK + (x & (NBR_BLOCK - 1));
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      j[i] = (int32_t)((load_u16(a.nbr_wide + (int64_t)(i - 1) * a.ldw, a.ldw, e) << 16) | c[i]);
+  }
+}
+
+// Pull source of direction i only.
+template <int Q, class LA>
+__device__ __forceinline__ int32_t pull_source(const LA& a, int64_t blk, uint32_t x, int i) {
+  const int32_t* __restrict__ bb = a.nbase + blk * (Q - 1) * NBR_BASES;
+  const uint32_t c = load_u16(a.nbr16 + (int64_t)(i - 1) * a.ld16, a.ld16, x);
+  const int32_t* b = bb + (i - 1) * NBR_BASES;
+  int32_t v = pull_decode(c, b[0], b[1], b[2], b[3]);
+  const int32_t flag = bb[0];
+  if (flag < 0)
+    v = (int32_t)((load_u16(a.nbr_wide + (int64_t)(i - 1) * a.ldw, a.ldw,
+                            (uint32_t)(-1 - flag) * NBR_BLOCK + (x & (NBR_BLOCK - 1))) << 16) | c);
+  return v;
+}
+
 template <class Lat, int P>
-__device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__ src,
-                                         const int32_t* __restrict__ nbr, int64_t x,
+__device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__ src, int64_t blk,
+                                         int64_t x,
                                          const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
                                          typename Prec<P>::C* g) {
   using C = typename Prec<P>::C;
   const uint32_t xo = (uint32_t)x;
   int32_t j[Lat::Q];
-#pragma unroll
-  for (int i = 1; i < Lat::Q; ++i) j[i] = load_idx(nbr + (int64_t)(i - 1) * a.ld_nbr, a.ld_nbr, xo);
+  pull_sources<Lat::Q>(a, blk, xo, j);
   static_assert(opposite_weights_equal<Lat>(), "w(opp(i)) == w(i)");
   g[0] = load_row<P>(src, a.n, xo, a.wr[0], a.inv_scale);
   const uint32_t nn = (uint32_t)a.n;
@@ -358,12 +414,11 @@ inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStr
 template <class Lat, int P, int BS, bool REC>
 __global__ __launch_bounds__(BS) void k_stream_collide(
     const typename Prec<P>::S* __restrict__ src, typename Prec<P>::S* __restrict__ dst,
-    const int32_t* __restrict__ nbr, int64_t x0, int64_t x1,
-    const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C* __restrict__ cap,
-    uint32_t* __restrict__ status) {
+    int64_t x0, int64_t x1, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+    typename Prec<P>::C* __restrict__ cap, uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   using Stager = WaveRecordStager<C, cap_stride(Lat::D)>;
-  static_assert(BS % 64 == 0, "whole wavefronts");
+  static_assert(BS == NBR_BLOCK, "a work-group covers one pull-table block");
   const int64_t blk = REC ? xcd_block2(blockIdx.x, gridDim.x, (a.cap_begin - x0) / BS)
                           : xcd_block(blockIdx.x, gridDim.x);
   const int64_t xr = x0 + blk * BS + threadIdx.x;
@@ -375,7 +430,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
   // nothing; the record staging needs every lane of the wave
   const int64_t x = valid ? xr : x1 - 1;
   C g[Lat::Q];
-  gather_g<Lat, P>(src, nbr, x, a, g);
+  gather_g<Lat, P>(src, (x0 >> 8) + blk, x, a, g);
   C drho, rho, u[3];
   macro_g<Lat, C>(g, a.rho0, drho, rho, u);
   const C uu = dot_uu<Lat, C>(u);

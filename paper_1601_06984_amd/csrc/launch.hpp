@@ -17,7 +17,11 @@ inline LevelArgs<C, Q> level_args(const SimState& s, int k) {
   const DevLevel& L = s.lv[k];
   LevelArgs<C, Q> a;
   a.n = L.n;
-  a.ld_nbr = L.n_act_max;
+  a.nbr16 = L.nbr16;
+  a.nbase = L.nbase;
+  a.nbr_wide = L.nbr_wide;
+  a.ld16 = L.ld16;
+  a.ldw = L.ldw;
   a.cap_begin = L.n_fluid - L.n_cap_fluid;
   a.n_fluid = L.n_fluid;
   a.omega = (C)L.omega;
@@ -49,7 +53,7 @@ struct Impl {
     // (capture sources, inner ghosts) over the XCDs
     launch_timed(k_stream_collide<Lat, P, BS, true>, dim3((unsigned)((n_act + BS - 1) / BS)),
                  dim3(BS), s.stream, s.launch_ev[0], s.launch_ev[1], (const S*)src, (S*)dst,
-                 (const int*)L.nbr, (int64_t)0, n_act, a, (C*)cap, s.status);
+                 (int64_t)0, n_act, a, (C*)cap, s.status);
   }
 
   static void fill_gff_ptr(SimState& s, int k, void* pdf, const void* cap_fine, void* cap_coarse) {

@@ -244,6 +244,75 @@ struct PhaseTimer {
   }
 };
 
+// Device form of the pull table (LevelPlan::nbr16 ...): per block and
+// direction the distinct neighbour indices are grouped greedily in
+// ascending order into runs shorter than NBR_SPAN, one base per run.
+void compress_pull_table(LevelPlan& lp, int q) {
+  const int64_t n = lp.n, act = lp.n_active_max(), nblk = lp.n_nbr_blocks();
+  const int64_t ld = nblk * NBR_BLOCK;
+  lp.nbr16.assign((size_t)(q - 1) * ld, (uint16_t)0xFFFFu);
+  lp.nbase.assign((size_t)nblk * (q - 1) * NBR_BASES, 0);
+  std::vector<char> wide((size_t)nblk, 0);
+  parallel_for(nblk, [&](int64_t b0, int64_t b1) {
+    int32_t vals[NBR_BLOCK];
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t x0 = b * NBR_BLOCK, x1 = std::min(act, x0 + NBR_BLOCK);
+      for (int i = 1; i < q && !wide[b]; ++i) {
+        const int32_t* row = &lp.nbr[(size_t)(i - 1) * n];
+        int cnt = 0;
+        for (int64_t x = x0; x < x1; ++x)
+          if (row[x] >= 0) vals[cnt++] = row[x];
+        std::sort(vals, vals + cnt);
+        int32_t base[NBR_BASES];
+        int nb = 0;
+        for (int t = 0; t < cnt; ++t)
+          if (nb == 0 || vals[t] - base[nb - 1] >= NBR_SPAN) {
+            if (nb == NBR_BASES) {
+              wide[b] = 1;
+              break;
+            }
+            base[nb++] = vals[t];
+          }
+        if (wide[b]) break;
+        int32_t* bb = &lp.nbase[((size_t)b * (q - 1) + (i - 1)) * NBR_BASES];
+        for (int t = 0; t < nb; ++t) bb[t] = base[t];
+        uint16_t* out = &lp.nbr16[(size_t)(i - 1) * ld];
+        for (int64_t x = x0; x < x1; ++x) {
+          const int32_t v = row[x];
+          if (v < 0) {
+            out[x] = (uint16_t)(0x10000 + v);
+            continue;
+          }
+          int t = nb - 1;
+          while (base[t] > v) --t;   // the run holding v starts at the last base <= v
+          out[x] = (uint16_t)(((uint32_t)t << 14) | (uint32_t)(v - base[t]));
+        }
+      }
+    }
+  });
+  lp.n_wide = 0;
+  const int64_t ld16 = ld;
+  std::vector<int64_t> wide_blocks;
+  for (int64_t b = 0; b < nblk; ++b)
+    if (wide[b]) wide_blocks.push_back(b);
+  lp.n_wide = (int64_t)wide_blocks.size();
+  const int64_t ldw = lp.n_wide * NBR_BLOCK;
+  lp.nbr_wide.assign((size_t)(q - 1) * ldw, (uint16_t)0xFFFFu);
+  for (int64_t w = 0; w < lp.n_wide; ++w) {
+    const int64_t b = wide_blocks[w];
+    int32_t* bb = &lp.nbase[(size_t)b * (q - 1) * NBR_BASES];
+    for (int t = 0; t < (q - 1) * NBR_BASES; ++t) bb[t] = 0;
+    bb[0] = (int32_t)(-1 - w);
+    const int64_t x0 = b * NBR_BLOCK, x1 = std::min(act, x0 + NBR_BLOCK);
+    for (int i = 1; i < q; ++i)
+      for (int64_t x = x0; x < x1; ++x) {
+        const uint32_t v = (uint32_t)lp.nbr[(size_t)(i - 1) * n + x];
+        lp.nbr16[(size_t)(i - 1) * ld16 + x] = (uint16_t)(v & 0xFFFFu);
+        lp.nbr_wide[(size_t)(i - 1) * ldw + (size_t)w * NBR_BLOCK + (x - x0)] = (uint16_t)(v >> 16);
+      }
+  }
+}
+
 void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
                 const uint64_t* solid_ids, int64_t n_solids) {
   const int d = P.d, q = P.q;
@@ -625,6 +694,7 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
       b[nb + j] = lp.bounce[2 * j + 1];
     }
     lp.bounce.swap(b);
+    compress_pull_table(lp, q);
   }
 
   T.mark("neighbours");
@@ -988,6 +1058,9 @@ int32_t mlbm_plan_export(const mlbm_plan* plan, int32_t k, int32_t table, void* 
     case MLBM_TABLE_GFF_SRC: src = lp.gff_src.data(); n = lp.gff_src.size() * 4; break;
     case MLBM_TABLE_CAPTURE: src = lp.cap_elem.data(); n = lp.cap_elem.size() * 4; break;
     case MLBM_TABLE_BOUNCE: src = lp.bounce.data(); n = lp.bounce.size() * 4; break;
+    case MLBM_TABLE_NBR16: src = lp.nbr16.data(); n = lp.nbr16.size() * 2; break;
+    case MLBM_TABLE_NBASE: src = lp.nbase.data(); n = lp.nbase.size() * 4; break;
+    case MLBM_TABLE_NBR_WIDE: src = lp.nbr_wide.data(); n = lp.nbr_wide.size() * 2; break;
     default: return fail(MLBM_E_ARG, "unknown table %d", table);
   }
   if (!host_dst) {

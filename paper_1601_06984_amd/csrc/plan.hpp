@@ -24,6 +24,18 @@ struct LevelPlan {
   std::vector<int32_t> grp_child;  // [children][n_groups] element idx on L
   std::vector<int32_t> bounce;     // [2][n_bounce] (element, direction)
 
+  // The pull table as the device holds it, over the updated range in blocks
+  // of NBR_BLOCK elements: per (block, direction) up to NBR_BASES base
+  // indices and per entry a 16-bit code (base << 14 | offset from it), or
+  // 0xFFFC..0xFFFF for the link codes -4..-1.  A block whose neighbours
+  // need more bases is "wide": nbase[b][0][0] = -1 - w marks it, its code
+  // rows hold the low 16 bits of the int32 entries and row block w of
+  // nbr_wide the high 16 bits.
+  std::vector<uint16_t> nbr16;     // [q-1][n_nbr_blocks * NBR_BLOCK]
+  std::vector<int32_t> nbase;      // [n_nbr_blocks][q-1][NBR_BASES]
+  std::vector<uint16_t> nbr_wide;  // [q-1][n_wide * NBR_BLOCK]
+  int64_t n_wide = 0;
+
   // adjoint tables
   std::vector<int32_t> unassigned[2];  // [2][cnt] (element, direction) fluid-range
                                        // entries no pull reads; variant 0: fluid
@@ -36,6 +48,7 @@ struct LevelPlan {
 
   int64_t n_gfc() const { return n_inner + n_outer; }
   int64_t n_active_max() const { return n_fluid + n_inner; }
+  int64_t n_nbr_blocks() const { return (n_active_max() + NBR_BLOCK - 1) / NBR_BLOCK; }
   int64_t n_cap_fluid() const { return (int64_t)cap_elem.size(); }
   int64_t n_cap() const { return n_cap_fluid() + n_gff; }
   int64_t n_bounce() const { return (int64_t)bounce.size() / 2; }

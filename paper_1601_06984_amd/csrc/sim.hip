@@ -42,7 +42,9 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
     DevLevel* L = s ? &s->lv[k] : nullptr;
     char* p0 = take((size_t)q * lp.n * sb);
     char* p1 = take((size_t)q * lp.n * sb);
-    char* nb = take((size_t)(q - 1) * lp.n_active_max() * 4);
+    char* n16 = take(lp.nbr16.size() * 2);
+    char* nbs = take(lp.nbase.size() * 4);
+    char* nwd = take(lp.nbr_wide.size() * 2);
     char* ce = take((size_t)lp.n_cap_fluid() * 4);
     char* cap = take((size_t)lp.n_cap() * cap_stride(d) * cb);
     char* gs = take((size_t)4 * lp.n_gff * 4);
@@ -52,7 +54,11 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
     if (L) {
       L->pdf[0] = p0;
       L->pdf[1] = p1;
-      L->nbr = (int32_t*)nb;
+      L->nbr16 = (uint16_t*)n16;
+      L->nbase = (int32_t*)nbs;
+      L->nbr_wide = (uint16_t*)nwd;
+      L->ld16 = lp.n_nbr_blocks() * NBR_BLOCK;
+      L->ldw = lp.n_wide * NBR_BLOCK;
       L->cap_elem = (int32_t*)ce;
       L->cap = cap;
       L->gff_slot = (int32_t*)gs;
@@ -262,9 +268,9 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
   for (int k = 0; k < plan->nlev() && e == hipSuccess; ++k) {
     const auto& lp = plan->lv[k];
     DevLevel& L = s.lv[k];
-    if (L.n_act_max && e == hipSuccess)
-      e = hipMemcpy2DAsync(L.nbr, L.n_act_max * 4, lp.nbr.data(), lp.n * 4, L.n_act_max * 4,
-                           s.q - 1, hipMemcpyHostToDevice, s.stream);
+    up(L.nbr16, lp.nbr16.data(), lp.nbr16.size() * 2);
+    up(L.nbase, lp.nbase.data(), lp.nbase.size() * 4);
+    up(L.nbr_wide, lp.nbr_wide.data(), lp.nbr_wide.size() * 2);
     up(L.cap_elem, lp.cap_elem.data(), lp.cap_elem.size() * 4);
     up(L.gff_slot, lp.gff_slot.data(), lp.gff_slot.size() * 4);
     up(L.grp_src, lp.grp_src.data(), lp.grp_src.size() * 4);

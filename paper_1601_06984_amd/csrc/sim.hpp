@@ -18,7 +18,10 @@ struct DevLevel {
   int64_t n = 0, n_fluid = 0, n_inner = 0, n_outer = 0, n_gff = 0, n_act_max = 0;
   int64_t n_cap_fluid = 0, n_cap = 0, n_groups = 0, n_bounce = 0;
   void* pdf[2] = {nullptr, nullptr};  // storage arrays [q][n]
-  int32_t* nbr = nullptr;             // [q-1][n_act_max]
+  uint16_t* nbr16 = nullptr;          // pull table, device form: [q-1][ld16]
+  int32_t* nbase = nullptr;           // [blocks][q-1][NBR_BASES]
+  uint16_t* nbr_wide = nullptr;       // [q-1][ldw] high halves of wide blocks
+  int64_t ld16 = 0, ldw = 0;
   int32_t* cap_elem = nullptr;        // [n_cap_fluid]
   void* cap = nullptr;                // [n_cap][cap_stride] compute type
   int32_t* gff_slot = nullptr;        // [4][n_gff] capture slots on level+1

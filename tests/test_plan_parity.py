@@ -105,6 +105,44 @@ def test_plan_tables_bit_exact(name):
         assert got == ob
 
 
+COMPRESS_MESHES = dict(MESHES)
+# large enough to hold blocks whose neighbours need more than four bases
+COMPRESS_MESHES["tgv64_refined"] = lambda: W.refined_box_mesh("D3Q19", 6, 16, 48)
+
+
+@pytest.mark.parametrize("name", sorted(COMPRESS_MESHES))
+def test_compressed_pull_table_decodes_to_the_table(name):
+    """The device form of the pull table (16-bit codes against per-block
+    bases, int32 rows for wide blocks) decodes to exactly the int32 table
+    over every updated element."""
+    plan = M.Plan.from_spec(COMPRESS_MESHES[name]())
+    n_wide = 0
+    for k, inf in enumerate(plan.info):
+        nbr = plan.export(k, "nbr")
+        q1 = nbr.shape[0]
+        act = inf["n_fluid"] + inf["n_gfc_inner"]
+        nblk = (act + 255) // 256
+        c16 = plan.export(k, "nbr16").astype(np.int64)
+        base = plan.export(k, "nbase").reshape(nblk, q1, 4).astype(np.int64)
+        hi = plan.export(k, "nbr_wide").astype(np.int64)
+        flag = base[:, 0, 0]
+        n_wide += int((flag < 0).sum())
+        assert c16.shape == (q1, nblk * 256)
+        x = np.arange(act)
+        b = x // 256
+        w = np.where(flag[b] < 0, -1 - flag[b], -1)
+        for i in range(q1):
+            c = c16[i, :act]
+            dec = np.where(c >= 0xFFFC, c - 0x10000,
+                           base[b, i, np.minimum(c >> 14, 3)] + (c & 0x3FFF))
+            if (w >= 0).any():
+                full = (hi[i, w[w >= 0] * 256 + x[w >= 0] % 256] << 16) | c[w >= 0]
+                dec[w >= 0] = np.where(full >= 1 << 31, full - (1 << 32), full)
+            assert np.array_equal(dec, nbr[i, :act]), (name, k, i)
+    if name == "tgv64_refined":
+        assert n_wide > 0
+
+
 def test_every_header_symbol_is_exported():
     with open(os.path.join(ROOT, "include", "mlbm.h")) as fh:
         text = fh.read()
