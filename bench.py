@@ -41,13 +41,13 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
 # kernel sources they were measured on (KERNEL_SOURCES digest); with any
 # other source the bench reports traffic as null.
 PMC_TRAFFIC = {
-    "sources_sha256_16": "ac47cbb96c58738e",
+    "sources_sha256_16": "aa3b18f8c3592a15",
     "bytes_per_launch": {
-        "tgv64/f32/6": 57943984,
-        "tgv64/f32/7": 71208900,
-        "sphere3/f32/9": 2892928884,
-        "sphere3/f32/10": 974847491,
-        "sphere3/f32/11": 1079896740,
+        "tgv64/f32/6": 50323598,
+        "tgv64/f32/7": 61994284,
+        "sphere3/f32/9": 2485504992,
+        "sphere3/f32/10": 858820358,
+        "sphere3/f32/11": 940315938,
     },
 }
 KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")
