@@ -259,7 +259,7 @@ def _dir_perm(c_lib, c_oracle):
     return [int(np.where((c_oracle == c_lib[i]).all(1))[0][0]) for i in range(len(c_lib))]
 
 
-def cpu_baseline(wl, steps, gpu_pdfs=None, lattice=None):
+def cpu_baseline(wl, steps, gpu_pdfs=None, lattice=None, single_steps=0):
     """The FP64 oracle as it stands, on the host, for `steps` coarse steps
     from the workload's initial state.  With `gpu_pdfs` ({precision: list of
     (treeids, [q][n_fluid] post-collision pdfs) per level}, taken after the
@@ -281,12 +281,30 @@ def cpu_baseline(wl, steps, gpu_pdfs=None, lattice=None):
     sim.step(steps)
     dt = time.perf_counter() - t0
     upd = sum(om.lev(L).n_fluid << (L - om.level0) for L in range(om.level0, om.lmax + 1))
+    # the same oracle on one thread, for a shorter sample
+    single = None
+    if single_steps:
+        nt = torch.get_num_threads()
+        torch.set_num_threads(1)
+        s1 = osolver.OracleSim(om, wl["tau0"], u_in=None if wl["u_in"] is None
+                               else torch.tensor(wl["u_in"], dtype=torch.float64))
+        s1.init(rho, u, S)
+        t1 = time.perf_counter()
+        s1.step(single_steps)
+        dt1 = time.perf_counter() - t1
+        torch.set_num_threads(nt)
+        single = dict(value=upd * single_steps / dt1 / 1e6, unit="MLUPS", cores=1,
+                      sample=f"{single_steps} coarse steps from the same initial state "
+                             f"({dt1:.1f} s wall)")
+        del s1
     out = dict(value=upd * steps / dt / 1e6, unit="MLUPS", cores=torch.get_num_threads(),
                kind="oracle",
                sample=f"{steps} coarse steps of the same mesh from the same initial state "
                       f"({dt:.1f} s wall, FP64, torch CPU ops, "
                       f"{platform.processor() or platform.machine()}, "
                       f"{os.cpu_count()} logical CPUs visible)")
+    if single:
+        out["single_thread"] = single
     if gpu_pdfs:
         perm = _dir_perm(lattice, np.asarray(sim.lat.c))
         errs = {}
@@ -378,6 +396,8 @@ def main():
                     help="also time F64/F16S and report the fixed-error study")
     ap.add_argument("--cpu-steps", type=int, default=100,
                     help="coarse steps of the oracle (also the accuracy check length)")
+    ap.add_argument("--cpu-single-steps", type=int, default=10,
+                    help="coarse steps of the oracle timed again on one thread")
     ap.add_argument("--drag-steps", type=int, default=0,
                     help="sphere workloads: run this many coarse steps in F32 and F16S "
                          "from the initial state and report the drag coefficient")
@@ -596,7 +616,8 @@ def main():
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         c, _ = M.lattice(plan.stencil)
-        cb = cpu_baseline(wl, args.cpu_steps, gpu_pdfs, np.asarray(c))
+        cb = cpu_baseline(wl, args.cpu_steps, gpu_pdfs, np.asarray(c),
+                          single_steps=args.cpu_single_steps)
         errs = cb.pop("max_rel_pdf_err_vs_oracle", None)
         if errs and "precision_study" in out:
             for p, e in errs.items():

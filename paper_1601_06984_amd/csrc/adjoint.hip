@@ -165,8 +165,8 @@ struct Adj {
     if (k + 1 < (int)s.lv.size()) {
       tape_advance(s, k + 1, 2 * j);
       tape_advance(s, k + 1, 2 * j + 1);
-      I::fill_gff_ptr(s, k, A.X[j + 1], s.adj.lv[k + 1].cap[2 * j + 1], A.cap[j]);
-      I::fill_gfc_ptr(s, k + 1, s.adj.lv[k + 1].X[2 * j + 2], A.cap[j]);
+      I::fill_sync_ptr(s, k, A.X[j + 1], s.adj.lv[k + 1].cap[2 * j + 1], A.cap[j],
+                       s.adj.lv[k + 1].X[2 * j + 2]);
     }
   }
 

@@ -494,22 +494,18 @@ __device__ __forceinline__ bool emit_ghost(typename Prec<P>::S* __restrict__ pdf
 // the fine capture buffer; target is the parent's centre.  Closed form of
 // the compact interpolation at the tetrahedron's centroid:
 // u = mean(u_k) - 1/4 (a_xx + a_yy + a_zz) per component.
-template <class Lat, int P>
-__global__ __launch_bounds__(64) void k_fill_gff(
-    typename Prec<P>::S* __restrict__ pdf, int64_t gff_begin, int64_t n_gff,
-    const int32_t* __restrict__ slots, const typename Prec<P>::C* __restrict__ cap_fine,
-    typename Prec<P>::C* __restrict__ cap_coarse, int64_t cap_gff_begin,
-    const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C fneq_scale,
-    uint32_t* __restrict__ status) {
-  using C = typename Prec<P>::C;
+// gff_values gives the ghost's pre-collision drho, u and g^neq (rescaled to
+// the coarse level); gff_record_value gives slot c of its capture record.
+template <class Lat, class C>
+__device__ __forceinline__ void gff_values(const int32_t* __restrict__ slots, int64_t n_gff,
+                                           int64_t j, const C* __restrict__ cap_fine,
+                                           C fneq_scale, C& drho, C* u, C* fneq) {
   constexpr int D = Lat::D;
-  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (j >= n_gff) return;
   Rec<Lat, C> r[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) r[k].p = cap_fine + (int64_t)slots[k * n_gff + j] * cap_stride(D);
-  C u[3] = {0, 0, 0};
-  C drho = 0;
+  u[0] = u[1] = u[2] = C(0);
+  drho = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     drho += r[k].drho();
@@ -545,20 +541,24 @@ __global__ __launch_bounds__(64) void k_fill_gff(
     u[0] -= C(0.25) * (axx + ayy);
     u[1] -= C(0.25) * (bxx + byy);
   }
-  C fneq[Lat::Q];
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
     fneq[i] = C(0.25) * (r[0].fneq(i) + r[1].fneq(i) + r[2].fneq(i) + r[3].fneq(i)) * fneq_scale;
-  const bool ok = emit_ghost<Lat, P>(pdf, gff_begin + j, a, drho, u, fneq);
-  // pre-collision record of the ghost: it is a GhostFromCoarser source
-  RecordWriter<C> w{cap_coarse + (cap_gff_begin + j) * cap_stride(D), {}};
-  const C rho = a.rho0 + drho;
+}
+
+// Capture-record values of an interpolated ghost, in slot order, handed to
+// a writer (the S of the record uses the target level's omega).
+template <class Lat, class C, class Wr>
+__device__ __forceinline__ void ghost_record(Wr& w, C drho, const C* u, const C* fneq, C omega,
+                                             C rho0) {
+  constexpr int D = Lat::D;
+  const C rho = rho0 + drho;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) w.put(cap_fneq(D) + i, fneq[i]);
   w.put(cap_rho(D), drho);
 #pragma unroll
   for (int b = 0; b < D; ++b) w.put(cap_u(D) + b, u[b]);
-  const C pref = -C(1.5) * a.omega / rho;
+  const C pref = -C(1.5) * omega / rho;
 #pragma unroll
   for (int k = 0; k < Lat::NS; ++k) {
     const int aa = strain_a(D, k), bb = strain_b(D, k);
@@ -572,7 +572,45 @@ __global__ __launch_bounds__(64) void k_fill_gff(
     w.put(cap_s(D) + k, pref * s);
   }
   w.finish(cap_used(D));
+}
+
+// Plain writer into an LDS row (no padding stores).
+template <class C>
+struct RowWriter {
+  C* p;
+  __device__ __forceinline__ void put(int c, C v) { p[c] = v; }
+  __device__ __forceinline__ void finish(int) {}
+};
+
+// One GhostFromFiner ghost j: pdfs and capture record.
+template <class Lat, int P>
+__device__ __forceinline__ void gff_ghost(
+    int64_t j, typename Prec<P>::S* __restrict__ pdf, int64_t gff_begin, int64_t n_gff,
+    const int32_t* __restrict__ slots, const typename Prec<P>::C* __restrict__ cap_fine,
+    typename Prec<P>::C* __restrict__ cap_coarse, int64_t cap_gff_begin,
+    const LevelArgs<typename Prec<P>::C, Lat::Q>& a, typename Prec<P>::C fneq_scale,
+    uint32_t* __restrict__ status) {
+  using C = typename Prec<P>::C;
+  C drho, u[3], fneq[Lat::Q];
+  gff_values<Lat, C>(slots, n_gff, j, cap_fine, fneq_scale, drho, u, fneq);
+  const bool ok = emit_ghost<Lat, P>(pdf, gff_begin + j, a, drho, u, fneq);
+  // pre-collision record of the ghost: it is a GhostFromCoarser source
+  RecordWriter<C> w{cap_coarse + (cap_gff_begin + j) * cap_stride(Lat::D), {}};
+  ghost_record<Lat, C>(w, drho, u, fneq, a.omega, a.rho0);
   if (!ok) atomicOr(status, (uint32_t)MLBM_STATUS_F16_OVERFLOW);
+}
+
+template <class Lat, int P>
+__global__ __launch_bounds__(64) void k_fill_gff(
+    typename Prec<P>::S* __restrict__ pdf, int64_t gff_begin, int64_t n_gff,
+    const int32_t* __restrict__ slots, const typename Prec<P>::C* __restrict__ cap_fine,
+    typename Prec<P>::C* __restrict__ cap_coarse, int64_t cap_gff_begin,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C fneq_scale,
+    uint32_t* __restrict__ status) {
+  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (j >= n_gff) return;
+  gff_ghost<Lat, P>(j, pdf, gff_begin, n_gff, slots, cap_fine, cap_coarse, cap_gff_begin, a,
+                    fneq_scale, status);
 }
 
 // GhostFromCoarser (Sec. 2.2) of fine level, both layers.  One work-group
@@ -581,29 +619,50 @@ __global__ __launch_bounds__(64) void k_fill_gff(
 // the parent's children.  For child octant s the sources are
 // H = P, K = P + (s_x, s_y, 0), M = P + (s_x, 0, s_z), N = P + (0, s_y, s_z)
 // (2D: P, P + s_x, P + s_y, P + s_x + s_y); target at s/4.
+// Coarse GhostFromFiner records computed in place of being read, for a
+// GhostFromCoarser fill that runs in the same launch as the GhostFromFiner
+// fill producing them: records at slots >= rec0 belong to coarse ghost
+// slot - rec0, whose four fine sources are in slots / cap_fine.
+template <class C>
+struct GffOnTheFly {
+  int64_t rec0 = INT64_MAX;
+  const int32_t* slots = nullptr;
+  int64_t n_gff = 0;
+  const C* cap_fine = nullptr;
+  C fneq_scale = 0, omega = 0, rho0 = 0;
+};
+
+template <int D> constexpr int gfc_lds_stride() { return cap_used(D) | 1; }  // odd: no conflicts
+template <int D> constexpr int gfc_groups_per_block() { return 64 / group_children(D); }
+
 template <class Lat, int P>
-__global__ __launch_bounds__(64) void k_fill_gfc(
-    typename Prec<P>::S* __restrict__ pdf, int64_t n_groups,
-    const int32_t* __restrict__ grp_src, const int32_t* __restrict__ grp_child,
+__device__ __forceinline__ void gfc_groups(
+    int64_t blk, typename Prec<P>::C* __restrict__ sh, typename Prec<P>::S* __restrict__ pdf,
+    int64_t n_groups, const int32_t* __restrict__ grp_src, const int32_t* __restrict__ grp_child,
     const typename Prec<P>::C* __restrict__ cap_coarse,
-    const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C fneq_scale,
-    uint32_t* __restrict__ status) {
+    const LevelArgs<typename Prec<P>::C, Lat::Q>& a, typename Prec<P>::C fneq_scale,
+    const GffOnTheFly<typename Prec<P>::C>& fly, uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D;
   constexpr int NB = group_slots(D), NC = group_children(D);
-  constexpr int GPB = 64 / NC;
+  constexpr int GPB = gfc_groups_per_block<D>();
   constexpr int ST = cap_stride(D);
   constexpr int USED = cap_used(D);            // components actually read
-  constexpr int LST = USED | 1;                // odd LDS stride: no bank conflicts
-  __shared__ C sh[GPB * NB * LST];
-  const int64_t g0 = (int64_t)blockIdx.x * GPB;
+  constexpr int LST = gfc_lds_stride<D>();
+  const int64_t g0 = blk * GPB;
   // one record per thread and pass: a single slot lookup, contiguous reads
   for (int r = threadIdx.x; r < GPB * NB; r += 64) {
     const int gl = r / NB, sl = r % NB;
     const int64_t g = g0 + gl;
     const int32_t slot = g < n_groups ? grp_src[(int64_t)sl * n_groups + g] : -1;
     C* dst = sh + r * LST;
-    if (slot >= 0) {
+    if (slot >= fly.rec0) {
+      C drho, u[3], fneq[Lat::Q];
+      gff_values<Lat, C>(fly.slots, fly.n_gff, slot - fly.rec0, fly.cap_fine, fly.fneq_scale,
+                         drho, u, fneq);
+      RowWriter<C> w{dst};
+      ghost_record<Lat, C>(w, drho, u, fneq, fly.omega, fly.rho0);
+    } else if (slot >= 0) {
       const C* src = cap_coarse + (int64_t)slot * ST;
 #pragma unroll
       for (int c = 0; c < USED; ++c) dst[c] = src[c];
@@ -672,6 +731,58 @@ __global__ __launch_bounds__(64) void k_fill_gfc(
   }
   if (!emit_ghost<Lat, P>(pdf, target, a, drho, u, fneq))
     atomicOr(status, (uint32_t)MLBM_STATUS_F16_OVERFLOW);
+}
+
+template <class Lat, int P>
+__global__ __launch_bounds__(64) void k_fill_gfc(
+    typename Prec<P>::S* __restrict__ pdf, int64_t n_groups,
+    const int32_t* __restrict__ grp_src, const int32_t* __restrict__ grp_child,
+    const typename Prec<P>::C* __restrict__ cap_coarse,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C fneq_scale,
+    uint32_t* __restrict__ status) {
+  using C = typename Prec<P>::C;
+  constexpr int D = Lat::D;
+  __shared__ C sh[gfc_groups_per_block<D>() * group_slots(D) * gfc_lds_stride<D>()];
+  gfc_groups<Lat, P>(blockIdx.x, sh, pdf, n_groups, grp_src, grp_child, cap_coarse, a, fneq_scale,
+                     GffOnTheFly<C>{}, status);
+}
+
+// Both fills of one synchronisation of levels (k, k+1) in one launch: work-
+// groups [0, nb_gff) fill the GhostFromFiner ghosts of level k (pdfs and
+// records), the rest the GhostFromCoarser ghosts of level k+1, which compute
+// the coarse GhostFromFiner records they read from the fine records instead
+// of waiting for them.  Same results as k_fill_gff then k_fill_gfc.
+template <class Lat, int P>
+__global__ __launch_bounds__(64) void k_fill_sync(
+    int64_t nb_gff,
+    typename Prec<P>::S* __restrict__ pdf_c, int64_t gff_begin, int64_t n_gff,
+    const int32_t* __restrict__ gff_slot, const typename Prec<P>::C* __restrict__ cap_fine,
+    typename Prec<P>::C* __restrict__ cap_coarse, int64_t cap_gff_begin,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> ac, typename Prec<P>::C scale_gff,
+    typename Prec<P>::S* __restrict__ pdf_f, int64_t n_groups,
+    const int32_t* __restrict__ grp_src, const int32_t* __restrict__ grp_child,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> af, typename Prec<P>::C scale_gfc,
+    uint32_t* __restrict__ status) {
+  using C = typename Prec<P>::C;
+  constexpr int D = Lat::D;
+  __shared__ C sh[gfc_groups_per_block<D>() * group_slots(D) * gfc_lds_stride<D>()];
+  if ((int64_t)blockIdx.x < nb_gff) {
+    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (j < n_gff)
+      gff_ghost<Lat, P>(j, pdf_c, gff_begin, n_gff, gff_slot, cap_fine, cap_coarse,
+                        cap_gff_begin, ac, scale_gff, status);
+    return;
+  }
+  GffOnTheFly<C> fly;
+  fly.rec0 = cap_gff_begin;
+  fly.slots = gff_slot;
+  fly.n_gff = n_gff;
+  fly.cap_fine = cap_fine;
+  fly.fneq_scale = scale_gff;
+  fly.omega = ac.omega;
+  fly.rho0 = ac.rho0;
+  gfc_groups<Lat, P>((int64_t)blockIdx.x - nb_gff, sh, pdf_f, n_groups, grp_src, grp_child,
+                     (const C*)cap_coarse, af, scale_gfc, fly, status);
 }
 
 // -------------------------------------------------------------- init ------

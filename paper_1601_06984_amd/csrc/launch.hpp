@@ -81,6 +81,34 @@ struct Impl {
                        s.status);
   }
 
+  // GhostFromFiner of level k and GhostFromCoarser of level k+1 in one
+  // launch (k_fill_sync); pdf_c / pdf_f are the arrays receiving the ghosts
+  static void fill_sync_ptr(SimState& s, int k, void* pdf_c, const void* cap_fine,
+                            void* cap_coarse, void* pdf_f) {
+    DevLevel& L = s.lv[k];
+    DevLevel& F = s.lv[k + 1];
+    constexpr int GPB = 64 / group_children(Lat::D);
+    const int64_t nb_gff = (L.n_gff + 63) / 64;
+    const int64_t nb_gfc = (F.n_groups + GPB - 1) / GPB;
+    if (nb_gff + nb_gfc == 0) return;
+    auto ac = level_args<C, Lat::Q>(s, k);
+    auto af = level_args<C, Lat::Q>(s, k + 1);
+    const C scale_gff = (C)(2.0 * F.omega / L.omega);
+    const C scale_gfc = (C)(L.omega / (2.0 * F.omega));
+    hipLaunchKernelGGL((k_fill_sync<Lat, P>), dim3((unsigned)(nb_gff + nb_gfc)), dim3(64), 0,
+                       s.stream, nb_gff, (S*)pdf_c, L.n_fluid + L.n_inner + L.n_outer, L.n_gff,
+                       (const int32_t*)L.gff_slot, (const C*)cap_fine, (C*)cap_coarse,
+                       L.n_cap_fluid, ac, scale_gff, (S*)pdf_f, F.n_groups,
+                       (const int32_t*)F.grp_src, (const int32_t*)F.grp_child, af, scale_gfc,
+                       s.status);
+  }
+
+  static void fill_sync(SimState& s, int k) {
+    DevLevel& L = s.lv[k];
+    DevLevel& F = s.lv[k + 1];
+    fill_sync_ptr(s, k, L.pdf[L.parity], F.cap, L.cap, F.pdf[F.parity]);
+  }
+
   static void stream_collide(SimState& s, int k, int64_t n_act) {
     DevLevel& L = s.lv[k];
     stream_collide_ptr(s, k, n_act, L.pdf[L.parity], L.pdf[L.parity ^ 1], L.cap);

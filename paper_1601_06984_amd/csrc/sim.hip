@@ -124,6 +124,7 @@ void sc_level(SimState& s, int k) {
 }
 
 void fill_gff(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_gff(s, k)); }
+void fill_sync(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_sync(s, k)); }
 void fill_gfc(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_gfc(s, k)); }
 
 void advance(SimState& s, int k) {
@@ -131,8 +132,7 @@ void advance(SimState& s, int k) {
   if (k + 1 < (int)s.lv.size()) {
     advance(s, k + 1);
     advance(s, k + 1);
-    fill_gff(s, k);
-    fill_gfc(s, k + 1);
+    fill_sync(s, k);   // GhostFromFiner(k) and GhostFromCoarser(k+1)
   }
 }
 
@@ -538,7 +538,7 @@ int32_t mlbm_launches_per_step(const mlbm_sim* sim, int64_t* launches) {
     const auto& L = s.lv[k];
     const int64_t reps = (int64_t)1 << k;
     total += reps;
-    if (k + 1 < s.lv.size()) total += reps * ((L.n_gff ? 1 : 0) + (s.lv[k + 1].n_groups ? 1 : 0));
+    if (k + 1 < s.lv.size()) total += reps * ((L.n_gff || s.lv[k + 1].n_groups) ? 1 : 0);
   }
   *launches = total;
   return MLBM_OK;
