@@ -411,42 +411,41 @@ inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStr
     hipLaunchKernelGGL(kernel, grid, block, 0, st, static_cast<KArgs>(args)...);
 }
 
-template <class Lat, int P, int BS, bool REC>
-__global__ __launch_bounds__(BS) void k_stream_collide(
-    const typename Prec<P>::S* __restrict__ src, typename Prec<P>::S* __restrict__ dst,
-    int64_t x0, int64_t x1, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
-    typename Prec<P>::C* __restrict__ cap, uint32_t* __restrict__ status) {
+// The stream-collide of work-group `blk` of a level whose updated range is
+// [0, x1): elements blk*BS .. blk*BS+BS-1.  `stage` is the work-group's
+// record staging area.
+template <class Lat, int P, int BS>
+__device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
+                                        const typename Prec<P>::S* __restrict__ src,
+                                        typename Prec<P>::S* __restrict__ dst,
+                                        const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
+                                        typename Prec<P>::C* __restrict__ cap,
+                                        uint32_t* __restrict__ status,
+                                        typename Prec<P>::C* __restrict__ stage) {
   using C = typename Prec<P>::C;
   using Stager = WaveRecordStager<C, cap_stride(Lat::D)>;
   static_assert(BS == NBR_BLOCK, "a work-group covers one pull-table block");
-  const int64_t blk = REC ? xcd_block2(blockIdx.x, gridDim.x, (a.cap_begin - x0) / BS)
-                          : xcd_block(blockIdx.x, gridDim.x);
-  const int64_t xr = x0 + blk * BS + threadIdx.x;
+  if (blk * BS >= x1) return;   // padding work-group (whole group)
+  const int64_t xr = blk * BS + threadIdx.x;
   const bool valid = xr < x1;
-  if constexpr (!REC) {
-    if (!valid) return;
-  }
-  // lanes past the end recompute the last element (in bounds) and store
-  // nothing; the record staging needs every lane of the wave
+  // lanes past the end recompute the last element (in bounds, same block)
+  // and store nothing; the record staging needs every lane of the wave
   const int64_t x = valid ? xr : x1 - 1;
   C g[Lat::Q];
-  gather_g<Lat, P>(src, (x0 >> 8) + blk, x, a, g);
+  gather_g<Lat, P>(src, blk, x, a, g);
   C drho, rho, u[3];
   macro_g<Lat, C>(g, a.rho0, drho, rho, u);
   const C uu = dot_uu<Lat, C>(u);
   // interpolation sources keep their pre-collision moments
-  if constexpr (REC) {
-    __shared__ C stage[(BS / 64) * Stager::LDS_PER_WAVE];
-    const bool is_src = valid && x >= a.cap_begin && x < a.n_fluid;
-    const uint64_t m = __ballot(is_src);
-    if (m) {   // wave-uniform
-      const int lane = threadIdx.x & 63;
-      Stager w{stage + (threadIdx.x >> 6) * Stager::LDS_PER_WAVE, cap,
-               (xr - lane) - a.cap_begin, m, lane, {}};
-      record_values<Lat, C>(w, g, drho, rho, u, uu, a.omega);
-    }
-    if (!valid) return;
+  const bool is_src = valid && x >= a.cap_begin && x < a.n_fluid;
+  const uint64_t m = __ballot(is_src);
+  if (m) {   // wave-uniform
+    const int lane = threadIdx.x & 63;
+    Stager w{stage + (threadIdx.x >> 6) * Stager::LDS_PER_WAVE, cap, (xr - lane) - a.cap_begin,
+             m, lane, {}};
+    record_values<Lat, C>(w, g, drho, rho, u, uu, a.omega);
   }
+  if (!valid) return;
   bool ok = true;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
@@ -457,6 +456,58 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
   if (!finite || !ok)
     atomicOr(status, (finite ? 0u : (uint32_t)MLBM_STATUS_NONFINITE) |
                          (ok ? 0u : (uint32_t)MLBM_STATUS_F16_OVERFLOW));
+}
+
+template <class C, int D>
+constexpr int sc_stage_values(int bs) {
+  return (bs / 64) * WaveRecordStager<C, cap_stride(D)>::LDS_PER_WAVE;
+}
+
+// One level's stream-collide over [0, x1); the block map balances the plain
+// range and the tail (capture sources, inner ghosts) over the XCDs.
+template <class Lat, int P, int BS>
+__global__ __launch_bounds__(BS) void k_stream_collide(
+    const typename Prec<P>::S* __restrict__ src, typename Prec<P>::S* __restrict__ dst,
+    int64_t x1, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+    typename Prec<P>::C* __restrict__ cap, uint32_t* __restrict__ status) {
+  using C = typename Prec<P>::C;
+  __shared__ C stage[sc_stage_values<C, Lat::D>(BS)];
+  const int64_t blk = xcd_block2(blockIdx.x, gridDim.x, a.cap_begin / BS);
+  sc_body<Lat, P, BS>(blk, x1, src, dst, a, cap, status, stage);
+}
+
+// Stream-collides of several levels in one launch.  Consecutive
+// stream-collides of different levels in the schedule touch disjoint data
+// (each reads and writes only its own level), so they can run as one grid:
+// segment s holds work-groups [first[s], first[s] + nb[s]); every segment
+// starts at a multiple of 8 (on XCD 0), so it keeps the XCD-sliced block map
+// of a launch of its own, and the few work-groups between segments exit.
+constexpr int SC_MAX_SEG = 6;
+template <class C, class S, int Q>
+struct ScMulti {
+  int nseg;
+  int64_t first[SC_MAX_SEG];
+  int64_t nb[SC_MAX_SEG];
+  int64_t n_act[SC_MAX_SEG];
+  const S* src[SC_MAX_SEG];
+  S* dst[SC_MAX_SEG];
+  C* cap[SC_MAX_SEG];
+  LevelArgs<C, Q> a[SC_MAX_SEG];
+};
+
+template <class Lat, int P, int BS>
+__global__ __launch_bounds__(BS) void k_stream_collide_multi(
+    const ScMulti<typename Prec<P>::C, typename Prec<P>::S, Lat::Q> m,
+    uint32_t* __restrict__ status) {
+  using C = typename Prec<P>::C;
+  __shared__ C stage[sc_stage_values<C, Lat::D>(BS)];
+  int sg = 0;
+  while (sg + 1 < m.nseg && (int64_t)blockIdx.x >= m.first[sg + 1]) ++sg;
+  const int64_t b = (int64_t)blockIdx.x - m.first[sg];
+  if (b >= m.nb[sg]) return;
+  const LevelArgs<C, Lat::Q>& a = m.a[sg];
+  const int64_t blk = xcd_block2(b, m.nb[sg], a.cap_begin / BS);
+  sc_body<Lat, P, BS>(blk, m.n_act[sg], m.src[sg], m.dst[sg], a, m.cap[sg], status, stage);
 }
 
 // --------------------------------------------------- interpolation --------

@@ -51,9 +51,36 @@ struct Impl {
     auto a = level_args<C, Lat::Q>(s, k);
     // one launch; the block map balances the plain range and the tail
     // (capture sources, inner ghosts) over the XCDs
-    launch_timed(k_stream_collide<Lat, P, BS, true>, dim3((unsigned)((n_act + BS - 1) / BS)),
+    launch_timed(k_stream_collide<Lat, P, BS>, dim3((unsigned)((n_act + BS - 1) / BS)),
                  dim3(BS), s.stream, s.launch_ev[0], s.launch_ev[1], (const S*)src, (S*)dst,
-                 (int64_t)0, n_act, a, (C*)cap, s.status);
+                 n_act, a, (C*)cap, s.status);
+  }
+
+  // stream-collides of distinct levels (jobs) in one launch
+  static void stream_collide_multi(SimState& s, const ScJob* jobs, int n) {
+    if (n == 1) {
+      stream_collide_ptr(s, jobs[0].k, jobs[0].n_act, jobs[0].src, jobs[0].dst, jobs[0].cap);
+      return;
+    }
+    ScMulti<C, S, Lat::Q> m{};
+    int64_t total = 0;
+    m.nseg = 0;
+    for (int j = 0; j < n; ++j) {
+      if (jobs[j].n_act <= 0) continue;
+      const int sg = m.nseg++;
+      const int64_t nb = (jobs[j].n_act + BS - 1) / BS;
+      m.first[sg] = total;
+      m.nb[sg] = nb;
+      m.n_act[sg] = jobs[j].n_act;
+      m.src[sg] = (const S*)jobs[j].src;
+      m.dst[sg] = (S*)jobs[j].dst;
+      m.cap[sg] = (C*)jobs[j].cap;
+      m.a[sg] = level_args<C, Lat::Q>(s, jobs[j].k);
+      total += (nb + 7) / 8 * 8;
+    }
+    if (!m.nseg) return;
+    hipLaunchKernelGGL((k_stream_collide_multi<Lat, P, BS>), dim3((unsigned)total), dim3(BS), 0,
+                       s.stream, m, s.status);
   }
 
   static void fill_gff_ptr(SimState& s, int k, void* pdf, const void* cap_fine, void* cap_coarse) {

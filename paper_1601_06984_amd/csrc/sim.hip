@@ -103,10 +103,32 @@ hipEvent_t prof_event(SimState& s) {
   return s.prof.pool[s.prof.used++];
 }
 
+// Launches the pending stream-collides (one per level) as one grid.
+void flush_sc(SimState& s) {
+  if (s.pending.empty()) return;
+  MLBM_DISPATCH(s, I::stream_collide_multi(s, s.pending.data(), (int)s.pending.size()));
+  s.pending.clear();
+}
+
 void sc_level(SimState& s, int k) {
   DevLevel& L = s.lv[k];
   const bool first = (k > 0) && (L.substep == 0);
   const int64_t n_act = L.n_fluid + (first ? L.n_inner : 0);
+  if (!s.prof.on) {
+    // consecutive stream-collides of different levels share a launch; a
+    // second one of the same level depends on the first
+    for (const auto& j : s.pending)
+      if (j.k == k) {
+        flush_sc(s);
+        break;
+      }
+    if ((int)s.pending.size() == SC_MAX_SEG) flush_sc(s);
+    s.pending.push_back(ScJob{k, n_act, L.pdf[L.parity], L.pdf[L.parity ^ 1], L.cap});
+    L.parity ^= 1;
+    if (k > 0) L.substep ^= 1;
+    return;
+  }
+  flush_sc(s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (s.prof.on && n_act > 0) {
     e0 = prof_event(s);
@@ -124,7 +146,10 @@ void sc_level(SimState& s, int k) {
 }
 
 void fill_gff(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_gff(s, k)); }
-void fill_sync(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_sync(s, k)); }
+void fill_sync(SimState& s, int k) {
+  flush_sc(s);
+  MLBM_DISPATCH(s, I::fill_sync(s, k));
+}
 void fill_gfc(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_gfc(s, k)); }
 
 void advance(SimState& s, int k) {
@@ -158,6 +183,7 @@ static hipError_t two_step_graph(SimState& s, hipGraphExec_t* exec) {
   if (e == hipSuccess) {
     advance(s, 0);
     advance(s, 0);
+    flush_sc(s);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s.stream, &graph);
     if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
@@ -363,6 +389,7 @@ int32_t mlbm_step(mlbm_sim* sim, int64_t n_coarse) {
     advance(s, 0);
     s.time++;
   }
+  flush_sc(s);
   return check_launch("mlbm_step");
 }
 

@@ -52,6 +52,16 @@ struct Profiler {
 struct AdjOp;
 struct AdjChunk;
 
+// A stream-collide waiting to be launched together with those of other
+// levels (see mlbm::flush_sc).
+struct ScJob {
+  int k;
+  int64_t n_act;
+  const void* src;
+  void* dst;
+  void* cap;
+};
+
 // Adjoint state: the tape of one coarse step and the lambda arrays.
 struct AdjLevel {
   std::vector<void*> X;        // tape pdf arrays, substeps 0..2^k
@@ -110,6 +120,7 @@ struct SimState {
   // when set, the next stream-collide launch records these events with its
   // own dispatch timestamps (start, stop)
   hipEvent_t launch_ev[2] = {nullptr, nullptr};
+  std::vector<ScJob> pending;          // stream-collides not yet launched
   AdjState adj;
   // graphs of two coarse steps, keyed by the parity state they start from
   hipStream_t capture_stream = nullptr;
