@@ -41,13 +41,13 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
 # kernel sources they were measured on (KERNEL_SOURCES digest); with any
 # other source the bench reports traffic as null.
 PMC_TRAFFIC = {
-    "sources_sha256_16": "aa3b18f8c3592a15",
+    "sources_sha256_16": "1b6e372a87ef563b",
     "bytes_per_launch": {
-        "tgv64/f32/6": 50323598,
-        "tgv64/f32/7": 61994284,
-        "sphere3/f32/9": 2485504992,
-        "sphere3/f32/10": 858820358,
-        "sphere3/f32/11": 940315938,
+        "tgv64/f32/6": 50350589,
+        "tgv64/f32/7": 62029214,
+        "sphere3/f32/9": 2484177045,
+        "sphere3/f32/10": 858616248,
+        "sphere3/f32/11": 939861796,
     },
 }
 KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")
@@ -127,13 +127,18 @@ def weighted_updates(plan):
 
 def index_bytes_per_update(plan, k):
     """Bytes of the pull table read per updated element of level index k, as
-    the device holds it: a 16-bit code per direction, the high halves for
-    the blocks that need int32 entries, and the block's bases (4 int32 per
-    direction per 256 elements)."""
+    the device holds it: a 16-bit code per direction that is not a Morton
+    direction of its block, the high halves for the blocks that need int32
+    entries, and per 256 elements the block's header (4 int32) and bases
+    (4 int32 per direction)."""
     q1 = plan.q - 1
-    base = plan.export(k, "nbase").reshape(-1, q1, 4)
-    wide_frac = float((base[:, 0, 0] < 0).mean()) if len(base) else 0.0
-    return 2 * q1 * (1.0 + wide_frac) + 16.0 * q1 / 256.0
+    hdr = plan.export(k, "nbr_hdr").reshape(-1, 4).astype(np.int64)
+    if not len(hdr):
+        return 0.0
+    mor = np.array([bin(v & 0xFFFFFFFF).count("1") for v in hdr[:, 0].tolist()])
+    wide = hdr[:, 2] >= 0
+    codes = 2.0 * (q1 - mor) + np.where(wide, 2.0 * q1, 0.0)
+    return float(codes.mean()) + 16.0 * (q1 + 1) / 256.0
 
 
 def make_sim(M, torch, wl, plan, precision):

@@ -87,14 +87,21 @@ enum {
   MLBM_TABLE_BOUNCE = 6,   /* int32 [2][n_bounce]: (element, direction i)
                               fluid links whose pull source is solid        */
   /* The NBR table over the updated elements as the device holds it, in
-   * blocks of 256 elements.  For block b and direction i >= 1, code c of
-   * element x: c >= 0xFFFC is the link code c - 0x10000 (-4..-1);
-   * otherwise the source is NBASE[b][i-1][c >> 14] + (c & 0x3FFF).  A
-   * block with NBASE[b][0][0] = -1 - w < 0 is wide: its entry is the int32
+   * blocks of 256 elements, with H = NBR_HDR[b] = {regmask, kself, w, 0}.
+   * Direction i >= 1 of block b is "Morton" if bit i of regmask is set:
+   * with m = x + kself and mo = the Morton code of x - c_i formed from m by
+   * dilated arithmetic, all mod 2^32 (the level-local Morton code is the
+   * treeID minus the level's first treeID), and {k0, k1, t0, t1} =
+   * NBASE[b][i-1], the source is mo + ((mo - t0) >= t1 ? k1 : k0)
+   * (unsigned compare); its codes are not read.  Otherwise code c of
+   * element x: c >= 0xFFFC is the link code c - 0x10000 (-4..-1), else the
+   * source is NBASE[b][i-1][c >> 14] + (c & 0x3FFF).  A block with w >= 0
+   * is wide (regmask 0): its entry is the int32
    * (NBR_WIDE[i-1][w * 256 + x - 256 b] << 16) | c. */
   MLBM_TABLE_NBR16 = 7,    /* uint16 [q-1][n_blocks * 256]                  */
   MLBM_TABLE_NBASE = 8,    /* int32 [n_blocks][q-1][4]                      */
-  MLBM_TABLE_NBR_WIDE = 9  /* uint16 [q-1][n_wide * 256]                    */
+  MLBM_TABLE_NBR_WIDE = 9, /* uint16 [q-1][n_wide * 256]                    */
+  MLBM_TABLE_NBR_HDR = 10  /* int32 [n_blocks][4]                           */
 };
 
 /* Fields of mlbm_plan_level_info, in this order (int64 each). */
@@ -145,6 +152,14 @@ int32_t mlbm_plan_create(int32_t stencil, int32_t level0,
                          const uint64_t* solid_ids, int64_t n_solids,
                          mlbm_plan** out);
 void mlbm_plan_destroy(mlbm_plan* plan);
+/* Policy for Morton directions of the device pull table (MLBM_TABLE_NBR_HDR)
+ * in plans created after the call: a block uses them if at least
+ * block_min_directions of its directions qualify (1..26), a level if they
+ * cover at least level_min_fraction (0..1) of its (block, direction) pairs;
+ * defaults 0.5 and 6.  Results do not depend on it, only the traffic and
+ * instruction mix of the stream-collide.  Process-wide; not to be called
+ * while another thread creates a plan.  MLBM_E_ARG for values out of range. */
+int32_t mlbm_set_morton_policy(double level_min_fraction, int32_t block_min_directions);
 /* Number of levels (Lmax - L0 + 1) and L0. */
 int32_t mlbm_plan_levels(const mlbm_plan* plan, int32_t* n_levels,
                          int32_t* level0);

@@ -20,7 +20,8 @@ E_ARG, E_MESH, E_STATE, E_HIP, E_OOM = -1, -2, -3, -4, -5
 DIAG_MASS, DIAG_KE, DIAG_FORCE = 1, 2, 4
 STATUS_NONFINITE, STATUS_F16_OVERFLOW = 1, 2
 TABLE_TREEID, TABLE_COORDS, TABLE_NBR, TABLE_GFC_SRC, TABLE_GFF_SRC, \
-    TABLE_CAPTURE, TABLE_BOUNCE, TABLE_NBR16, TABLE_NBASE, TABLE_NBR_WIDE = range(10)
+    TABLE_CAPTURE, TABLE_BOUNCE, TABLE_NBR16, TABLE_NBASE, TABLE_NBR_WIDE, \
+    TABLE_NBR_HDR = range(11)
 STATE_PDF_POST, STATE_MOMENTS = 0, 1
 INFO_FIELDS = ("level", "n", "n_fluid", "n_gfc_inner", "n_gfc_outer", "n_gff",
                "n_cap_fluid", "n_cap", "n_gfc_groups", "n_bounce")
@@ -38,6 +39,7 @@ SIGNATURES = {
     "mlbm_plan_create": (_i32, [_i32, _i32, _pi32, _pi32, _pi32, _pu64, _i64, _pu64, _i64,
                                 C.POINTER(_p)]),
     "mlbm_plan_destroy": (None, [_p]),
+    "mlbm_set_morton_policy": (_i32, [C.c_double, _i32]),
     "mlbm_plan_levels": (_i32, [_p, _pi32, _pi32]),
     "mlbm_plan_level_info": (_i32, [_p, _i32, _pi64]),
     "mlbm_plan_export": (_i32, [_p, _i32, _i32, _p, _psz]),

@@ -24,6 +24,12 @@ def lattice(stencil: str):
     return c, w
 
 
+def set_morton_policy(level_min_fraction: float = 0.5, block_min_directions: int = 6):
+    """Policy for Morton directions of the device pull table in plans created
+    afterwards (mlbm_set_morton_policy); the defaults restore the library's."""
+    check(lib().mlbm_set_morton_policy(float(level_min_fraction), int(block_min_directions)))
+
+
 def _i32arr(v):
     a = np.ascontiguousarray(np.asarray(v, dtype=np.int32))
     return a, a.ctypes.data_as(_lib._pi32)
@@ -72,7 +78,8 @@ class Plan:
                "nbr": _lib.TABLE_NBR, "gfc_src": _lib.TABLE_GFC_SRC,
                "gff_src": _lib.TABLE_GFF_SRC, "capture": _lib.TABLE_CAPTURE,
                "bounce": _lib.TABLE_BOUNCE, "nbr16": _lib.TABLE_NBR16,
-               "nbase": _lib.TABLE_NBASE, "nbr_wide": _lib.TABLE_NBR_WIDE}[table]
+               "nbase": _lib.TABLE_NBASE, "nbr_wide": _lib.TABLE_NBR_WIDE,
+               "nbr_hdr": _lib.TABLE_NBR_HDR}[table]
         nbytes = C.c_size_t()
         check(lib().mlbm_plan_export(self._h, k, tid, None, C.byref(nbytes)))
         dtype = {"treeid": np.uint64, "nbr16": np.uint16, "nbr_wide": np.uint16}.get(table, np.int32)

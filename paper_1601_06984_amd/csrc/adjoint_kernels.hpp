@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_seed_ke(const typename Prec<P>::S* __re
   }
   C g[Lat::Q];
 #pragma unroll
-  for (int i = 0; i < Lat::Q; ++i) g[i] = load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[i], a.inv_scale);
+  for (int i = 0; i < Lat::Q; ++i) g[i] = load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[Lat::wclass(i)], a.inv_scale);
   C drho, rho, u[3];
   macro_g<Lat, C>(g, a.rho0, drho, rho, u);
   const C uu = dot_uu<Lat, C>(u);
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 5 : 1) void k_adj_sc
         if (ci > 0) mu += lj[b];
         if (ci < 0) mu -= lj[b];
       }
-      const int32_t v = pull_source<Q>(a, blk, xo, i);
+      const int32_t v = pull_source<Lat>(a, blk, xo, i);
       // scatter to the entry the pull read: (i, v), or (opp(i), x) for
       // bounce-back; one descriptor over the pair of opposite rows
       const int pair = (i & 1) ? i : i - 1;
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_adj_copy_pre(
   tmp[t * Q] = C(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i)
-    tmp[t * Q + i] = pull_source<Q>(a, x >> 8, (uint32_t)x, i) == MLBM_NBR_COPY ? mu[i] : C(0);
+    tmp[t * Q + i] = pull_source<Lat>(a, x >> 8, (uint32_t)x, i) == MLBM_NBR_COPY ? mu[i] : C(0);
 }
 
 // COPY links, part 2 (after k_adj_sc): lam_old[i][x] += tmp[t][i].

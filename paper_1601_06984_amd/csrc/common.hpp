@@ -29,6 +29,8 @@ struct D2Q9 {
   MLBM_HD static constexpr double w(int i) {
     return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
   }
+  // weight class: 0 rest, 1 axis, 2 diagonal
+  MLBM_HD static constexpr int wclass(int i) { return i == 0 ? 0 : (i <= 4 ? 1 : 2); }
   MLBM_HD static constexpr int opp(int i) {
     return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
   }
@@ -48,6 +50,8 @@ struct D3Q19 {
   MLBM_HD static constexpr double w(int i) {
     return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
   }
+  // weight class: 0 rest, 1 axis, 2 diagonal
+  MLBM_HD static constexpr int wclass(int i) { return i == 0 ? 0 : (i <= 6 ? 1 : 2); }
   MLBM_HD static constexpr int opp(int i) {
     return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
   }
@@ -80,6 +84,45 @@ constexpr int NBR_BLOCK = 256;
 constexpr int NBR_BASES = 4;
 constexpr int NBR_SPAN = 16380;
 constexpr uint32_t NBR_CODE0 = 0xFFFCu;
+// Per-block header of the pull table: mask of directions whose sources
+// follow from Morton arithmetic, Morton code minus index of the block's
+// elements (mod 2^32), wide row block (-1: none), unused.
+constexpr int NBR_HDR = 4;
+// offset past every code row: a lane that needs no code loads from here and
+// gets 0 from the buffer range check, without a memory access
+constexpr uint32_t NBR_NO_CODE = 0x7FFFFFF8u;
+// Default policy for Morton directions (mlbm_set_morton_policy): a block
+// takes them only if at least NBR_MIN_MORTON qualify, and a level only if
+// at least NBR_LEVEL_MIN_MORTON of its (block, direction) pairs would: a
+// block mixing both kinds decodes both readings, and a level with Morton
+// directions reads each block's header before its codes, which costs more
+// than a few saved code reads give back.
+constexpr int NBR_MIN_MORTON = 6;
+constexpr double NBR_LEVEL_MIN_MORTON = 0.5;
+
+// Level-local Morton code (treeID minus the level's first ID; bit b of axis
+// a at position d*b + a), kept to its low 32 bits.  Moving one cell along an
+// axis adds or subtracts the axis's lowest bit with the carry passed through
+// the other axes' bits (dilated integer arithmetic); modulo 2^32 this gives
+// the low 32 bits of the exact code.
+template <int D>
+MLBM_HD constexpr uint32_t morton_axis_bits(int a) {
+  return D == 3 ? (a == 0 ? 0x49249249u : (a == 1 ? 0x92492492u : 0x24924924u))
+                : (a == 0 ? 0x55555555u : 0xAAAAAAAAu);
+}
+template <int D>
+MLBM_HD inline uint32_t morton_step(uint32_t m, int a, int s) {
+  const uint32_t mask = morton_axis_bits<D>(a), one = 1u << a;
+  const uint32_t t = s > 0 ? (m | ~mask) + one : (m & mask) - one;
+  return (t & mask) | (m & ~mask);
+}
+// Morton code of the cell the pull of direction i reads: x - c_i.
+template <class Lat>
+MLBM_HD inline uint32_t morton_pull(uint32_t m, int i) {
+  for (int a = 0; a < Lat::D; ++a)
+    if (Lat::c(i, a) != 0) m = morton_step<Lat::D>(m, a, -Lat::c(i, a));
+  return m;
+}
 
 // Work-group order.  Consecutive work-groups of a launch go to the 8 XCDs in
 // turn (dispatch position b runs on XCD b mod 8), and each XCD has its own

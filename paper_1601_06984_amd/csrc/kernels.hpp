@@ -132,14 +132,16 @@ struct LevelArgs {
   const uint16_t* nbr16;
   const int32_t* nbase;
   const uint16_t* nbr_wide;
+  const int32_t* nhdr;  // [blocks][NBR_HDR]
+  int32_t morton;       // nonzero: blocks may hold Morton directions
   int64_t ld16, ldw;
   int64_t cap_begin;  // fluid elements [cap_begin, n_fluid) are sources
   int64_t n_fluid;
   C omega;            // BGK relaxation rate of the level
   C rho0;
   C scale, inv_scale; // F16S scale s_L and 1/s_L
-  C wr[Q];            // w_i rho0
-  C geq[Q];           // f^eq_i(rho0, u_in) - w_i rho0 for EQ faces
+  C wr[3];            // w_i rho0 per weight class (Lat::wclass)
+  const C* geq;       // device [Q]: f^eq_i(rho0, u_in) - w_i rho0 for EQ faces
   double u_in[3];     // EQ-face velocity
 };
 
@@ -188,7 +190,8 @@ __device__ __forceinline__ C dot_uu(const C* u) {
 
 // ------------------------------------------------------ pull gather ------
 // g_i(x) = g*_i(nbr_i(x)) with boundary codes: BOUNCE -> g*_opp(i)(x),
-// COPY -> g*_i(x), EQ -> f^eq(rho0, u_in); MISSING gives NaN.
+// COPY -> g*_i(x), EQ -> f^eq(rho0, u_in).  MISSING never occurs in an
+// updated range: the planner rejects meshes where it would.
 __device__ __forceinline__ uint32_t load_u16(const uint16_t* row, int64_t len, uint32_t e) {
   return (uint32_t)(uint16_t)__builtin_amdgcn_raw_buffer_load_b16(row_rsrc(row, len * 2),
                                                                   (int)(e * 2u), 0, 0);
@@ -203,41 +206,106 @@ __device__ __forceinline__ int32_t pull_decode(uint32_t c, int32_t b0, int32_t b
   return c >= NBR_CODE0 ? (int32_t)c - 0x10000 : base + (int32_t)(c & 0x3FFFu);
 }
 
+// Source of a Morton direction (see LevelPlan): the Morton code of x - c_i
+// shifted by the constant of its run; {k0, k1, t0, t1} are the slot values.
+template <class Lat>
+__device__ __forceinline__ int32_t morton_source(uint32_t m, int i, int32_t k0, int32_t k1,
+                                                 int32_t t0, int32_t t1) {
+  const uint32_t mo = morton_pull<Lat>(m, i);
+  return (int32_t)(mo + ((mo - (uint32_t)t0) >= (uint32_t)t1 ? (uint32_t)k1 : (uint32_t)k0));
+}
+
 // Pull sources j[1..Q-1] of element x in pull-table block blk (x >> 8).
 // Kernels whose work-groups cover whole blocks pass a block index that is
-// uniform over the work-group, so the bases come through scalar loads.  The
-// code loads and the base loads are independent; the wide-block flag is the
-// first base, so no load waits for another before the decode.
-template <int Q, class LA>
-__device__ __forceinline__ void pull_sources(const LA& a, int64_t blk, uint32_t x, int32_t* j) {
+// uniform over the work-group, so the header and slots come through scalar
+// loads.  Directions whose sources follow from Morton arithmetic read no
+// codes (their lanes load past the end of the row, which the buffer range
+// check answers with 0 and no memory access).  Both readings of a slot are
+// formed and one is kept by a mask, without branches, so that the code
+// loads of all directions are in flight together.
+template <class Lat, int MODE, class LA>
+__device__ __forceinline__ void pull_sources_mode(const LA& a, int64_t blk, uint32_t x,
+                                                  uint32_t regm, uint32_t m, int32_t* j) {
+  // MODE 0: every direction decodes its code; 1: every direction is a
+  // Morton direction; 2: the mask regm chooses per direction
+  constexpr int Q = Lat::Q;
   const int32_t* __restrict__ bb = a.nbase + blk * (Q - 1) * NBR_BASES;
-  uint32_t c[Q];
+  int32_t s[Q][NBR_BASES];
 #pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    c[i] = load_u16(a.nbr16 + (int64_t)(i - 1) * a.ld16, a.ld16, x);
-    const int32_t* b = bb + (i - 1) * NBR_BASES;
-    j[i] = pull_decode(c[i], b[0], b[1], b[2], b[3]);
-  }
-  const int32_t flag = bb[0];
-  if (flag < 0) {   // wide block: codes are the low halves of int32 entries
-    const uint32_t e = (uint32_t)(-1 - flag) * NBR_BLOCK + (x & (NBR_BLOCK - 1));
+  for (int i = 1; i < Q; ++i)
+#pragma unroll
+    for (int t = 0; t < NBR_BASES; ++t) s[i][t] = bb[(i - 1) * NBR_BASES + t];
+  uint32_t c[Q];
+  if constexpr (MODE != 1) {
 #pragma unroll
     for (int i = 1; i < Q; ++i)
-      j[i] = (int32_t)((load_u16(a.nbr_wide + (int64_t)(i - 1) * a.ldw, a.ldw, e) << 16) | c[i]);
+      c[i] = load_u16(a.nbr16 + (int64_t)(i - 1) * a.ld16, a.ld16,
+                      (MODE == 2 && ((regm >> i) & 1u)) ? NBR_NO_CODE : x);
+  }
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if constexpr (MODE == 0) {
+      j[i] = pull_decode(c[i], s[i][0], s[i][1], s[i][2], s[i][3]);
+    } else if constexpr (MODE == 1) {
+      j[i] = morton_source<Lat>(m, i, s[i][0], s[i][1], s[i][2], s[i][3]);
+    } else {
+      const uint32_t keep = 0u - ((regm >> i) & 1u);
+      const uint32_t jm = (uint32_t)morton_source<Lat>(m, i, s[i][0], s[i][1], s[i][2], s[i][3]);
+      const uint32_t jc = (uint32_t)pull_decode(c[i], s[i][0], s[i][1], s[i][2], s[i][3]);
+      j[i] = (int32_t)((jm & keep) | (jc & ~keep));
+    }
+  }
+  if constexpr (MODE == 0) {
+    const int32_t w = a.nhdr[blk * NBR_HDR + 2];
+    if (w >= 0) {   // wide block: codes are the low halves of int32 entries
+      const uint32_t e = (uint32_t)w * NBR_BLOCK + (x & (NBR_BLOCK - 1));
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        j[i] = (int32_t)((load_u16(a.nbr_wide + (int64_t)(i - 1) * a.ldw, a.ldw, e) << 16) | c[i]);
+    }
   }
 }
 
+// Pull sources j[1..Q-1] of element x in pull-table block blk (x >> 8).
+// Kernels whose work-groups cover whole blocks pass a block index that is
+// uniform over the work-group, so the header and slots come through scalar
+// loads and the choice below is a branch of the whole wave.  Directions
+// whose sources follow from Morton arithmetic read no codes (in a mixed
+// block their lanes load past the end of the row, which the buffer range
+// check answers with 0 and no memory access); a mixed block forms both
+// readings of a slot and keeps one by a mask, without branches, so that the
+// code loads of all directions are in flight together.
+template <class Lat, class LA>
+__device__ __forceinline__ void pull_sources(const LA& a, int64_t blk, uint32_t x, int32_t* j) {
+  constexpr uint32_t ALL = (1u << Lat::Q) - 2u;
+  if (!a.morton) {   // the level's blocks all decode codes: no header wait
+    pull_sources_mode<Lat, 0>(a, blk, x, 0u, 0u, j);
+    return;
+  }
+  const int32_t* __restrict__ hd = a.nhdr + blk * NBR_HDR;
+  const uint32_t regm = (uint32_t)hd[0];
+  const uint32_t m = x + (uint32_t)hd[1];
+  if (regm == 0)
+    pull_sources_mode<Lat, 0>(a, blk, x, regm, m, j);
+  else if (regm == ALL)
+    pull_sources_mode<Lat, 1>(a, blk, x, regm, m, j);
+  else
+    pull_sources_mode<Lat, 2>(a, blk, x, regm, m, j);
+}
+
 // Pull source of direction i only.
-template <int Q, class LA>
+template <class Lat, class LA>
 __device__ __forceinline__ int32_t pull_source(const LA& a, int64_t blk, uint32_t x, int i) {
-  const int32_t* __restrict__ bb = a.nbase + blk * (Q - 1) * NBR_BASES;
+  const int32_t* __restrict__ hd = a.nhdr + blk * NBR_HDR;
+  const int32_t* b = a.nbase + (blk * (Lat::Q - 1) + (i - 1)) * NBR_BASES;
+  if (a.morton && (((uint32_t)hd[0] >> i) & 1u))
+    return morton_source<Lat>(x + (uint32_t)hd[1], i, b[0], b[1], b[2], b[3]);
   const uint32_t c = load_u16(a.nbr16 + (int64_t)(i - 1) * a.ld16, a.ld16, x);
-  const int32_t* b = bb + (i - 1) * NBR_BASES;
   int32_t v = pull_decode(c, b[0], b[1], b[2], b[3]);
-  const int32_t flag = bb[0];
-  if (flag < 0)
+  const int32_t w = hd[2];
+  if (w >= 0)
     v = (int32_t)((load_u16(a.nbr_wide + (int64_t)(i - 1) * a.ldw, a.ldw,
-                            (uint32_t)(-1 - flag) * NBR_BLOCK + (x & (NBR_BLOCK - 1))) << 16) | c);
+                            (uint32_t)w * NBR_BLOCK + (x & (NBR_BLOCK - 1))) << 16) | c);
   return v;
 }
 
@@ -249,25 +317,32 @@ __device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__
   using C = typename Prec<P>::C;
   const uint32_t xo = (uint32_t)x;
   int32_t j[Lat::Q];
-  pull_sources<Lat::Q>(a, blk, xo, j);
+  pull_sources<Lat>(a, blk, xo, j);
   static_assert(opposite_weights_equal<Lat>(), "w(opp(i)) == w(i)");
   g[0] = load_row<P>(src, a.n, xo, a.wr[0], a.inv_scale);
   const uint32_t nn = (uint32_t)a.n;
+  uint32_t eqm = 0;   // directions pulled from an EQ face
 #pragma unroll
   for (int i = 1; i < Lat::Q; ++i) {
     // rows 2k-1 and 2k hold opposite directions: one descriptor over the
     // pair serves both the pull (row i) and halfway bounce-back (row
     // opp(i) at x) without a per-lane choice of base address; opposite
-    // directions have equal weights, so wr[i] fits both
+    // directions have equal weights, so one weight fits both
     const int pair = (i & 1) ? i : i - 1;
     const int32_t v = j[i];
     const uint32_t e = v >= 0 ? (uint32_t)v : xo;
     const uint32_t off = v == MLBM_NBR_BOUNCE ? (uint32_t)(Lat::opp(i) - pair) * nn + xo
                                              : (uint32_t)(i - pair) * nn + e;
-    C val = load_row<P>(src + (int64_t)pair * a.n, 2 * a.n, off, a.wr[i], a.inv_scale);
-    if (v == MLBM_NBR_EQ) val = a.geq[i];
-    if (v == MLBM_NBR_MISSING) val = C(__builtin_nan(""));
-    g[i] = val;
+    g[i] = load_row<P>(src + (int64_t)pair * a.n, 2 * a.n, off, a.wr[Lat::wclass(i)], a.inv_scale);
+    eqm |= (v == MLBM_NBR_EQ ? 1u : 0u) << i;
+  }
+  // elements next to an EQ face (few): the face's equilibrium replaces what
+  // the lanes loaded (their own entry); the values are read only here, so
+  // they hold no registers in the common path
+  if (eqm) {
+#pragma unroll
+    for (int i = 1; i < Lat::Q; ++i)
+      if ((eqm >> i) & 1u) g[i] = a.geq[i];
   }
 }
 
@@ -411,9 +486,9 @@ inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStr
     hipLaunchKernelGGL(kernel, grid, block, 0, st, static_cast<KArgs>(args)...);
 }
 
-// The stream-collide of work-group `blk` of a level whose updated range is
-// [0, x1): elements blk*BS .. blk*BS+BS-1.  `stage` is the work-group's
-// record staging area.
+// The stream-collide of work-group `blk` (blk*BS < x1) of a level whose
+// updated range is [0, x1): elements blk*BS .. blk*BS+BS-1.  `stage` is the
+// work-group's record staging area.
 template <class Lat, int P, int BS>
 __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
                                         const typename Prec<P>::S* __restrict__ src,
@@ -425,7 +500,6 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
   using C = typename Prec<P>::C;
   using Stager = WaveRecordStager<C, cap_stride(Lat::D)>;
   static_assert(BS == NBR_BLOCK, "a work-group covers one pull-table block");
-  if (blk * BS >= x1) return;   // padding work-group (whole group)
   const int64_t xr = blk * BS + threadIdx.x;
   const bool valid = xr < x1;
   // lanes past the end recompute the last element (in bounds, same block)
@@ -450,7 +524,7 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
-    ok &= store_row<P>(dst + (int64_t)i * a.n, a.n, (uint32_t)x, gs, a.wr[i], a.scale);
+    ok &= store_row<P>(dst + (int64_t)i * a.n, a.n, (uint32_t)x, gs, a.wr[Lat::wclass(i)], a.scale);
   }
   const bool finite = (rho == rho) && (rho - rho == C(0));
   if (!finite || !ok)
@@ -535,7 +609,7 @@ __device__ __forceinline__ bool emit_ghost(typename Prec<P>::S* __restrict__ pdf
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const C gs = geq_i<Lat, C>(i, drho, rho, u, uu) + (C(1) - a.omega) * fneq[i];
-    ok &= store_g<P>(pdf, (int64_t)i * a.n + x, gs, a.wr[i], a.scale);
+    ok &= store_g<P>(pdf, (int64_t)i * a.n + x, gs, a.wr[Lat::wclass(i)], a.scale);
   }
   return ok;
 }
@@ -891,7 +965,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho_in,
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const double gs = g[i] + omega * (geq_i<Lat, double>(i, drho, rho, u, uu) - g[i]);
-    store_g<P>(pdf, (int64_t)i * a.n + x, (typename Prec<P>::C)gs, a.wr[i], a.scale);
+    store_g<P>(pdf, (int64_t)i * a.n + x, (typename Prec<P>::C)gs, a.wr[Lat::wclass(i)], a.scale);
   }
 }
 
@@ -941,7 +1015,7 @@ __global__ __launch_bounds__(256) void k_get_pdf(const typename Prec<P>::S* __re
   if (x >= n) return;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
-    out[(int64_t)i * n + x] = (double)a.wr[i] + (double)load_g<P>(pdf, (int64_t)i * n + x, a.wr[i], a.inv_scale);
+    out[(int64_t)i * n + x] = (double)a.wr[Lat::wclass(i)] + (double)load_g<P>(pdf, (int64_t)i * n + x, a.wr[Lat::wclass(i)], a.inv_scale);
 }
 
 template <class Lat, int P>
@@ -952,8 +1026,8 @@ __global__ __launch_bounds__(256) void k_set_pdf(typename Prec<P>::S* __restrict
   if (x >= n) return;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
-    store_g<P>(pdf, (int64_t)i * n + x, (typename Prec<P>::C)(in[(int64_t)i * n + x] - (double)a.wr[i]),
-               a.wr[i], a.scale);
+    store_g<P>(pdf, (int64_t)i * n + x, (typename Prec<P>::C)(in[(int64_t)i * n + x] - (double)a.wr[Lat::wclass(i)]),
+               a.wr[Lat::wclass(i)], a.scale);
 }
 
 template <class Lat, int P>
@@ -965,7 +1039,7 @@ __global__ __launch_bounds__(256) void k_get_moments(const typename Prec<P>::S* 
   if (x >= nf) return;
   double g[Lat::Q];
 #pragma unroll
-  for (int i = 0; i < Lat::Q; ++i) g[i] = (double)load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[i], a.inv_scale);
+  for (int i = 0; i < Lat::Q; ++i) g[i] = (double)load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[Lat::wclass(i)], a.inv_scale);
   double drho, rho, u[3];
   macro_g<Lat, double>(g, (double)a.rho0, drho, rho, u);
   out[x] = rho;
@@ -1001,7 +1075,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(
        x += (int64_t)gridDim.x * 256) {
     double g[Lat::Q];
 #pragma unroll
-    for (int i = 0; i < Lat::Q; ++i) g[i] = (double)load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[i], a.inv_scale);
+    for (int i = 0; i < Lat::Q; ++i) g[i] = (double)load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[Lat::wclass(i)], a.inv_scale);
     double drho, rho, u[3];
     macro_g<Lat, double>(g, (double)a.rho0, drho, rho, u);
     m += drho;
@@ -1014,7 +1088,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(
     const int64_t x = bounce[t];
     const int j = bounce[n_bounce + t];
     const int i = Lat::opp(j);
-    const double f = (double)a.wr[i] + (double)load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[i], a.inv_scale);
+    const double f = (double)a.wr[Lat::wclass(i)] + (double)load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[Lat::wclass(i)], a.inv_scale);
 #pragma unroll
     for (int b = 0; b < Lat::D; ++b) F[b] += 2.0 * Lat::c(i, b) * f;
   }

@@ -20,6 +20,8 @@ inline LevelArgs<C, Q> level_args(const SimState& s, int k) {
   a.nbr16 = L.nbr16;
   a.nbase = L.nbase;
   a.nbr_wide = L.nbr_wide;
+  a.nhdr = L.nhdr;
+  a.morton = L.morton ? 1 : 0;
   a.ld16 = L.ld16;
   a.ldw = L.ldw;
   a.cap_begin = L.n_fluid - L.n_cap_fluid;
@@ -28,10 +30,8 @@ inline LevelArgs<C, Q> level_args(const SimState& s, int k) {
   a.rho0 = (C)s.rho0;
   a.scale = (C)std::ldexp(1.0, L.f16_exp);
   a.inv_scale = (C)std::ldexp(1.0, -L.f16_exp);
-  for (int i = 0; i < Q; ++i) {
-    a.wr[i] = (C)s.wr[i];
-    a.geq[i] = (C)s.geq[i];
-  }
+  for (int i = 0; i < Q; ++i) a.wr[s.d == 3 ? D3Q19::wclass(i) : D2Q9::wclass(i)] = (C)s.wr[i];
+  a.geq = (const C*)s.geq_dev;
   for (int b = 0; b < 3; ++b) a.u_in[b] = s.u_in[b];
   return a;
 }

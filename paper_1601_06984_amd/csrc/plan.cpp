@@ -247,7 +247,96 @@ struct PhaseTimer {
 // Device form of the pull table (LevelPlan::nbr16 ...): per block and
 // direction the distinct neighbour indices are grouped greedily in
 // ascending order into runs shorter than NBR_SPAN, one base per run.
-void compress_pull_table(LevelPlan& lp, int q) {
+// Morton-direction policy for plans created from now on.
+double g_morton_level_min = NBR_LEVEL_MIN_MORTON;
+int g_morton_block_min = NBR_MIN_MORTON;
+
+// Marks the (block, direction) pairs whose sources follow from Morton
+// arithmetic: every element of the block has Morton code x + kself, and
+// the sources of direction i are mo + k0 below the threshold t0 + t1 and
+// mo + k1 from it, mo being the Morton code of x - c_i (all mod 2^32).
+// A block keeps them if it has g_morton_block_min of them, the level only
+// if they cover g_morton_level_min of its (block, direction) pairs.
+template <class Lat>
+void mark_morton_directions(LevelPlan& lp, uint64_t first, const std::vector<char>& wide) {
+  constexpr int q = Lat::Q;
+  const int64_t n = lp.n, act = lp.n_active_max(), nblk = lp.n_nbr_blocks();
+  const int64_t ld = nblk * NBR_BLOCK;
+  std::vector<uint32_t> regm((size_t)nblk, 0), kself((size_t)nblk, 0);
+  std::vector<uint32_t> slot((size_t)nblk * (q - 1) * 4, 0);
+  parallel_for(nblk, [&](int64_t b0, int64_t b1) {
+    std::pair<uint32_t, uint32_t> rk[NBR_BLOCK];
+    uint32_t m[NBR_BLOCK];
+    for (int64_t b = b0; b < b1; ++b) {
+      if (wide[b]) continue;
+      const int64_t x0 = b * NBR_BLOCK;
+      const int cnt = (int)(std::min(act, x0 + NBR_BLOCK) - x0);
+      const uint32_t ks = (uint32_t)(lp.tid[x0] - first) - (uint32_t)x0;
+      bool same = true;
+      for (int l = 0; l < cnt && same; ++l) {
+        m[l] = (uint32_t)(lp.tid[x0 + l] - first);
+        same = m[l] - (uint32_t)(x0 + l) == ks;
+      }
+      if (!same) continue;
+      uint32_t rm = 0;
+      uint32_t* sl = &slot[(size_t)b * (q - 1) * 4];
+      for (int i = 1; i < q; ++i) {
+        const int32_t* row = &lp.nbr[(size_t)(i - 1) * n + x0];
+        bool ok = true;
+        uint32_t t0 = 0xFFFFFFFFu;
+        for (int l = 0; l < cnt && ok; ++l) {
+          ok = row[l] >= 0;
+          const uint32_t mo = morton_pull<Lat>(m[l], i);
+          rk[l] = {mo, (uint32_t)row[l] - mo};
+          t0 = std::min(t0, mo);
+        }
+        if (!ok) continue;
+        for (int l = 0; l < cnt; ++l) rk[l].first -= t0;
+        std::sort(rk, rk + cnt);
+        if (rk[cnt - 1].first >= 0x80000000u) continue;
+        const uint32_t k0 = rk[0].second;
+        int l = 0;
+        while (l < cnt && rk[l].second == k0) ++l;
+        const uint32_t t1 = l < cnt ? rk[l].first : 0xFFFFFFFFu;
+        const uint32_t k1 = l < cnt ? rk[l].second : k0;
+        for (; l < cnt && ok; ++l) ok = rk[l].second == k1;
+        if (!ok) continue;
+        rm |= 1u << i;
+        uint32_t* s4 = sl + (i - 1) * 4;
+        s4[0] = k0;
+        s4[1] = k1;
+        s4[2] = t0;
+        s4[3] = t1;
+      }
+      if (__builtin_popcount(rm) >= g_morton_block_min) {
+        regm[b] = rm;
+        kself[b] = ks;
+      }
+    }
+  });
+  int64_t pairs = 0;
+  for (int64_t b = 0; b < nblk; ++b) pairs += __builtin_popcount(regm[b]);
+  lp.morton = pairs > 0 && (double)pairs >= g_morton_level_min * (double)(nblk * (q - 1));
+  if (!lp.morton) return;
+  parallel_for(nblk, [&](int64_t b0, int64_t b1) {
+    for (int64_t b = b0; b < b1; ++b) {
+      if (!regm[b]) continue;
+      const int64_t x0 = b * NBR_BLOCK;
+      const int cnt = (int)(std::min(act, x0 + NBR_BLOCK) - x0);
+      for (int i = 1; i < q; ++i) {
+        if (!((regm[b] >> i) & 1u)) continue;
+        int32_t* bb = &lp.nbase[((size_t)b * (q - 1) + (i - 1)) * NBR_BASES];
+        const uint32_t* s4 = &slot[((size_t)b * (q - 1) + (i - 1)) * 4];
+        for (int t = 0; t < 4; ++t) bb[t] = (int32_t)s4[t];
+        for (int e = 0; e < cnt; ++e) lp.nbr16[(size_t)(i - 1) * ld + x0 + e] = 0;
+      }
+      lp.nhdr[(size_t)b * NBR_HDR + 0] = (int32_t)regm[b];
+      lp.nhdr[(size_t)b * NBR_HDR + 1] = (int32_t)kself[b];
+    }
+  });
+}
+
+void compress_pull_table(LevelPlan& lp, int q, int d, uint64_t first) {
   const int64_t n = lp.n, act = lp.n_active_max(), nblk = lp.n_nbr_blocks();
   const int64_t ld = nblk * NBR_BLOCK;
   lp.nbr16.assign((size_t)(q - 1) * ld, (uint16_t)0xFFFFu);
@@ -298,11 +387,13 @@ void compress_pull_table(LevelPlan& lp, int q) {
   lp.n_wide = (int64_t)wide_blocks.size();
   const int64_t ldw = lp.n_wide * NBR_BLOCK;
   lp.nbr_wide.assign((size_t)(q - 1) * ldw, (uint16_t)0xFFFFu);
+  lp.nhdr.assign((size_t)nblk * NBR_HDR, 0);
+  for (int64_t b = 0; b < nblk; ++b) lp.nhdr[(size_t)b * NBR_HDR + 2] = -1;
   for (int64_t w = 0; w < lp.n_wide; ++w) {
     const int64_t b = wide_blocks[w];
     int32_t* bb = &lp.nbase[(size_t)b * (q - 1) * NBR_BASES];
     for (int t = 0; t < (q - 1) * NBR_BASES; ++t) bb[t] = 0;
-    bb[0] = (int32_t)(-1 - w);
+    lp.nhdr[(size_t)b * NBR_HDR + 2] = (int32_t)w;
     const int64_t x0 = b * NBR_BLOCK, x1 = std::min(act, x0 + NBR_BLOCK);
     for (int i = 1; i < q; ++i)
       for (int64_t x = x0; x < x1; ++x) {
@@ -311,6 +402,10 @@ void compress_pull_table(LevelPlan& lp, int q) {
         lp.nbr_wide[(size_t)(i - 1) * ldw + (size_t)w * NBR_BLOCK + (x - x0)] = (uint16_t)(v >> 16);
       }
   }
+  if (d == 3)
+    mark_morton_directions<D3Q19>(lp, first, wide);
+  else
+    mark_morton_directions<D2Q9>(lp, first, wide);
 }
 
 void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
@@ -694,7 +789,7 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
       b[nb + j] = lp.bounce[2 * j + 1];
     }
     lp.bounce.swap(b);
-    compress_pull_table(lp, q);
+    compress_pull_table(lp, q, d, level_first_id(L, d));
   }
 
   T.mark("neighbours");
@@ -971,6 +1066,15 @@ int32_t mlbm_lattice(int32_t stencil, int32_t* q, int32_t* c, double* w) {
   return MLBM_OK;
 }
 
+int32_t mlbm_set_morton_policy(double level_min_fraction, int32_t block_min_directions) {
+  if (!(level_min_fraction >= 0.0 && level_min_fraction <= 1.0) || block_min_directions < 1 ||
+      block_min_directions > 26)
+    return fail(MLBM_E_ARG, "bad Morton policy (%g, %d)", level_min_fraction, block_min_directions);
+  g_morton_level_min = level_min_fraction;
+  g_morton_block_min = block_min_directions;
+  return MLBM_OK;
+}
+
 int32_t mlbm_plan_create(int32_t stencil, int32_t level0, const int32_t* box_origin,
                          const int32_t* box_extent, const int32_t* face_bc,
                          const uint64_t* leaf_ids, int64_t n_leaves,
@@ -1060,6 +1164,7 @@ int32_t mlbm_plan_export(const mlbm_plan* plan, int32_t k, int32_t table, void* 
     case MLBM_TABLE_BOUNCE: src = lp.bounce.data(); n = lp.bounce.size() * 4; break;
     case MLBM_TABLE_NBR16: src = lp.nbr16.data(); n = lp.nbr16.size() * 2; break;
     case MLBM_TABLE_NBASE: src = lp.nbase.data(); n = lp.nbase.size() * 4; break;
+    case MLBM_TABLE_NBR_HDR: src = lp.nhdr.data(); n = lp.nhdr.size() * 4; break;
     case MLBM_TABLE_NBR_WIDE: src = lp.nbr_wide.data(); n = lp.nbr_wide.size() * 2; break;
     default: return fail(MLBM_E_ARG, "unknown table %d", table);
   }

@@ -28,12 +28,17 @@ struct LevelPlan {
   // of NBR_BLOCK elements: per (block, direction) up to NBR_BASES base
   // indices and per entry a 16-bit code (base << 14 | offset from it), or
   // 0xFFFC..0xFFFF for the link codes -4..-1.  A block whose neighbours
-  // need more bases is "wide": nbase[b][0][0] = -1 - w marks it, its code
-  // rows hold the low 16 bits of the int32 entries and row block w of
-  // nbr_wide the high 16 bits.
+  // need more bases is "wide": nhdr[b][2] = w marks it, its code rows hold
+  // the low 16 bits of the int32 entries and row block w of nbr_wide the
+  // high 16 bits.  A direction whose sources in the block are the Morton
+  // neighbours of the elements shifted by at most two constants (runs of
+  // the treeID order split at one Morton threshold) reads no codes: its
+  // bit is set in nhdr[b][0] and its slot holds {k0, k1, t0, t1}.
   std::vector<uint16_t> nbr16;     // [q-1][n_nbr_blocks * NBR_BLOCK]
   std::vector<int32_t> nbase;      // [n_nbr_blocks][q-1][NBR_BASES]
   std::vector<uint16_t> nbr_wide;  // [q-1][n_wide * NBR_BLOCK]
+  std::vector<int32_t> nhdr;       // [n_nbr_blocks][NBR_HDR]
+  bool morton = false;             // some blocks hold Morton directions
   int64_t n_wide = 0;
 
   // adjoint tables

@@ -45,6 +45,7 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
     char* n16 = take(lp.nbr16.size() * 2);
     char* nbs = take(lp.nbase.size() * 4);
     char* nwd = take(lp.nbr_wide.size() * 2);
+    char* nhd = take(lp.nhdr.size() * 4);
     char* ce = take((size_t)lp.n_cap_fluid() * 4);
     char* cap = take((size_t)lp.n_cap() * cap_stride(d) * cb);
     char* gs = take((size_t)4 * lp.n_gff * 4);
@@ -57,6 +58,7 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
       L->nbr16 = (uint16_t*)n16;
       L->nbase = (int32_t*)nbs;
       L->nbr_wide = (uint16_t*)nwd;
+      L->nhdr = (int32_t*)nhd;
       L->ld16 = lp.n_nbr_blocks() * NBR_BLOCK;
       L->ldw = lp.n_wide * NBR_BLOCK;
       L->cap_elem = (int32_t*)ce;
@@ -71,11 +73,13 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
   char* part = take((size_t)P.nlev() * DIAG_BLOCKS * DIAG_VALS * 8);
   char* dl = take((size_t)P.nlev() * sizeof(DiagLevel));
   char* md = take(256 * 8);
+  char* gq = take((size_t)q * cb);
   if (s) {
     s->status = (uint32_t*)st;
     s->partial = (double*)part;
     s->diag_levels = dl;
     s->maxdev = (double*)md;
+    s->geq_dev = gq;
   }
   return off;
 }
@@ -266,6 +270,7 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
     L.n_cap = lp.n_cap();
     L.n_groups = lp.n_groups;
     L.n_bounce = lp.n_bounce();
+    L.morton = lp.morton;
     const double tau = 0.5 + std::ldexp(tau0 - 0.5, lp.level - plan->level0);
     L.omega = 1.0 / tau;
     L.f16_exp = f16_exp ? f16_exp[k] : 0;
@@ -297,6 +302,7 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
     up(L.nbr16, lp.nbr16.data(), lp.nbr16.size() * 2);
     up(L.nbase, lp.nbase.data(), lp.nbase.size() * 4);
     up(L.nbr_wide, lp.nbr_wide.data(), lp.nbr_wide.size() * 2);
+    up(L.nhdr, lp.nhdr.data(), lp.nhdr.size() * 4);
     up(L.cap_elem, lp.cap_elem.data(), lp.cap_elem.size() * 4);
     up(L.gff_slot, lp.gff_slot.data(), lp.gff_slot.size() * 4);
     up(L.grp_src, lp.grp_src.data(), lp.grp_src.size() * 4);
@@ -311,6 +317,12 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
     dl[k].rho0_nf = rho0 * (double)plan->lv[k].n_fluid;
   }
   up(s.diag_levels, dl.data(), dl.size() * sizeof(DiagLevel));
+  std::vector<double> geq_d(s.geq, s.geq + s.q);
+  std::vector<float> geq_f(s.geq, s.geq + s.q);
+  if (compute_bytes(precision) == 8)
+    up(s.geq_dev, geq_d.data(), geq_d.size() * 8);
+  else
+    up(s.geq_dev, geq_f.data(), geq_f.size() * 4);
   if (e == hipSuccess) e = hipMemsetAsync(s.status, 0, 256, s.stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
   if (e != hipSuccess) {

@@ -21,6 +21,8 @@ struct DevLevel {
   uint16_t* nbr16 = nullptr;          // pull table, device form: [q-1][ld16]
   int32_t* nbase = nullptr;           // [blocks][q-1][NBR_BASES]
   uint16_t* nbr_wide = nullptr;       // [q-1][ldw] high halves of wide blocks
+  int32_t* nhdr = nullptr;            // [blocks][NBR_HDR]
+  bool morton = false;                // blocks may hold Morton directions
   int64_t ld16 = 0, ldw = 0;
   int32_t* cap_elem = nullptr;        // [n_cap_fluid]
   void* cap = nullptr;                // [n_cap][cap_stride] compute type
@@ -113,6 +115,7 @@ struct SimState {
   double* partial = nullptr;
   void* diag_levels = nullptr;
   double* maxdev = nullptr;
+  void* geq_dev = nullptr;             // [q] EQ-face values in the compute type
   std::vector<bool> inited;
   bool filled = false;
   int64_t time = 0;

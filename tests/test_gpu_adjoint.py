@@ -84,12 +84,14 @@ CASES = [
     ("d3q19_2lev_ke", lambda: W.refined_box_mesh("D3Q19", 4, 4, 12), 16, 4, 0.56),
     ("d2q9_2lev_ke", lambda: W.refined_box_mesh("D2Q9", 5, 8, 24), 32, 6, 0.6),
     ("d2q9_3lev_ke", lambda: W.refined_box_mesh("D2Q9", 5, 8, 24, extra_levels=[(20, 44)]), 32, 3, 0.7),
+    # a coarse level whose blocks hold Morton directions of the pull table
+    ("d3q19_morton_ke", lambda: W.refined_box_mesh("D3Q19", 5, 14, 18), 32, 3, 0.56),
 ]
 
 
 @pytest.mark.parametrize("name,spec_fn,n0,steps,tau0", CASES)
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-8), ("f32", 2e-4)])
-def test_ke_gradient_matches_oracle_reverse(name, spec_fn, n0, steps, tau0, precision, tol):
+def test_ke_gradient_matches_oracle_reverse(name, spec_fn, n0, steps, tau0, precision, tol, morton):
     spec = spec_fn()
     fields = lambda p: W.tgv_perturbed_fields(p, n0, 0.03)
     _say(name, precision, steps)

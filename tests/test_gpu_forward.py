@@ -46,7 +46,7 @@ def test_config1_d2q9_f64_tgv_200_steps():
 
 @pytest.mark.timeout(400)
 @pytest.mark.parametrize("base,lo,hi", [(5, 8, 24), (6, 16, 48)])
-def test_config2_d3q19_f32_100_steps(base, lo, hi):
+def test_config2_d3q19_f32_100_steps(base, lo, hi, morton):
     """D3Q19 TGV with the central cube refined, u0 = 0.02, Re = 100
     (tau0 = 0.5 + 3 u0 N/(2 pi Re)), FP32 storage and collision: max
     relative pdf error <= 1e-5 after 100 coarse steps (64^3 is the full
@@ -82,8 +82,11 @@ def test_config2_d3q19_f16s_100_steps():
     ("d2q9_3lev", lambda: W.refined_box_mesh("D2Q9", 5, 8, 24, extra_levels=[(20, 44)]), 32, 20),
     ("d3q19_3lev", lambda: W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)]), 16, 6),
     ("d2q9_half", lambda: W.half_refined_2d(5), 32, 40),
+    # coarse levels whose blocks hold Morton directions of the pull table
+    ("d3q19_morton", lambda: W.refined_box_mesh("D3Q19", 5, 14, 18), 32, 8),
+    ("d2q9_morton", lambda: W.refined_box_mesh("D2Q9", 7, 56, 72), 128, 20),
 ])
-def test_multilevel_f64_against_oracle(name, spec_fn, n0, steps):
+def test_multilevel_f64_against_oracle(name, spec_fn, n0, steps, morton):
     spec = spec_fn()
     _say(name, "f64", steps)
     osim = H.oracle_run(spec, 0.7, H.tgv(n0, 0.03), steps)
@@ -209,6 +212,30 @@ def test_graph_replay_matches_direct_launches():
     for n in (1, 4, 3, 6):
         a.step(n)
         b.step(n)
+    for k in range(a.plan.n_levels):
+        assert torch.equal(a.get_pdf(k), b.get_pdf(k))
+
+
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19"])
+def test_grouped_launches_match_per_level_launches(stencil):
+    """Stream-collides of different levels launched as one grid give the
+    same bits as one launch per level (the profiled schedule), on three
+    levels where groups of two and three levels occur."""
+    if stencil == "D3Q19":
+        spec = W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)])
+    else:
+        spec = W.refined_box_mesh("D2Q9", 5, 6, 26, extra_levels=[(20, 36)])
+    n0 = 16 if stencil == "D3Q19" else 32
+    _say(f"grouped vs per-level launches {stencil}")
+    a = H.gpu_sim(spec, "f32", 0.56, H.tgv(n0, 0.03))
+    b = H.gpu_sim(spec, "f32", 0.56, H.tgv(n0, 0.03))
+    a.use_graphs(False)
+    b.use_graphs(False)
+    b.profile(True)
+    for n in (1, 2, 3):
+        a.step(n)
+        b.step(n)
+    b.profile(False)
     for k in range(a.plan.n_levels):
         assert torch.equal(a.get_pdf(k), b.get_pdf(k))
 

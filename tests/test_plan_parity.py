@@ -108,15 +108,38 @@ def test_plan_tables_bit_exact(name):
 COMPRESS_MESHES = dict(MESHES)
 # large enough to hold blocks whose neighbours need more than four bases
 COMPRESS_MESHES["tgv64_refined"] = lambda: W.refined_box_mesh("D3Q19", 6, 16, 48)
+# levels that take Morton directions under the default policy
+COMPRESS_MESHES["sphere_d12"] = lambda: W.sphere_channel_mesh(12, 3, outlet="eq")
+COMPRESS_MESHES["d3q19_morton"] = lambda: W.refined_box_mesh("D3Q19", 5, 14, 18)
+COMPRESS_MESHES["d2q9_morton"] = lambda: W.refined_box_mesh("D2Q9", 7, 56, 72)
+
+
+def _morton_pull(m, c, d):
+    """Low 32 bits of the Morton code of (cell of code m) - c: each axis
+    step moves the axis's interleaved bits by one, carrying through the
+    other axes' bits (the 32-bit masks of bit positions d*b + a)."""
+    masks = [0x49249249, 0x92492492, 0x24924924] if d == 3 else [0x55555555, 0xAAAAAAAA]
+    m = m.astype(np.uint64)
+    full = np.uint64(0xFFFFFFFF)
+    for a in range(d):
+        s = -c[a]
+        if s == 0:
+            continue
+        mask = np.uint64(masks[a]); one = np.uint64(1 << a)
+        t = ((m | (~mask & full)) + one) if s > 0 else ((m & mask) + full + np.uint64(1) - one)
+        m = ((t & mask) | (m & (~mask & full))) & full
+    return m
 
 
 @pytest.mark.parametrize("name", sorted(COMPRESS_MESHES))
-def test_compressed_pull_table_decodes_to_the_table(name):
-    """The device form of the pull table (16-bit codes against per-block
-    bases, int32 rows for wide blocks) decodes to exactly the int32 table
-    over every updated element."""
+def test_compressed_pull_table_decodes_to_the_table(name, morton):
+    """The device form of the pull table (Morton directions, 16-bit codes
+    against per-block bases, int32 rows for wide blocks) decodes to exactly
+    the int32 table over every updated element."""
     plan = M.Plan.from_spec(COMPRESS_MESHES[name]())
-    n_wide = 0
+    d = plan.d
+    cvel, _ = M.lattice(plan.stencil)
+    n_wide = n_mor = n_dir = 0
     for k, inf in enumerate(plan.info):
         nbr = plan.export(k, "nbr")
         q1 = nbr.shape[0]
@@ -124,23 +147,63 @@ def test_compressed_pull_table_decodes_to_the_table(name):
         nblk = (act + 255) // 256
         c16 = plan.export(k, "nbr16").astype(np.int64)
         base = plan.export(k, "nbase").reshape(nblk, q1, 4).astype(np.int64)
+        hdr = plan.export(k, "nbr_hdr").reshape(nblk, 4).astype(np.int64)
         hi = plan.export(k, "nbr_wide").astype(np.int64)
-        flag = base[:, 0, 0]
-        n_wide += int((flag < 0).sum())
+        tid = plan.export(k, "treeid")
+        coords = plan.export(k, "coords")
+        n_wide += int((hdr[:, 2] >= 0).sum())
         assert c16.shape == (q1, nblk * 256)
         x = np.arange(act)
         b = x // 256
-        w = np.where(flag[b] < 0, -1 - flag[b], -1)
+        w = hdr[b, 2]
+        regm = hdr[b, 0] & 0xFFFFFFFF
+        m = (x + (hdr[b, 1] & 0xFFFFFFFF)) & 0xFFFFFFFF
+        # the block's Morton codes are its treeIDs minus the level's first ID
+        mor_blk = hdr[b, 0] != 0
+        first = tid[0] - _morton_of(coords[:, :1], d, plan.level0 + k)[0]
+        assert np.array_equal(m[mor_blk].astype(np.uint64),
+                              (tid[:act][mor_blk] - first) & np.uint64(0xFFFFFFFF))
         for i in range(q1):
             c = c16[i, :act]
             dec = np.where(c >= 0xFFFC, c - 0x10000,
                            base[b, i, np.minimum(c >> 14, 3)] + (c & 0x3FFF))
+            mor = ((regm >> (i + 1)) & 1).astype(bool)
+            if mor.any():
+                ci = [int(v) for v in cvel[i + 1]]
+                mo = _morton_pull(m[mor], ci, d).astype(np.int64)
+                bb = base[b[mor], i] & 0xFFFFFFFF
+                sel = ((mo - bb[:, 2]) & 0xFFFFFFFF) >= bb[:, 3]
+                src = (mo + np.where(sel, bb[:, 1], bb[:, 0])) & 0xFFFFFFFF
+                dec[mor] = np.where(src >= 1 << 31, src - (1 << 32), src)
+                assert (w[mor] < 0).all()
             if (w >= 0).any():
                 full = (hi[i, w[w >= 0] * 256 + x[w >= 0] % 256] << 16) | c[w >= 0]
                 dec[w >= 0] = np.where(full >= 1 << 31, full - (1 << 32), full)
             assert np.array_equal(dec, nbr[i, :act]), (name, k, i)
+            n_mor += int(mor.sum()); n_dir += act
     if name == "tgv64_refined":
         assert n_wide > 0
+    if name in ("sphere_d12", "d3q19_morton", "d2q9_morton") or (
+            morton == "morton" and name == "tgv64_refined"):
+        assert n_mor > 0.15 * n_dir, (name, n_mor, n_dir)
+    if morton == "default" and name == "tgv64_refined":
+        assert n_mor == 0   # levels with few Morton directions keep the codes
+
+
+def test_morton_policy_rejects_bad_values():
+    with pytest.raises(M.MLBMError):
+        M.set_morton_policy(1.5, 6)
+    with pytest.raises(M.MLBMError):
+        M.set_morton_policy(0.5, 0)
+    M.set_morton_policy()
+
+
+def _morton_of(coords, d, L):
+    m = np.zeros(coords.shape[1], dtype=np.uint64)
+    for bit in range(L):
+        for a in range(d):
+            m |= ((coords[a].astype(np.uint64) >> np.uint64(bit)) & np.uint64(1)) << np.uint64(d * bit + a)
+    return m
 
 
 def test_every_header_symbol_is_exported():
