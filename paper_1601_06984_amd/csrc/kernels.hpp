@@ -595,6 +595,30 @@ struct Rec {
   __device__ C fneq(int i) const { return p[cap_fneq(Lat::D) + i]; }
 };
 
+// A capture record read into registers with 16-byte loads (records start at
+// multiples of their 64-byte-or-more stride; the loads stay inside it).
+template <class Lat, class C>
+struct RecV {
+  static constexpr int V = 16 / (int)sizeof(C);
+  static constexpr int N = (cap_used(Lat::D) + V - 1) / V;
+  static_assert(N * V <= cap_stride(Lat::D), "record loads stay in the record");
+  typedef C VT __attribute__((ext_vector_type(16 / sizeof(C))));
+  C v[N * V];
+  __device__ __forceinline__ void load(const C* __restrict__ p) {
+    const VT* q = reinterpret_cast<const VT*>(p);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const VT t = q[k];
+#pragma unroll
+      for (int e = 0; e < V; ++e) v[k * V + e] = t[e];
+    }
+  }
+  __device__ C drho() const { return v[cap_rho(Lat::D)]; }
+  __device__ C u(int a) const { return v[cap_u(Lat::D) + a]; }
+  __device__ C S(int k) const { return v[cap_s(Lat::D) + k]; }
+  __device__ C fneq(int i) const { return v[cap_fneq(Lat::D) + i]; }
+};
+
 // Writes the interpolated ghost: g* = g_eq(rho, u) + (1 - omega_t) g^neq
 // into the pdf array; optionally its pre-collision record.
 template <class Lat, int P>
@@ -626,9 +650,9 @@ __device__ __forceinline__ void gff_values(const int32_t* __restrict__ slots, in
                                            int64_t j, const C* __restrict__ cap_fine,
                                            C fneq_scale, C& drho, C* u, C* fneq) {
   constexpr int D = Lat::D;
-  Rec<Lat, C> r[4];
+  RecV<Lat, C> r[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) r[k].p = cap_fine + (int64_t)slots[k * n_gff + j] * cap_stride(D);
+  for (int k = 0; k < 4; ++k) r[k].load(cap_fine + (int64_t)slots[k * n_gff + j] * cap_stride(D));
   u[0] = u[1] = u[2] = C(0);
   drho = 0;
 #pragma unroll
@@ -788,9 +812,10 @@ __device__ __forceinline__ void gfc_groups(
       RowWriter<C> w{dst};
       ghost_record<Lat, C>(w, drho, u, fneq, fly.omega, fly.rho0);
     } else if (slot >= 0) {
-      const C* src = cap_coarse + (int64_t)slot * ST;
+      RecV<Lat, C> src;
+      src.load(cap_coarse + (int64_t)slot * ST);
 #pragma unroll
-      for (int c = 0; c < USED; ++c) dst[c] = src[c];
+      for (int c = 0; c < USED; ++c) dst[c] = src.v[c];
     } else {
 #pragma unroll
       for (int c = 0; c < USED; ++c) dst[c] = C(0);
