@@ -41,13 +41,13 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
 # kernel sources they were measured on (KERNEL_SOURCES digest); with any
 # other source the bench reports traffic as null.
 PMC_TRAFFIC = {
-    "sources_sha256_16": "1b6e372a87ef563b",
+    "sources_sha256_16": "c57700e466eadd5e",
     "bytes_per_launch": {
-        "tgv64/f32/6": 50350589,
-        "tgv64/f32/7": 62029214,
-        "sphere3/f32/9": 2484177045,
-        "sphere3/f32/10": 858616248,
-        "sphere3/f32/11": 939861796,
+        "tgv64/f32/6": 50374846,
+        "tgv64/f32/7": 62132005,
+        "sphere3/f32/9": 2159699769,
+        "sphere3/f32/10": 862944533,
+        "sphere3/f32/11": 844016952,
     },
 }
 KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")
