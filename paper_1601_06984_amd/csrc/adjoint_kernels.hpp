@@ -171,12 +171,13 @@ __global__ __launch_bounds__(256) void k_seed_drag(const int32_t* __restrict__ b
 // Gathers the tape state, forms mu = (d g*/d g)^T lam* [+ (d rec/d g)^T
 // lam_rec] in streamed passes over the directions (no per-direction
 // temporaries beyond g and lam*), and scatters each mu_i to the entry its
-// pull read.  COPY links are added by k_adj_copy_* around this kernel.
-// REC instantiations cover the tail of the element range, where capture
-// sources (with a record adjoint) and inner ghosts live; the plain
-// instantiation carries no record code and needs fewer registers.
+// pull read, with the sources decoded once for both.  COPY links are added
+// by k_adj_copy_* around this kernel.  REC instantiations cover the tail
+// of the element range, where capture sources (with a record adjoint) and
+// inner ghosts live; the plain instantiation carries no record code and
+// fits 4 waves per SIMD without spills.
 template <class Lat, int P, bool REC>
-__global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 5 : 1) void k_adj_sc(
+__global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc(
     const typename Prec<P>::S* __restrict__ X, int64_t x0, int64_t x1,
     const LevelArgs<typename Prec<P>::C, Lat::Q> a,
     const typename Prec<P>::C* __restrict__ lam_new, typename Prec<P>::C* __restrict__ lam_cap,
@@ -190,7 +191,9 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 5 : 1) void k_adj_sc
   double acc[DPART] = {0, 0, 0, 0, 0};
   if (x < x1) {
     C g[Q], ls[Q];
-    gather_g<Lat, P>(X, blk, x, a, g);
+    int32_t j[Q];   // pull sources: gathered from, then scattered to
+    pull_sources<Lat>(a, blk, (uint32_t)x, j);
+    gather_from<Lat, P>(X, x, a, j, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i) ls[i] = load_elem(lam_new + (int64_t)i * a.n, a.n, (uint32_t)x);
     C drho, rho, u[3];
@@ -294,7 +297,7 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 5 : 1) void k_adj_sc
         if (ci > 0) mu += lj[b];
         if (ci < 0) mu -= lj[b];
       }
-      const int32_t v = pull_source<Lat>(a, blk, xo, i);
+      const int32_t v = j[i];
       // scatter to the entry the pull read: (i, v), or (opp(i), x) for
       // bounce-back; one descriptor over the pair of opposite rows
       const int pair = (i & 1) ? i : i - 1;

@@ -309,15 +309,13 @@ __device__ __forceinline__ int32_t pull_source(const LA& a, int64_t blk, uint32_
   return v;
 }
 
+// The pulled values g_i(x) for the sources j[1..Q-1] of element x.
 template <class Lat, int P>
-__device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__ src, int64_t blk,
-                                         int64_t x,
-                                         const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
-                                         typename Prec<P>::C* g) {
+__device__ __forceinline__ void gather_from(const typename Prec<P>::S* __restrict__ src, int64_t x,
+                                            const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
+                                            const int32_t* j, typename Prec<P>::C* g) {
   using C = typename Prec<P>::C;
   const uint32_t xo = (uint32_t)x;
-  int32_t j[Lat::Q];
-  pull_sources<Lat>(a, blk, xo, j);
   static_assert(opposite_weights_equal<Lat>(), "w(opp(i)) == w(i)");
   g[0] = load_row<P>(src, a.n, xo, a.wr[0], a.inv_scale);
   const uint32_t nn = (uint32_t)a.n;
@@ -344,6 +342,16 @@ __device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__
     for (int i = 1; i < Lat::Q; ++i)
       if ((eqm >> i) & 1u) g[i] = a.geq[i];
   }
+}
+
+template <class Lat, int P>
+__device__ __forceinline__ void gather_g(const typename Prec<P>::S* __restrict__ src, int64_t blk,
+                                         int64_t x,
+                                         const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
+                                         typename Prec<P>::C* g) {
+  int32_t j[Lat::Q];
+  pull_sources<Lat>(a, blk, (uint32_t)x, j);
+  gather_from<Lat, P>(src, x, a, j, g);
 }
 
 // Writes the values of one record in slot order with 16-byte stores: each
