@@ -41,13 +41,13 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
 # kernel sources they were measured on (KERNEL_SOURCES digest); with any
 # other source the bench reports traffic as null.
 PMC_TRAFFIC = {
-    "sources_sha256_16": "c57700e466eadd5e",
+    "sources_sha256_16": "5144296138036deb",
     "bytes_per_launch": {
-        "tgv64/f32/6": 50374846,
-        "tgv64/f32/7": 62132005,
-        "sphere3/f32/9": 2159699769,
-        "sphere3/f32/10": 862944533,
-        "sphere3/f32/11": 844016952,
+        "tgv64/f32/6": 50376008,
+        "tgv64/f32/7": 62092772,
+        "sphere3/f32/9": 2157113400,
+        "sphere3/f32/10": 864117815,
+        "sphere3/f32/11": 844197612,
     },
 }
 KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")
