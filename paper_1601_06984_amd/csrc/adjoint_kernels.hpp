@@ -185,14 +185,16 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc
   using C = typename Prec<P>::C;
   constexpr int Q = Lat::Q, D = Lat::D, NS = Lat::NS;
   __shared__ double sm[4 * DPART];
-  // x0 is a multiple of the pull-table block: a work-group is one block
+  __shared__ int32_t slots[NBR_SLOTS];
+  // x0 is a multiple of the pull-table block: a work-group is one block,
+  // holding at least one element of [x0, x1)
   const int64_t blk = (x0 >> 8) + blockIdx.x;
   const int64_t x = x0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
   double acc[DPART] = {0, 0, 0, 0, 0};
+  int32_t j[Q];   // pull sources: gathered from, then scattered to
+  pull_sources_wg<Lat>(a, blk, (uint32_t)(x < x1 ? x : x1 - 1), j, slots);
   if (x < x1) {
     C g[Q], ls[Q];
-    int32_t j[Q];   // pull sources: gathered from, then scattered to
-    pull_sources<Lat>(a, blk, (uint32_t)x, j);
     gather_from<Lat, P>(X, x, a, j, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i) ls[i] = load_elem(lam_new + (int64_t)i * a.n, a.n, (uint32_t)x);

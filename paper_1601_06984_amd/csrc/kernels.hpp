@@ -293,6 +293,77 @@ __device__ __forceinline__ void pull_sources(const LA& a, int64_t blk, uint32_t 
     pull_sources_mode<Lat, 2>(a, blk, x, regm, m, j);
 }
 
+// Work-group form of pull_sources: every thread of the work-group calls it
+// with the same block.  The block's slots (NBR_SLOTS ints) are staged in
+// LDS by the first threads while the code loads are in flight, and each
+// lane reads the one base it needs from LDS: no scalar registers hold the
+// 4 (q-1) slot values.
+constexpr int NBR_SLOTS = 18 * NBR_BASES;   // D3Q19; D2Q9 uses the first 32
+template <class Lat, int MODE, class LA>
+__device__ __forceinline__ void pull_sources_wg_mode(const LA& a, int64_t blk, uint32_t x,
+                                                     uint32_t regm, uint32_t m, int32_t* j,
+                                                     int32_t* __restrict__ sl) {
+  constexpr int Q = Lat::Q, NSL = (Q - 1) * NBR_BASES;
+  static_assert(NSL <= NBR_SLOTS && NSL <= 256, "slots fit the staging area");
+  uint32_t c[Q];
+  if constexpr (MODE != 1) {
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      c[i] = load_u16(a.nbr16 + (int64_t)(i - 1) * a.ld16, a.ld16,
+                      (MODE == 2 && ((regm >> i) & 1u)) ? NBR_NO_CODE : x);
+  }
+  if (threadIdx.x < NSL) sl[threadIdx.x] = a.nbase[blk * NSL + threadIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int o = (i - 1) * NBR_BASES;
+    if constexpr (MODE == 0) {
+      j[i] = c[i] >= NBR_CODE0 ? (int32_t)c[i] - 0x10000
+                               : sl[o + (int)(c[i] >> 14)] + (int32_t)(c[i] & 0x3FFFu);
+    } else {
+      const uint32_t mo = morton_pull<Lat>(m, i);
+      const uint32_t sm = (mo - (uint32_t)sl[o + 2]) >= (uint32_t)sl[o + 3] ? 1u : 0u;
+      if constexpr (MODE == 1) {
+        j[i] = (int32_t)(mo + (uint32_t)sl[o + (int)sm]);
+      } else {
+        const uint32_t keep = 0u - ((regm >> i) & 1u);
+        const uint32_t idx = (sm & keep) | ((c[i] >> 14) & ~keep);
+        const uint32_t off = (mo & keep) | ((c[i] & 0x3FFFu) & ~keep);
+        const int32_t v = (int32_t)((uint32_t)sl[o + (int)idx] + off);
+        j[i] = c[i] >= NBR_CODE0 ? (int32_t)c[i] - 0x10000 : v;   // Morton lanes read c = 0
+      }
+    }
+  }
+  if constexpr (MODE == 0) {
+    const int32_t w = a.nhdr[blk * NBR_HDR + 2];
+    if (w >= 0) {   // wide block: codes are the low halves of int32 entries
+      const uint32_t e = (uint32_t)w * NBR_BLOCK + (x & (NBR_BLOCK - 1));
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        j[i] = (int32_t)((load_u16(a.nbr_wide + (int64_t)(i - 1) * a.ldw, a.ldw, e) << 16) | c[i]);
+    }
+  }
+}
+
+template <class Lat, class LA>
+__device__ __forceinline__ void pull_sources_wg(const LA& a, int64_t blk, uint32_t x, int32_t* j,
+                                                int32_t* __restrict__ sl) {
+  constexpr uint32_t ALL = (1u << Lat::Q) - 2u;
+  if (!a.morton) {
+    pull_sources_wg_mode<Lat, 0>(a, blk, x, 0u, 0u, j, sl);
+    return;
+  }
+  const int32_t* __restrict__ hd = a.nhdr + blk * NBR_HDR;
+  const uint32_t regm = (uint32_t)hd[0];
+  const uint32_t m = x + (uint32_t)hd[1];
+  if (regm == 0)
+    pull_sources_wg_mode<Lat, 0>(a, blk, x, regm, m, j, sl);
+  else if (regm == ALL)
+    pull_sources_wg_mode<Lat, 1>(a, blk, x, regm, m, j, sl);
+  else
+    pull_sources_wg_mode<Lat, 2>(a, blk, x, regm, m, j, sl);
+}
+
 // Pull source of direction i only.
 template <class Lat, class LA>
 __device__ __forceinline__ int32_t pull_source(const LA& a, int64_t blk, uint32_t x, int i) {
@@ -496,7 +567,8 @@ inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStr
 
 // The stream-collide of work-group `blk` (blk*BS < x1) of a level whose
 // updated range is [0, x1): elements blk*BS .. blk*BS+BS-1.  `stage` is the
-// work-group's record staging area.
+// work-group's record staging area, `slots` its pull-table slot area; every
+// thread of the work-group calls it.
 template <class Lat, int P, int BS>
 __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
                                         const typename Prec<P>::S* __restrict__ src,
@@ -504,7 +576,8 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
                                         const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
                                         typename Prec<P>::C* __restrict__ cap,
                                         uint32_t* __restrict__ status,
-                                        typename Prec<P>::C* __restrict__ stage) {
+                                        typename Prec<P>::C* __restrict__ stage,
+                                        int32_t* __restrict__ slots) {
   using C = typename Prec<P>::C;
   using Stager = WaveRecordStager<C, cap_stride(Lat::D)>;
   static_assert(BS == NBR_BLOCK, "a work-group covers one pull-table block");
@@ -514,7 +587,11 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
   // and store nothing; the record staging needs every lane of the wave
   const int64_t x = valid ? xr : x1 - 1;
   C g[Lat::Q];
-  gather_g<Lat, P>(src, blk, x, a, g);
+  {
+    int32_t j[Lat::Q];
+    pull_sources_wg<Lat>(a, blk, (uint32_t)x, j, slots);
+    gather_from<Lat, P>(src, x, a, j, g);
+  }
   C drho, rho, u[3];
   macro_g<Lat, C>(g, a.rho0, drho, rho, u);
   const C uu = dot_uu<Lat, C>(u);
@@ -554,8 +631,9 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
     typename Prec<P>::C* __restrict__ cap, uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   __shared__ C stage[sc_stage_values<C, Lat::D>(BS)];
+  __shared__ int32_t slots[NBR_SLOTS];
   const int64_t blk = xcd_block2(blockIdx.x, gridDim.x, a.cap_begin / BS);
-  sc_body<Lat, P, BS>(blk, x1, src, dst, a, cap, status, stage);
+  sc_body<Lat, P, BS>(blk, x1, src, dst, a, cap, status, stage, slots);
 }
 
 // Stream-collides of several levels in one launch.  Consecutive
@@ -583,13 +661,15 @@ __global__ __launch_bounds__(BS) void k_stream_collide_multi(
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   __shared__ C stage[sc_stage_values<C, Lat::D>(BS)];
+  __shared__ int32_t slots[NBR_SLOTS];
   int sg = 0;
   while (sg + 1 < m.nseg && (int64_t)blockIdx.x >= m.first[sg + 1]) ++sg;
   const int64_t b = (int64_t)blockIdx.x - m.first[sg];
   if (b >= m.nb[sg]) return;
   const LevelArgs<C, Lat::Q>& a = m.a[sg];
   const int64_t blk = xcd_block2(b, m.nb[sg], a.cap_begin / BS);
-  sc_body<Lat, P, BS>(blk, m.n_act[sg], m.src[sg], m.dst[sg], a, m.cap[sg], status, stage);
+  sc_body<Lat, P, BS>(blk, m.n_act[sg], m.src[sg], m.dst[sg], a, m.cap[sg], status, stage,
+                      slots);
 }
 
 // --------------------------------------------------- interpolation --------
