@@ -216,8 +216,9 @@ def test_graph_replay_matches_direct_launches():
         assert torch.equal(a.get_pdf(k), b.get_pdf(k))
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19"])
-def test_grouped_launches_match_per_level_launches(stencil):
+def test_grouped_launches_match_per_level_launches(stencil, precision):
     """Stream-collides of different levels launched as one grid give the
     same bits as one launch per level (the profiled schedule), on three
     levels where groups of two and three levels occur."""
@@ -226,9 +227,9 @@ def test_grouped_launches_match_per_level_launches(stencil):
     else:
         spec = W.refined_box_mesh("D2Q9", 5, 6, 26, extra_levels=[(20, 36)])
     n0 = 16 if stencil == "D3Q19" else 32
-    _say(f"grouped vs per-level launches {stencil}")
-    a = H.gpu_sim(spec, "f32", 0.56, H.tgv(n0, 0.03))
-    b = H.gpu_sim(spec, "f32", 0.56, H.tgv(n0, 0.03))
+    _say(f"grouped vs per-level launches {stencil} {precision}")
+    a = H.gpu_sim(spec, precision, 0.56, H.tgv(n0, 0.03))
+    b = H.gpu_sim(spec, precision, 0.56, H.tgv(n0, 0.03))
     a.use_graphs(False)
     b.use_graphs(False)
     b.profile(True)
