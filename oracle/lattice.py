@@ -1,9 +1,9 @@
 """DdQq velocity sets (Sec. 2.1).
 
-The paper uses D2Q9 and D3Q27; this oracle provides D2Q9 and D3Q19, the
-two stencils the hot path runs.  Weights are the standard ones for which
-sum_i w_i = 1, sum_i w_i c_ia c_ib = cs2 delta_ab and the fourth moment is
-isotropic with cs2 = 1/3.
+The paper runs D2Q9 and D3Q27; this oracle provides those two and D3Q19.
+Weights are the standard ones for which sum_i w_i = 1,
+sum_i w_i c_ia c_ib = cs2 delta_ab and the fourth moment is isotropic with
+cs2 = 1/3.
 """
 from __future__ import annotations
 
@@ -68,5 +68,17 @@ def d3q19() -> Lattice:
     return _make("D3Q19", vecs, wts)
 
 
+def d3q27() -> Lattice:
+    """Every c in {-1, 0, 1}^3: weight 8/27 at rest, 2/27 along an axis, 1/54
+    across an edge (two non-zero components), 1/216 to a corner."""
+    vecs, wts = [], []
+    by_count = {0: 8.0 / 27.0, 1: 2.0 / 27.0, 2: 1.0 / 54.0, 3: 1.0 / 216.0}
+    for v in np.ndindex(3, 3, 3):
+        c = tuple(x - 1 for x in v)
+        vecs.append(c)
+        wts.append(by_count[sum(1 for x in c if x != 0)])
+    return _make("D3Q27", vecs, wts)
+
+
 def get(name: str) -> Lattice:
-    return {"D2Q9": d2q9, "D3Q19": d3q19}[name]()
+    return {"D2Q9": d2q9, "D3Q19": d3q19, "D3Q27": d3q27}[name]()

@@ -56,7 +56,7 @@ def test_treeid_decode_matches_recursive_enumeration():
 
 
 # ---------------------------------------------------------------- P2/P3 ----
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
 def test_lattice_isotropy(name):
     lat = lattice.get(name)
     c, w = lat.c.astype(float), lat.w
@@ -72,7 +72,7 @@ def test_lattice_isotropy(name):
         assert (lat.c[lat.opp[i]] == -lat.c[i]).all()
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
 def test_equilibrium_moments(name):
     """Eq. feq with the '-u.u' reading: sum f^eq = rho, sum c f^eq = rho u,
     sum cc f^eq = rho cs2 I + rho u u exactly (the printed '+' sign fails the
@@ -97,7 +97,7 @@ def test_equilibrium_moments(name):
     assert (wrong.sum(0) - rho).abs().max() > 1e-4
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
 def test_strain_of_chapman_enskog_fneq_is_identity(name):
     """Sec. 2.1 strain formula applied to the Chapman-Enskog f^neq(S)
     returns S for any symmetric S and any omega."""
@@ -146,7 +146,7 @@ def _pdf(lat, rho, u, S, omega):
             + physics.fneq_from_strain(rho_t, S_t, omega, lat))
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
 @pytest.mark.parametrize("kind", ["gfc", "gff"])
 def test_compact_interpolation_exact_on_quadratic_fields(name, kind):
     """Eqs. compact_3D_u / compact_3D_s and Steps 1-5: with constant rho and
@@ -296,6 +296,7 @@ def _level_fields(m, L, u_fn, S_fn, rho):
 @pytest.mark.parametrize("spec_fn", [
     lambda: W.refined_box_mesh("D2Q9", 5, 8, 24),
     lambda: W.refined_box_mesh("D3Q19", 4, 4, 12),
+    lambda: W.refined_box_mesh("D3Q27", 4, 4, 12),
 ])
 def test_mesh_fill_exact_on_quadratic_field(spec_fn):
     """The sync fill of a whole mesh (source tables, octant signs, target
@@ -441,6 +442,7 @@ def test_uniform_flow_preserved_multilevel():
     (lambda: W.refined_box_mesh("D3Q19", 4, 4, 12), 16, 12),
     (lambda: W.refined_box_mesh("D2Q9", 5, 8, 24, extra_levels=[(20, 44)]), 32, 12),
     (lambda: W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)]), 16, 3),
+    (lambda: W.refined_box_mesh("D3Q27", 4, 2, 14, extra_levels=[(10, 18)]), 16, 3),
 ])
 def test_nan_poisoning_never_reaches_fluid(spec_fn, n0, steps):
     """Ghost slots start as NaN and missing pull sources give NaN; after full

@@ -25,7 +25,7 @@ FACE_KINDS = ("periodic", "eq", "copy", "wall")
 class MeshSpec:
     """Input description of one multilevel mesh.
 
-    stencil     "D2Q9" or "D3Q19"
+    stencil     "D2Q9", "D3Q19" or "D3Q27"
     level0      coarsest level present; the root cube spans 2**level0 cells
     leaf_ids    uint64 treeIDs of all fluid leaves (any order)
     solid_ids   uint64 treeIDs of solid cells (finest level)
@@ -196,7 +196,8 @@ def sphere_channel_mesh(d_finest: int, n_levels: int, *,
                         length=(-15.0, 49.0), half_width=15.0,
                         boxes_in_d=((-5.0, 19.0, 5.0), (-2.5, 9.5, 2.5),
                                     (-1.25, 4.75, 1.25)),
-                        inflow_only_eq: bool = False, outlet: str = "copy") -> MeshSpec:
+                        inflow_only_eq: bool = False, outlet: str = "copy",
+                        stencil: str = "D3Q19") -> MeshSpec:
     """Channel [-15D,49D]x[-15D,15D]^2 with a sphere of diameter D at the
     origin and nested refinement boxes around it (Sec. 4.3 geometry).
 
@@ -207,6 +208,7 @@ def sphere_channel_mesh(d_finest: int, n_levels: int, *,
     equilibrium; the outlet x+ copies its own post-collision values
     (outlet="copy") or also carries the free-stream equilibrium
     (outlet="eq").  The sphere centre sits on a vertex of the finest grid.
+    stencil     "D3Q19" or "D3Q27"
     """
     assert 1 <= n_levels <= 1 + len(boxes_in_d)
     ratio = 1 << (n_levels - 1)
@@ -236,7 +238,8 @@ def sphere_channel_mesh(d_finest: int, n_levels: int, *,
     faces = ("eq", outlet, "eq", "eq", "eq", "eq")
     if inflow_only_eq:
         faces = ("eq", outlet, "periodic", "periodic", "periodic", "periodic")
-    return nested_mesh(f"sphere_D{d_finest}_L{n_levels}", "D3Q19", level0, ext,
+    assert stencil in ("D3Q19", "D3Q27")
+    return nested_mesh(f"sphere_D{d_finest}_L{n_levels}", stencil, level0, ext,
                        boxes, faces, solid=solid,
                        meta={"D": d_finest, "centre_finest": tuple(centre),
                              "n_levels": n_levels})
