@@ -39,7 +39,7 @@ extern "C" {
 #endif
 
 /* ---- enumerations --------------------------------------------------- */
-enum { MLBM_D2Q9 = 0, MLBM_D3Q19 = 1 };
+enum { MLBM_D2Q9 = 0, MLBM_D3Q19 = 1, MLBM_D3Q27 = 2 };
 
 /* Storage precision of the pdfs.  F64: double, FP64 collision.  F32: float,
  * FP32 collision.  F16S: half holding s_L * (f_i - w_i rho0) with a

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libmlbm.so")
 
 # enums mirrored from include/mlbm.h
-D2Q9, D3Q19 = 0, 1
+D2Q9, D3Q19, D3Q27 = 0, 1, 2
 F64, F32, F16S = 0, 1, 2
 FACE = {"periodic": 0, "eq": 1, "copy": 2, "wall": 3}
 NBR_MISSING, NBR_BOUNCE, NBR_EQ, NBR_COPY = -1, -2, -3, -4

@@ -8,7 +8,7 @@ import numpy as np
 from . import _lib
 from ._lib import check, lib
 
-_STENCILS = {"D2Q9": _lib.D2Q9, "D3Q19": _lib.D3Q19}
+_STENCILS = {"D2Q9": _lib.D2Q9, "D3Q19": _lib.D3Q19, "D3Q27": _lib.D3Q27}
 _PRECISIONS = {"f64": _lib.F64, "f32": _lib.F32, "f16s": _lib.F16S}
 
 
@@ -42,7 +42,7 @@ class Plan:
                  leaf_ids, solid_ids=()):
         self.stencil = stencil
         self.d = 2 if stencil == "D2Q9" else 3
-        self.q = 9 if stencil == "D2Q9" else 19
+        self.q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}[stencil]
         self._h = C.c_void_p()
         o, po = _i32arr(box_origin)
         e, pe = _i32arr(box_extent)

@@ -78,7 +78,7 @@ size_t layout_adjoint(const SimState& s, const mlbm_plan& P, char* base, AdjStat
   };
   const int q = s.q, d = s.d;
   const size_t sb = sbytes(s.precision), cb = cbytes(s.precision);
-  const size_t st = cap_stride(d);
+  const size_t st = cap_stride(q);
   for (int k = 0; k < P.nlev(); ++k) {
     const auto& lp = P.lv[k];
     AdjLevel* A = a ? &a->lv[k] : nullptr;
@@ -187,7 +187,7 @@ struct Adj {
                        ng, A.gfc_slot, A.gfc_oct, (const C*)cap_coarse, lam, L.n, (C*)A.T,
                        (C)L.omega, (C)Cl.omega, (C)s.rho0, s.adj.part + off * DPART);
     off += nb;
-    constexpr int W = cap_used(Lat::D);
+    constexpr int W = cap_used(Lat::Q);
     const int64_t work = Cl.n_cap * W;
     hipLaunchKernelGGL((k_adj_gfc_gather<Lat, C>), dim3((unsigned)blocks(work, 256)), dim3(256), 0,
                        s.stream, A.csr_ptr, A.csr_ent, Cl.n_cap, (const C*)A.T,
@@ -298,7 +298,7 @@ struct Adj {
           hipLaunchKernelGGL((k_seed_drag<Lat, C>), dim3((unsigned)blocks(L.n_bounce, 256)), dim3(256),
                              0, s.stream, L.bounce, L.n_bounce, L.n, scale, lam);
       }
-      const int64_t ncap = L.n_cap * cap_stride(s.d);
+      const int64_t ncap = L.n_cap * cap_stride(s.q);
       if (ncap)
         hipLaunchKernelGGL((k_fill_value<C>), dim3((unsigned)blocks(ncap, 256)), dim3(256), 0, s.stream,
                            (C*)A.lam_cap, ncap, C(0));
@@ -361,21 +361,21 @@ struct Adj {
   }
 };
 
+#define MLBM_ADJ_DISPATCH_P(s, LAT, CALL)                                             \
+  do {                                                                               \
+    if ((s).precision == MLBM_F64) { using J = Adj<LAT, MLBM_F64>; CALL; }            \
+    else if ((s).precision == MLBM_F32) { using J = Adj<LAT, MLBM_F32>; CALL; }       \
+    else { using J = Adj<LAT, MLBM_F16S>; CALL; }                                     \
+  } while (0)
 #define MLBM_ADJ_DISPATCH(s, CALL)                                                   \
   do {                                                                               \
-    if ((s).d == 3) {                                                                \
-      if ((s).precision == MLBM_F64) { using J = Adj<D3Q19, MLBM_F64>; CALL; }        \
-      else if ((s).precision == MLBM_F32) { using J = Adj<D3Q19, MLBM_F32>; CALL; }   \
-      else { using J = Adj<D3Q19, MLBM_F16S>; CALL; }                                 \
-    } else {                                                                         \
-      if ((s).precision == MLBM_F64) { using J = Adj<D2Q9, MLBM_F64>; CALL; }         \
-      else if ((s).precision == MLBM_F32) { using J = Adj<D2Q9, MLBM_F32>; CALL; }    \
-      else { using J = Adj<D2Q9, MLBM_F16S>; CALL; }                                  \
-    }                                                                                \
+    if ((s).stencil == MLBM_D3Q19) MLBM_ADJ_DISPATCH_P(s, D3Q19, CALL);              \
+    else if ((s).stencil == MLBM_D3Q27) MLBM_ADJ_DISPATCH_P(s, D3Q27, CALL);         \
+    else MLBM_ADJ_DISPATCH_P(s, D2Q9, CALL);                                         \
   } while (0)
 
 bool plan_matches(const SimState& s, const mlbm_plan& P) {
-  if ((int)s.lv.size() != P.nlev() || s.d != P.d) return false;
+  if ((int)s.lv.size() != P.nlev() || s.d != P.d || s.stencil != P.stencil) return false;
   for (int k = 0; k < P.nlev(); ++k)
     if (s.lv[k].n != P.lv[k].n || s.lv[k].n_fluid != P.lv[k].n_fluid ||
         s.lv[k].n_cap != P.lv[k].n_cap())

@@ -84,22 +84,22 @@ __device__ __forceinline__ void collide_adjoint(const C* g, const C* ls, const C
 #pragma unroll
       for (int i = 0; i < Q; ++i) pi += C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * (g[i] - geq[i]);
       S[k] = pref * pi;
-      const C lS = lrec[cap_s(D) + k];
+      const C lS = lrec[cap_s(Lat::Q) + k];
       lrho -= lS * S[k] / rho;
       dw += (double)lS * (double)S[k] / (double)omega;
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      C lf = lrec[cap_fneq(D) + i];
+      C lf = lrec[cap_fneq(Lat::Q) + i];
 #pragma unroll
       for (int k = 0; k < Lat::NS; ++k)
-        lf += pref * C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * lrec[cap_s(D) + k];
+        lf += pref * C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * lrec[cap_s(Lat::Q) + k];
       lg[i] += lf;
       lgeq[i] -= lf;
     }
-    ldrho += lrec[cap_rho(D)];
+    ldrho += lrec[cap_rho(Lat::Q)];
 #pragma unroll
-    for (int a = 0; a < D; ++a) lu[a] += lrec[cap_u(D) + a];
+    for (int a = 0; a < D; ++a) lu[a] += lrec[cap_u(Lat::Q) + a];
   }
   geq_adjoint<Lat, C>(lgeq, rho, u, uu, ldrho, lrho, lu);
   C lj[3] = {0, 0, 0};
@@ -210,16 +210,16 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc
     if constexpr (REC) {
       src = x >= a.cap_begin && x < a.n_fluid;
       if (src) {
-        C* r = lam_cap + (x - a.cap_begin) * cap_stride(D);
-        ldrho += r[cap_rho(D)];
+        C* r = lam_cap + (x - a.cap_begin) * cap_stride(Lat::Q);
+        ldrho += r[cap_rho(Lat::Q)];
 #pragma unroll
-        for (int b = 0; b < D; ++b) lu[b] += r[cap_u(D) + b];
+        for (int b = 0; b < D; ++b) lu[b] += r[cap_u(Lat::Q) + b];
 #pragma unroll
-        for (int k = 0; k < NS; ++k) lr_S[k] = r[cap_s(D) + k];
+        for (int k = 0; k < NS; ++k) lr_S[k] = r[cap_s(Lat::Q) + k];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) lr_f[i] = r[cap_fneq(D) + i];
+        for (int i = 0; i < Q; ++i) lr_f[i] = r[cap_fneq(Lat::Q) + i];
 #pragma unroll
-        for (int c = 0; c < cap_used(D); ++c) r[c] = C(0);  // consumed
+        for (int c = 0; c < cap_used(Lat::Q); ++c) r[c] = C(0);  // consumed
         pref = -C(1.5) * om / rho;
         // S of the record: lrho and omega contributions
         C pi[NS];
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_adj_copy_pre(
   for (int i = 0; i < Q; ++i) ls[i] = lam_new[(int64_t)i * a.n + x];
   const bool src = x >= a.cap_begin && x < a.n_fluid;
   double dummy = 0;
-  collide_adjoint<Lat, C>(g, ls, src ? lam_cap + (x - a.cap_begin) * cap_stride(D) : nullptr,
+  collide_adjoint<Lat, C>(g, ls, src ? lam_cap + (x - a.cap_begin) * cap_stride(Lat::Q) : nullptr,
                           a.rho0, a.omega, mu, dummy);
   tmp[t * Q] = C(0);
 #pragma unroll
@@ -499,7 +499,7 @@ __device__ __forceinline__ void strain_terms(const C* const* S, int sx, int sy, 
 template <class Lat, class C>
 __device__ __forceinline__ void ghost_adjoint(const C* const* rec, const C* beta, C r, C omega_t,
                                               C omega_s, C rho0, int sx, int sy, int sz, C wd,
-                                              C wc, const C* lgs, const C* lrec, C (*lsrc)[32],
+                                              C wc, const C* lgs, const C* lrec, C (*lsrc)[cap_stride(Lat::Q)],
                                               double& d_t, double& d_s) {
   constexpr int D = Lat::D, Q = Lat::Q, NS = Lat::NS;
   // forward recompute
@@ -507,17 +507,17 @@ __device__ __forceinline__ void ghost_adjoint(const C* const* rec, const C* beta
   const C* S[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    drho += beta[k] * rec[k][cap_rho(D)];
+    drho += beta[k] * rec[k][cap_rho(Lat::Q)];
 #pragma unroll
-    for (int b = 0; b < D; ++b) u[b] += beta[k] * rec[k][cap_u(D) + b];
-    S[k] = rec[k] + cap_s(D);
+    for (int b = 0; b < D; ++b) u[b] += beta[k] * rec[k][cap_u(Lat::Q) + b];
+    S[k] = rec[k] + cap_s(Lat::Q);
   }
   strain_terms<D, C>(S, sx, sy, sz, wd, wc, u);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     C m = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) m += beta[k] * rec[k][cap_fneq(D) + i];
+    for (int k = 0; k < 4; ++k) m += beta[k] * rec[k][cap_fneq(Lat::Q) + i];
     fneq[i] = r * m;
   }
   const C rho = rho0 + drho;
@@ -540,21 +540,21 @@ __device__ __forceinline__ void ghost_adjoint(const C* const* rec, const C* beta
 #pragma unroll
       for (int i = 0; i < Q; ++i) pi += C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * fneq[i];
       const C Sk = pref * pi;
-      const C lS = lrec[cap_s(D) + k];
+      const C lS = lrec[cap_s(Lat::Q) + k];
       lrho -= lS * Sk / rho;
       dt += (double)lS * (double)Sk / (double)omega_t;
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      C lf = lrec[cap_fneq(D) + i];
+      C lf = lrec[cap_fneq(Lat::Q) + i];
 #pragma unroll
       for (int k = 0; k < NS; ++k)
-        lf += pref * C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * lrec[cap_s(D) + k];
+        lf += pref * C(Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k))) * lrec[cap_s(Lat::Q) + k];
       lfneq[i] += lf;
     }
-    ldrho += lrec[cap_rho(D)];
+    ldrho += lrec[cap_rho(Lat::Q)];
 #pragma unroll
-    for (int b = 0; b < D; ++b) lu[b] += lrec[cap_u(D) + b];
+    for (int b = 0; b < D; ++b) lu[b] += lrec[cap_u(Lat::Q) + b];
   }
   // rescale r = omega_s dt_t / (omega_t dt_s): d r/d omega_s = r/omega_s,
   // d r/d omega_t = -r/omega_t
@@ -575,13 +575,13 @@ __device__ __forceinline__ void ghost_adjoint(const C* const* rec, const C* beta
   strain_terms_adjoint<D, C>(lu, sx, sy, sz, wd, wc, lS);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    lsrc[k][cap_rho(D)] = beta[k] * ldrho;
+    lsrc[k][cap_rho(Lat::Q)] = beta[k] * ldrho;
 #pragma unroll
-    for (int b = 0; b < D; ++b) lsrc[k][cap_u(D) + b] = beta[k] * lu[b];
+    for (int b = 0; b < D; ++b) lsrc[k][cap_u(Lat::Q) + b] = beta[k] * lu[b];
 #pragma unroll
-    for (int c = 0; c < NS; ++c) lsrc[k][cap_s(D) + c] = lS[k][c];
+    for (int c = 0; c < NS; ++c) lsrc[k][cap_s(Lat::Q) + c] = lS[k][c];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) lsrc[k][cap_fneq(D) + i] = beta[k] * r * lfneq[i];
+    for (int i = 0; i < Q; ++i) lsrc[k][cap_fneq(Lat::Q) + i] = beta[k] * r * lfneq[i];
   }
   d_t += dt;
   d_s += ds;
@@ -606,27 +606,27 @@ __global__ __launch_bounds__(64) void k_adj_gff(
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       sl[k] = slots[k * n_gff + j];
-      rec[k] = cap_fine + (int64_t)sl[k] * cap_stride(D);
+      rec[k] = cap_fine + (int64_t)sl[k] * cap_stride(Lat::Q);
     }
     C lgs[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) lgs[i] = lam[(int64_t)i * n + gff_begin + j];
-    C* lr = lam_cap_coarse + (cap_gff_begin + j) * cap_stride(D);
-    C lrec[cap_used(D)];
+    C* lr = lam_cap_coarse + (cap_gff_begin + j) * cap_stride(Lat::Q);
+    C lrec[cap_used(Lat::Q)];
 #pragma unroll
-    for (int c = 0; c < cap_used(D); ++c) {
+    for (int c = 0; c < cap_used(Lat::Q); ++c) {
       lrec[c] = lr[c];
       lr[c] = C(0);
     }
     const C beta[4] = {C(0.25), C(0.25), C(0.25), C(0.25)};
-    C lsrc[4][32];
+    C lsrc[4][cap_stride(Lat::Q)];
     ghost_adjoint<Lat, C>(rec, beta, C(2) * omega_f / omega_c, omega_c, omega_f, rho0, 1, 1, 1,
                           C(0.25), C(0), lgs, lrec, lsrc, acc[0], acc[1]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      C* dst = lam_cap_fine + (int64_t)sl[k] * cap_stride(D);
+      C* dst = lam_cap_fine + (int64_t)sl[k] * cap_stride(Lat::Q);
 #pragma unroll
-      for (int c = 0; c < cap_used(D); ++c) dst[c] += lsrc[k][c];
+      for (int c = 0; c < cap_used(Lat::Q); ++c) dst[c] += lsrc[k][c];
     }
   }
   block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
@@ -649,7 +649,7 @@ __global__ __launch_bounds__(64) void k_adj_gfc(
   if (j < n_gfc) {
     const C* rec[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) rec[k] = cap_coarse + (int64_t)slots[k * n_gfc + j] * cap_stride(D);
+    for (int k = 0; k < 4; ++k) rec[k] = cap_coarse + (int64_t)slots[k * n_gfc + j] * cap_stride(Lat::Q);
     const int o = oct[j];
     const int sx = (o & 1) ? 1 : -1, sy = (o & 2) ? 1 : -1, sz = (o & 4) ? 1 : -1;
     C lgs[Q];
@@ -664,14 +664,14 @@ __global__ __launch_bounds__(64) void k_adj_gfc(
       beta[0] = C(9.0 / 16.0); beta[1] = beta[2] = C(3.0 / 16.0); beta[3] = C(1.0 / 16.0);
       wd = C(3.0 / 16.0); wc = C(0);
     }
-    C lsrc[4][32];
+    C lsrc[4][cap_stride(Lat::Q)];
     ghost_adjoint<Lat, C>(rec, beta, omega_c / (C(2) * omega_f), omega_f, omega_c, rho0, sx, sy,
                           sz, wd, wc, lgs, nullptr, lsrc, acc[0], acc[1]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      C* dst = T + (j * 4 + k) * cap_stride(D);
+      C* dst = T + (j * 4 + k) * cap_stride(Lat::Q);
 #pragma unroll
-      for (int c = 0; c < cap_used(D); ++c) dst[c] = lsrc[k][c];
+      for (int c = 0; c < cap_used(Lat::Q); ++c) dst[c] = lsrc[k][c];
     }
   }
   block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
@@ -684,13 +684,13 @@ __global__ __launch_bounds__(256) void k_adj_gfc_gather(const int32_t* __restric
                                                         int64_t n_slots, const C* __restrict__ T,
                                                         C* __restrict__ lam_cap) {
   constexpr int D = Lat::D;
-  constexpr int W = cap_used(D);
+  constexpr int W = cap_used(Lat::Q);
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t s = t / W, c = t % W;
   if (s >= n_slots) return;
   C v = 0;
-  for (int32_t e = ptr[s]; e < ptr[s + 1]; ++e) v += T[(int64_t)ent[e] * cap_stride(D) + c];
-  if (ptr[s + 1] > ptr[s]) lam_cap[s * cap_stride(D) + c] += v;
+  for (int32_t e = ptr[s]; e < ptr[s + 1]; ++e) v += T[(int64_t)ent[e] * cap_stride(Lat::Q) + c];
+  if (ptr[s + 1] > ptr[s]) lam_cap[s * cap_stride(Lat::Q) + c] += v;
 }
 
 // Init reverse: f = f^eq(rho, u) + f^neq(S) per fluid element, collided into
@@ -717,11 +717,11 @@ __global__ __launch_bounds__(256) void k_adj_init(
       ls[i] = lam[(int64_t)i * a.n + x];
     }
     const bool src = x >= a.cap_begin;
-    C lrec[cap_used(D)];
+    C lrec[cap_used(Lat::Q)];
     if (src) {
-      C* r = lam_cap + (x - a.cap_begin) * cap_stride(D);
+      C* r = lam_cap + (x - a.cap_begin) * cap_stride(Lat::Q);
 #pragma unroll
-      for (int c = 0; c < cap_used(D); ++c) {
+      for (int c = 0; c < cap_used(Lat::Q); ++c) {
         lrec[c] = r[c];
         r[c] = C(0);
       }

@@ -57,6 +57,30 @@ struct D3Q19 {
   }
 };
 
+// D3Q27: rest, 6 axis, 12 edge (as D3Q19), 8 corner directions; opposite
+// directions sit in rows 2k-1, 2k.
+struct D3Q27 {
+  static constexpr int D = 3, Q = 27, STENCIL = MLBM_D3Q27;
+  static constexpr int NS = 6;
+  MLBM_HD static constexpr int c(int i, int a) {
+    constexpr int t[27][3] = {
+        {0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},  {0, 0, 1},
+        {0, 0, -1},  {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0},  {1, 0, 1},
+        {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},  {0, 1, 1},   {0, -1, -1}, {0, 1, -1},
+        {0, -1, 1},  {1, 1, 1},   {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1},
+        {-1, 1, -1}, {-1, 1, 1},  {1, -1, -1}};
+    return t[i][a];
+  }
+  MLBM_HD static constexpr double w(int i) {
+    return i == 0 ? 8.0 / 27.0 : (i <= 6 ? 2.0 / 27.0 : (i <= 18 ? 1.0 / 54.0 : 1.0 / 216.0));
+  }
+  // weight class: 0 rest, 1 axis, 2 edge, 3 corner
+  MLBM_HD static constexpr int wclass(int i) { return i == 0 ? 0 : (i <= 6 ? 1 : (i <= 18 ? 2 : 3)); }
+  MLBM_HD static constexpr int opp(int i) {
+    return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
+  }
+};
+
 // Strain component order (a, b) for NS components.
 MLBM_HD constexpr int strain_a(int d, int k) {
   return d == 3 ? (k == 0 ? 0 : k == 1 ? 1 : k == 2 ? 2 : k == 3 ? 0 : k == 4 ? 1 : 0)
@@ -67,7 +91,24 @@ MLBM_HD constexpr int strain_b(int d, int k) {
                 : (k == 0 ? 0 : k == 1 ? 1 : 1);
 }
 
-inline int stencil_q(int stencil) { return stencil == MLBM_D2Q9 ? 9 : 19; }
+inline int stencil_q(int stencil) {
+  return stencil == MLBM_D2Q9 ? 9 : (stencil == MLBM_D3Q27 ? 27 : 19);
+}
+// Lattice constants by stencil for host code.
+inline int stencil_c(int stencil, int i, int a) {
+  return stencil == MLBM_D2Q9 ? D2Q9::c(i, a)
+                              : (stencil == MLBM_D3Q27 ? D3Q27::c(i, a) : D3Q19::c(i, a));
+}
+inline double stencil_w(int stencil, int i) {
+  return stencil == MLBM_D2Q9 ? D2Q9::w(i) : (stencil == MLBM_D3Q27 ? D3Q27::w(i) : D3Q19::w(i));
+}
+inline int stencil_wclass(int stencil, int i) {
+  return stencil == MLBM_D2Q9 ? D2Q9::wclass(i)
+                              : (stencil == MLBM_D3Q27 ? D3Q27::wclass(i) : D3Q19::wclass(i));
+}
+inline int stencil_opp(int stencil, int i) {
+  return stencil == MLBM_D2Q9 ? D2Q9::opp(i) : (stencil == MLBM_D3Q27 ? D3Q27::opp(i) : D3Q19::opp(i));
+}
 inline int stencil_d(int stencil) { return stencil == MLBM_D2Q9 ? 2 : 3; }
 
 // Opposite directions carry equal weights (true of every symmetric lattice).
@@ -149,15 +190,17 @@ MLBM_HD inline int64_t xcd_block2(int64_t b, int64_t nb, int64_t nb1) {
   return x * q1 + (x < r1 ? x : r1) + (k - cnt2);
 }
 
-// Capture record: f^neq (q), drho, u (d), S (NS), padded to a power of two
-// (3D FP32: one 128-byte line).  f^neq and drho come first so that the q+1
-// values formed in the collide loop fill whole 16-byte chunks.
-MLBM_HD constexpr int cap_stride(int d) { return d == 3 ? 32 : 16; }
+// Capture record: f^neq (q), drho, u (d), S (NS), padded to 16, 32 or 48
+// values for D2Q9, D3Q19, D3Q27 (a multiple of the record stager's 64-byte
+// phase; D3Q19 FP32: one 128-byte line).  f^neq and drho come first so that
+// the q+1 values formed in the collide loop fill whole 16-byte chunks.
+MLBM_HD constexpr int cap_dim(int q) { return q == 9 ? 2 : 3; }
+MLBM_HD constexpr int cap_stride(int q) { return q == 27 ? 48 : (q == 19 ? 32 : 16); }
 MLBM_HD constexpr int cap_fneq(int) { return 0; }
-MLBM_HD constexpr int cap_rho(int d) { return d == 3 ? 19 : 9; }
-MLBM_HD constexpr int cap_u(int d) { return cap_rho(d) + 1; }
-MLBM_HD constexpr int cap_s(int d) { return cap_u(d) + d; }
-MLBM_HD constexpr int cap_used(int d) { return cap_s(d) + (d == 3 ? 6 : 3); }
+MLBM_HD constexpr int cap_rho(int q) { return q; }
+MLBM_HD constexpr int cap_u(int q) { return cap_rho(q) + 1; }
+MLBM_HD constexpr int cap_s(int q) { return cap_u(q) + cap_dim(q); }
+MLBM_HD constexpr int cap_used(int q) { return cap_s(q) + (cap_dim(q) == 3 ? 6 : 3); }
 
 // Neighbourhood slots of a GhostFromCoarser parent group: 3D uses the
 // parent and its 12 edge neighbours, 2D the parent and its 8 neighbours.

@@ -140,7 +140,7 @@ struct LevelArgs {
   C omega;            // BGK relaxation rate of the level
   C rho0;
   C scale, inv_scale; // F16S scale s_L and 1/s_L
-  C wr[3];            // w_i rho0 per weight class (Lat::wclass)
+  C wr[4];            // w_i rho0 per weight class (Lat::wclass)
   const C* geq;       // device [Q]: f^eq_i(rho0, u_in) - w_i rho0 for EQ faces
   double u_in[3];     // EQ-face velocity
 };
@@ -298,7 +298,7 @@ __device__ __forceinline__ void pull_sources(const LA& a, int64_t blk, uint32_t 
 // LDS by the first threads while the code loads are in flight, and each
 // lane reads the one base it needs from LDS: no scalar registers hold the
 // 4 (q-1) slot values.
-constexpr int NBR_SLOTS = 18 * NBR_BASES;   // D3Q19; D2Q9 uses the first 32
+constexpr int NBR_SLOTS = 26 * NBR_BASES;   // D3Q27; smaller lattices use a prefix
 template <class Lat, int MODE, class LA>
 __device__ __forceinline__ void pull_sources_wg_mode(const LA& a, int64_t blk, uint32_t x,
                                                      uint32_t regm, uint32_t m, int32_t* j,
@@ -455,7 +455,7 @@ template <class Lat, class C, class Wr>
 __device__ __forceinline__ void record_values(Wr& w, const C* g, C drho, C rho, const C* u, C uu,
                                               C omega) {
   constexpr int D = Lat::D;
-  static_assert(cap_fneq(D) == 0 && cap_rho(D) == Lat::Q, "record layout");
+  static_assert(cap_fneq(Lat::Q) == 0 && cap_rho(Lat::Q) == Lat::Q, "record layout");
   // streamed: each g^neq_i is handed on and folded into the second moments
   // as it is formed, so no per-direction array stays live
   C pi[Lat::NS];
@@ -464,7 +464,7 @@ __device__ __forceinline__ void record_values(Wr& w, const C* g, C drho, C rho, 
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const C fneq = g[i] - geq_i<Lat, C>(i, drho, rho, u, uu);
-    w.put(cap_fneq(D) + i, fneq);
+    w.put(cap_fneq(Lat::Q) + i, fneq);
 #pragma unroll
     for (int k = 0; k < Lat::NS; ++k) {
       const int cc = Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k));
@@ -472,13 +472,13 @@ __device__ __forceinline__ void record_values(Wr& w, const C* g, C drho, C rho, 
       if (cc < 0) pi[k] -= fneq;
     }
   }
-  w.put(cap_rho(D), drho);
+  w.put(cap_rho(Lat::Q), drho);
 #pragma unroll
-  for (int a = 0; a < D; ++a) w.put(cap_u(D) + a, u[a]);
+  for (int a = 0; a < D; ++a) w.put(cap_u(Lat::Q) + a, u[a]);
   const C pref = -C(1.5) * omega / rho;
 #pragma unroll
-  for (int k = 0; k < Lat::NS; ++k) w.put(cap_s(D) + k, pref * pi[k]);
-  w.finish(cap_used(D));
+  for (int k = 0; k < Lat::NS; ++k) w.put(cap_s(Lat::Q) + k, pref * pi[k]);
+  w.finish(cap_used(Lat::Q));
 }
 
 template <class Lat, class C, class R>
@@ -579,7 +579,7 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
                                         typename Prec<P>::C* __restrict__ stage,
                                         int32_t* __restrict__ slots) {
   using C = typename Prec<P>::C;
-  using Stager = WaveRecordStager<C, cap_stride(Lat::D)>;
+  using Stager = WaveRecordStager<C, cap_stride(Lat::Q)>;
   static_assert(BS == NBR_BLOCK, "a work-group covers one pull-table block");
   const int64_t xr = blk * BS + threadIdx.x;
   const bool valid = xr < x1;
@@ -617,9 +617,9 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
                          (ok ? 0u : (uint32_t)MLBM_STATUS_F16_OVERFLOW));
 }
 
-template <class C, int D>
+template <class C, int Q>
 constexpr int sc_stage_values(int bs) {
-  return (bs / 64) * WaveRecordStager<C, cap_stride(D)>::LDS_PER_WAVE;
+  return (bs / 64) * WaveRecordStager<C, cap_stride(Q)>::LDS_PER_WAVE;
 }
 
 // One level's stream-collide over [0, x1); the block map balances the plain
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
     int64_t x1, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
     typename Prec<P>::C* __restrict__ cap, uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
-  __shared__ C stage[sc_stage_values<C, Lat::D>(BS)];
+  __shared__ C stage[sc_stage_values<C, Lat::Q>(BS)];
   __shared__ int32_t slots[NBR_SLOTS];
   const int64_t blk = xcd_block2(blockIdx.x, gridDim.x, a.cap_begin / BS);
   sc_body<Lat, P, BS>(blk, x1, src, dst, a, cap, status, stage, slots);
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide_multi(
     const ScMulti<typename Prec<P>::C, typename Prec<P>::S, Lat::Q> m,
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
-  __shared__ C stage[sc_stage_values<C, Lat::D>(BS)];
+  __shared__ C stage[sc_stage_values<C, Lat::Q>(BS)];
   __shared__ int32_t slots[NBR_SLOTS];
   int sg = 0;
   while (sg + 1 < m.nseg && (int64_t)blockIdx.x >= m.first[sg + 1]) ++sg;
@@ -677,10 +677,10 @@ __global__ __launch_bounds__(BS) void k_stream_collide_multi(
 template <class Lat, class C>
 struct Rec {
   const C* p;
-  __device__ C drho() const { return p[cap_rho(Lat::D)]; }
-  __device__ C u(int a) const { return p[cap_u(Lat::D) + a]; }
-  __device__ C S(int k) const { return p[cap_s(Lat::D) + k]; }
-  __device__ C fneq(int i) const { return p[cap_fneq(Lat::D) + i]; }
+  __device__ C drho() const { return p[cap_rho(Lat::Q)]; }
+  __device__ C u(int a) const { return p[cap_u(Lat::Q) + a]; }
+  __device__ C S(int k) const { return p[cap_s(Lat::Q) + k]; }
+  __device__ C fneq(int i) const { return p[cap_fneq(Lat::Q) + i]; }
 };
 
 // A capture record read into registers with 16-byte loads (records start at
@@ -688,8 +688,8 @@ struct Rec {
 template <class Lat, class C>
 struct RecV {
   static constexpr int V = 16 / (int)sizeof(C);
-  static constexpr int N = (cap_used(Lat::D) + V - 1) / V;
-  static_assert(N * V <= cap_stride(Lat::D), "record loads stay in the record");
+  static constexpr int N = (cap_used(Lat::Q) + V - 1) / V;
+  static_assert(N * V <= cap_stride(Lat::Q), "record loads stay in the record");
   typedef C VT __attribute__((ext_vector_type(16 / sizeof(C))));
   C v[N * V];
   __device__ __forceinline__ void load(const C* __restrict__ p) {
@@ -701,10 +701,10 @@ struct RecV {
       for (int e = 0; e < V; ++e) v[k * V + e] = t[e];
     }
   }
-  __device__ C drho() const { return v[cap_rho(Lat::D)]; }
-  __device__ C u(int a) const { return v[cap_u(Lat::D) + a]; }
-  __device__ C S(int k) const { return v[cap_s(Lat::D) + k]; }
-  __device__ C fneq(int i) const { return v[cap_fneq(Lat::D) + i]; }
+  __device__ C drho() const { return v[cap_rho(Lat::Q)]; }
+  __device__ C u(int a) const { return v[cap_u(Lat::Q) + a]; }
+  __device__ C S(int k) const { return v[cap_s(Lat::Q) + k]; }
+  __device__ C fneq(int i) const { return v[cap_fneq(Lat::Q) + i]; }
 };
 
 // Writes the interpolated ghost: g* = g_eq(rho, u) + (1 - omega_t) g^neq
@@ -740,7 +740,7 @@ __device__ __forceinline__ void gff_values(const int32_t* __restrict__ slots, in
   constexpr int D = Lat::D;
   RecV<Lat, C> r[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) r[k].load(cap_fine + (int64_t)slots[k * n_gff + j] * cap_stride(D));
+  for (int k = 0; k < 4; ++k) r[k].load(cap_fine + (int64_t)slots[k * n_gff + j] * cap_stride(Lat::Q));
   u[0] = u[1] = u[2] = C(0);
   drho = 0;
 #pragma unroll
@@ -791,10 +791,10 @@ __device__ __forceinline__ void ghost_record(Wr& w, C drho, const C* u, const C*
   constexpr int D = Lat::D;
   const C rho = rho0 + drho;
 #pragma unroll
-  for (int i = 0; i < Lat::Q; ++i) w.put(cap_fneq(D) + i, fneq[i]);
-  w.put(cap_rho(D), drho);
+  for (int i = 0; i < Lat::Q; ++i) w.put(cap_fneq(Lat::Q) + i, fneq[i]);
+  w.put(cap_rho(Lat::Q), drho);
 #pragma unroll
-  for (int b = 0; b < D; ++b) w.put(cap_u(D) + b, u[b]);
+  for (int b = 0; b < D; ++b) w.put(cap_u(Lat::Q) + b, u[b]);
   const C pref = -C(1.5) * omega / rho;
 #pragma unroll
   for (int k = 0; k < Lat::NS; ++k) {
@@ -806,9 +806,9 @@ __device__ __forceinline__ void ghost_record(Wr& w, C drho, const C* u, const C*
       if (cc > 0) s += fneq[i];
       if (cc < 0) s -= fneq[i];
     }
-    w.put(cap_s(D) + k, pref * s);
+    w.put(cap_s(Lat::Q) + k, pref * s);
   }
-  w.finish(cap_used(D));
+  w.finish(cap_used(Lat::Q));
 }
 
 // Plain writer into an LDS row (no padding stores).
@@ -832,7 +832,7 @@ __device__ __forceinline__ void gff_ghost(
   gff_values<Lat, C>(slots, n_gff, j, cap_fine, fneq_scale, drho, u, fneq);
   const bool ok = emit_ghost<Lat, P>(pdf, gff_begin + j, a, drho, u, fneq);
   // pre-collision record of the ghost: it is a GhostFromCoarser source
-  RecordWriter<C> w{cap_coarse + (cap_gff_begin + j) * cap_stride(Lat::D), {}};
+  RecordWriter<C> w{cap_coarse + (cap_gff_begin + j) * cap_stride(Lat::Q), {}};
   ghost_record<Lat, C>(w, drho, u, fneq, a.omega, a.rho0);
   if (!ok) atomicOr(status, (uint32_t)MLBM_STATUS_F16_OVERFLOW);
 }
@@ -869,7 +869,7 @@ struct GffOnTheFly {
   C fneq_scale = 0, omega = 0, rho0 = 0;
 };
 
-template <int D> constexpr int gfc_lds_stride() { return cap_used(D) | 1; }  // odd: no conflicts
+template <int Q> constexpr int gfc_lds_stride() { return cap_used(Q) | 1; }  // odd: no conflicts
 template <int D> constexpr int gfc_groups_per_block() { return 64 / group_children(D); }
 
 template <class Lat, int P>
@@ -883,9 +883,9 @@ __device__ __forceinline__ void gfc_groups(
   constexpr int D = Lat::D;
   constexpr int NB = group_slots(D), NC = group_children(D);
   constexpr int GPB = gfc_groups_per_block<D>();
-  constexpr int ST = cap_stride(D);
-  constexpr int USED = cap_used(D);            // components actually read
-  constexpr int LST = gfc_lds_stride<D>();
+  constexpr int ST = cap_stride(Lat::Q);
+  constexpr int USED = cap_used(Lat::Q);            // components actually read
+  constexpr int LST = gfc_lds_stride<Lat::Q>();
   const int64_t g0 = blk * GPB;
   // one record per thread and pass: a single slot lookup, contiguous reads
   for (int r = threadIdx.x; r < GPB * NB; r += 64) {
@@ -980,7 +980,7 @@ __global__ __launch_bounds__(64) void k_fill_gfc(
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D;
-  __shared__ C sh[gfc_groups_per_block<D>() * group_slots(D) * gfc_lds_stride<D>()];
+  __shared__ C sh[gfc_groups_per_block<D>() * group_slots(D) * gfc_lds_stride<Lat::Q>()];
   gfc_groups<Lat, P>(blockIdx.x, sh, pdf, n_groups, grp_src, grp_child, cap_coarse, a, fneq_scale,
                      GffOnTheFly<C>{}, status);
 }
@@ -1003,7 +1003,7 @@ __global__ __launch_bounds__(64) void k_fill_sync(
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D;
-  __shared__ C sh[gfc_groups_per_block<D>() * group_slots(D) * gfc_lds_stride<D>()];
+  __shared__ C sh[gfc_groups_per_block<D>() * group_slots(D) * gfc_lds_stride<Lat::Q>()];
   if ((int64_t)blockIdx.x < nb_gff) {
     const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (j < n_gff)
@@ -1091,7 +1091,7 @@ __global__ __launch_bounds__(256) void k_init_capture(
   if (s >= n_cap) return;
   double g[Lat::Q];
   init_g<Lat>(rho_in, u_in, S_in, nf, cap_elem[s], rho0, omega, g);
-  write_record<Lat, double>(cap + s * cap_stride(Lat::D), g, rho0, omega);
+  write_record<Lat, double>(cap + s * cap_stride(Lat::Q), g, rho0, omega);
 }
 
 // Max |f - w rho0| over the initial state of a level (FP16 scale choice).

@@ -30,7 +30,8 @@ inline LevelArgs<C, Q> level_args(const SimState& s, int k) {
   a.rho0 = (C)s.rho0;
   a.scale = (C)std::ldexp(1.0, L.f16_exp);
   a.inv_scale = (C)std::ldexp(1.0, -L.f16_exp);
-  for (int i = 0; i < Q; ++i) a.wr[s.d == 3 ? D3Q19::wclass(i) : D2Q9::wclass(i)] = (C)s.wr[i];
+  for (int i = 0; i < 4; ++i) a.wr[i] = C(0);
+  for (int i = 0; i < Q; ++i) a.wr[stencil_wclass(s.stencil, i)] = (C)s.wr[i];
   a.geq = (const C*)s.geq_dev;
   for (int b = 0; b < 3; ++b) a.u_in[b] = s.u_in[b];
   return a;
@@ -215,17 +216,17 @@ struct Impl {
 };
 
 // ---- dispatch -------------------------------------------------------------
+#define MLBM_DISPATCH_P(s, LAT, CALL)                                       \
+  do {                                                                      \
+    if ((s).precision == MLBM_F64) { using I = Impl<LAT, MLBM_F64>; CALL; }  \
+    else if ((s).precision == MLBM_F32) { using I = Impl<LAT, MLBM_F32>; CALL; } \
+    else { using I = Impl<LAT, MLBM_F16S>; CALL; }                          \
+  } while (0)
 #define MLBM_DISPATCH(s, CALL)                                              \
   do {                                                                      \
-    if ((s).d == 3) {                                                       \
-      if ((s).precision == MLBM_F64) { using I = Impl<D3Q19, MLBM_F64>; CALL; } \
-      else if ((s).precision == MLBM_F32) { using I = Impl<D3Q19, MLBM_F32>; CALL; } \
-      else { using I = Impl<D3Q19, MLBM_F16S>; CALL; }                      \
-    } else {                                                                \
-      if ((s).precision == MLBM_F64) { using I = Impl<D2Q9, MLBM_F64>; CALL; } \
-      else if ((s).precision == MLBM_F32) { using I = Impl<D2Q9, MLBM_F32>; CALL; } \
-      else { using I = Impl<D2Q9, MLBM_F16S>; CALL; }                       \
-    }                                                                       \
+    if ((s).stencil == MLBM_D3Q19) MLBM_DISPATCH_P(s, D3Q19, CALL);         \
+    else if ((s).stencil == MLBM_D3Q27) MLBM_DISPATCH_P(s, D3Q27, CALL);    \
+    else MLBM_DISPATCH_P(s, D2Q9, CALL);                                    \
   } while (0)
 
 

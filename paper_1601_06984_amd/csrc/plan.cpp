@@ -228,11 +228,6 @@ void parallel_sort(std::vector<T>& v) {
   }
 }
 
-template <class Lat>
-void velocity(int i, int64_t* v) {
-  for (int a = 0; a < Lat::D; ++a) v[a] = Lat::c(i, a);
-}
-
 struct PhaseTimer {
   bool on = std::getenv("MLBM_PLAN_TIMING") != nullptr;
   std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
@@ -402,7 +397,9 @@ void compress_pull_table(LevelPlan& lp, int q, int d, uint64_t first) {
         lp.nbr_wide[(size_t)(i - 1) * ldw + (size_t)w * NBR_BLOCK + (x - x0)] = (uint16_t)(v >> 16);
       }
   }
-  if (d == 3)
+  if (q == 27)
+    mark_morton_directions<D3Q27>(lp, first, wide);
+  else if (q == 19)
     mark_morton_directions<D3Q19>(lp, first, wide);
   else
     mark_morton_directions<D2Q9>(lp, first, wide);
@@ -722,11 +719,11 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
     const int64_t n = lp.n;
     lp.nbr.assign((size_t)(q - 1) * n, MLBM_NBR_MISSING);
     const CellMap& m = w.map;
-    int64_t vel[19][3];
-    int64_t delta[19];
+    int64_t vel[27][3];
+    int64_t delta[27];
     for (int i = 0; i < q; ++i) {
       int64_t v[3] = {0, 0, 0};
-      if (d == 3) velocity<D3Q19>(i, v); else velocity<D2Q9>(i, v);
+      for (int a = 0; a < d; ++a) v[a] = stencil_c(P.stencil, i, a);
       int64_t stride = 1;
       delta[i] = 0;
       for (int a = 0; a < d; ++a) {
@@ -969,7 +966,7 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
           const int32_t y = lp.nbr[(size_t)(i - 1) * n + x];
           if (y >= 0 && y < nf) hit[(size_t)i * nf + y] = 1;
           if (y == MLBM_NBR_BOUNCE && x < nf) {
-            const int o = d == 3 ? D3Q19::opp(i) : D2Q9::opp(i);
+            const int o = stencil_opp(P.stencil, i);
             hit[(size_t)o * nf + x] = 1;
           }
         }
@@ -1054,14 +1051,14 @@ const char* mlbm_error_string(int32_t code) {
 const char* mlbm_last_error(void) { return g_last_error.c_str(); }
 
 int32_t mlbm_lattice(int32_t stencil, int32_t* q, int32_t* c, double* w) {
-  if (stencil != MLBM_D2Q9 && stencil != MLBM_D3Q19)
+  if (stencil != MLBM_D2Q9 && stencil != MLBM_D3Q19 && stencil != MLBM_D3Q27)
     return fail(MLBM_E_ARG, "unknown stencil %d", stencil);
   const int Q = stencil_q(stencil), D = stencil_d(stencil);
   if (q) *q = Q;
   for (int i = 0; i < Q; ++i) {
     for (int a = 0; a < D; ++a)
-      if (c) c[i * D + a] = stencil == MLBM_D2Q9 ? D2Q9::c(i, a) : D3Q19::c(i, a);
-    if (w) w[i] = stencil == MLBM_D2Q9 ? D2Q9::w(i) : D3Q19::w(i);
+      if (c) c[i * D + a] = stencil_c(stencil, i, a);
+    if (w) w[i] = stencil_w(stencil, i);
   }
   return MLBM_OK;
 }
@@ -1081,7 +1078,7 @@ int32_t mlbm_plan_create(int32_t stencil, int32_t level0, const int32_t* box_ori
                          const uint64_t* solid_ids, int64_t n_solids, mlbm_plan** out) {
   if (!out) return fail(MLBM_E_ARG, "out is NULL");
   *out = nullptr;
-  if (stencil != MLBM_D2Q9 && stencil != MLBM_D3Q19)
+  if (stencil != MLBM_D2Q9 && stencil != MLBM_D3Q19 && stencil != MLBM_D3Q27)
     return fail(MLBM_E_ARG, "unknown stencil %d", stencil);
   if (!box_origin || !box_extent || !face_bc || (!leaf_ids && n_leaves) ||
       (!solid_ids && n_solids) || n_leaves <= 0 || n_solids < 0)

@@ -47,7 +47,7 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
     char* nwd = take(lp.nbr_wide.size() * 2);
     char* nhd = take(lp.nhdr.size() * 4);
     char* ce = take((size_t)lp.n_cap_fluid() * 4);
-    char* cap = take((size_t)lp.n_cap() * cap_stride(d) * cb);
+    char* cap = take((size_t)lp.n_cap() * cap_stride(q) * cb);
     char* gs = take((size_t)4 * lp.n_gff * 4);
     char* grs = take((size_t)NB * lp.n_groups * 4);
     char* grc = take((size_t)NC * lp.n_groups * 4);
@@ -278,14 +278,9 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
   }
   // lattice constants: w_i rho0 and the EQ-face equilibrium deviation
   for (int i = 0; i < s.q; ++i) {
-    double w, cu = 0, uu = 0;
-    if (s.d == 3) {
-      w = D3Q19::w(i);
-      for (int a = 0; a < 3; ++a) cu += D3Q19::c(i, a) * s.u_in[a];
-    } else {
-      w = D2Q9::w(i);
-      for (int a = 0; a < 2; ++a) cu += D2Q9::c(i, a) * s.u_in[a];
-    }
+    const double w = stencil_w(s.stencil, i);
+    double cu = 0, uu = 0;
+    for (int a = 0; a < s.d; ++a) cu += stencil_c(s.stencil, i, a) * s.u_in[a];
     for (int a = 0; a < s.d; ++a) uu += s.u_in[a] * s.u_in[a];
     s.wr[i] = w * rho0;
     s.geq[i] = w * rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);

@@ -86,6 +86,8 @@ CASES = [
     ("d2q9_3lev_ke", lambda: W.refined_box_mesh("D2Q9", 5, 8, 24, extra_levels=[(20, 44)]), 32, 3, 0.7),
     # a coarse level whose blocks hold Morton directions of the pull table
     ("d3q19_morton_ke", lambda: W.refined_box_mesh("D3Q19", 5, 14, 18), 32, 3, 0.56),
+    ("d3q27_2lev_ke", lambda: W.refined_box_mesh("D3Q27", 4, 4, 12), 16, 4, 0.56),
+    ("d3q27_morton_ke", lambda: W.refined_box_mesh("D3Q27", 5, 14, 18), 32, 3, 0.56),
 ]
 
 
@@ -104,17 +106,18 @@ def test_ke_gradient_matches_oracle_reverse(name, spec_fn, n0, steps, tau0, prec
     assert abs(dtau - gto) <= tol * abs(gto)
 
 
-def _compact_sphere():
+def _compact_sphere(stencil="D3Q19"):
     return W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-1.5, 2.0), half_width=1.5,
-                                 boxes_in_d=((-0.75, 1.0, 0.75),))
+                                 boxes_in_d=((-0.75, 1.0, 0.75),), stencil=stencil)
 
 
+@pytest.mark.parametrize("stencil", ["D3Q19", "D3Q27"])
 @pytest.mark.parametrize("objective,steps", [("ke", 3), ("drag_x", 6)])
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-8), ("f32", 5e-4)])
-def test_gradients_with_boundaries(objective, steps, precision, tol):
+def test_gradients_with_boundaries(objective, steps, precision, tol, stencil):
     """Bounce-back, equilibrium faces (d/du_in, far from zero here) and the
     copy outlet in reverse, against the oracle's reverse pass."""
-    spec = _compact_sphere()
+    spec = _compact_sphere(stencil)
     uin = np.array([0.04, 0.0, 0.0])
     fields = lambda p: W.uniform_fields(len(p), 3, uin)
     _say("sphere", objective, precision)

@@ -64,6 +64,23 @@ def test_config2_d3q19_f32_100_steps(base, lo, hi, morton):
     assert sim.status() == 0
 
 
+def test_d3q27_f32_and_f16s_100_steps():
+    """D3Q27 TGV, 32^3 with the central 16^3 refined, 100 coarse steps: FP32
+    within 1e-5 and FP16-shifted within 2e-3 (max relative pdf error)."""
+    n0 = 32
+    tau0 = 0.5 + 3 * 0.02 * n0 / (2 * np.pi * 100)
+    spec = W.refined_box_mesh("D3Q27", 5, 8, 24)
+    _say("D3Q27 f32/f16s 32")
+    osim = H.oracle_run(spec, tau0, H.tgv(n0, 0.02), 100)
+    for precision, tol in (("f32", 1e-5), ("f16s", 2e-3)):
+        sim = H.gpu_sim(spec, precision, tau0, H.tgv(n0, 0.02))
+        sim.step(100)
+        err = H.compare_post(sim, osim)
+        print("max rel pdf err", precision, err)
+        assert err < tol
+        assert sim.status() == 0
+
+
 def test_config2_d3q19_f16s_100_steps():
     n0 = 32
     tau0 = 0.5 + 3 * 0.02 * n0 / (2 * np.pi * 100)
@@ -85,6 +102,8 @@ def test_config2_d3q19_f16s_100_steps():
     # coarse levels whose blocks hold Morton directions of the pull table
     ("d3q19_morton", lambda: W.refined_box_mesh("D3Q19", 5, 14, 18), 32, 8),
     ("d2q9_morton", lambda: W.refined_box_mesh("D2Q9", 7, 56, 72), 128, 20),
+    ("d3q27_3lev", lambda: W.refined_box_mesh("D3Q27", 4, 2, 14, extra_levels=[(10, 18)]), 16, 6),
+    ("d3q27_morton", lambda: W.refined_box_mesh("D3Q27", 5, 14, 18), 32, 8),
 ])
 def test_multilevel_f64_against_oracle(name, spec_fn, n0, steps, morton):
     spec = spec_fn()
@@ -95,17 +114,18 @@ def test_multilevel_f64_against_oracle(name, spec_fn, n0, steps, morton):
     assert H.compare_post(sim, osim) < 1e-12
 
 
-def _sphere_small():
+def _sphere_small(stencil="D3Q19"):
     return W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0), half_width=2.0,
-                                 boxes_in_d=((-1.0, 1.5, 1.0),))
+                                 boxes_in_d=((-1.0, 1.5, 1.0),), stencil=stencil)
 
 
+@pytest.mark.parametrize("stencil", ["D3Q19", "D3Q27"])
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_sphere_boundaries_and_drag(precision, tol):
+def test_sphere_boundaries_and_drag(precision, tol, stencil):
     """Bounce-back, equilibrium inflow/lateral faces, copy outlet on a small
     two-level sphere channel; drag (momentum exchange) against the oracle's
     literal Sec. 2.3 sum."""
-    spec = _sphere_small()
+    spec = _sphere_small(stencil)
     uin = np.array([0.04, 0.0, 0.0])
     fields = lambda pos: W.uniform_fields(len(pos), 3, uin)
     _say("sphere small", precision)
@@ -122,7 +142,8 @@ def test_sphere_boundaries_and_drag(precision, tol):
     assert F[0] > 0
 
 
-@pytest.mark.parametrize("stencil,base,lo,hi", [("D2Q9", 5, 8, 24), ("D3Q19", 4, 4, 12)])
+@pytest.mark.parametrize("stencil,base,lo,hi", [("D2Q9", 5, 8, 24), ("D3Q19", 4, 4, 12),
+                                                ("D3Q27", 4, 4, 12)])
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-14), ("f32", 2e-7)])
 def test_fill_exact_on_quadratic_fields(stencil, base, lo, hi, precision, tol):
     """Eqs. compact_3D_u / compact_3D_s on the GPU: initialise a quadratic
@@ -217,16 +238,16 @@ def test_graph_replay_matches_direct_launches():
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
-@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
 def test_grouped_launches_match_per_level_launches(stencil, precision):
     """Stream-collides of different levels launched as one grid give the
     same bits as one launch per level (the profiled schedule), on three
     levels where groups of two and three levels occur."""
-    if stencil == "D3Q19":
-        spec = W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)])
+    if stencil != "D2Q9":
+        spec = W.refined_box_mesh(stencil, 4, 2, 14, extra_levels=[(10, 18)])
     else:
         spec = W.refined_box_mesh("D2Q9", 5, 6, 26, extra_levels=[(20, 36)])
-    n0 = 16 if stencil == "D3Q19" else 32
+    n0 = 16 if stencil != "D2Q9" else 32
     _say(f"grouped vs per-level launches {stencil} {precision}")
     a = H.gpu_sim(spec, precision, 0.56, H.tgv(n0, 0.03))
     b = H.gpu_sim(spec, precision, 0.56, H.tgv(n0, 0.03))

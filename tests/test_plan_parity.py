@@ -29,6 +29,11 @@ MESHES = {
     "d3q19_sphere_3lev": lambda: W.sphere_channel_mesh(8, 3, length=(-3.0, 5.0), half_width=3.0,
                                                        boxes_in_d=((-2.0, 3.0, 2.0),
                                                                    (-1.0, 2.0, 1.0))),
+    "d3q27_three_level": lambda: W.refined_box_mesh("D3Q27", 4, 2, 14, extra_levels=[(10, 18)]),
+    "d3q27_sphere_small": lambda: W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0),
+                                                        half_width=2.0,
+                                                        boxes_in_d=((-1.0, 1.5, 1.0),),
+                                                        stencil="D3Q27"),
 }
 
 CODE_MAP = {omesh.BOUNCE: _lib.NBR_BOUNCE, omesh.EQ: _lib.NBR_EQ,
@@ -112,6 +117,7 @@ COMPRESS_MESHES["tgv64_refined"] = lambda: W.refined_box_mesh("D3Q19", 6, 16, 48
 COMPRESS_MESHES["sphere_d12"] = lambda: W.sphere_channel_mesh(12, 3, outlet="eq")
 COMPRESS_MESHES["d3q19_morton"] = lambda: W.refined_box_mesh("D3Q19", 5, 14, 18)
 COMPRESS_MESHES["d2q9_morton"] = lambda: W.refined_box_mesh("D2Q9", 7, 56, 72)
+COMPRESS_MESHES["d3q27_morton"] = lambda: W.refined_box_mesh("D3Q27", 5, 14, 18)
 
 
 def _morton_pull(m, c, d):
@@ -184,7 +190,7 @@ def test_compressed_pull_table_decodes_to_the_table(name, morton):
     if name == "tgv64_refined":
         assert n_wide > 0
     if name in ("sphere_d12", "d3q19_morton", "d2q9_morton") or (
-            morton == "morton" and name == "tgv64_refined"):
+            morton == "morton" and name in ("tgv64_refined", "d3q27_morton")):
         assert n_mor > 0.15 * n_dir, (name, n_mor, n_dir)
     if morton == "default" and name == "tgv64_refined":
         assert n_mor == 0   # levels with few Morton directions keep the codes
