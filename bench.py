@@ -78,23 +78,27 @@ def tgv_tau(n0, u0=0.02, re=100.0):
 
 
 def workload(name):
+    # a "_q27" suffix runs the same workload on the D3Q27 lattice
+    stencil = "D3Q19"
+    if name.endswith("_q27"):
+        stencil, name = "D3Q27", name[:-4]
     if name == "tgv64":
         n0, u0 = 64, 0.02
-        spec = W.refined_box_mesh("D3Q19", 6, 16, 48)
-        desc = ("D3Q19 periodic Taylor-Green vortex, 64^3 coarse with the central "
+        spec = W.refined_box_mesh(stencil, 6, 16, 48)
+        desc = (f"{stencil} periodic Taylor-Green vortex, 64^3 coarse with the central "
                 "32^3 coarse cells refined once (2 levels), u0=0.02, Re=100")
         return dict(spec=spec, tau0=tgv_tau(n0, u0), fields=lambda p: W.tgv_fields(p, n0, u0),
                     u_in=None, desc=desc, n0=n0, u0=u0, tgv=True)
     if name == "tgv32":
         n0, u0 = 32, 0.02
-        spec = W.refined_box_mesh("D3Q19", 5, 8, 24)
-        desc = "D3Q19 periodic Taylor-Green vortex, 32^3 coarse, central 16^3 refined"
+        spec = W.refined_box_mesh(stencil, 5, 8, 24)
+        desc = f"{stencil} periodic Taylor-Green vortex, 32^3 coarse, central 16^3 refined"
         return dict(spec=spec, tau0=tgv_tau(n0, u0), fields=lambda p: W.tgv_fields(p, n0, u0),
                     u_in=None, desc=desc, n0=n0, u0=u0, tgv=True)
     if name == "tgv128":
         n0, u0 = 128, 0.01
-        spec = W.refined_box_mesh("D3Q19", 7, 32, 96)
-        desc = "D3Q19 periodic Taylor-Green vortex, 128^3 coarse, central 64^3 refined"
+        spec = W.refined_box_mesh(stencil, 7, 32, 96)
+        desc = f"{stencil} periodic Taylor-Green vortex, 128^3 coarse, central 64^3 refined"
         return dict(spec=spec, tau0=tgv_tau(64, 0.02), fields=lambda p: W.tgv_fields(p, n0, u0),
                     u_in=None, desc=desc, n0=n0, u0=u0, tgv=True)
     if name == "sphere4":
@@ -102,10 +106,10 @@ def workload(name):
         # cells, boxes [-5D,19D]x[-5D,5D]^2, [-2.5D,9.5D]x[-2.5D,2.5D]^2,
         # [-1.25D,4.75D]x[-1.25D,1.25D]^2; about 449 M elements
         uin = 0.04
-        spec = W.sphere_channel_mesh(128, 4, outlet="eq")
+        spec = W.sphere_channel_mesh(128, 4, outlet="eq", stencil=stencil)
         tau_f = 0.5 + 3.0 * uin * 128 / 100.0
         tau0 = 0.5 + (tau_f - 0.5) / 8.0
-        desc = ("D3Q19 channel [-15D,49D]x[-15D,15D]^2 with a sphere of D=128 finest "
+        desc = (f"{stencil} channel [-15D,49D]x[-15D,15D]^2 with a sphere of D=128 finest "
                 "cells, 4 nested levels, Re=100, free-stream equilibrium u=0.04 on all faces")
         return dict(spec=spec, tau0=tau0, u_in=[uin, 0.0, 0.0], uniform_u=[uin, 0.0, 0.0],
                     desc=desc, tgv=False)
@@ -113,10 +117,10 @@ def workload(name):
         uin = 0.04
         # free-stream equilibrium on every face: a zero-gradient (copy)
         # outlet destabilises BGK at the coarse level's tau = 0.507
-        spec = W.sphere_channel_mesh(24, 3, outlet="eq")
+        spec = W.sphere_channel_mesh(24, 3, outlet="eq", stencil=stencil)
         tau_f = 0.5 + 3.0 * uin * 24 / 100.0     # Re = u D / nu on the finest level
         tau0 = 0.5 + (tau_f - 0.5) / 4.0
-        desc = ("D3Q19 channel [-15D,49D]x[-15D,15D]^2 with a sphere of D=24 finest "
+        desc = (f"{stencil} channel [-15D,49D]x[-15D,15D]^2 with a sphere of D=24 finest "
                 "cells, 3 nested levels, Re=100, free-stream equilibrium u=0.04 on all faces")
         return dict(spec=spec, tau0=tau0, u_in=[uin, 0.0, 0.0], uniform_u=[uin, 0.0, 0.0],
                     fields=lambda p: W.uniform_fields(len(p), 3, [uin, 0.0, 0.0]),
