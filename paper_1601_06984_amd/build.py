@@ -30,21 +30,25 @@ def _run(cmd):
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source and link ``lib/libmlbm.so``; returns its path."""
+    """Compile every source (in parallel) and link ``lib/libmlbm.so``;
+    returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
-    objs = []
+    jobs = []
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-c", src, "-o", obj])
-        objs.append(obj)
+        jobs.append((["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-c", src, "-o", obj],
+                     obj))
     for src in HIP_SOURCES:
         if not os.path.exists(os.path.join(CSRC, src)):
             continue
         obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc] + HIPCC_FLAGS + ["-c", src, "-o", obj])
-        objs.append(obj)
+        jobs.append(([hipcc] + HIPCC_FLAGS + ["-c", src, "-o", obj], obj))
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        list(ex.map(lambda j: _run(j[0]), jobs))
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs)
     os.replace(tmp, LIB)
