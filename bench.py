@@ -41,16 +41,16 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
 # kernel sources they were measured on (KERNEL_SOURCES digest); with any
 # other source the bench reports traffic as null.
 PMC_TRAFFIC = {
-    "sources_sha256_16": "6f6b6349276e0527",
+    "sources_sha256_16": "beec9a7da18ecc10",
     "bytes_per_launch": {
-        "tgv64/f32/6": 50044567,
-        "tgv64/f32/7": 61673365,
-        "sphere3/f32/9": 2184482157,
-        "sphere3/f32/10": 866141246,
-        "sphere3/f32/11": 851126068,
-        "sphere3/f16s/9": 1106556171,
-        "sphere3/f16s/10": 527023979,
-        "sphere3/f16s/11": 456072607,
+        "tgv64/f32/6": 47456316,
+        "tgv64/f32/7": 60055297,
+        "sphere3/f32/9": 2185274417,
+        "sphere3/f32/10": 814125269,
+        "sphere3/f32/11": 851188462,
+        "sphere3/f16s/9": 1106094398,
+        "sphere3/f16s/10": 470624062,
+        "sphere3/f16s/11": 455669397,
     },
 }
 KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")

@@ -156,7 +156,7 @@ void mlbm_plan_destroy(mlbm_plan* plan);
  * in plans created after the call: a block uses them if at least
  * block_min_directions of its directions qualify (1..26), a level if they
  * cover at least level_min_fraction (0..1) of its (block, direction) pairs;
- * defaults 0.5 and 6.  Results do not depend on it, only the traffic and
+ * defaults 0 and 6.  Results do not depend on it, only the traffic and
  * instruction mix of the stream-collide.  Process-wide; not to be called
  * while another thread creates a plan.  MLBM_E_ARG for values out of range. */
 int32_t mlbm_set_morton_policy(double level_min_fraction, int32_t block_min_directions);

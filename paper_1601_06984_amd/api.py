@@ -24,7 +24,7 @@ def lattice(stencil: str):
     return c, w
 
 
-def set_morton_policy(level_min_fraction: float = 0.5, block_min_directions: int = 6):
+def set_morton_policy(level_min_fraction: float = 0.0, block_min_directions: int = 6):
     """Policy for Morton directions of the device pull table in plans created
     afterwards (mlbm_set_morton_policy); the defaults restore the library's."""
     check(lib().mlbm_set_morton_policy(float(level_min_fraction), int(block_min_directions)))

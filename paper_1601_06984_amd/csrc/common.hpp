@@ -133,13 +133,13 @@ constexpr int NBR_HDR = 4;
 // gets 0 from the buffer range check, without a memory access
 constexpr uint32_t NBR_NO_CODE = 0x7FFFFFF8u;
 // Default policy for Morton directions (mlbm_set_morton_policy): a block
-// takes them only if at least NBR_MIN_MORTON qualify, and a level only if
-// at least NBR_LEVEL_MIN_MORTON of its (block, direction) pairs would: a
-// block mixing both kinds decodes both readings, and a level with Morton
-// directions reads each block's header before its codes, which costs more
-// than a few saved code reads give back.
+// takes them only if at least NBR_MIN_MORTON qualify (a block mixing both
+// kinds decodes both readings), and a level only if at least
+// NBR_LEVEL_MIN_MORTON of its (block, direction) pairs would (a level with
+// Morton directions reads each block's header before its codes; with the
+// slots staged in LDS that wait measures as nothing, so every level may).
 constexpr int NBR_MIN_MORTON = 6;
-constexpr double NBR_LEVEL_MIN_MORTON = 0.5;
+constexpr double NBR_LEVEL_MIN_MORTON = 0.0;
 
 // Level-local Morton code (treeID minus the level's first ID; bit b of axis
 // a at position d*b + a), kept to its low 32 bits.  Moving one cell along an
