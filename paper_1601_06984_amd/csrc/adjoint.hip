@@ -217,12 +217,10 @@ struct Adj {
     C* lnew = lam_of(s, k, j + 1);
     C* lold = lam_of(s, k, j);
     // entries no pull assigns: the ghost rows and the listed fluid entries
-    if (L.n > L.n_fluid)
-      hipLaunchKernelGGL((k_zero_ghost_rows<C>), dim3((unsigned)blocks((L.n - L.n_fluid) * Lat::Q, 256)),
-                         dim3(256), 0, s.stream, lold, L.n, L.n_fluid, Lat::Q);
-    if (A.n_unas[v])
-      hipLaunchKernelGGL((k_zero_entries<C>), dim3((unsigned)blocks(A.n_unas[v], 256)), dim3(256), 0,
-                         s.stream, lold, L.n, A.unas[v], A.n_unas[v]);
+    const int64_t nz = (L.n - L.n_fluid) * Lat::Q + A.n_unas[v];
+    if (nz)
+      hipLaunchKernelGGL((k_zero_unassigned<C>), dim3((unsigned)blocks(nz, 256)), dim3(256), 0,
+                         s.stream, lold, L.n, L.n_fluid, Lat::Q, A.unas[v], A.n_unas[v]);
     if (A.n_copy)
       hipLaunchKernelGGL((k_adj_copy_pre<Lat, P>), dim3((unsigned)blocks(A.n_copy, 256)), dim3(256), 0,
                          s.stream, (const S*)X, A.copy_el, A.n_copy, n_act, a,

@@ -371,20 +371,22 @@ __global__ __launch_bounds__(256) void k_adj_copy_add(const int32_t* __restrict_
   }
 }
 
+// Both zeroings of the entries no pull assigns, in one launch: threads
+// [0, (n - begin) q) clear the ghost rows, the next cnt the listed
+// (element, direction) entries of the fluid range.
 template <class C>
-__global__ __launch_bounds__(256) void k_zero_entries(C* __restrict__ lam, int64_t n,
-                                                      const int32_t* __restrict__ list, int64_t cnt) {
+__global__ __launch_bounds__(256) void k_zero_unassigned(C* __restrict__ lam, int64_t n,
+                                                         int64_t begin, int q,
+                                                         const int32_t* __restrict__ list,
+                                                         int64_t cnt) {
+  const int64_t w = n - begin, nr = w * q;
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t < cnt) lam[(int64_t)list[cnt + t] * n + list[t]] = C(0);
-}
-
-template <class C>
-__global__ __launch_bounds__(256) void k_zero_ghost_rows(C* __restrict__ lam, int64_t n,
-                                                         int64_t begin, int q) {
-  const int64_t w = n - begin;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= w * q) return;
-  lam[(t / w) * n + begin + t % w] = C(0);
+  if (t < nr) {
+    lam[(t / w) * n + begin + t % w] = C(0);
+  } else if (t - nr < cnt) {
+    const int64_t e = t - nr;
+    lam[(int64_t)list[cnt + e] * n + list[e]] = C(0);
+  }
 }
 
 // --------------------------------------------- interpolation transposes ----
