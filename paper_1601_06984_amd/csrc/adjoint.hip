@@ -155,16 +155,29 @@ struct Adj {
 
   static const void* X_of(const AdjLevel& A, int j) { return (j == 0 && A.X0) ? A.X0 : A.X[j]; }
 
-  // forward rerun of one coarse step on the tape
-  static void tape_advance(SimState& s, int k, int j) {
+  // forward rerun of one coarse step on the tape; as in the forward
+  // schedule, consecutive stream-collides of different levels share a
+  // launch (queued in `q`)
+  static void tape_flush(SimState& s, std::vector<ScJob>& q) {
+    if (q.empty()) return;
+    I::stream_collide_multi(s, q.data(), (int)q.size());
+    q.clear();
+  }
+  static void tape_advance(SimState& s, int k, int j, std::vector<ScJob>& q) {
     AdjLevel& A = s.adj.lv[k];
     DevLevel& L = s.lv[k];
     const bool first = k > 0 && (j % 2 == 0);
-    I::stream_collide_ptr(s, k, L.n_fluid + (first ? L.n_inner : 0), X_of(A, j), A.X[j + 1],
-                          A.cap[j]);
+    for (const auto& jb : q)
+      if (jb.k == k) {
+        tape_flush(s, q);
+        break;
+      }
+    if ((int)q.size() == SC_MAX_SEG) tape_flush(s, q);
+    q.push_back(ScJob{k, L.n_fluid + (first ? L.n_inner : 0), X_of(A, j), A.X[j + 1], A.cap[j]});
     if (k + 1 < (int)s.lv.size()) {
-      tape_advance(s, k + 1, 2 * j);
-      tape_advance(s, k + 1, 2 * j + 1);
+      tape_advance(s, k + 1, 2 * j, q);
+      tape_advance(s, k + 1, 2 * j + 1, q);
+      tape_flush(s, q);
       I::fill_sync_ptr(s, k, A.X[j + 1], s.adj.lv[k + 1].cap[2 * j + 1], A.cap[j],
                        s.adj.lv[k + 1].X[2 * j + 2]);
     }
@@ -316,7 +329,9 @@ struct Adj {
   }
 
   static void step(SimState& s) {
-    tape_advance(s, 0, 0);
+    std::vector<ScJob> q;
+    tape_advance(s, 0, 0, q);
+    tape_flush(s, q);
     int64_t off = 0;
     reverse(s, 0, 0, off);
     reduce(s, s.adj.ops_step, s.adj.n_ops_step, s.adj.chunks_step, s.adj.n_chunks_step);
