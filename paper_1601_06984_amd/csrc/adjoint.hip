@@ -157,16 +157,23 @@ struct Adj {
 
   // forward rerun of one coarse step on the tape; as in the forward
   // schedule, consecutive stream-collides of different levels share a
-  // launch (queued in `q`)
+  // launch (queued in `q`), and so do consecutive fills (`qf`)
   static void tape_flush(SimState& s, std::vector<ScJob>& q) {
     if (q.empty()) return;
     I::stream_collide_multi(s, q.data(), (int)q.size());
     q.clear();
   }
-  static void tape_advance(SimState& s, int k, int j, std::vector<ScJob>& q) {
+  static void tape_flush_fill(SimState& s, std::vector<FillJob>& qf) {
+    if (qf.empty()) return;
+    I::fill_sync_multi(s, qf.data(), (int)qf.size());
+    qf.clear();
+  }
+  static void tape_advance(SimState& s, int k, int j, std::vector<ScJob>& q,
+                           std::vector<FillJob>& qf) {
     AdjLevel& A = s.adj.lv[k];
     DevLevel& L = s.lv[k];
     const bool first = k > 0 && (j % 2 == 0);
+    tape_flush_fill(s, qf);
     for (const auto& jb : q)
       if (jb.k == k) {
         tape_flush(s, q);
@@ -175,11 +182,12 @@ struct Adj {
     if ((int)q.size() == SC_MAX_SEG) tape_flush(s, q);
     q.push_back(ScJob{k, L.n_fluid + (first ? L.n_inner : 0), X_of(A, j), A.X[j + 1], A.cap[j]});
     if (k + 1 < (int)s.lv.size()) {
-      tape_advance(s, k + 1, 2 * j, q);
-      tape_advance(s, k + 1, 2 * j + 1, q);
+      tape_advance(s, k + 1, 2 * j, q, qf);
+      tape_advance(s, k + 1, 2 * j + 1, q, qf);
       tape_flush(s, q);
-      I::fill_sync_ptr(s, k, A.X[j + 1], s.adj.lv[k + 1].cap[2 * j + 1], A.cap[j],
-                       s.adj.lv[k + 1].X[2 * j + 2]);
+      if ((int)qf.size() == FILL_MAX_SEG) tape_flush_fill(s, qf);
+      qf.push_back(FillJob{k, A.X[j + 1], s.adj.lv[k + 1].cap[2 * j + 1], A.cap[j],
+                           s.adj.lv[k + 1].X[2 * j + 2]});
     }
   }
 
@@ -330,8 +338,10 @@ struct Adj {
 
   static void step(SimState& s) {
     std::vector<ScJob> q;
-    tape_advance(s, 0, 0, q);
+    std::vector<FillJob> qf;
+    tape_advance(s, 0, 0, q, qf);
     tape_flush(s, q);
+    tape_flush_fill(s, qf);
     int64_t off = 0;
     reverse(s, 0, 0, off);
     reduce(s, s.adj.ops_step, s.adj.n_ops_step, s.adj.chunks_step, s.adj.n_chunks_step);

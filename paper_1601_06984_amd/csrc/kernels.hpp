@@ -985,42 +985,70 @@ __global__ __launch_bounds__(64) void k_fill_gfc(
                      GffOnTheFly<C>{}, status);
 }
 
-// Both fills of one synchronisation of levels (k, k+1) in one launch: work-
-// groups [0, nb_gff) fill the GhostFromFiner ghosts of level k (pdfs and
-// records), the rest the GhostFromCoarser ghosts of level k+1, which compute
-// the coarse GhostFromFiner records they read from the fine records instead
-// of waiting for them.  Same results as k_fill_gff then k_fill_gfc.
+// The fills of one synchronisation of levels (k, k+1), for one or several
+// level pairs (segments) per launch.  In a segment, work-groups
+// [0, nb_gff) fill the GhostFromFiner ghosts of level k (pdfs and records),
+// the rest the GhostFromCoarser ghosts of level k+1, which compute the
+// coarse GhostFromFiner records they read from the fine records instead of
+// waiting for them (same results as k_fill_gff then k_fill_gfc).
+// Consecutive fills of the schedule, fill(k+1) then fill(k), touch disjoint
+// data: each writes the GhostFromFiner ghosts and records of its coarse
+// level and the GhostFromCoarser ghosts of its fine level, and reads only
+// fluid capture records.
+constexpr int FILL_MAX_SEG = 4;
+template <class C, class S, int Q>
+struct FillSeg {
+  int64_t first, nb_gff, nb;     // work-groups [first, first + nb); GFF part first
+  S* pdf_c;
+  int64_t gff_begin, n_gff;
+  const int32_t* gff_slot;
+  const C* cap_fine;
+  C* cap_coarse;
+  int64_t cap_gff_begin;
+  LevelArgs<C, Q> ac;
+  C scale_gff;
+  S* pdf_f;
+  int64_t n_groups;
+  const int32_t* grp_src;
+  const int32_t* grp_child;
+  LevelArgs<C, Q> af;
+  C scale_gfc;
+};
+template <class C, class S, int Q>
+struct FillMulti {
+  int nseg;
+  FillSeg<C, S, Q> seg[FILL_MAX_SEG];
+};
+
 template <class Lat, int P>
 __global__ __launch_bounds__(64) void k_fill_sync(
-    int64_t nb_gff,
-    typename Prec<P>::S* __restrict__ pdf_c, int64_t gff_begin, int64_t n_gff,
-    const int32_t* __restrict__ gff_slot, const typename Prec<P>::C* __restrict__ cap_fine,
-    typename Prec<P>::C* __restrict__ cap_coarse, int64_t cap_gff_begin,
-    const LevelArgs<typename Prec<P>::C, Lat::Q> ac, typename Prec<P>::C scale_gff,
-    typename Prec<P>::S* __restrict__ pdf_f, int64_t n_groups,
-    const int32_t* __restrict__ grp_src, const int32_t* __restrict__ grp_child,
-    const LevelArgs<typename Prec<P>::C, Lat::Q> af, typename Prec<P>::C scale_gfc,
+    const FillMulti<typename Prec<P>::C, typename Prec<P>::S, Lat::Q> m,
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D;
   __shared__ C sh[gfc_groups_per_block<D>() * group_slots(D) * gfc_lds_stride<Lat::Q>()];
-  if ((int64_t)blockIdx.x < nb_gff) {
-    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (j < n_gff)
-      gff_ghost<Lat, P>(j, pdf_c, gff_begin, n_gff, gff_slot, cap_fine, cap_coarse,
-                        cap_gff_begin, ac, scale_gff, status);
+  int sg = 0;
+  while (sg + 1 < m.nseg && (int64_t)blockIdx.x >= m.seg[sg + 1].first) ++sg;
+  const auto& f = m.seg[sg];
+  const int64_t b = (int64_t)blockIdx.x - f.first;
+  if (b >= f.nb) return;
+  if (b < f.nb_gff) {
+    const int64_t j = b * 64 + threadIdx.x;
+    if (j < f.n_gff)
+      gff_ghost<Lat, P>(j, f.pdf_c, f.gff_begin, f.n_gff, f.gff_slot, f.cap_fine, f.cap_coarse,
+                        f.cap_gff_begin, f.ac, f.scale_gff, status);
     return;
   }
   GffOnTheFly<C> fly;
-  fly.rec0 = cap_gff_begin;
-  fly.slots = gff_slot;
-  fly.n_gff = n_gff;
-  fly.cap_fine = cap_fine;
-  fly.fneq_scale = scale_gff;
-  fly.omega = ac.omega;
-  fly.rho0 = ac.rho0;
-  gfc_groups<Lat, P>((int64_t)blockIdx.x - nb_gff, sh, pdf_f, n_groups, grp_src, grp_child,
-                     (const C*)cap_coarse, af, scale_gfc, fly, status);
+  fly.rec0 = f.cap_gff_begin;
+  fly.slots = f.gff_slot;
+  fly.n_gff = f.n_gff;
+  fly.cap_fine = f.cap_fine;
+  fly.fneq_scale = f.scale_gff;
+  fly.omega = f.ac.omega;
+  fly.rho0 = f.ac.rho0;
+  gfc_groups<Lat, P>(b - f.nb_gff, sh, f.pdf_f, f.n_groups, f.grp_src, f.grp_child,
+                     (const C*)f.cap_coarse, f.af, f.scale_gfc, fly, status);
 }
 
 // -------------------------------------------------------------- init ------

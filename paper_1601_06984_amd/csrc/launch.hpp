@@ -110,25 +110,51 @@ struct Impl {
   }
 
   // GhostFromFiner of level k and GhostFromCoarser of level k+1 in one
-  // launch (k_fill_sync); pdf_c / pdf_f are the arrays receiving the ghosts
+  // launch; pdf_c / pdf_f are the arrays receiving the ghosts.  The same
+  // kernel as grouped fills (one segment), so both give the same bits.
   static void fill_sync_ptr(SimState& s, int k, void* pdf_c, const void* cap_fine,
                             void* cap_coarse, void* pdf_f) {
-    DevLevel& L = s.lv[k];
-    DevLevel& F = s.lv[k + 1];
+    const FillJob job{k, pdf_c, cap_fine, cap_coarse, pdf_f};
+    fill_sync_multi(s, &job, 1);
+  }
+
+  // fills of several level pairs (jobs) in one launch
+  static void fill_sync_multi(SimState& s, const FillJob* jobs, int n) {
     constexpr int GPB = 64 / group_children(Lat::D);
-    const int64_t nb_gff = (L.n_gff + 63) / 64;
-    const int64_t nb_gfc = (F.n_groups + GPB - 1) / GPB;
-    if (nb_gff + nb_gfc == 0) return;
-    auto ac = level_args<C, Lat::Q>(s, k);
-    auto af = level_args<C, Lat::Q>(s, k + 1);
-    const C scale_gff = (C)(2.0 * F.omega / L.omega);
-    const C scale_gfc = (C)(L.omega / (2.0 * F.omega));
-    hipLaunchKernelGGL((k_fill_sync<Lat, P>), dim3((unsigned)(nb_gff + nb_gfc)), dim3(64), 0,
-                       s.stream, nb_gff, (S*)pdf_c, L.n_fluid + L.n_inner + L.n_outer, L.n_gff,
-                       (const int32_t*)L.gff_slot, (const C*)cap_fine, (C*)cap_coarse,
-                       L.n_cap_fluid, ac, scale_gff, (S*)pdf_f, F.n_groups,
-                       (const int32_t*)F.grp_src, (const int32_t*)F.grp_child, af, scale_gfc,
-                       s.status);
+    FillMulti<C, S, Lat::Q> m{};
+    m.nseg = 0;
+    int64_t total = 0;
+    for (int j = 0; j < n; ++j) {
+      const int k = jobs[j].k;
+      DevLevel& L = s.lv[k];
+      DevLevel& F = s.lv[k + 1];
+      const int64_t nb_gff = (L.n_gff + 63) / 64;
+      const int64_t nb_gfc = (F.n_groups + GPB - 1) / GPB;
+      if (nb_gff + nb_gfc == 0) continue;
+      auto& f = m.seg[m.nseg++];
+      f.first = total;
+      f.nb_gff = nb_gff;
+      f.nb = nb_gff + nb_gfc;
+      f.pdf_c = (S*)jobs[j].pdf_c;
+      f.gff_begin = L.n_fluid + L.n_inner + L.n_outer;
+      f.n_gff = L.n_gff;
+      f.gff_slot = L.gff_slot;
+      f.cap_fine = (const C*)jobs[j].cap_fine;
+      f.cap_coarse = (C*)jobs[j].cap_coarse;
+      f.cap_gff_begin = L.n_cap_fluid;
+      f.ac = level_args<C, Lat::Q>(s, k);
+      f.scale_gff = (C)(2.0 * F.omega / L.omega);
+      f.pdf_f = (S*)jobs[j].pdf_f;
+      f.n_groups = F.n_groups;
+      f.grp_src = F.grp_src;
+      f.grp_child = F.grp_child;
+      f.af = level_args<C, Lat::Q>(s, k + 1);
+      f.scale_gfc = (C)(L.omega / (2.0 * F.omega));
+      total += f.nb;
+    }
+    if (!m.nseg) return;
+    hipLaunchKernelGGL((k_fill_sync<Lat, P>), dim3((unsigned)total), dim3(64), 0, s.stream,
+                       m, s.status);
   }
 
   static void fill_sync(SimState& s, int k) {

@@ -114,10 +114,19 @@ void flush_sc(SimState& s) {
   s.pending.clear();
 }
 
+// Launches the pending fills (consecutive fills of different level pairs)
+// as one grid.
+void flush_fill(SimState& s) {
+  if (s.pending_fill.empty()) return;
+  MLBM_DISPATCH(s, I::fill_sync_multi(s, s.pending_fill.data(), (int)s.pending_fill.size()));
+  s.pending_fill.clear();
+}
+
 void sc_level(SimState& s, int k) {
   DevLevel& L = s.lv[k];
   const bool first = (k > 0) && (L.substep == 0);
   const int64_t n_act = L.n_fluid + (first ? L.n_inner : 0);
+  flush_fill(s);   // a stream-collide reads the ghosts the fills write
   if (!s.prof.on) {
     // consecutive stream-collides of different levels share a launch; a
     // second one of the same level depends on the first
@@ -151,8 +160,21 @@ void sc_level(SimState& s, int k) {
 
 void fill_gff(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_gff(s, k)); }
 void fill_sync(SimState& s, int k) {
-  flush_sc(s);
-  MLBM_DISPATCH(s, I::fill_sync(s, k));
+  flush_sc(s);   // the fills read the records the stream-collides write
+  if (s.prof.on) {
+    flush_fill(s);
+    MLBM_DISPATCH(s, I::fill_sync(s, k));
+    return;
+  }
+  for (const auto& j : s.pending_fill)
+    if (j.k == k) {
+      flush_fill(s);
+      break;
+    }
+  if ((int)s.pending_fill.size() == FILL_MAX_SEG) flush_fill(s);
+  DevLevel& L = s.lv[k];
+  DevLevel& F = s.lv[k + 1];
+  s.pending_fill.push_back(FillJob{k, L.pdf[L.parity], F.cap, L.cap, F.pdf[F.parity]});
 }
 void fill_gfc(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_gfc(s, k)); }
 
@@ -188,6 +210,7 @@ static hipError_t two_step_graph(SimState& s, hipGraphExec_t* exec) {
     advance(s, 0);
     advance(s, 0);
     flush_sc(s);
+    flush_fill(s);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s.stream, &graph);
     if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
@@ -397,6 +420,7 @@ int32_t mlbm_step(mlbm_sim* sim, int64_t n_coarse) {
     s.time++;
   }
   flush_sc(s);
+  flush_fill(s);
   return check_launch("mlbm_step");
 }
 

@@ -63,6 +63,14 @@ struct ScJob {
   void* dst;
   void* cap;
 };
+// A fill of levels (k, k+1) waiting likewise (see mlbm::flush_fill).
+struct FillJob {
+  int k;
+  void* pdf_c;
+  const void* cap_fine;
+  void* cap_coarse;
+  void* pdf_f;
+};
 
 // Adjoint state: the tape of one coarse step and the lambda arrays.
 struct AdjLevel {
@@ -124,6 +132,7 @@ struct SimState {
   // own dispatch timestamps (start, stop)
   hipEvent_t launch_ev[2] = {nullptr, nullptr};
   std::vector<ScJob> pending;          // stream-collides not yet launched
+  std::vector<FillJob> pending_fill;   // fills not yet launched
   AdjState adj;
   // graphs of two coarse steps, keyed by the parity state they start from
   hipStream_t capture_stream = nullptr;
