@@ -41,16 +41,16 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
 # kernel sources they were measured on (KERNEL_SOURCES digest); with any
 # other source the bench reports traffic as null.
 PMC_TRAFFIC = {
-    "sources_sha256_16": "beec9a7da18ecc10",
+    "sources_sha256_16": "2034e547407f3128",
     "bytes_per_launch": {
-        "tgv64/f32/6": 47456316,
-        "tgv64/f32/7": 60055297,
-        "sphere3/f32/9": 2185274417,
-        "sphere3/f32/10": 814125269,
-        "sphere3/f32/11": 851188462,
-        "sphere3/f16s/9": 1106094398,
-        "sphere3/f16s/10": 470624062,
-        "sphere3/f16s/11": 455669397,
+        "tgv64/f32/6": 47457046,
+        "tgv64/f32/7": 60037740,
+        "sphere3/f32/9": 2194922668,
+        "sphere3/f32/10": 814110470,
+        "sphere3/f32/11": 851185561,
+        "sphere3/f16s/9": 1109497288,
+        "sphere3/f16s/10": 470736011,
+        "sphere3/f16s/11": 455727153,
     },
 }
 KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")
