@@ -48,7 +48,7 @@ void step_ops(const SimState& s, int k, int j, OpBuilder& ob) {
   const int nlev = (int)s.lv.size();
   if (k + 1 < nlev) {
     const auto& F = s.lv[k + 1];
-    if (F.n_inner + F.n_outer) ob.add(blocks(F.n_inner + F.n_outer, 64), k + 1, k);
+    if (F.n_groups) ob.add(blocks(F.n_groups, 64 / group_children(s.d)), k + 1, k);
     if (s.lv[k].n_gff) ob.add(blocks(s.lv[k].n_gff, 64), k, k + 1);
     step_ops(s, k + 1, 2 * j + 1, ob);
     step_ops(s, k + 1, 2 * j, ob);
@@ -62,7 +62,7 @@ void step_ops(const SimState& s, int k, int j, OpBuilder& ob) {
 void init_ops(const SimState& s, OpBuilder& ob) {
   const int nlev = (int)s.lv.size();
   for (int k = nlev - 1; k >= 1; --k)
-    if (s.lv[k].n_inner + s.lv[k].n_outer) ob.add(blocks(s.lv[k].n_inner + s.lv[k].n_outer, 64), k, k - 1);
+    if (s.lv[k].n_groups) ob.add(blocks(s.lv[k].n_groups, 64 / group_children(s.d)), k, k - 1);
   for (int k = nlev - 2; k >= 0; --k)
     if (s.lv[k].n_gff) ob.add(blocks(s.lv[k].n_gff, 64), k, k + 1);
   for (int k = 0; k < nlev; ++k) ob.add(blocks(s.lv[k].n_fluid, 256), k, -1);
@@ -98,11 +98,9 @@ size_t layout_adjoint(const SimState& s, const mlbm_plan& P, char* base, AdjStat
     char* u1 = take(lp.unassigned[1].size() * 4);
     char* ce = take(lp.copy_elems.size() * 4);
     char* ct = take(lp.copy_elems.size() * q * cb);
-    char* gs = take(lp.gfc_slot.size() * 4);
-    char* go = take(lp.gfc_oct.size());
     char* cp = take(lp.csr_ptr.size() * 4);
     char* cn = take(lp.csr_ent.size() * 4);
-    char* T = take((size_t)4 * lp.n_gfc() * st * cb);
+    char* T = take((size_t)group_slots(d) * lp.n_groups * st * cb);
     if (A) {
       A->lam[0] = l0;
       A->lam[1] = l1;
@@ -114,8 +112,6 @@ size_t layout_adjoint(const SimState& s, const mlbm_plan& P, char* base, AdjStat
       A->copy_el = (int32_t*)ce;
       A->n_copy = (int64_t)lp.copy_elems.size();
       A->copy_tmp = ct;
-      A->gfc_slot = (int32_t*)gs;
-      A->gfc_oct = (int8_t*)go;
       A->csr_ptr = (int32_t*)cp;
       A->csr_ent = (int32_t*)cn;
       A->T = T;
@@ -200,13 +196,13 @@ struct Adj {
   static void gfc_reverse(SimState& s, int k, const void* cap_coarse, C* lam, int64_t& off) {
     DevLevel& L = s.lv[k];
     AdjLevel& A = s.adj.lv[k];
-    const int64_t ng = L.n_inner + L.n_outer;
-    if (!ng) return;
+    if (!L.n_groups) return;
     const DevLevel& Cl = s.lv[k - 1];
-    const int64_t nb = blocks(ng, 64);
-    hipLaunchKernelGGL((k_adj_gfc<Lat, P>), dim3((unsigned)nb), dim3(64), 0, s.stream, L.n_fluid,
-                       ng, A.gfc_slot, A.gfc_oct, (const C*)cap_coarse, lam, L.n, (C*)A.T,
-                       (C)L.omega, (C)Cl.omega, (C)s.rho0, s.adj.part + off * DPART);
+    const int64_t nb = blocks(L.n_groups, 64 / group_children(Lat::D));
+    hipLaunchKernelGGL((k_adj_gfc<Lat, P>), dim3((unsigned)nb), dim3(64), 0, s.stream,
+                       L.n_groups, (const int32_t*)L.grp_src, (const int32_t*)L.grp_child,
+                       (const C*)cap_coarse, lam, L.n, (C*)A.T, (C)L.omega, (C)Cl.omega,
+                       (C)s.rho0, s.adj.part + off * DPART);
     off += nb;
     constexpr int W = cap_used(Lat::Q);
     const int64_t work = Cl.n_cap * W;
@@ -458,8 +454,6 @@ int32_t mlbm_adjoint_attach(mlbm_sim* sim, const mlbm_plan* plan, void* workspac
     up(A.unas[0], lp.unassigned[0].data(), lp.unassigned[0].size() * 4);
     up(A.unas[1], lp.unassigned[1].data(), lp.unassigned[1].size() * 4);
     up(A.copy_el, lp.copy_elems.data(), lp.copy_elems.size() * 4);
-    up(A.gfc_slot, lp.gfc_slot.data(), lp.gfc_slot.size() * 4);
-    up(A.gfc_oct, lp.gfc_oct.data(), lp.gfc_oct.size());
     up(A.csr_ptr, lp.csr_ptr.data(), lp.csr_ptr.size() * 4);
     up(A.csr_ent, lp.csr_ent.data(), lp.csr_ent.size() * 4);
     A.cur = 0;

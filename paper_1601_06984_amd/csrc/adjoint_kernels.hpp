@@ -634,47 +634,75 @@ __global__ __launch_bounds__(64) void k_adj_gff(
   block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
 }
 
-// GhostFromCoarser reverse, phase 1: one thread per ghost of the fine level
-// writes the adjoints of its four source records to T[ghost][4][stride].
+// GhostFromCoarser reverse, phase 1.  One work-group takes GPB parent
+// groups, one thread per child ghost (as the forward fill); each child forms
+// the adjoints of its four source records, and the group sums them per
+// neighbourhood slot in LDS, children in a fixed order, before writing one
+// row per (group, slot) to T[group][slot][stride].
 template <class Lat, int P>
 __global__ __launch_bounds__(64) void k_adj_gfc(
-    int64_t n_fluid, int64_t n_gfc, const int32_t* __restrict__ slots,
-    const int8_t* __restrict__ oct, const typename Prec<P>::C* __restrict__ cap_coarse,
+    int64_t n_groups, const int32_t* __restrict__ grp_src, const int32_t* __restrict__ grp_child,
+    const typename Prec<P>::C* __restrict__ cap_coarse,
     const typename Prec<P>::C* __restrict__ lam, int64_t n, typename Prec<P>::C* __restrict__ T,
     typename Prec<P>::C omega_f, typename Prec<P>::C omega_c, typename Prec<P>::C rho0,
     double* __restrict__ part) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D, Q = Lat::Q;
+  constexpr int NB = group_slots(D), NC = group_children(D), GPB = 64 / NC;
+  constexpr int ST = cap_stride(Q), USED = cap_used(Q);
+  __shared__ C sums[GPB * NB * USED];
   __shared__ double sm[DPART];
-  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  for (int e = threadIdx.x; e < GPB * NB * USED; e += 64) sums[e] = C(0);
+  const int gl = threadIdx.x / NC, c = threadIdx.x % NC;
+  const int64_t g = (int64_t)blockIdx.x * GPB + gl;
+  const int32_t target = g < n_groups ? grp_child[(int64_t)c * n_groups + g] : -1;
   double acc[DPART] = {0, 0, 0, 0, 0};
-  if (j < n_gfc) {
-    const C* rec[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) rec[k] = cap_coarse + (int64_t)slots[k * n_gfc + j] * cap_stride(Lat::Q);
-    const int o = oct[j];
-    const int sx = (o & 1) ? 1 : -1, sy = (o & 2) ? 1 : -1, sz = (o & 4) ? 1 : -1;
-    C lgs[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) lgs[i] = lam[(int64_t)i * n + n_fluid + j];
+  C lsrc[4][ST];
+  int sl[4] = {0, 0, 0, 0};
+  if (target >= 0) {
+    const int sx = (c & 1) ? 1 : -1, sy = (c & 2) ? 1 : -1, sz = (c & 4) ? 1 : -1;
     C beta[4];
     C wd, wc;
     if constexpr (D == 3) {
+      sl[0] = group_slot_of(3, 0, 0, 0);     // H
+      sl[1] = group_slot_of(3, sx, sy, 0);   // K
+      sl[2] = group_slot_of(3, sx, 0, sz);   // M
+      sl[3] = group_slot_of(3, 0, sy, sz);   // N
       beta[0] = C(0.625); beta[1] = beta[2] = beta[3] = C(0.125);
       wd = C(3.0 / 16.0); wc = C(1.0 / 16.0);
     } else {
+      sl[0] = group_slot_of(2, 0, 0, 0);     // P
+      sl[1] = group_slot_of(2, sx, 0, 0);    // P + s_x
+      sl[2] = group_slot_of(2, 0, sy, 0);    // P + s_y
+      sl[3] = group_slot_of(2, sx, sy, 0);   // P + s_x + s_y
       beta[0] = C(9.0 / 16.0); beta[1] = beta[2] = C(3.0 / 16.0); beta[3] = C(1.0 / 16.0);
       wd = C(3.0 / 16.0); wc = C(0);
     }
-    C lsrc[4][cap_stride(Lat::Q)];
+    const C* rec[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      rec[k] = cap_coarse + (int64_t)grp_src[(int64_t)sl[k] * n_groups + g] * ST;
+    C lgs[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lgs[i] = lam[(int64_t)i * n + target];
     ghost_adjoint<Lat, C>(rec, beta, omega_c / (C(2) * omega_f), omega_f, omega_c, rho0, sx, sy,
                           sz, wd, wc, lgs, nullptr, lsrc, acc[0], acc[1]);
+  }
+  __syncthreads();
+  // children of a group add in turn (its four slots are distinct)
+  for (int p = 0; p < NC; ++p) {
+    if (c == p && target >= 0) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      C* dst = T + (j * 4 + k) * cap_stride(Lat::Q);
+      for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int c = 0; c < cap_used(Lat::Q); ++c) dst[c] = lsrc[k][c];
+        for (int cc = 0; cc < USED; ++cc) sums[(gl * NB + sl[k]) * USED + cc] += lsrc[k][cc];
     }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < GPB * NB * USED; e += 64) {
+    const int g2 = e / (NB * USED), r = e % (NB * USED);
+    const int64_t gg = (int64_t)blockIdx.x * GPB + g2;
+    if (gg < n_groups) T[(gg * NB + r / USED) * ST + r % USED] = sums[e];
   }
   block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
 }

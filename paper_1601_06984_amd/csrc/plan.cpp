@@ -989,33 +989,28 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
           lp.copy_elems.push_back((int32_t)x);
           break;
         }
-    const int64_t ng = lp.n_gfc();
-    lp.gfc_slot.assign((size_t)4 * ng, -1);
-    lp.gfc_oct.assign((size_t)ng, 0);
+    // GhostFromCoarser transpose: each parent group sums its children's
+    // contributions per neighbourhood slot; coarse capture slot s then
+    // gathers the rows (group * NB + slot) that refer to it
     lp.csr_ptr.clear();
     lp.csr_ent.clear();
-    if (ng) {
+    if (lp.n_gfc() && lp.n_groups) {
+      const int NB = group_slots(d);
       const int64_t ncap_c = P.lv[k - 1].n_cap();
       std::vector<int32_t> count((size_t)ncap_c + 1, 0);
-      for (int64_t j = 0; j < ng; ++j) {
-        int oct = 0;
-        for (int a = 0; a < d; ++a) oct |= (lp.coords[(size_t)a * n + nf + j] & 1) << a;
-        lp.gfc_oct[j] = (int8_t)oct;
-        for (int t = 0; t < 4; ++t) {
-          const int32_t sl = slot_of[k - 1][lp.gfc_src[(size_t)t * ng + j]];
-          if (sl < 0) throw MeshError("internal: GhostFromCoarser source without a slot");
-          lp.gfc_slot[(size_t)t * ng + j] = sl;
-          count[sl + 1]++;
+      for (int64_t g2 = 0; g2 < lp.n_groups; ++g2)
+        for (int sl = 0; sl < NB; ++sl) {
+          const int32_t s2 = lp.grp_src[(size_t)sl * lp.n_groups + g2];
+          if (s2 >= 0) count[s2 + 1]++;
         }
-      }
       for (int64_t s2 = 0; s2 < ncap_c; ++s2) count[s2 + 1] += count[s2];
       lp.csr_ptr = count;
-      lp.csr_ent.assign((size_t)4 * ng, 0);
+      lp.csr_ent.assign((size_t)count[ncap_c], 0);
       std::vector<int32_t> fillp(count.begin(), count.end() - 1);
-      for (int64_t j = 0; j < ng; ++j)  // ascending ghost order within each row
-        for (int t = 0; t < 4; ++t) {
-          const int32_t sl = lp.gfc_slot[(size_t)t * ng + j];
-          lp.csr_ent[fillp[sl]++] = (int32_t)(j * 4 + t);
+      for (int64_t g2 = 0; g2 < lp.n_groups; ++g2)  // ascending (group, slot) in each row
+        for (int sl = 0; sl < NB; ++sl) {
+          const int32_t s2 = lp.grp_src[(size_t)sl * lp.n_groups + g2];
+          if (s2 >= 0) lp.csr_ent[fillp[s2]++] = (int32_t)(g2 * NB + sl);
         }
     }
   }

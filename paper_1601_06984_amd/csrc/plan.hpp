@@ -46,10 +46,8 @@ struct LevelPlan {
                                        // entries no pull reads; variant 0: fluid
                                        // updated, 1: fluid and inner ghosts
   std::vector<int32_t> copy_elems;     // updated elements with a COPY link
-  std::vector<int32_t> gfc_slot;       // [4][n_gfc] source capture slots on L-1
-  std::vector<int8_t> gfc_oct;         // [n_gfc] octant bits (x, y, z) of the ghost
   std::vector<int32_t> csr_ptr;        // [n_cap(L-1)+1] coarse slot -> contributions
-  std::vector<int32_t> csr_ent;        // ghost * 4 + source index
+  std::vector<int32_t> csr_ent;        // group * group_slots + neighbourhood slot
 
   int64_t n_gfc() const { return n_inner + n_outer; }
   int64_t n_active_max() const { return n_fluid + n_inner; }

@@ -85,8 +85,6 @@ struct AdjLevel {
   int32_t* copy_el = nullptr;
   int64_t n_copy = 0;
   void* copy_tmp = nullptr;
-  int32_t* gfc_slot = nullptr;
-  int8_t* gfc_oct = nullptr;
   int32_t* csr_ptr = nullptr;
   int32_t* csr_ent = nullptr;
   void* T = nullptr;
