@@ -732,15 +732,14 @@ __device__ __forceinline__ bool emit_ghost(typename Prec<P>::S* __restrict__ pdf
 // the compact interpolation at the tetrahedron's centroid:
 // u = mean(u_k) - 1/4 (a_xx + a_yy + a_zz) per component.
 // gff_values gives the ghost's pre-collision drho, u and g^neq (rescaled to
-// the coarse level); gff_record_value gives slot c of its capture record.
+// the coarse level) from the capture slots s[4] of its four fine sources.
 template <class Lat, class C>
-__device__ __forceinline__ void gff_values(const int32_t* __restrict__ slots, int64_t n_gff,
-                                           int64_t j, const C* __restrict__ cap_fine,
+__device__ __forceinline__ void gff_values(const int32_t* s, const C* __restrict__ cap_fine,
                                            C fneq_scale, C& drho, C* u, C* fneq) {
   constexpr int D = Lat::D;
   RecV<Lat, C> r[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) r[k].load(cap_fine + (int64_t)slots[k * n_gff + j] * cap_stride(Lat::Q));
+  for (int k = 0; k < 4; ++k) r[k].load(cap_fine + (int64_t)s[k] * cap_stride(Lat::Q));
   u[0] = u[1] = u[2] = C(0);
   drho = 0;
 #pragma unroll
@@ -829,7 +828,10 @@ __device__ __forceinline__ void gff_ghost(
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   C drho, u[3], fneq[Lat::Q];
-  gff_values<Lat, C>(slots, n_gff, j, cap_fine, fneq_scale, drho, u, fneq);
+  int32_t s[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s[k] = slots[k * n_gff + j];
+  gff_values<Lat, C>(s, cap_fine, fneq_scale, drho, u, fneq);
   const bool ok = emit_ghost<Lat, P>(pdf, gff_begin + j, a, drho, u, fneq);
   // pre-collision record of the ghost: it is a GhostFromCoarser source
   RecordWriter<C> w{cap_coarse + (cap_gff_begin + j) * cap_stride(Lat::Q), {}};
@@ -858,13 +860,13 @@ __global__ __launch_bounds__(64) void k_fill_gff(
 // (2D: P, P + s_x, P + s_y, P + s_x + s_y); target at s/4.
 // Coarse GhostFromFiner records computed in place of being read, for a
 // GhostFromCoarser fill that runs in the same launch as the GhostFromFiner
-// fill producing them: records at slots >= rec0 belong to coarse ghost
-// slot - rec0, whose four fine sources are in slots / cap_fine.
+// fill producing them.  With `tab` set the staging reads the group table's
+// int4 rows (see LevelPlan::grp_tab): {slot, -, -, -} for a record read from
+// memory, {-2 - f0, f1, f2, f3} for one formed from the fine records f0..f3
+// (one load fewer on that path), {-1, -, -, -} for an absent cell.
 template <class C>
 struct GffOnTheFly {
-  int64_t rec0 = INT64_MAX;
-  const int32_t* slots = nullptr;
-  int64_t n_gff = 0;
+  const int4* tab = nullptr;
   const C* cap_fine = nullptr;
   C fneq_scale = 0, omega = 0, rho0 = 0;
 };
@@ -891,12 +893,19 @@ __device__ __forceinline__ void gfc_groups(
   for (int r = threadIdx.x; r < GPB * NB; r += 64) {
     const int gl = r / NB, sl = r % NB;
     const int64_t g = g0 + gl;
-    const int32_t slot = g < n_groups ? grp_src[(int64_t)sl * n_groups + g] : -1;
+    int4 t = {-1, 0, 0, 0};
+    if (g < n_groups) {
+      if (fly.tab)
+        t = fly.tab[(int64_t)sl * n_groups + g];
+      else
+        t.x = grp_src[(int64_t)sl * n_groups + g];
+    }
+    const int32_t slot = t.x;
     C* dst = sh + r * LST;
-    if (slot >= fly.rec0) {
+    if (slot <= -2) {
       C drho, u[3], fneq[Lat::Q];
-      gff_values<Lat, C>(fly.slots, fly.n_gff, slot - fly.rec0, fly.cap_fine, fly.fneq_scale,
-                         drho, u, fneq);
+      const int32_t fs[4] = {-2 - t.x, t.y, t.z, t.w};
+      gff_values<Lat, C>(fs, fly.cap_fine, fly.fneq_scale, drho, u, fneq);
       RowWriter<C> w{dst};
       ghost_record<Lat, C>(w, drho, u, fneq, fly.omega, fly.rho0);
     } else if (slot >= 0) {
@@ -1010,6 +1019,7 @@ struct FillSeg {
   S* pdf_f;
   int64_t n_groups;
   const int32_t* grp_src;
+  const int4* grp_tab;
   const int32_t* grp_child;
   LevelArgs<C, Q> af;
   C scale_gfc;
@@ -1040,9 +1050,7 @@ __global__ __launch_bounds__(64) void k_fill_sync(
     return;
   }
   GffOnTheFly<C> fly;
-  fly.rec0 = f.cap_gff_begin;
-  fly.slots = f.gff_slot;
-  fly.n_gff = f.n_gff;
+  fly.tab = f.grp_tab;
   fly.cap_fine = f.cap_fine;
   fly.fneq_scale = f.scale_gff;
   fly.omega = f.ac.omega;

@@ -147,6 +147,7 @@ struct Impl {
       f.pdf_f = (S*)jobs[j].pdf_f;
       f.n_groups = F.n_groups;
       f.grp_src = F.grp_src;
+      f.grp_tab = (const int4*)F.grp_tab;
       f.grp_child = F.grp_child;
       f.af = level_args<C, Lat::Q>(s, k + 1);
       f.scale_gfc = (C)(L.omega / (2.0 * F.omega));

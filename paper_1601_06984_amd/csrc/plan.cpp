@@ -951,6 +951,21 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
     }
     (void)n;
     (void)L;
+    // staging rows of the synchronous fill (coarse GhostFromFiner records
+    // are formed from their fine sources, whose slots the row carries)
+    lp.grp_tab.assign((size_t)4 * NB * lp.n_groups, 0);
+    const int64_t rec0 = cp.n_cap_fluid();
+    for (int64_t e = 0; e < NB * lp.n_groups; ++e) {
+      const int32_t s2 = lp.grp_src[e];
+      int32_t* t = &lp.grp_tab[(size_t)4 * e];
+      if (s2 >= rec0) {
+        const int64_t j = s2 - rec0;
+        for (int u = 0; u < 4; ++u) t[u] = cp.gff_slot[(size_t)u * cp.n_gff + j];
+        t[0] = -2 - t[0];
+      } else {
+        t[0] = s2;
+      }
+    }
   }
 
   // ---- adjoint tables ------------------------------------------------------

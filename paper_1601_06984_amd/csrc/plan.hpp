@@ -21,6 +21,11 @@ struct LevelPlan {
   std::vector<int32_t> gff_slot;   // [4][n_gff] capture slots on L+1
   int64_t n_groups = 0;            // GhostFromCoarser parent groups
   std::vector<int32_t> grp_src;    // [slots][n_groups] capture slots on L-1
+  // [slots][n_groups][4]: the synchronous fill's staging rows.  A slot whose
+  // L-1 record is a GhostFromFiner ghost's (formed on the fly from the L
+  // records) holds {-2 - f0, f1, f2, f3}, the capture slots on L of that
+  // ghost's four sources; other slots {grp_src, 0, 0, 0}.
+  std::vector<int32_t> grp_tab;
   std::vector<int32_t> grp_child;  // [children][n_groups] element idx on L
   std::vector<int32_t> bounce;     // [2][n_bounce] (element, direction)
 

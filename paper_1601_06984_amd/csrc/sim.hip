@@ -50,6 +50,7 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
     char* cap = take((size_t)lp.n_cap() * cap_stride(q) * cb);
     char* gs = take((size_t)4 * lp.n_gff * 4);
     char* grs = take((size_t)NB * lp.n_groups * 4);
+    char* grt = take(lp.grp_tab.size() * 4);
     char* grc = take((size_t)NC * lp.n_groups * 4);
     char* bb = take((size_t)2 * lp.n_bounce() * 4);
     if (L) {
@@ -65,6 +66,7 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
       L->cap = cap;
       L->gff_slot = (int32_t*)gs;
       L->grp_src = (int32_t*)grs;
+      L->grp_tab = (int32_t*)grt;
       L->grp_child = (int32_t*)grc;
       L->bounce = (int32_t*)bb;
     }
@@ -324,6 +326,7 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
     up(L.cap_elem, lp.cap_elem.data(), lp.cap_elem.size() * 4);
     up(L.gff_slot, lp.gff_slot.data(), lp.gff_slot.size() * 4);
     up(L.grp_src, lp.grp_src.data(), lp.grp_src.size() * 4);
+    up(L.grp_tab, lp.grp_tab.data(), lp.grp_tab.size() * 4);
     up(L.grp_child, lp.grp_child.data(), lp.grp_child.size() * 4);
     up(L.bounce, lp.bounce.data(), lp.bounce.size() * 4);
   }

@@ -28,6 +28,7 @@ struct DevLevel {
   void* cap = nullptr;                // [n_cap][cap_stride] compute type
   int32_t* gff_slot = nullptr;        // [4][n_gff] capture slots on level+1
   int32_t* grp_src = nullptr;         // [slots][n_groups] capture slots on level-1
+  int32_t* grp_tab = nullptr;         // [slots][n_groups][4] fill staging rows
   int32_t* grp_child = nullptr;       // [children][n_groups] element indices
   int32_t* bounce = nullptr;          // [2][n_bounce]
   int parity = 0;                     // index of the current pdf array
