@@ -41,16 +41,16 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
 # kernel sources they were measured on (KERNEL_SOURCES digest); with any
 # other source the bench reports traffic as null.
 PMC_TRAFFIC = {
-    "sources_sha256_16": "2034e547407f3128",
+    "sources_sha256_16": "8498598eff456f97",
     "bytes_per_launch": {
-        "tgv64/f32/6": 47457046,
-        "tgv64/f32/7": 60037740,
-        "sphere3/f32/9": 2194922668,
-        "sphere3/f32/10": 814110470,
-        "sphere3/f32/11": 851185561,
-        "sphere3/f16s/9": 1109497288,
-        "sphere3/f16s/10": 470736011,
-        "sphere3/f16s/11": 455727153,
+        "tgv64/f32/6": 47456247,
+        "tgv64/f32/7": 60030745,
+        "sphere3/f32/9": 2194974019,
+        "sphere3/f32/10": 814036093,
+        "sphere3/f32/11": 851637035,
+        "sphere3/f16s/9": 1109490710,
+        "sphere3/f16s/10": 470897279,
+        "sphere3/f16s/11": 455938831,
     },
 }
 KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")
