@@ -224,75 +224,148 @@ struct Adj {
     off += nb;
   }
 
-  static void sc_reverse(SimState& s, int k, int j, const void* X, int64_t& off) {
-    DevLevel& L = s.lv[k];
-    AdjLevel& A = s.adj.lv[k];
-    const bool first = k > 0 && (j % 2 == 0);
-    const int64_t n_act = L.n_fluid + (first ? L.n_inner : 0);
-    const int v = first ? 1 : 0;
-    auto a = level_args<C, Lat::Q>(s, k);
-    C* lnew = lam_of(s, k, j + 1);
-    C* lold = lam_of(s, k, j);
-    // entries no pull assigns: the ghost rows and the listed fluid entries
-    const int64_t nz = (L.n - L.n_fluid) * Lat::Q + A.n_unas[v];
-    if (nz)
-      hipLaunchKernelGGL((k_zero_unassigned<C>), dim3((unsigned)blocks(nz, 256)), dim3(256), 0,
-                         s.stream, lold, L.n, L.n_fluid, Lat::Q, A.unas[v], A.n_unas[v]);
-    if (A.n_copy)
-      hipLaunchKernelGGL((k_adj_copy_pre<Lat, P>), dim3((unsigned)blocks(A.n_copy, 256)), dim3(256), 0,
-                         s.stream, (const S*)X, A.copy_el, A.n_copy, n_act, a,
-                         (const C*)lnew, (const C*)A.lam_cap, (C*)A.copy_tmp);
-    // plain fluid [0, cb) without records; the split is rounded down to a
-    // pull-table block so each work-group covers one block
-    const int64_t cb = (L.n_fluid - L.n_cap_fluid) / NBR_BLOCK * NBR_BLOCK;
-    const int64_t nb1 = blocks(cb, 256), nb2 = blocks(n_act - cb, 256);
+  // One reverse stream-collide: level k, sub-step j, its tape state X and
+  // its partial-record offset.
+  struct RevJob {
+    int k, v;
+    const void* X;
+    int64_t n_act, cb, nb1, nb2, off;
+    C* lnew;
+    C* lold;
+  };
+
+  static void rev_segment(SimState& s, const RevJob& jb, bool tail, AdjScMulti<C, S, Lat::Q>& m,
+                          int64_t& total) {
+    const int64_t nb = tail ? jb.nb2 : jb.nb1;
+    if (!nb) return;
+    auto& f = m.seg[m.nseg++];
+    f.first = total;
+    f.nb = nb;
+    f.X = (const S*)jb.X;
+    f.x0 = tail ? jb.cb : 0;
+    f.x1 = tail ? jb.n_act : jb.cb;
+    f.a = level_args<C, Lat::Q>(s, jb.k);
+    f.lam_new = jb.lnew;
+    f.lam_cap = (C*)s.adj.lv[jb.k].lam_cap;
+    f.lam_old = jb.lold;
+    f.part = s.adj.part + (jb.off + (tail ? jb.nb1 : 0)) * DPART;
+    total += nb;
+  }
+
+  // Launches reverse stream-collides of distinct levels together: zeroing
+  // and copy-link kernels per level around one tail launch (sources and
+  // inner ghosts: more work per element, few blocks) on the side stream
+  // beside one plain launch; all of them read lam_new and scatter to
+  // disjoint lam_old entries.  A profiled run launches one level at a time
+  // on one stream, timing it with events.
+  static void rev_run(SimState& s, const RevJob* jobs, int n) {
+    if (!n) return;
+    for (int t = 0; t < n; ++t) {
+      const RevJob& jb = jobs[t];
+      DevLevel& L = s.lv[jb.k];
+      AdjLevel& A = s.adj.lv[jb.k];
+      // entries no pull assigns: the ghost rows and the listed fluid entries
+      const int64_t nz = (L.n - L.n_fluid) * Lat::Q + A.n_unas[jb.v];
+      if (nz)
+        hipLaunchKernelGGL((k_zero_unassigned<C>), dim3((unsigned)blocks(nz, 256)), dim3(256), 0,
+                           s.stream, jb.lold, L.n, L.n_fluid, Lat::Q, A.unas[jb.v], A.n_unas[jb.v]);
+      if (A.n_copy)
+        hipLaunchKernelGGL((k_adj_copy_pre<Lat, P>), dim3((unsigned)blocks(A.n_copy, 256)), dim3(256),
+                           0, s.stream, (const S*)jb.X, A.copy_el, A.n_copy, jb.n_act,
+                           level_args<C, Lat::Q>(s, jb.k), (const C*)jb.lnew,
+                           (const C*)A.lam_cap, (C*)A.copy_tmp);
+    }
+    AdjScMulti<C, S, Lat::Q> mt{}, mp{};
+    int64_t nt = 0, np = 0;
+    for (int t = 0; t < n; ++t) {
+      rev_segment(s, jobs[t], true, mt, nt);
+      rev_segment(s, jobs[t], false, mp, np);
+    }
     // profiling: the first launch records the start, the last the end
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (s.prof.on && nb1 + nb2 > 0) {
+    if (s.prof.on && n == 1 && nt + np > 0) {
       e0 = prof_event(s);
       e1 = prof_event(s);
     }
     const bool ev = e0 && e1;
-    // the tail (sources and inner ghosts: more work per element, few
-    // blocks) runs on the side stream beside the plain range; both only
-    // read lam_new and scatter to disjoint lam_old entries.  Profiled runs
-    // keep them in order on one stream so each can be timed.
-    const bool fork = nb1 && nb2 && !s.prof.on && s.adj.side;
+    const bool fork = nt && np && !s.prof.on && s.adj.side;
     hipStream_t tail_stream = s.stream;
     if (fork && hipEventRecord(s.adj.fork, s.stream) == hipSuccess &&
         hipStreamWaitEvent(s.adj.side, s.adj.fork, 0) == hipSuccess)
       tail_stream = s.adj.side;
-    if (nb2)
-      launch_timed(k_adj_sc<Lat, P, true>, dim3((unsigned)nb2), dim3(256), tail_stream,
-                   ev ? e0 : nullptr, (ev && !nb1) ? e1 : nullptr, (const S*)X,
-                   cb, n_act, a, (const C*)lnew, (C*)A.lam_cap, lold,
-                   s.adj.part + (off + nb1) * DPART);
-    if (nb1)
-      launch_timed(k_adj_sc<Lat, P, false>, dim3((unsigned)nb1), dim3(256), s.stream,
-                   (ev && !nb2) ? e0 : nullptr, ev ? e1 : nullptr, (const S*)X,
-                   (int64_t)0, cb, a, (const C*)lnew, (C*)A.lam_cap, lold, s.adj.part + off * DPART);
+    if (nt)
+      launch_timed(k_adj_sc<Lat, P, true>, dim3((unsigned)nt), dim3(256), tail_stream,
+                   ev ? e0 : nullptr, (ev && !np) ? e1 : nullptr, mt);
+    if (np)
+      launch_timed(k_adj_sc<Lat, P, false>, dim3((unsigned)np), dim3(256), s.stream,
+                   (ev && !nt) ? e0 : nullptr, ev ? e1 : nullptr, mp);
     if (tail_stream != s.stream) {
       (void)hipEventRecord(s.adj.join, tail_stream);
       (void)hipStreamWaitEvent(s.stream, s.adj.join, 0);
     }
-    if (ev) s.prof.rec.push_back({1, k, n_act, e0, e1});
-    off += nb1 + nb2;
-    if (A.n_copy)
-      hipLaunchKernelGGL((k_adj_copy_add<Lat::Q, C>), dim3((unsigned)blocks(A.n_copy, 256)), dim3(256),
-                         0, s.stream, A.copy_el, A.n_copy, L.n, (const C*)A.copy_tmp, lold);
+    if (ev) s.prof.rec.push_back({1, jobs[0].k, jobs[0].n_act, e0, e1});
+    for (int t = 0; t < n; ++t) {
+      const RevJob& jb = jobs[t];
+      AdjLevel& A = s.adj.lv[jb.k];
+      if (A.n_copy)
+        hipLaunchKernelGGL((k_adj_copy_add<Lat::Q, C>), dim3((unsigned)blocks(A.n_copy, 256)),
+                           dim3(256), 0, s.stream, A.copy_el, A.n_copy, s.lv[jb.k].n,
+                           (const C*)A.copy_tmp, jb.lold);
+    }
   }
 
-  static void reverse(SimState& s, int k, int j, int64_t& off) {
+  static void rev_flush(SimState& s, std::vector<RevJob>& q) {
+    rev_run(s, q.data(), (int)q.size());
+    q.clear();
+  }
+
+  // Queues the reverse stream-collide of level k, sub-step j (partial
+  // records from `off` on); consecutive ones of different levels share
+  // launches.
+  static void sc_reverse(SimState& s, int k, int j, const void* X, int64_t& off,
+                         std::vector<RevJob>& q) {
+    DevLevel& L = s.lv[k];
+    const bool first = k > 0 && (j % 2 == 0);
+    RevJob jb;
+    jb.k = k;
+    jb.v = first ? 1 : 0;
+    jb.X = X;
+    jb.n_act = L.n_fluid + (first ? L.n_inner : 0);
+    // plain fluid [0, cb) without records; the split is rounded down to a
+    // pull-table block so each work-group covers one block
+    jb.cb = (L.n_fluid - L.n_cap_fluid) / NBR_BLOCK * NBR_BLOCK;
+    jb.nb1 = blocks(jb.cb, 256);
+    jb.nb2 = blocks(jb.n_act - jb.cb, 256);
+    jb.off = off;
+    jb.lnew = lam_of(s, k, j + 1);
+    jb.lold = lam_of(s, k, j);
+    off += jb.nb1 + jb.nb2;
+    if (s.prof.on) {
+      rev_flush(s, q);
+      rev_run(s, &jb, 1);
+      return;
+    }
+    for (const auto& o : q)
+      if (o.k == k) {
+        rev_flush(s, q);
+        break;
+      }
+    if ((int)q.size() == ADJ_MAX_SEG) rev_flush(s, q);
+    q.push_back(jb);
+  }
+
+  static void reverse(SimState& s, int k, int j, int64_t& off, std::vector<RevJob>& q) {
     const int nlev = (int)s.lv.size();
     AdjLevel& A = s.adj.lv[k];
     if (k + 1 < nlev) {
       AdjLevel& F = s.adj.lv[k + 1];
+      rev_flush(s, q);   // the fill transposes read the lambdas they leave
       gfc_reverse(s, k + 1, A.cap[j], lam_of(s, k + 1, 2 * j + 2), off);
       gff_reverse(s, k, F.cap[2 * j + 1], lam_of(s, k, j + 1), off);
-      reverse(s, k + 1, 2 * j + 1, off);
-      reverse(s, k + 1, 2 * j, off);
+      reverse(s, k + 1, 2 * j + 1, off, q);
+      reverse(s, k + 1, 2 * j, off, q);
     }
-    sc_reverse(s, k, j, X_of(A, j), off);
+    sc_reverse(s, k, j, X_of(A, j), off, q);
   }
 
   static void seed(SimState& s, int objective) {
@@ -339,7 +412,9 @@ struct Adj {
     tape_flush(s, q);
     tape_flush_fill(s, qf);
     int64_t off = 0;
-    reverse(s, 0, 0, off);
+    std::vector<RevJob> rq;
+    reverse(s, 0, 0, off, rq);
+    rev_flush(s, rq);
     reduce(s, s.adj.ops_step, s.adj.n_ops_step, s.adj.chunks_step, s.adj.n_chunks_step);
     s.adj.lv[0].cur ^= 1;  // level 0 took one substep; finer levels an even count
   }

@@ -176,20 +176,20 @@ __global__ __launch_bounds__(256) void k_seed_drag(const int32_t* __restrict__ b
 // of the element range, where capture sources (with a record adjoint) and
 // inner ghosts live; the plain instantiation carries no record code and
 // fits 4 waves per SIMD without spills.
+// Work-group `bid` of the range [x0, x1): every thread calls it.
 template <class Lat, int P, bool REC>
-__global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc(
-    const typename Prec<P>::S* __restrict__ X, int64_t x0, int64_t x1,
-    const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+__device__ __forceinline__ void adj_sc_body(
+    int64_t bid, const typename Prec<P>::S* __restrict__ X, int64_t x0, int64_t x1,
+    const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
     const typename Prec<P>::C* __restrict__ lam_new, typename Prec<P>::C* __restrict__ lam_cap,
-    typename Prec<P>::C* __restrict__ lam_old, double* __restrict__ part) {
+    typename Prec<P>::C* __restrict__ lam_old, double* __restrict__ part, double* sm,
+    int32_t* slots) {
   using C = typename Prec<P>::C;
   constexpr int Q = Lat::Q, D = Lat::D, NS = Lat::NS;
-  __shared__ double sm[4 * DPART];
-  __shared__ int32_t slots[NBR_SLOTS];
   // x0 is a multiple of the pull-table block: a work-group is one block,
   // holding at least one element of [x0, x1)
-  const int64_t blk = (x0 >> 8) + blockIdx.x;
-  const int64_t x = x0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t blk = (x0 >> 8) + bid;
+  const int64_t x = x0 + bid * 256 + threadIdx.x;
   double acc[DPART] = {0, 0, 0, 0, 0};
   int32_t j[Q];   // pull sources: gathered from, then scattered to
   pull_sources_wg<Lat>(a, blk, (uint32_t)(x < x1 ? x : x1 - 1), j, slots);
@@ -321,7 +321,40 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc
     }
     acc[0] = dw;
   }
-  block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
+  block_sums(sm, acc, DPART, part + bid * DPART);
+}
+
+// Reverse stream-collides of several levels (segments) in one launch: the
+// transposes of consecutive stream-collides of different levels touch
+// disjoint data.  A single one is a launch with one segment.
+constexpr int ADJ_MAX_SEG = 4;
+template <class C, class S, int Q>
+struct AdjScSeg {
+  int64_t first, nb;   // work-groups [first, first + nb)
+  const S* X;
+  int64_t x0, x1;
+  LevelArgs<C, Q> a;
+  const C* lam_new;
+  C* lam_cap;
+  C* lam_old;
+  double* part;
+};
+template <class C, class S, int Q>
+struct AdjScMulti {
+  int nseg;
+  AdjScSeg<C, S, Q> seg[ADJ_MAX_SEG];
+};
+
+template <class Lat, int P, bool REC>
+__global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc(
+    const AdjScMulti<typename Prec<P>::C, typename Prec<P>::S, Lat::Q> m) {
+  __shared__ double sm[4 * DPART];
+  __shared__ int32_t slots[NBR_SLOTS];
+  int sg = 0;
+  while (sg + 1 < m.nseg && (int64_t)blockIdx.x >= m.seg[sg + 1].first) ++sg;
+  const auto& f = m.seg[sg];
+  adj_sc_body<Lat, P, REC>((int64_t)blockIdx.x - f.first, f.X, f.x0, f.x1, f.a, f.lam_new,
+                           f.lam_cap, f.lam_old, f.part, sm, slots);
 }
 
 // COPY links, part 1 (before k_adj_sc consumes the record adjoints):

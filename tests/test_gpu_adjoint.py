@@ -106,6 +106,40 @@ def test_ke_gradient_matches_oracle_reverse(name, spec_fn, n0, steps, tau0, prec
     assert abs(dtau - gto) <= tol * abs(gto)
 
 
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19"])
+def test_grouped_reverse_launches_match_per_level(stencil):
+    """The reverse step launches consecutive reverse stream-collides of
+    different levels (and the tape's forward kernels) together; a profiled
+    run launches one level at a time.  Both give the same bits."""
+    if stencil == "D3Q19":
+        spec = W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)])
+        n0 = 16
+    else:
+        spec = W.refined_box_mesh("D2Q9", 5, 8, 24, extra_levels=[(20, 44)])
+        n0 = 32
+    fields = lambda p: W.tgv_perturbed_fields(p, n0, 0.03)
+    _say("grouped vs per-level reverse", stencil)
+    out = []
+    for prof in (False, True):
+        sim = H.gpu_sim(spec, "f64", 0.7, fields)
+        sim.adjoint_attach()
+        if prof:
+            sim.profile(True)
+        ckpts = []
+        for _ in range(3):
+            ckpts.append(sim.save_checkpoint())
+            sim.step(1)
+        sim.adjoint_seed("ke")
+        for t in reversed(range(3)):
+            sim.adjoint_step(ckpts[t])
+        lam = [sim.adjoint_lambda(k).clone() for k in range(sim.plan.n_levels)]
+        dtau, _, duin = sim.adjoint_params()
+        out.append((lam, dtau))
+    for a, b in zip(out[0][0], out[1][0]):
+        assert torch.equal(a, b)
+    assert out[0][1] == out[1][1]
+
+
 def _compact_sphere(stencil="D3Q19"):
     return W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-1.5, 2.0), half_width=1.5,
                                  boxes_in_d=((-0.75, 1.0, 0.75),), stencil=stencil)
