@@ -21,6 +21,18 @@ synchronous fill of all GhostFromFiner and then all GhostFromCoarser.
 Boundary rules for pull sources: halfway bounce-back from a solid cell or
 wall face takes f*_{opp(i)}(x); an 'eq' face supplies f^eq(rho0, u_in); a
 'copy' face takes the element's own f*_i(x).
+
+Curved walls (Sec. 2.3, the linear interpolated bounce-back of Bouzidi,
+Firdaouss and Lallemand, 2001): a link from fluid element x along c_i into a
+solid cell may carry the fraction q in [0, 1] of the link at which the wall
+cuts it.  With ibar = opp(i) and x2 the element at x - c_i:
+
+    q <  1/2: f_ibar(x, t+1) = 2q f*_i(x) + (1 - 2q) f*_i(x2)
+    q >= 1/2: f_ibar(x, t+1) = f*_i(x) / (2q) + (1 - 1/(2q)) f*_ibar(x)
+
+Both give halfway bounce-back at q = 1/2.  Reading taken: where x - c_i is
+not an element (a solid cell, a face), a link with q < 1/2 falls back to
+halfway bounce-back.  Links without a fraction stay halfway.
 """
 from __future__ import annotations
 
@@ -33,7 +45,7 @@ from .mesh import BOUNCE, COPY, EQ, MISSING
 
 class OracleSim:
     def __init__(self, mesh, tau0, rho0: float = 1.0, u_in=None,
-                 poison: bool = True, dtype=torch.float64):
+                 poison: bool = True, dtype=torch.float64, walls=None):
         self.mesh = mesh
         self.lat = mesh.lattice
         self.dtype = dtype
@@ -49,6 +61,7 @@ class OracleSim:
         self.poison = poison
         self.f = {}
         self._stream_tables = {L: self._tables(L) for L in range(self.L0, self.Lmax + 1)}
+        self.walls = {} if walls is None else wall_links(mesh, *walls)
         self.time = 0  # coarse steps
 
     # ------------------------------------------------------------------
@@ -148,7 +161,28 @@ class OracleSim:
         tb = self._stream_tables[L]
         f = fstar.reshape(-1)[tb["flat"]]
         f = torch.where(tb["eq"], self.feq_inflow()[:, None].expand_as(f), f)
-        return torch.where(tb["miss"], self._filler(f.shape[1]), f)
+        f = torch.where(tb["miss"], self._filler(f.shape[1]), f)
+        if L in self.walls:
+            f = self.curved_walls(L, fstar, f)
+        return f
+
+    def curved_walls(self, L, fstar, f):
+        """Replace the halfway bounce-back values of links that carry a wall
+        fraction by the linear interpolated bounce-back (module docstring)."""
+        x, i, q, x2 = self.walls[L]
+        ibar = torch.from_numpy(self.lat.opp[i])
+        x, i = torch.from_numpy(x), torch.from_numpy(i)
+        q = torch.as_tensor(q, dtype=self.dtype)
+        has2 = torch.from_numpy(x2 >= 0)
+        x2 = torch.from_numpy(np.where(x2 >= 0, x2, 0))
+        own = fstar[i, x]                       # f*_i(x), moving into the wall
+        near = 2 * q * own + (1 - 2 * q) * fstar[i, x2]
+        near = torch.where(has2, near, own)
+        qf = torch.where(q >= 0.5, q, torch.ones_like(q))
+        far = own / (2 * qf) + (1 - 1 / (2 * qf)) * fstar[ibar, x]
+        out = f.clone()
+        out[ibar, x] = torch.where(q < 0.5, near, far)
+        return out
 
     def stream_collide(self, L):
         fstar = physics.collide(self.f[L], self.omega[L], self.lat)
@@ -217,3 +251,45 @@ class OracleSim:
             FL = (c[i] * vals[:, None]).sum(0)
             total = total + FL * float(2 ** ((d - 1) * (self.Lmax - L)))
         return total
+
+
+def wall_links(mesh, ids, dirs, q):
+    """Per level, the links (x, i, q, x2) of fluid elements x (layout index)
+    whose neighbour x + c_i is solid, from treeIDs, directions i pointing
+    into the solid and wall fractions q in [0, 1]; x2 is the element at
+    x - c_i, or a negative code where there is none."""
+    ids = np.asarray(ids, dtype=np.uint64)
+    dirs = np.asarray(dirs, dtype=np.int64)
+    q = np.asarray(q, dtype=np.float64)
+    if not (len(ids) == len(dirs) == len(q)):
+        raise ValueError("wall links: sizes differ")
+    if len(q) and (not np.isfinite(q).all() or q.min() < 0 or q.max() > 1):
+        raise ValueError("wall fraction outside [0, 1]")
+    lat = mesh.lattice
+    out = {}
+    for L in range(mesh.level0, mesh.lmax + 1):
+        t = mesh.lev(L)
+        fl = t.tid[:t.n_fluid]
+        if len(fl) == 0:
+            continue
+        order = np.argsort(fl)
+        srt = fl[order]
+        pos = np.minimum(np.searchsorted(srt, ids), len(fl) - 1)
+        on = srt[pos] == ids
+        if not on.any():
+            continue
+        x = order[pos[on]]
+        i = dirs[on]
+        if (i <= 0).any() or (i >= lat.q).any():
+            raise ValueError("wall link direction out of range")
+        ibar = lat.opp[i]
+        if (t.nbr[ibar, x] != BOUNCE).any():
+            raise ValueError("wall link whose neighbour is not solid")
+        key = x * lat.q + i
+        if len(np.unique(key)) != len(key):
+            raise ValueError("wall link given twice")
+        out[L] = (x, i, q[on], t.nbr[i, x])
+    found = sum(len(v[0]) for v in out.values())
+    if found != len(ids):
+        raise ValueError("wall link on an element that is not a fluid leaf")
+    return out

@@ -500,3 +500,87 @@ def test_mass_drift_multilevel_is_small():
     sim.step(100)
     drift = abs(float(sim.mass()) - M0) / M0
     assert drift < 1e-5
+
+
+# ------------------------------------------ curved walls (Sec. 2.3) --------
+def _channel_wall_offset(stencil, q_low, q_high, h=24, tau=0.8):
+    """Effective distance between the walls, from the decay rate of the
+    lowest shear mode, minus the distance the wall fractions place them at."""
+    spec = W.plane_channel_mesh(stencil, 5, 2, h)
+    m = mesh.build(spec)
+    walls = W.plane_wall_links(spec, m.lattice.c, q_low, q_high)
+    z_lo = 1.5 - q_low
+    H = (h - 1.5 + q_high) - z_lo
+    sim = solver.OracleSim(m, tau, walls=walls)
+    pos = m.positions(5)[:m.lev(5).n_fluid]
+    r, u, S = W.shear_wave_fields(pos, z_lo, H, 0.01)
+    sim.init({5: r}, {5: u}, {5: S})
+    sim.step(400)
+    e1 = float(sim.kinetic_energy())
+    sim.step(1200)
+    e2 = float(sim.kinetic_energy())
+    nu = (tau - 0.5) / 3.0
+    rate = math.log(e1 / e2) / (2 * 1200)          # energy decays at 2 nu k^2
+    return math.pi * math.sqrt(nu / rate) - H
+
+
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
+@pytest.mark.parametrize("q_low,q_high", [(0.25, 0.25), (0.75, 0.75), (0.1, 0.9)])
+def test_curved_wall_sits_where_the_fraction_puts_it(stencil, q_low, q_high):
+    """Sec. 2.3 (linear interpolated bounce-back): a shear wave between two
+    parallel walls decays as exp(-nu (pi/H)^2 t) with H the distance between
+    the walls.  The walls are placed by the fractions alone (the solid rows
+    do not move), so the measured H must follow q to well under the quarter
+    cell that separates the cases; halfway bounce-back would give H = 22
+    for all of them.  Measured offset: about -0.012 cells at h = 24."""
+    off = _channel_wall_offset(stencil, q_low, q_high)
+    assert abs(off) < 0.05, off
+
+
+def _compact_sphere(stencil="D3Q19"):
+    return W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-1.5, 2.0), half_width=1.5,
+                                 boxes_in_d=((-0.75, 1.0, 0.75),), stencil=stencil)
+
+
+def test_wall_fraction_one_half_is_halfway_bounce_back():
+    """At q = 1/2 both branches of the interpolated rule reduce to halfway
+    bounce-back: runs with and without the fractions agree exactly, state
+    and momentum-exchange force."""
+    spec = _compact_sphere()
+    m = mesh.build(spec)
+    ids, dirs, q = W.sphere_wall_links(spec, m.lattice.c)
+    assert len(ids) > 100
+    out = []
+    for walls in (None, (ids, dirs, np.full(len(q), 0.5))):
+        sim = solver.OracleSim(m, 0.6, u_in=[0.04, 0.0, 0.0], walls=walls)
+        rho, u, S = {}, {}, {}
+        for L in range(m.level0, m.lmax + 1):
+            nf = m.lev(L).n_fluid
+            rho[L], u[L], S[L] = np.ones(nf), np.zeros((nf, 3)), np.zeros((nf, 3, 3))
+            u[L][:, 0] = 0.04
+        sim.init(rho, u, S)
+        sim.step(3)
+        out.append((sim.f[m.lmax].clone(), sim.force()))
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+
+
+def test_fluid_at_rest_stays_at_rest_with_curved_walls():
+    """The interpolation weights of each branch sum to one, so fluid at
+    rest next to walls at any fractions stays at rest and feels no force."""
+    spec = _compact_sphere()
+    m = mesh.build(spec)
+    ids, dirs, q = W.sphere_wall_links(spec, m.lattice.c)
+    assert q.min() < 0.2 and q.max() > 0.8
+    sim = solver.OracleSim(m, 0.6, walls=(ids, dirs, q))
+    rho, u, S = {}, {}, {}
+    for L in range(m.level0, m.lmax + 1):
+        nf = m.lev(L).n_fluid
+        rho[L], u[L], S[L] = np.ones(nf), np.zeros((nf, 3)), np.zeros((nf, 3, 3))
+    sim.init(rho, u, S)
+    sim.step(3)
+    w = m.lattice.w_t(torch.float64)[:, None]
+    for L in range(m.level0, m.lmax + 1):
+        nf = m.lev(L).n_fluid
+        assert (sim.f[L][:, :nf] - w).abs().max() < 1e-15
+    assert sim.force().abs().max() < 1e-13

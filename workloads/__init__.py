@@ -14,12 +14,15 @@ x bit least significant, then y, then z.  Encoding lives here only to
 produce inputs; each consumer has its own decoder.
 """
 from .meshes import (MeshSpec, partition_example, refined_box_mesh,
-                     half_refined_2d, sphere_channel_mesh, uniform_box_mesh)
+                     half_refined_2d, sphere_channel_mesh, uniform_box_mesh,
+                     plane_channel_mesh, plane_wall_links, sphere_wall_links)
 from .fields import (tgv_fields, tgv_perturbed_fields, fourier_perturbation,
-                     uniform_fields)
+                     uniform_fields, shear_wave_fields)
 
 __all__ = [
     "MeshSpec", "partition_example", "refined_box_mesh", "half_refined_2d",
     "sphere_channel_mesh", "uniform_box_mesh", "tgv_fields",
     "tgv_perturbed_fields", "fourier_perturbation", "uniform_fields",
+    "plane_channel_mesh", "plane_wall_links", "sphere_wall_links",
+    "shear_wave_fields",
 ]

@@ -83,3 +83,18 @@ def tgv_perturbed_fields(pos: np.ndarray, n0: int, u0: float,
 def uniform_fields(n: int, d: int, u, rho0: float = 1.0):
     u = np.broadcast_to(np.asarray(u, dtype=np.float64), (n, d)).copy()
     return np.full(n, rho0), u, np.zeros((n, d, d))
+
+
+def shear_wave_fields(pos: np.ndarray, z_wall: float, height: float, u0: float,
+                      rho0: float = 1.0):
+    """Lowest shear mode between two parallel walls: u_x = u0 sin(k (z - z_wall))
+    with k = pi / height, z the last coordinate; it decays as exp(-nu k^2 t)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n, d = pos.shape
+    k = np.pi / height
+    z = pos[:, d - 1] - z_wall
+    u = np.zeros((n, d))
+    u[:, 0] = u0 * np.sin(k * z)
+    S = np.zeros((n, d, d))
+    S[:, 0, d - 1] = S[:, d - 1, 0] = 0.5 * u0 * k * np.cos(k * z)
+    return np.full(n, rho0), u, S

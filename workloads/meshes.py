@@ -243,3 +243,89 @@ def sphere_channel_mesh(d_finest: int, n_levels: int, *,
                        boxes, faces, solid=solid,
                        meta={"D": d_finest, "centre_finest": tuple(centre),
                              "n_levels": n_levels})
+
+
+# ----------------------------------------------------------------------------
+# wall fractions of links into solid cells (geometry of curved walls)
+# ----------------------------------------------------------------------------
+# A link from a fluid element along lattice velocity c_i into a solid cell is
+# described by (treeID of the fluid element, i, q): q in [0, 1] is the
+# fraction of the link, from the element's centre, at which the wall surface
+# cuts it.  The velocity set ``c`` (q x d integers) is the caller's, so the
+# direction indices mean what the consumer's lattice says.
+
+def plane_channel_mesh(stencil: str, level0: int, width: int, height: int) -> MeshSpec:
+    """Single-level channel: periodic along the first d-1 axes (``width``
+    cells each) and ``height`` cells along the last axis, whose first and
+    last cell rows are solid."""
+    d = 2 if stencil == "D2Q9" else 3
+    ext = (width,) * (d - 1) + (height,)
+
+    def solid(cells):
+        z = cells[:, d - 1]
+        return (z == 0) | (z == height - 1)
+
+    return nested_mesh(f"channel_{stencil}_{width}x{height}", stencil, level0, ext, [],
+                       ("periodic",) * (2 * d), solid=solid,
+                       meta={"height": height, "level": level0})
+
+
+def plane_wall_links(spec: MeshSpec, c: np.ndarray, q_low: float, q_high: float):
+    """Links of a ``plane_channel_mesh`` into its solid rows; the lower wall
+    cuts every link at fraction q_low, the upper at q_high (planar walls at
+    z = 1.5 - q_low and z = height - 1.5 + q_high in cell units, cell
+    centres at integer + 0.5)."""
+    d = spec.dim
+    h, L = spec.meta["height"], spec.meta["level"]
+    w = spec.box_extent[0]
+    lat = np.asarray(c, dtype=np.int64)
+    ids, dirs, qs = [], [], []
+    axes = [np.arange(w)] * (d - 1)
+    grid = np.stack([g.ravel() for g in np.meshgrid(*axes, indexing="ij")], 1) \
+        if d > 1 else np.zeros((1, 0), np.int64)
+    for row, sgn, qv in ((1, -1, q_low), (h - 2, 1, q_high)):
+        cells = np.concatenate([grid, np.full((len(grid), 1), row)], 1)
+        tid = encode_tree_ids(L, cells)
+        for i in range(1, len(lat)):
+            if lat[i, d - 1] == sgn:
+                ids.append(tid)
+                dirs.append(np.full(len(tid), i, np.int32))
+                qs.append(np.full(len(tid), qv))
+    return (np.concatenate(ids), np.concatenate(dirs), np.concatenate(qs))
+
+
+def sphere_wall_links(spec: MeshSpec, c: np.ndarray):
+    """Links of a ``sphere_channel_mesh`` into the sphere, with the fraction
+    at which the sphere surface cuts each (ray from the fluid cell's centre
+    along c_i; the cell's centre lies outside, the solid neighbour's inside,
+    so the first crossing is in [0, 1))."""
+    d = 3
+    lmax = spec.level0 + spec.meta["n_levels"] - 1
+    centre = np.asarray(spec.meta["centre_finest"], dtype=np.float64)
+    r = 0.5 * spec.meta["D"]
+    lo = np.floor(centre - r - 2).astype(np.int64)
+    hi = np.ceil(centre + r + 2).astype(np.int64)
+    cells = _box_cells(tuple(lo), tuple(hi))
+    a = cells.astype(np.float64) + 0.5 - centre
+    fluid = (a * a).sum(1) >= r * r
+    cells, a = cells[fluid], a[fluid]
+    tid = encode_tree_ids(lmax, cells)
+    leaf = np.isin(tid, spec.leaf_ids)
+    cells, a, tid = cells[leaf], a[leaf], tid[leaf]
+    lat = np.asarray(c, dtype=np.float64)
+    ids, dirs, qs = [], [], []
+    for i in range(1, len(lat)):
+        ci = lat[i]
+        b = a + ci
+        hit = (b * b).sum(1) < r * r
+        if not hit.any():
+            continue
+        aa = a[hit]
+        A = float(ci @ ci)
+        B = aa @ ci
+        C = (aa * aa).sum(1) - r * r
+        t = (-B - np.sqrt(np.maximum(B * B - A * C, 0.0))) / A
+        ids.append(tid[hit])
+        dirs.append(np.full(int(hit.sum()), i, np.int32))
+        qs.append(np.clip(t, 0.0, 1.0))
+    return (np.concatenate(ids), np.concatenate(dirs), np.concatenate(qs))
