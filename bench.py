@@ -78,10 +78,25 @@ def tgv_tau(n0, u0=0.02, re=100.0):
 
 
 def workload(name):
-    # a "_q27" suffix runs the same workload on the D3Q27 lattice
+    wl = _workload(name)
+    wl["name"] = name
+    return wl
+
+
+def _workload(name):
+    # a "_q27" suffix runs the same workload on the D3Q27 lattice; a "_bz"
+    # suffix gives a sphere workload curved walls (the fraction at which the
+    # sphere cuts each link into it, linear interpolated bounce-back)
     stencil = "D3Q19"
     if name.endswith("_q27"):
         stencil, name = "D3Q27", name[:-4]
+    if name.endswith("_bz"):
+        wl = _workload(name[:-3] + ("_q27" if stencil == "D3Q27" else ""))
+        if wl.get("tgv"):
+            raise SystemExit("curved walls need a sphere workload")
+        wl["walls"] = True
+        wl["desc"] += "; curved walls (linear interpolated bounce-back)"
+        return wl
     if name == "tgv64":
         n0, u0 = 64, 0.02
         spec = W.refined_box_mesh(stencil, 6, 16, 48)
@@ -438,6 +453,9 @@ def main():
     wl = workload(args.workload)
     print(f"[bench] workload {args.workload}: planning", file=sys.stderr, flush=True)
     plan = M.Plan.from_spec(wl["spec"])
+    if wl.get("walls"):
+        spec = wl["spec"]
+        plan.set_walls(*W.sphere_wall_links(spec, M.lattice(spec.stencil)[0]))
     upd = weighted_updates(plan)
     prec = args.precision
     sim = make_sim(M, torch, wl, plan, prec)

@@ -101,7 +101,19 @@ enum {
   MLBM_TABLE_NBR16 = 7,    /* uint16 [q-1][n_blocks * 256]                  */
   MLBM_TABLE_NBASE = 8,    /* int32 [n_blocks][q-1][4]                      */
   MLBM_TABLE_NBR_WIDE = 9, /* uint16 [q-1][n_wide * 256]                    */
-  MLBM_TABLE_NBR_HDR = 10  /* int32 [n_blocks][4]                           */
+  MLBM_TABLE_NBR_HDR = 10, /* int32 [n_blocks][4]                           */
+  /* Links that carry a wall fraction (mlbm_plan_set_walls), sorted by
+   * element then direction: {element x, pull direction j (its source
+   * x - c_j is solid), second node x2 = the element at x + c_j (the pull
+   * source of opp(j); -1 if that is not an element), weight class}. */
+  MLBM_TABLE_WALL = 11,    /* int32 [n_wall][4]                             */
+  MLBM_TABLE_WALL_Q = 12,  /* double [n_wall]: wall fraction q of each link */
+  MLBM_TABLE_WALL_BLK = 13,/* int32 [n_blocks]: per block of 256 updated
+                              elements its row of WALL_ROW, or -1 if none of
+                              its elements has such a link (empty if
+                              n_wall = 0)                                    */
+  MLBM_TABLE_WALL_ROW = 14 /* int32 [n_rows][257]: first link of each
+                              element of the block, then the block's end    */
 };
 
 /* Fields of mlbm_plan_level_info, in this order (int64 each). */
@@ -109,7 +121,7 @@ enum {
   MLBM_INFO_LEVEL = 0, MLBM_INFO_N = 1, MLBM_INFO_N_FLUID = 2,
   MLBM_INFO_N_GFC_INNER = 3, MLBM_INFO_N_GFC_OUTER = 4, MLBM_INFO_N_GFF = 5,
   MLBM_INFO_N_CAP_FLUID = 6, MLBM_INFO_N_CAP = 7, MLBM_INFO_N_GFC_GROUPS = 8,
-  MLBM_INFO_N_BOUNCE = 9, MLBM_INFO_FIELDS = 10
+  MLBM_INFO_N_BOUNCE = 9, MLBM_INFO_N_WALL = 10, MLBM_INFO_FIELDS = 11
 };
 
 /* State selectors for mlbm_get_state / mlbm_set_state. */
@@ -160,6 +172,28 @@ void mlbm_plan_destroy(mlbm_plan* plan);
  * instruction mix of the stream-collide.  Process-wide; not to be called
  * while another thread creates a plan.  MLBM_E_ARG for values out of range. */
 int32_t mlbm_set_morton_policy(double level_min_fraction, int32_t block_min_directions);
+/* Curved walls (Sec. 2.3; linear interpolated bounce-back of Bouzidi,
+ * Firdaouss and Lallemand): link t runs from the fluid leaf ids[t] along
+ * lattice velocity dirs[t] (mlbm_lattice order, pointing into the solid)
+ * to a solid cell; the wall cuts it at fraction q[t] in [0, 1] of the link
+ * from the element's centre.  With i = dirs[t], ibar = opp(i) and x2 the
+ * element at x - c_i, the stream step then takes
+ *   q <  1/2: f_ibar(x, t+1) = 2q f*_i(x) + (1 - 2q) f*_i(x2)
+ *             (halfway bounce-back f*_i(x) where x - c_i is no element)
+ *   q >= 1/2: f_ibar(x, t+1) = f*_i(x)/(2q) + (1 - 1/(2q)) f*_ibar(x)
+ * instead of halfway bounce-back, and the momentum-exchange force
+ * (MLBM_DIAG_FORCE) sums c_i (f*_i(x) + f_ibar(x, t+1)) over its links.
+ * Replaces the plan's previous set (n = 0 clears it).  Host arrays are
+ * copied.  Affects simulations created afterwards, whose workspace grows
+ * (query mlbm_sim_workspace_bytes after this call).  The adjoint does not
+ * cover these links: mlbm_adjoint_workspace_bytes / _attach return
+ * MLBM_E_STATE for a simulation with any.  Errors (the plan is left
+ * unchanged): MLBM_E_ARG (NULL arrays with n > 0, a direction out of
+ * range, q outside [0, 1] or not finite, a link given twice), MLBM_E_MESH
+ * (an id that is not a fluid leaf, or a link whose neighbour is not
+ * solid).  Host only. */
+int32_t mlbm_plan_set_walls(mlbm_plan* plan, const uint64_t* ids, const int32_t* dirs,
+                            const double* q, int64_t n);
 /* Number of levels (Lmax - L0 + 1) and L0. */
 int32_t mlbm_plan_levels(const mlbm_plan* plan, int32_t* n_levels,
                          int32_t* level0);

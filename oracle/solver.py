@@ -280,8 +280,8 @@ def wall_links(mesh, ids, dirs, q):
             continue
         x = order[pos[on]]
         i = dirs[on]
-        if (i <= 0).any() or (i >= lat.q).any():
-            raise ValueError("wall link direction out of range")
+        if (i < 0).any() or (i >= lat.q).any() or not np.abs(lat.c[i]).sum(1).all():
+            raise ValueError("wall link direction out of range or at rest")
         ibar = lat.opp[i]
         if (t.nbr[ibar, x] != BOUNCE).any():
             raise ValueError("wall link whose neighbour is not solid")

@@ -21,10 +21,10 @@ DIAG_MASS, DIAG_KE, DIAG_FORCE = 1, 2, 4
 STATUS_NONFINITE, STATUS_F16_OVERFLOW = 1, 2
 TABLE_TREEID, TABLE_COORDS, TABLE_NBR, TABLE_GFC_SRC, TABLE_GFF_SRC, \
     TABLE_CAPTURE, TABLE_BOUNCE, TABLE_NBR16, TABLE_NBASE, TABLE_NBR_WIDE, \
-    TABLE_NBR_HDR = range(11)
+    TABLE_NBR_HDR, TABLE_WALL, TABLE_WALL_Q, TABLE_WALL_BLK, TABLE_WALL_ROW = range(15)
 STATE_PDF_POST, STATE_MOMENTS = 0, 1
 INFO_FIELDS = ("level", "n", "n_fluid", "n_gfc_inner", "n_gfc_outer", "n_gff",
-               "n_cap_fluid", "n_cap", "n_gfc_groups", "n_bounce")
+               "n_cap_fluid", "n_cap", "n_gfc_groups", "n_bounce", "n_wall")
 
 _p = C.c_void_p
 _i32, _i64, _u32, _sz = C.c_int32, C.c_int64, C.c_uint32, C.c_size_t
@@ -40,6 +40,7 @@ SIGNATURES = {
                                 C.POINTER(_p)]),
     "mlbm_plan_destroy": (None, [_p]),
     "mlbm_set_morton_policy": (_i32, [C.c_double, _i32]),
+    "mlbm_plan_set_walls": (_i32, [_p, _pu64, _pi32, _pd, _i64]),
     "mlbm_plan_levels": (_i32, [_p, _pi32, _pi32]),
     "mlbm_plan_level_info": (_i32, [_p, _i32, _pi64]),
     "mlbm_plan_export": (_i32, [_p, _i32, _i32, _p, _psz]),

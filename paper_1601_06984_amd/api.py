@@ -58,11 +58,31 @@ class Plan:
         l0 = C.c_int32()
         check(lib().mlbm_plan_levels(self._h, C.byref(n), C.byref(l0)))
         self.n_levels, self.level0 = n.value, l0.value
+        self._read_info()
+
+    def _read_info(self):
         self.info = []
         for k in range(self.n_levels):
             buf = np.zeros(len(_lib.INFO_FIELDS), dtype=np.int64)
             check(lib().mlbm_plan_level_info(self._h, k, buf.ctypes.data_as(_lib._pi64)))
             self.info.append(dict(zip(_lib.INFO_FIELDS, (int(v) for v in buf))))
+
+    def set_walls(self, ids, dirs, q):
+        """Wall fractions of links into solid cells (linear interpolated
+        bounce-back): fluid leaf treeIDs, lattice directions pointing into
+        the solid (this library's order) and fractions in [0, 1].  Applies
+        to simulations created afterwards."""
+        ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
+        dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32))
+        q = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+        if not (len(ids) == len(dirs) == len(q)):
+            raise ValueError("set_walls: arrays of different lengths")
+        n = len(ids)
+        check(lib().mlbm_plan_set_walls(
+            self._h, ids.ctypes.data_as(_lib._pu64) if n else None,
+            dirs.ctypes.data_as(_lib._pi32) if n else None,
+            q.ctypes.data_as(_lib._pd) if n else None, n))
+        self._read_info()
 
     @classmethod
     def from_spec(cls, spec):
@@ -79,10 +99,13 @@ class Plan:
                "gff_src": _lib.TABLE_GFF_SRC, "capture": _lib.TABLE_CAPTURE,
                "bounce": _lib.TABLE_BOUNCE, "nbr16": _lib.TABLE_NBR16,
                "nbase": _lib.TABLE_NBASE, "nbr_wide": _lib.TABLE_NBR_WIDE,
-               "nbr_hdr": _lib.TABLE_NBR_HDR}[table]
+               "nbr_hdr": _lib.TABLE_NBR_HDR, "wall": _lib.TABLE_WALL,
+               "wall_q": _lib.TABLE_WALL_Q, "wall_blk": _lib.TABLE_WALL_BLK,
+               "wall_row": _lib.TABLE_WALL_ROW}[table]
         nbytes = C.c_size_t()
         check(lib().mlbm_plan_export(self._h, k, tid, None, C.byref(nbytes)))
-        dtype = {"treeid": np.uint64, "nbr16": np.uint16, "nbr_wide": np.uint16}.get(table, np.int32)
+        dtype = {"treeid": np.uint64, "nbr16": np.uint16, "nbr_wide": np.uint16,
+                 "wall_q": np.float64}.get(table, np.int32)
         out = np.zeros(nbytes.value // np.dtype(dtype).itemsize, dtype=dtype)
         check(lib().mlbm_plan_export(self._h, k, tid, out.ctypes.data_as(C.c_void_p),
                                      C.byref(nbytes)))
@@ -91,6 +114,10 @@ class Plan:
                 "nbr16": self.q - 1, "nbr_wide": self.q - 1}
         if table in rows:
             out = out.reshape(rows[table], -1)
+        if table == "wall":
+            out = out.reshape(-1, 4)
+        if table == "wall_row":
+            out = out.reshape(-1, 257)
         return out
 
     def __del__(self):

@@ -489,12 +489,22 @@ int32_t hip_check(hipError_t e, const char* what) {
 
 using namespace mlbm;
 
+namespace {
+bool has_wall_links(const SimState& s) {
+  for (const DevLevel& L : s.lv)
+    if (L.n_wall) return true;
+  return false;
+}
+}  // namespace
+
 extern "C" {
 
 int32_t mlbm_adjoint_workspace_bytes(const mlbm_sim* sim, const mlbm_plan* plan, size_t* bytes) {
   if (!sim || !plan || !bytes) return fail(MLBM_E_ARG, "NULL argument");
   const SimState& s = sim->s;
   if (!plan_matches(s, *plan)) return fail(MLBM_E_ARG, "plan does not belong to this simulation");
+  if (has_wall_links(s))
+    return fail(MLBM_E_STATE, "the adjoint does not cover links with a wall fraction");
   OpBuilder os, oi;
   step_ops(s, 0, 0, os);
   init_ops(s, oi);
@@ -506,6 +516,8 @@ int32_t mlbm_adjoint_attach(mlbm_sim* sim, const mlbm_plan* plan, void* workspac
   if (!sim || !plan || !workspace) return fail(MLBM_E_ARG, "NULL argument");
   SimState& s = sim->s;
   if (!plan_matches(s, *plan)) return fail(MLBM_E_ARG, "plan does not belong to this simulation");
+  if (has_wall_links(s))
+    return fail(MLBM_E_STATE, "the adjoint does not cover links with a wall fraction");
   if (((uintptr_t)workspace) & 255) return fail(MLBM_E_ARG, "workspace must be 256-byte aligned");
   OpBuilder os, oi;
   step_ops(s, 0, 0, os);

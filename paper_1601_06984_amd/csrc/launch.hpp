@@ -33,6 +33,11 @@ inline LevelArgs<C, Q> level_args(const SimState& s, int k) {
   for (int i = 0; i < 4; ++i) a.wr[i] = C(0);
   for (int i = 0; i < Q; ++i) a.wr[stencil_wclass(s.stencil, i)] = (C)s.wr[i];
   a.geq = (const C*)s.geq_dev;
+  a.wall = (const int4*)L.wall;
+  a.wall_q = L.wall_q;
+  a.wall_blk = L.wall_blk;
+  a.wall_row = L.wall_row;
+  a.n_wall = (int32_t)L.n_wall;
   for (int b = 0; b < 3; ++b) a.u_in[b] = s.u_in[b];
   return a;
 }
@@ -52,9 +57,14 @@ struct Impl {
     auto a = level_args<C, Lat::Q>(s, k);
     // one launch; the block map balances the plain range and the tail
     // (capture sources, inner ghosts) over the XCDs
-    launch_timed(k_stream_collide<Lat, P, BS>, dim3((unsigned)((n_act + BS - 1) / BS)),
-                 dim3(BS), s.stream, s.launch_ev[0], s.launch_ev[1], (const S*)src, (S*)dst,
-                 n_act, a, (C*)cap, s.status);
+    if (L.n_wall)
+      launch_timed(k_stream_collide<Lat, P, BS, true>, dim3((unsigned)((n_act + BS - 1) / BS)),
+                   dim3(BS), s.stream, s.launch_ev[0], s.launch_ev[1], (const S*)src, (S*)dst,
+                   n_act, a, (C*)cap, s.status);
+    else
+      launch_timed(k_stream_collide<Lat, P, BS, false>, dim3((unsigned)((n_act + BS - 1) / BS)),
+                   dim3(BS), s.stream, s.launch_ev[0], s.launch_ev[1], (const S*)src, (S*)dst,
+                   n_act, a, (C*)cap, s.status);
   }
 
   // stream-collides of distinct levels (jobs) in one launch
@@ -65,6 +75,7 @@ struct Impl {
     }
     ScMulti<C, S, Lat::Q> m{};
     int64_t total = 0;
+    bool walls = false;
     m.nseg = 0;
     for (int j = 0; j < n; ++j) {
       if (jobs[j].n_act <= 0) continue;
@@ -77,11 +88,16 @@ struct Impl {
       m.dst[sg] = (S*)jobs[j].dst;
       m.cap[sg] = (C*)jobs[j].cap;
       m.a[sg] = level_args<C, Lat::Q>(s, jobs[j].k);
+      walls |= s.lv[jobs[j].k].n_wall > 0;
       total += (nb + 7) / 8 * 8;
     }
     if (!m.nseg) return;
-    hipLaunchKernelGGL((k_stream_collide_multi<Lat, P, BS>), dim3((unsigned)total), dim3(BS), 0,
-                       s.stream, m, s.status);
+    if (walls)
+      hipLaunchKernelGGL((k_stream_collide_multi<Lat, P, BS, true>), dim3((unsigned)total),
+                         dim3(BS), 0, s.stream, m, s.status);
+    else
+      hipLaunchKernelGGL((k_stream_collide_multi<Lat, P, BS, false>), dim3((unsigned)total),
+                         dim3(BS), 0, s.stream, m, s.status);
   }
 
   static void fill_gff_ptr(SimState& s, int k, void* pdf, const void* cap_fine, void* cap_coarse) {

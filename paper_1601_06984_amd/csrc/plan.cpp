@@ -1130,6 +1130,93 @@ int32_t mlbm_plan_create(int32_t stencil, int32_t level0, const int32_t* box_ori
 
 void mlbm_plan_destroy(mlbm_plan* plan) { delete plan; }
 
+int32_t mlbm_plan_set_walls(mlbm_plan* plan, const uint64_t* ids, const int32_t* dirs,
+                            const double* q, int64_t n) {
+  if (!plan) return fail(MLBM_E_ARG, "plan is NULL");
+  if (n < 0 || (n > 0 && (!ids || !dirs || !q))) return fail(MLBM_E_ARG, "bad wall arrays");
+  const int Q = plan->q, d = plan->d, nl = plan->nlev();
+  struct Link { int64_t x; int32_t j, x2; double q; };
+  try {
+    // fluid elements of each level by treeID (the fluid segment keeps the
+    // interpolation sources at its end, so it is not sorted as a whole)
+    std::vector<std::vector<std::pair<uint64_t, int64_t>>> by_id(nl);
+    for (int k = 0; k < nl; ++k) {
+      const LevelPlan& lp = plan->lv[k];
+      by_id[k].resize((size_t)lp.n_fluid);
+      for (int64_t x = 0; x < lp.n_fluid; ++x) by_id[k][x] = {lp.tid[x], x};
+      std::sort(by_id[k].begin(), by_id[k].end());
+    }
+    std::vector<std::vector<Link>> per(nl);
+    for (int64_t t = 0; t < n; ++t) {
+      const int i = dirs[t];
+      if (i < 1 || i >= Q) return fail(MLBM_E_ARG, "wall link %lld: direction %d", (long long)t, i);
+      if (!(q[t] >= 0.0 && q[t] <= 1.0))
+        return fail(MLBM_E_ARG, "wall link %lld: fraction %g outside [0, 1]", (long long)t, q[t]);
+      int k = -1;
+      for (int kk = 0; kk < nl; ++kk) {
+        const int L = plan->lv[kk].level;
+        if (ids[t] >= level_first_id(L, d) && ids[t] < level_first_id(L + 1, d)) k = kk;
+      }
+      const LevelPlan* lp = k >= 0 ? &plan->lv[k] : nullptr;
+      int64_t x = -1;
+      if (lp) {
+        const auto& v = by_id[k];
+        auto it = std::lower_bound(v.begin(), v.end(), std::make_pair(ids[t], (int64_t)-1));
+        if (it != v.end() && it->first == ids[t]) x = it->second;
+      }
+      if (x < 0)
+        return fail(MLBM_E_MESH, "wall link %lld: %llu is not a fluid leaf", (long long)t,
+                    (unsigned long long)ids[t]);
+      const int j = stencil_opp(plan->stencil, i);
+      if (lp->nbr[(size_t)(j - 1) * lp->n + x] != MLBM_NBR_BOUNCE)
+        return fail(MLBM_E_MESH, "wall link %lld: the neighbour of %llu along %d is not solid",
+                    (long long)t, (unsigned long long)ids[t], i);
+      const int32_t s2 = lp->nbr[(size_t)(i - 1) * lp->n + x];
+      per[k].push_back({x, j, s2 >= 0 ? s2 : -1, q[t]});
+    }
+    std::vector<LevelPlan> next(nl);
+    for (int k = 0; k < nl; ++k) {
+      auto& v = per[k];
+      std::sort(v.begin(), v.end(), [](const Link& a, const Link& b) {
+        return a.x != b.x ? a.x < b.x : a.j < b.j;
+      });
+      for (size_t e = 1; e < v.size(); ++e)
+        if (v[e].x == v[e - 1].x && v[e].j == v[e - 1].j)
+          return fail(MLBM_E_ARG, "a wall link is given twice");
+      LevelPlan& o = next[k];
+      for (const Link& l : v) {
+        o.wall.insert(o.wall.end(),
+                      {(int32_t)l.x, l.j, l.x2, stencil_wclass(plan->stencil, l.j)});
+        o.wall_q.push_back(l.q);
+      }
+      if (!v.empty()) {
+        const int64_t nb = plan->lv[k].n_nbr_blocks();
+        o.wall_blk.assign((size_t)nb, -1);
+        size_t e = 0;
+        int32_t rows = 0;
+        for (int64_t b = 0; b < nb && e < v.size(); ++b) {
+          if (v[e].x >= (b + 1) * NBR_BLOCK) continue;
+          o.wall_blk[b] = rows++;
+          for (int64_t x = b * NBR_BLOCK; x <= (b + 1) * NBR_BLOCK; ++x) {
+            while (e < v.size() && v[e].x < x) ++e;
+            o.wall_row.push_back((int32_t)e);
+          }
+          while (e < v.size() && v[e].x < (b + 1) * NBR_BLOCK) ++e;
+        }
+      }
+    }
+    for (int k = 0; k < nl; ++k) {
+      plan->lv[k].wall.swap(next[k].wall);
+      plan->lv[k].wall_q.swap(next[k].wall_q);
+      plan->lv[k].wall_blk.swap(next[k].wall_blk);
+      plan->lv[k].wall_row.swap(next[k].wall_row);
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(MLBM_E_OOM, "host allocation failed while setting walls");
+  }
+  return MLBM_OK;
+}
+
 int32_t mlbm_plan_levels(const mlbm_plan* plan, int32_t* n_levels, int32_t* level0) {
   if (!plan) return fail(MLBM_E_ARG, "plan is NULL");
   if (n_levels) *n_levels = plan->nlev();
@@ -1151,6 +1238,7 @@ int32_t mlbm_plan_level_info(const mlbm_plan* plan, int32_t k, int64_t* out) {
   out[MLBM_INFO_N_CAP] = lp.n_cap();
   out[MLBM_INFO_N_GFC_GROUPS] = lp.n_groups;
   out[MLBM_INFO_N_BOUNCE] = lp.n_bounce();
+  out[MLBM_INFO_N_WALL] = lp.n_wall();
   return MLBM_OK;
 }
 
@@ -1173,6 +1261,10 @@ int32_t mlbm_plan_export(const mlbm_plan* plan, int32_t k, int32_t table, void* 
     case MLBM_TABLE_NBASE: src = lp.nbase.data(); n = lp.nbase.size() * 4; break;
     case MLBM_TABLE_NBR_HDR: src = lp.nhdr.data(); n = lp.nhdr.size() * 4; break;
     case MLBM_TABLE_NBR_WIDE: src = lp.nbr_wide.data(); n = lp.nbr_wide.size() * 2; break;
+    case MLBM_TABLE_WALL: src = lp.wall.data(); n = lp.wall.size() * 4; break;
+    case MLBM_TABLE_WALL_Q: src = lp.wall_q.data(); n = lp.wall_q.size() * 8; break;
+    case MLBM_TABLE_WALL_BLK: src = lp.wall_blk.data(); n = lp.wall_blk.size() * 4; break;
+    case MLBM_TABLE_WALL_ROW: src = lp.wall_row.data(); n = lp.wall_row.size() * 4; break;
     default: return fail(MLBM_E_ARG, "unknown table %d", table);
   }
   if (!host_dst) {

@@ -28,6 +28,15 @@ struct LevelPlan {
   std::vector<int32_t> grp_tab;
   std::vector<int32_t> grp_child;  // [children][n_groups] element idx on L
   std::vector<int32_t> bounce;     // [2][n_bounce] (element, direction)
+  // links with a wall fraction (linear interpolated bounce-back), sorted by
+  // element then pull direction: [n_wall][4] {x, j, x2, weight class of j},
+  // their fractions, per pull-table block its row of wall_row or -1
+  // [blocks], and per row the first link of each of the block's elements
+  // and the block's end [rows][NBR_BLOCK + 1]
+  std::vector<int32_t> wall;
+  std::vector<double> wall_q;
+  std::vector<int32_t> wall_blk;
+  std::vector<int32_t> wall_row;
 
   // The pull table as the device holds it, over the updated range in blocks
   // of NBR_BLOCK elements: per (block, direction) up to NBR_BASES base
@@ -60,6 +69,7 @@ struct LevelPlan {
   int64_t n_cap_fluid() const { return (int64_t)cap_elem.size(); }
   int64_t n_cap() const { return n_cap_fluid() + n_gff; }
   int64_t n_bounce() const { return (int64_t)bounce.size() / 2; }
+  int64_t n_wall() const { return (int64_t)wall_q.size(); }
 };
 
 }  // namespace mlbm

@@ -16,7 +16,7 @@ namespace mlbm {
 struct DevLevel {
   int level = 0;
   int64_t n = 0, n_fluid = 0, n_inner = 0, n_outer = 0, n_gff = 0, n_act_max = 0;
-  int64_t n_cap_fluid = 0, n_cap = 0, n_groups = 0, n_bounce = 0;
+  int64_t n_cap_fluid = 0, n_cap = 0, n_groups = 0, n_bounce = 0, n_wall = 0;
   void* pdf[2] = {nullptr, nullptr};  // storage arrays [q][n]
   uint16_t* nbr16 = nullptr;          // pull table, device form: [q-1][ld16]
   int32_t* nbase = nullptr;           // [blocks][q-1][NBR_BASES]
@@ -31,6 +31,10 @@ struct DevLevel {
   int32_t* grp_tab = nullptr;         // [slots][n_groups][4] fill staging rows
   int32_t* grp_child = nullptr;       // [children][n_groups] element indices
   int32_t* bounce = nullptr;          // [2][n_bounce]
+  int32_t* wall = nullptr;            // [n_wall][4] links with a wall fraction
+  double* wall_q = nullptr;           // [n_wall]
+  int32_t* wall_blk = nullptr;        // [blocks] row or -1 (null: no such links)
+  int32_t* wall_row = nullptr;        // [rows][NBR_BLOCK + 1]
   int parity = 0;                     // index of the current pdf array
   int substep = 0;                    // 0: next step is the first after a sync
   double omega = 1.0;

@@ -34,12 +34,12 @@ def fields_for(positions_by_level, level0, field_fn):
     return rho, u, S
 
 
-def oracle_run(spec, tau0, field_fn, steps, u_in=None, poison=True, om=None):
+def oracle_run(spec, tau0, field_fn, steps, u_in=None, poison=True, om=None, walls=None):
     om = om or omesh.build(spec)
     pos = {L: om.positions(L)[:om.lev(L).n_fluid] for L in range(om.level0, om.lmax + 1)}
     rho, u, S = fields_for(pos, om.level0, field_fn)
     sim = osolver.OracleSim(om, tau0, u_in=None if u_in is None else torch.tensor(u_in),
-                            poison=poison)
+                            poison=poison, walls=walls)
     sim.init(rho, u, S)
     sim.step(steps)
     return sim

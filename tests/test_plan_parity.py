@@ -267,3 +267,97 @@ def test_oracle_rejects_the_same_meshes():
     tight = W.refined_box_mesh("D2Q9", 4, 4, 12, extra_levels=[(8, 16)])
     with pytest.raises(omesh.MeshError):
         omesh.build(tight)
+
+
+# ------------------------------------------------ wall fractions ----------
+def _sphere_small(stencil="D3Q19"):
+    return W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0), half_width=2.0,
+                                 boxes_in_d=((-1.0, 1.5, 1.0),), stencil=stencil)
+
+
+@pytest.mark.parametrize("stencil", ["D3Q19", "D3Q27"])
+def test_wall_tables_match_oracle(stencil):
+    """Links with a wall fraction: element, pull direction, second node and
+    fraction equal the oracle's links (same treeIDs, bit-exact), sorted by
+    element then direction, with per-block first-link offsets."""
+    from oracle.solver import wall_links
+    spec = _sphere_small(stencil)
+    om = omesh.build(spec)
+    c_lib, _ = M.lattice(stencil)
+    perm = [int(np.where((om.lattice.c == c_lib[i]).all(1))[0][0]) for i in range(len(c_lib))]
+    ids, dirs, q = W.sphere_wall_links(spec, c_lib)
+    plan = M.Plan.from_spec(spec)
+    plan.set_walls(ids, dirs, q)
+    ow = wall_links(om, *W.sphere_wall_links(spec, om.lattice.c))
+    for k in range(plan.n_levels):
+        L = plan.level0 + k
+        n_w = plan.info[k]["n_wall"]
+        if L not in ow:
+            assert n_w == 0
+            continue
+        wt = plan.export(k, "wall")
+        wq = plan.export(k, "wall_q")
+        blk = plan.export(k, "wall_blk")
+        assert len(wt) == n_w == len(ow[L][0])
+        gt = plan.export(k, "treeid")
+        ot = om.lev(L).tid
+        # library links as (treeID, oracle direction into the solid, q, treeID of x2)
+        opp = lambda i: (i + 1) if i & 1 else (i - 1)
+        mine = sorted((int(gt[x]), perm[opp(int(j))], float(qq), int(gt[x2]) if x2 >= 0 else -1)
+                      for (x, j, x2, _), qq in zip(wt, wq))
+        x, i, qo, x2 = ow[L]
+        theirs = sorted((int(ot[a]), int(b), float(c), int(ot[e]) if e >= 0 else -1)
+                        for a, b, c, e in zip(x, i, qo, x2))
+        assert mine == theirs
+        key = wt[:, 0].astype(np.int64) * 64 + wt[:, 1]
+        assert (np.diff(key) > 0).all()
+        rows = plan.export(k, "wall_row")
+        assert len(rows) == (blk >= 0).sum()
+        seen = 0
+        for b in range(len(blk)):
+            has = (wt[:, 0] // 256 == b)
+            if blk[b] < 0:
+                assert not has.any()
+                continue
+            r = rows[blk[b]]
+            for e in range(256):   # element b*256+e owns links [r[e], r[e+1])
+                mine_e = np.where(wt[:, 0] == b * 256 + e)[0]
+                assert r[e + 1] - r[e] == len(mine_e)
+                if len(mine_e):
+                    assert r[e] == mine_e[0]
+            seen += int(r[256] - r[0])
+        assert seen == n_w
+
+
+def test_set_walls_rejects_bad_links():
+    spec = _sphere_small()
+    c_lib, _ = M.lattice("D3Q19")
+    ids, dirs, q = W.sphere_wall_links(spec, c_lib)
+    plan = M.Plan.from_spec(spec)
+    plan.set_walls(ids, dirs, q)
+    n0 = sum(i["n_wall"] for i in plan.info)
+    assert n0 == len(ids)
+
+    def code(ids_, dirs_, q_):
+        with pytest.raises(M.MLBMError) as e:
+            plan.set_walls(ids_, dirs_, q_)
+        return e.value.code
+    bad_q = q.copy()
+    bad_q[3] = 1.5
+    assert code(ids, dirs, bad_q) == _lib.E_ARG
+    bad_q[3] = np.nan
+    assert code(ids, dirs, bad_q) == _lib.E_ARG
+    bad_d = dirs.copy()
+    bad_d[0] = len(c_lib)
+    assert code(ids, bad_d, q) == _lib.E_ARG
+    assert code(np.concatenate([ids, ids[:1]]), np.concatenate([dirs, dirs[:1]]),
+                np.concatenate([q, q[:1]])) == _lib.E_ARG
+    # a direction whose neighbour is fluid
+    opp = (dirs[0] + 1) if dirs[0] & 1 else (dirs[0] - 1)
+    assert code(ids[:1], np.array([opp], np.int32), q[:1]) == _lib.E_MESH
+    # a solid cell is no fluid leaf
+    assert code(spec.solid_ids[:1], dirs[:1], q[:1]) == _lib.E_MESH
+    # failures leave the previous set in place; n = 0 clears it
+    assert sum(i["n_wall"] for i in plan.info) == n0
+    plan.set_walls([], [], [])
+    assert sum(i["n_wall"] for i in plan.info) == 0

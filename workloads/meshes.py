@@ -286,7 +286,7 @@ def plane_wall_links(spec: MeshSpec, c: np.ndarray, q_low: float, q_high: float)
     for row, sgn, qv in ((1, -1, q_low), (h - 2, 1, q_high)):
         cells = np.concatenate([grid, np.full((len(grid), 1), row)], 1)
         tid = encode_tree_ids(L, cells)
-        for i in range(1, len(lat)):
+        for i in range(len(lat)):
             if lat[i, d - 1] == sgn:
                 ids.append(tid)
                 dirs.append(np.full(len(tid), i, np.int32))
@@ -314,8 +314,10 @@ def sphere_wall_links(spec: MeshSpec, c: np.ndarray):
     cells, a, tid = cells[leaf], a[leaf], tid[leaf]
     lat = np.asarray(c, dtype=np.float64)
     ids, dirs, qs = [], [], []
-    for i in range(1, len(lat)):
+    for i in range(len(lat)):
         ci = lat[i]
+        if not ci.any():
+            continue
         b = a + ci
         hit = (b * b).sum(1) < r * r
         if not hit.any():
