@@ -107,13 +107,7 @@ enum {
    * x - c_j is solid), second node x2 = the element at x + c_j (the pull
    * source of opp(j); -1 if that is not an element), weight class}. */
   MLBM_TABLE_WALL = 11,    /* int32 [n_wall][4]                             */
-  MLBM_TABLE_WALL_Q = 12,  /* double [n_wall]: wall fraction q of each link */
-  MLBM_TABLE_WALL_BLK = 13,/* int32 [n_blocks]: per block of 256 updated
-                              elements its row of WALL_ROW, or -1 if none of
-                              its elements has such a link (empty if
-                              n_wall = 0)                                    */
-  MLBM_TABLE_WALL_ROW = 14 /* int32 [n_rows][257]: first link of each
-                              element of the block, then the block's end    */
+  MLBM_TABLE_WALL_Q = 12   /* double [n_wall]: wall fraction q of each link */
 };
 
 /* Fields of mlbm_plan_level_info, in this order (int64 each). */

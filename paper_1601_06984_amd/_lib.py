@@ -21,7 +21,7 @@ DIAG_MASS, DIAG_KE, DIAG_FORCE = 1, 2, 4
 STATUS_NONFINITE, STATUS_F16_OVERFLOW = 1, 2
 TABLE_TREEID, TABLE_COORDS, TABLE_NBR, TABLE_GFC_SRC, TABLE_GFF_SRC, \
     TABLE_CAPTURE, TABLE_BOUNCE, TABLE_NBR16, TABLE_NBASE, TABLE_NBR_WIDE, \
-    TABLE_NBR_HDR, TABLE_WALL, TABLE_WALL_Q, TABLE_WALL_BLK, TABLE_WALL_ROW = range(15)
+    TABLE_NBR_HDR, TABLE_WALL, TABLE_WALL_Q = range(13)
 STATE_PDF_POST, STATE_MOMENTS = 0, 1
 INFO_FIELDS = ("level", "n", "n_fluid", "n_gfc_inner", "n_gfc_outer", "n_gff",
                "n_cap_fluid", "n_cap", "n_gfc_groups", "n_bounce", "n_wall")

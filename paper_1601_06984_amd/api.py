@@ -100,8 +100,7 @@ class Plan:
                "bounce": _lib.TABLE_BOUNCE, "nbr16": _lib.TABLE_NBR16,
                "nbase": _lib.TABLE_NBASE, "nbr_wide": _lib.TABLE_NBR_WIDE,
                "nbr_hdr": _lib.TABLE_NBR_HDR, "wall": _lib.TABLE_WALL,
-               "wall_q": _lib.TABLE_WALL_Q, "wall_blk": _lib.TABLE_WALL_BLK,
-               "wall_row": _lib.TABLE_WALL_ROW}[table]
+               "wall_q": _lib.TABLE_WALL_Q}[table]
         nbytes = C.c_size_t()
         check(lib().mlbm_plan_export(self._h, k, tid, None, C.byref(nbytes)))
         dtype = {"treeid": np.uint64, "nbr16": np.uint16, "nbr_wide": np.uint16,
@@ -116,8 +115,6 @@ class Plan:
             out = out.reshape(rows[table], -1)
         if table == "wall":
             out = out.reshape(-1, 4)
-        if table == "wall_row":
-            out = out.reshape(-1, 257)
         return out
 
     def __del__(self):

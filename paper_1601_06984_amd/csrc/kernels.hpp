@@ -144,12 +144,9 @@ struct LevelArgs {
   const C* geq;       // device [Q]: f^eq_i(rho0, u_in) - w_i rho0 for EQ faces
   double u_in[3];     // EQ-face velocity
   // links with a wall fraction, sorted by element: {x, j, x2, weight class},
-  // fractions, per pull-table block its row of wall_row or -1 (null: none on
-  // the level), per row the first link of each element and the block's end
+  // and their fractions (null: none on the level)
   const int4* wall;
   const double* wall_q;
-  const int32_t* wall_blk;
-  const int32_t* wall_row;
   int32_t n_wall;
 };
 
@@ -425,14 +422,25 @@ __device__ __forceinline__ void gather_from(const typename Prec<P>::S* __restric
 
 // Links that carry a wall fraction q (linear interpolated bounce-back,
 // Sec. 2.3): the value pulled in direction j, whose source x - c_j is solid,
-// becomes, with o = opp(j) the direction into the wall,
+// is, with o = opp(j) the direction into the wall,
 //   q <  1/2: 2q g*_o(x) + (1 - 2q) g*_o(x2)   (x2 = x + c_j; none: g*_o(x))
 //   q >= 1/2: g*_o(x) / (2q) + (1 - 1/(2q)) g*_j(x)
 // The weights of each rule sum to one and w_o = w_j, so the rule holds for
-// the deviations g = f - w rho0 as for f.  A work-group whose block has no
-// such link leaves after one uniform load; in the others each element reads
-// its range of links from the block's row (no search, so the chain of
-// dependent loads is row -> link -> pdfs).
+// the deviations g = f - w rho0 as for f.
+//
+// Before a stream-collide of a level with such links this kernel writes
+// each link's value into the entry that the halfway bounce-back pull of the
+// link reads, g*_o(x): no other pull reads that entry (its pull would come
+// from x + c_o = x - c_j, which is solid), and the stream-collide then
+// gathers the interpolated value with no code of its own for the links.
+// The entry belongs to the state the stream-collide consumes and replaces.
+// One thread per link; every value is formed before any is written.  The
+// entries read are x's own and g*_o(x2); none written for another element
+// (x2 is fluid, and g*_o(x2) would be written only by a link of x2 in
+// direction j, whose solid source would be x).  Within an element, g*_j(x)
+// is read where the opposite link writes (an element between two walls);
+// an element's links lie in one chunk of 256 (the list is padded with
+// links x = -1), so the work-group barrier orders them.
 template <class Lat, class C>
 __device__ __forceinline__ C wall_weight(const LevelArgs<C, Lat::Q>& a, int cls) {
   C w = a.wr[0];
@@ -443,37 +451,34 @@ __device__ __forceinline__ C wall_weight(const LevelArgs<C, Lat::Q>& a, int cls)
 }
 
 template <class Lat, int P>
-__device__ __forceinline__ void curved_walls(const typename Prec<P>::S* __restrict__ src,
-                                             int64_t blk, int64_t x,
-                                             const LevelArgs<typename Prec<P>::C, Lat::Q>& a,
-                                             typename Prec<P>::C* g) {
+__global__ __launch_bounds__(256) void k_wall_prepass(
+    typename Prec<P>::S* __restrict__ src, const LevelArgs<typename Prec<P>::C, Lat::Q> a) {
   using C = typename Prec<P>::C;
-  const int32_t r = a.wall_blk[blk];
-  if (r < 0) return;
-  const int32_t* row = a.wall_row + (int64_t)r * (NBR_BLOCK + 1) + (x - blk * NBR_BLOCK);
-  const int32_t t1 = row[1];
-  for (int32_t t = row[0]; t < t1; ++t) {
-    const int4 w = a.wall[t];
-    const int jd = w.y;
-    const int o = (jd & 1) ? jd + 1 : jd - 1;   // rows 2k-1, 2k are opposite
-    const C wr = wall_weight<Lat, C>(a, w.w);
-    const C go = load_row<P>(src + (int64_t)o * a.n, a.n, (uint32_t)x, wr, a.inv_scale);
+  const int32_t t = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  int4 w = {-1, 0, -1, 0};
+  if (t < a.n_wall) w = a.wall[t];
+  const int jd = w.y;
+  const int o = (jd & 1) ? jd + 1 : jd - 1;   // rows 2k-1, 2k are opposite
+  const C wr = wall_weight<Lat, C>(a, w.w);
+  C v = C(0);
+  if (w.x >= 0) {
+    const C go = load_row<P>(src + (int64_t)o * a.n, a.n, (uint32_t)w.x, wr, a.inv_scale);
     const C q = (C)a.wall_q[t];
-    C v = go;
+    v = go;
     if (q < C(0.5)) {
       if (w.z >= 0)
         v = C(2) * q * go +
             (C(1) - C(2) * q) * load_row<P>(src + (int64_t)o * a.n, a.n, (uint32_t)w.z, wr,
                                             a.inv_scale);
     } else {
-      const C gj = load_row<P>(src + (int64_t)jd * a.n, a.n, (uint32_t)x, wr, a.inv_scale);
+      const C gj = load_row<P>(src + (int64_t)jd * a.n, a.n, (uint32_t)w.x, wr, a.inv_scale);
       const C r = C(1) / (C(2) * q);
       v = r * go + (C(1) - r) * gj;
     }
-#pragma unroll
-    for (int i = 1; i < Lat::Q; ++i)
-      if (i == jd) g[i] = v;
   }
+  __syncthreads();
+  // a convex combination of stored values: F16S cannot overflow
+  if (w.x >= 0) (void)store_row<P>(src + (int64_t)o * a.n, a.n, (uint32_t)w.x, v, wr, a.scale);
 }
 
 template <class Lat, int P>
@@ -629,10 +634,8 @@ inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStr
 // The stream-collide of work-group `blk` (blk*BS < x1) of a level whose
 // updated range is [0, x1): elements blk*BS .. blk*BS+BS-1.  `stage` is the
 // work-group's record staging area, `slots` its pull-table slot area; every
-// thread of the work-group calls it.  WALLS: the level has links with a wall
-// fraction (a separate instance, so levels without them run code that has
-// none of it).
-template <class Lat, int P, int BS, bool WALLS>
+// thread of the work-group calls it.
+template <class Lat, int P, int BS>
 __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
                                         const typename Prec<P>::S* __restrict__ src,
                                         typename Prec<P>::S* __restrict__ dst,
@@ -655,10 +658,6 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
     pull_sources_wg<Lat>(a, blk, (uint32_t)x, j, slots);
     gather_from<Lat, P>(src, x, a, j, g);
   }
-  // a grouped launch with walls on one level also runs the others' segments,
-  // whose tables are null
-  if constexpr (WALLS)
-    if (a.wall_blk) curved_walls<Lat, P>(src, blk, x, a, g);
   C drho, rho, u[3];
   macro_g<Lat, C>(g, a.rho0, drho, rho, u);
   const C uu = dot_uu<Lat, C>(u);
@@ -691,7 +690,7 @@ constexpr int sc_stage_values(int bs) {
 
 // One level's stream-collide over [0, x1); the block map balances the plain
 // range and the tail (capture sources, inner ghosts) over the XCDs.
-template <class Lat, int P, int BS, bool WALLS>
+template <class Lat, int P, int BS>
 __global__ __launch_bounds__(BS) void k_stream_collide(
     const typename Prec<P>::S* __restrict__ src, typename Prec<P>::S* __restrict__ dst,
     int64_t x1, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
@@ -700,7 +699,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
   __shared__ C stage[sc_stage_values<C, Lat::Q>(BS)];
   __shared__ int32_t slots[NBR_SLOTS];
   const int64_t blk = xcd_block2(blockIdx.x, gridDim.x, a.cap_begin / BS);
-  sc_body<Lat, P, BS, WALLS>(blk, x1, src, dst, a, cap, status, stage, slots);
+  sc_body<Lat, P, BS>(blk, x1, src, dst, a, cap, status, stage, slots);
 }
 
 // Stream-collides of several levels in one launch.  Consecutive
@@ -722,7 +721,7 @@ struct ScMulti {
   LevelArgs<C, Q> a[SC_MAX_SEG];
 };
 
-template <class Lat, int P, int BS, bool WALLS>
+template <class Lat, int P, int BS>
 __global__ __launch_bounds__(BS) void k_stream_collide_multi(
     const ScMulti<typename Prec<P>::C, typename Prec<P>::S, Lat::Q> m,
     uint32_t* __restrict__ status) {
@@ -735,8 +734,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide_multi(
   if (b >= m.nb[sg]) return;
   const LevelArgs<C, Lat::Q>& a = m.a[sg];
   const int64_t blk = xcd_block2(b, m.nb[sg], a.cap_begin / BS);
-  sc_body<Lat, P, BS, WALLS>(blk, m.n_act[sg], m.src[sg], m.dst[sg], a, m.cap[sg], status,
-                             stage, slots);
+  sc_body<Lat, P, BS>(blk, m.n_act[sg], m.src[sg], m.dst[sg], a, m.cap[sg], status, stage,
+                      slots);
 }
 
 // --------------------------------------------------- interpolation --------
@@ -1313,6 +1312,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(
   for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < a.n_wall;
        t += (int64_t)gridDim.x * 256) {
     const int4 w = a.wall[t];
+    if (w.x < 0) continue;   // padding
     const int j = w.y;
     const int i = (j & 1) ? j + 1 : j - 1;
     const double wr = (double)wall_weight<Lat, typename Prec<P>::C>(a, w.w);

@@ -35,8 +35,6 @@ inline LevelArgs<C, Q> level_args(const SimState& s, int k) {
   a.geq = (const C*)s.geq_dev;
   a.wall = (const int4*)L.wall;
   a.wall_q = L.wall_q;
-  a.wall_blk = L.wall_blk;
-  a.wall_row = L.wall_row;
   a.n_wall = (int32_t)L.n_wall;
   for (int b = 0; b < 3; ++b) a.u_in[b] = s.u_in[b];
   return a;
@@ -49,6 +47,16 @@ struct Impl {
   using C = typename Prec<P>::C;
   static constexpr int BS = 256;
 
+  // Links with a wall fraction of level k: their values go into the state
+  // `src` that the level's next stream-collide consumes (k_wall_prepass).
+  static void wall_prepass(SimState& s, int k, const void* src) {
+    DevLevel& L = s.lv[k];
+    if (!L.n_wall) return;
+    auto a = level_args<C, Lat::Q>(s, k);
+    hipLaunchKernelGGL((k_wall_prepass<Lat, P>), dim3((unsigned)((L.n_wall + 255) / 256)),
+                       dim3(256), 0, s.stream, (S*)const_cast<void*>(src), a);
+  }
+
   // Explicit-array forms (also used by the adjoint's tape).
   static void stream_collide_ptr(SimState& s, int k, int64_t n_act, const void* src, void* dst,
                                  void* cap) {
@@ -57,14 +65,10 @@ struct Impl {
     auto a = level_args<C, Lat::Q>(s, k);
     // one launch; the block map balances the plain range and the tail
     // (capture sources, inner ghosts) over the XCDs
-    if (L.n_wall)
-      launch_timed(k_stream_collide<Lat, P, BS, true>, dim3((unsigned)((n_act + BS - 1) / BS)),
-                   dim3(BS), s.stream, s.launch_ev[0], s.launch_ev[1], (const S*)src, (S*)dst,
-                   n_act, a, (C*)cap, s.status);
-    else
-      launch_timed(k_stream_collide<Lat, P, BS, false>, dim3((unsigned)((n_act + BS - 1) / BS)),
-                   dim3(BS), s.stream, s.launch_ev[0], s.launch_ev[1], (const S*)src, (S*)dst,
-                   n_act, a, (C*)cap, s.status);
+    wall_prepass(s, k, src);
+    launch_timed(k_stream_collide<Lat, P, BS>, dim3((unsigned)((n_act + BS - 1) / BS)),
+                 dim3(BS), s.stream, s.launch_ev[0], s.launch_ev[1], (const S*)src, (S*)dst,
+                 n_act, a, (C*)cap, s.status);
   }
 
   // stream-collides of distinct levels (jobs) in one launch
@@ -75,7 +79,6 @@ struct Impl {
     }
     ScMulti<C, S, Lat::Q> m{};
     int64_t total = 0;
-    bool walls = false;
     m.nseg = 0;
     for (int j = 0; j < n; ++j) {
       if (jobs[j].n_act <= 0) continue;
@@ -88,16 +91,12 @@ struct Impl {
       m.dst[sg] = (S*)jobs[j].dst;
       m.cap[sg] = (C*)jobs[j].cap;
       m.a[sg] = level_args<C, Lat::Q>(s, jobs[j].k);
-      walls |= s.lv[jobs[j].k].n_wall > 0;
+      wall_prepass(s, jobs[j].k, jobs[j].src);
       total += (nb + 7) / 8 * 8;
     }
     if (!m.nseg) return;
-    if (walls)
-      hipLaunchKernelGGL((k_stream_collide_multi<Lat, P, BS, true>), dim3((unsigned)total),
-                         dim3(BS), 0, s.stream, m, s.status);
-    else
-      hipLaunchKernelGGL((k_stream_collide_multi<Lat, P, BS, false>), dim3((unsigned)total),
-                         dim3(BS), 0, s.stream, m, s.status);
+    hipLaunchKernelGGL((k_stream_collide_multi<Lat, P, BS>), dim3((unsigned)total), dim3(BS), 0,
+                       s.stream, m, s.status);
   }
 
   static void fill_gff_ptr(SimState& s, int k, void* pdf, const void* cap_fine, void* cap_coarse) {

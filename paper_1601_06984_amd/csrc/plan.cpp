@@ -1189,27 +1189,28 @@ int32_t mlbm_plan_set_walls(mlbm_plan* plan, const uint64_t* ids, const int32_t*
                       {(int32_t)l.x, l.j, l.x2, stencil_wclass(plan->stencil, l.j)});
         o.wall_q.push_back(l.q);
       }
-      if (!v.empty()) {
-        const int64_t nb = plan->lv[k].n_nbr_blocks();
-        o.wall_blk.assign((size_t)nb, -1);
-        size_t e = 0;
-        int32_t rows = 0;
-        for (int64_t b = 0; b < nb && e < v.size(); ++b) {
-          if (v[e].x >= (b + 1) * NBR_BLOCK) continue;
-          o.wall_blk[b] = rows++;
-          for (int64_t x = b * NBR_BLOCK; x <= (b + 1) * NBR_BLOCK; ++x) {
-            while (e < v.size() && v[e].x < x) ++e;
-            o.wall_row.push_back((int32_t)e);
+      // device copy: an element's links (at most q - 1 < NBR_BLOCK) stay in
+      // one chunk of NBR_BLOCK, the work-group that forms and writes them
+      for (size_t e = 0; e < v.size();) {
+        size_t f = e;
+        while (f < v.size() && v[f].x == v[e].x) ++f;
+        const size_t used = o.wall_dev_q.size() % NBR_BLOCK;
+        if (used + (f - e) > (size_t)NBR_BLOCK)
+          for (size_t p = used; p < (size_t)NBR_BLOCK; ++p) {
+            o.wall_dev.insert(o.wall_dev.end(), {-1, 0, -1, 0});
+            o.wall_dev_q.push_back(0.5);
           }
-          while (e < v.size() && v[e].x < (b + 1) * NBR_BLOCK) ++e;
+        for (; e < f; ++e) {
+          o.wall_dev.insert(o.wall_dev.end(), o.wall.begin() + 4 * e, o.wall.begin() + 4 * e + 4);
+          o.wall_dev_q.push_back(v[e].q);
         }
       }
     }
     for (int k = 0; k < nl; ++k) {
       plan->lv[k].wall.swap(next[k].wall);
       plan->lv[k].wall_q.swap(next[k].wall_q);
-      plan->lv[k].wall_blk.swap(next[k].wall_blk);
-      plan->lv[k].wall_row.swap(next[k].wall_row);
+      plan->lv[k].wall_dev.swap(next[k].wall_dev);
+      plan->lv[k].wall_dev_q.swap(next[k].wall_dev_q);
     }
   } catch (const std::bad_alloc&) {
     return fail(MLBM_E_OOM, "host allocation failed while setting walls");
@@ -1263,8 +1264,6 @@ int32_t mlbm_plan_export(const mlbm_plan* plan, int32_t k, int32_t table, void* 
     case MLBM_TABLE_NBR_WIDE: src = lp.nbr_wide.data(); n = lp.nbr_wide.size() * 2; break;
     case MLBM_TABLE_WALL: src = lp.wall.data(); n = lp.wall.size() * 4; break;
     case MLBM_TABLE_WALL_Q: src = lp.wall_q.data(); n = lp.wall_q.size() * 8; break;
-    case MLBM_TABLE_WALL_BLK: src = lp.wall_blk.data(); n = lp.wall_blk.size() * 4; break;
-    case MLBM_TABLE_WALL_ROW: src = lp.wall_row.data(); n = lp.wall_row.size() * 4; break;
     default: return fail(MLBM_E_ARG, "unknown table %d", table);
   }
   if (!host_dst) {

@@ -30,13 +30,12 @@ struct LevelPlan {
   std::vector<int32_t> bounce;     // [2][n_bounce] (element, direction)
   // links with a wall fraction (linear interpolated bounce-back), sorted by
   // element then pull direction: [n_wall][4] {x, j, x2, weight class of j},
-  // their fractions, per pull-table block its row of wall_row or -1
-  // [blocks], and per row the first link of each of the block's elements
-  // and the block's end [rows][NBR_BLOCK + 1]
+  // and their fractions; the device copy is padded with links {-1, 0, -1, 0}
+  // so that no element's links straddle a chunk of NBR_BLOCK links
   std::vector<int32_t> wall;
   std::vector<double> wall_q;
-  std::vector<int32_t> wall_blk;
-  std::vector<int32_t> wall_row;
+  std::vector<int32_t> wall_dev;
+  std::vector<double> wall_dev_q;
 
   // The pull table as the device holds it, over the updated range in blocks
   // of NBR_BLOCK elements: per (block, direction) up to NBR_BASES base
@@ -70,6 +69,7 @@ struct LevelPlan {
   int64_t n_cap() const { return n_cap_fluid() + n_gff; }
   int64_t n_bounce() const { return (int64_t)bounce.size() / 2; }
   int64_t n_wall() const { return (int64_t)wall_q.size(); }
+  int64_t n_wall_dev() const { return (int64_t)wall_dev_q.size(); }
 };
 
 }  // namespace mlbm

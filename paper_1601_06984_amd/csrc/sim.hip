@@ -53,10 +53,8 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
     char* grt = take(lp.grp_tab.size() * 4);
     char* grc = take((size_t)NC * lp.n_groups * 4);
     char* bb = take((size_t)2 * lp.n_bounce() * 4);
-    char* wl = take(lp.wall.size() * 4);
-    char* wq = take(lp.wall_q.size() * 8);
-    char* wb = take(lp.wall_blk.size() * 4);
-    char* wrw = take(lp.wall_row.size() * 4);
+    char* wl = take(lp.wall_dev.size() * 4);
+    char* wq = take(lp.wall_dev_q.size() * 8);
     if (L) {
       L->pdf[0] = p0;
       L->pdf[1] = p1;
@@ -75,8 +73,6 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
       L->bounce = (int32_t*)bb;
       L->wall = lp.n_wall() ? (int32_t*)wl : nullptr;
       L->wall_q = lp.n_wall() ? (double*)wq : nullptr;
-      L->wall_blk = lp.n_wall() ? (int32_t*)wb : nullptr;
-      L->wall_row = lp.n_wall() ? (int32_t*)wrw : nullptr;
     }
   }
   char* st = take(256);
@@ -303,7 +299,7 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
     L.n_cap = lp.n_cap();
     L.n_groups = lp.n_groups;
     L.n_bounce = lp.n_bounce();
-    L.n_wall = lp.n_wall();
+    L.n_wall = lp.n_wall_dev();
     L.morton = lp.morton;
     const double tau = 0.5 + std::ldexp(tau0 - 0.5, lp.level - plan->level0);
     L.omega = 1.0 / tau;
@@ -338,10 +334,8 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
     up(L.grp_tab, lp.grp_tab.data(), lp.grp_tab.size() * 4);
     up(L.grp_child, lp.grp_child.data(), lp.grp_child.size() * 4);
     up(L.bounce, lp.bounce.data(), lp.bounce.size() * 4);
-    up(L.wall, lp.wall.data(), lp.wall.size() * 4);
-    up(L.wall_q, lp.wall_q.data(), lp.wall_q.size() * 8);
-    up(L.wall_blk, lp.wall_blk.data(), lp.wall_blk.size() * 4);
-    up(L.wall_row, lp.wall_row.data(), lp.wall_row.size() * 4);
+    up(L.wall, lp.wall_dev.data(), lp.wall_dev.size() * 4);
+    up(L.wall_q, lp.wall_dev_q.data(), lp.wall_dev_q.size() * 8);
   }
   std::vector<DiagLevel> dl(plan->nlev());
   for (int k = 0; k < plan->nlev(); ++k) {

@@ -31,10 +31,8 @@ struct DevLevel {
   int32_t* grp_tab = nullptr;         // [slots][n_groups][4] fill staging rows
   int32_t* grp_child = nullptr;       // [children][n_groups] element indices
   int32_t* bounce = nullptr;          // [2][n_bounce]
-  int32_t* wall = nullptr;            // [n_wall][4] links with a wall fraction
-  double* wall_q = nullptr;           // [n_wall]
-  int32_t* wall_blk = nullptr;        // [blocks] row or -1 (null: no such links)
-  int32_t* wall_row = nullptr;        // [rows][NBR_BLOCK + 1]
+  int32_t* wall = nullptr;            // [n_wall][4] links with a wall fraction,
+  double* wall_q = nullptr;           // [n_wall]    padded (the plan's device copy)
   int parity = 0;                     // index of the current pdf array
   int substep = 0;                    // 0: next step is the first after a sync
   double omega = 1.0;

@@ -65,6 +65,27 @@ def test_channel_walls_match_oracle(stencil, q_low, q_high, precision):
     assert H.compare_post(sim, osim) < TOL[precision]
 
 
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
+@pytest.mark.parametrize("q_low,q_high", [(0.7, 0.8), (0.3, 0.6)])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_single_row_between_walls(stencil, q_low, q_high, precision):
+    """One fluid row between two walls: every element has links into both,
+    so a link with q >= 1/2 reads the entry its opposite link's value goes
+    to, and a link with q < 1/2 has no second element (halfway rule)."""
+    import paper_1601_06984_amd as M
+    spec = W.plane_channel_mesh(stencil, 5, 4, 3)
+    om, lw, ow = _both(spec, lambda c: W.plane_wall_links(spec, c, q_low, q_high))
+    d = spec.dim
+    fields = lambda pos: W.uniform_fields(len(pos), d, [0.03] + [0.0] * (d - 1))
+    _say("single row", stencil, q_low, q_high, precision)
+    osim = H.oracle_run(spec, 0.8, fields, 4, om=om, walls=ow)
+    plan = M.Plan.from_spec(spec)
+    plan.set_walls(*lw)
+    sim = H.gpu_sim(spec, precision, 0.8, fields, plan=plan)
+    sim.step(4)
+    assert H.compare_post(sim, osim) < TOL[precision]
+
+
 def _sphere_small(stencil):
     return W.sphere_channel_mesh(8, 2, l0_per_d=4, length=(-2.0, 3.0), half_width=2.0,
                                  boxes_in_d=((-1.0, 1.5, 1.0),), stencil=stencil)

@@ -279,7 +279,7 @@ def _sphere_small(stencil="D3Q19"):
 def test_wall_tables_match_oracle(stencil):
     """Links with a wall fraction: element, pull direction, second node and
     fraction equal the oracle's links (same treeIDs, bit-exact), sorted by
-    element then direction, with per-block first-link offsets."""
+    element then direction."""
     from oracle.solver import wall_links
     spec = _sphere_small(stencil)
     om = omesh.build(spec)
@@ -297,7 +297,6 @@ def test_wall_tables_match_oracle(stencil):
             continue
         wt = plan.export(k, "wall")
         wq = plan.export(k, "wall_q")
-        blk = plan.export(k, "wall_blk")
         assert len(wt) == n_w == len(ow[L][0])
         gt = plan.export(k, "treeid")
         ot = om.lev(L).tid
@@ -311,22 +310,6 @@ def test_wall_tables_match_oracle(stencil):
         assert mine == theirs
         key = wt[:, 0].astype(np.int64) * 64 + wt[:, 1]
         assert (np.diff(key) > 0).all()
-        rows = plan.export(k, "wall_row")
-        assert len(rows) == (blk >= 0).sum()
-        seen = 0
-        for b in range(len(blk)):
-            has = (wt[:, 0] // 256 == b)
-            if blk[b] < 0:
-                assert not has.any()
-                continue
-            r = rows[blk[b]]
-            for e in range(256):   # element b*256+e owns links [r[e], r[e+1])
-                mine_e = np.where(wt[:, 0] == b * 256 + e)[0]
-                assert r[e + 1] - r[e] == len(mine_e)
-                if len(mine_e):
-                    assert r[e] == mine_e[0]
-            seen += int(r[256] - r[0])
-        assert seen == n_w
 
 
 def test_set_walls_rejects_bad_links():
