@@ -22,8 +22,8 @@ import torch
 from .solver import OracleSim
 
 
-def run_objective(mesh, tau0, rho, u, S, n_steps, objective="ke", u_in=None):
-    sim = OracleSim(mesh, tau0, u_in=u_in, poison=False)
+def run_objective(mesh, tau0, rho, u, S, n_steps, objective="ke", u_in=None, walls=None):
+    sim = OracleSim(mesh, tau0, u_in=u_in, poison=False, walls=walls)
     sim.init(rho, u, S)
     sim.step(n_steps)
     if objective == "ke":
@@ -34,7 +34,7 @@ def run_objective(mesh, tau0, rho, u, S, n_steps, objective="ke", u_in=None):
 
 
 def gradient(mesh, tau0: float, rho, u, S, n_steps: int, objective="ke",
-             u_in=None):
+             u_in=None, walls=None):
     """Returns (J, dJ/dtau0, {L: dJ/du0_L (n_fluid, d)}, dJ/du_in or None)."""
     tau = torch.tensor(float(tau0), dtype=torch.float64, requires_grad=True)
     uu = {L: torch.tensor(np.asarray(u[L]), dtype=torch.float64, requires_grad=True)
@@ -42,7 +42,7 @@ def gradient(mesh, tau0: float, rho, u, S, n_steps: int, objective="ke",
     uin = None
     if u_in is not None:
         uin = torch.tensor(np.asarray(u_in), dtype=torch.float64, requires_grad=True)
-    J = run_objective(mesh, tau, rho, uu, S, n_steps, objective, uin)
+    J = run_objective(mesh, tau, rho, uu, S, n_steps, objective, uin, walls)
     inputs = [tau] + [uu[L] for L in sorted(uu)] + ([uin] if uin is not None else [])
     grads = torch.autograd.grad(J, inputs, allow_unused=True)
     g_tau = grads[0]
@@ -54,7 +54,7 @@ def gradient(mesh, tau0: float, rho, u, S, n_steps: int, objective="ke",
 
 
 def central_difference(mesh, tau0, rho, u, S, n_steps, objective="ke",
-                       du=None, dtau=0.0, duin=None, u_in=None, eps=1e-6):
+                       du=None, dtau=0.0, duin=None, u_in=None, eps=1e-6, walls=None):
     """(J(x + eps d) - J(x - eps d)) / (2 eps) along the direction
     (du per level, dtau, duin)."""
     def shifted(sign):
@@ -65,5 +65,5 @@ def central_difference(mesh, tau0, rho, u, S, n_steps, objective="ke",
             uin2 = np.asarray(u_in) + sign * eps * (duin if duin is not None else 0.0)
         with torch.no_grad():
             return float(run_objective(mesh, tau0 + sign * eps * dtau, rho, u2, S,
-                                       n_steps, objective, uin2))
+                                       n_steps, objective, uin2, walls))
     return (shifted(+1) - shifted(-1)) / (2 * eps)
