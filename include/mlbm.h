@@ -179,9 +179,9 @@ int32_t mlbm_set_morton_policy(double level_min_fraction, int32_t block_min_dire
  * (MLBM_DIAG_FORCE) sums c_i (f*_i(x) + f_ibar(x, t+1)) over its links.
  * Replaces the plan's previous set (n = 0 clears it).  Host arrays are
  * copied.  Affects simulations created afterwards, whose workspace grows
- * (query mlbm_sim_workspace_bytes after this call).  The adjoint does not
- * cover these links: mlbm_adjoint_workspace_bytes / _attach return
- * MLBM_E_STATE for a simulation with any.  Errors (the plan is left
+ * (query mlbm_sim_workspace_bytes after this call).  The adjoint covers
+ * the links (the transposed rule and the drag seed of the interpolated
+ * values); its workspace grows with them.  Errors (the plan is left
  * unchanged): MLBM_E_ARG (NULL arrays with n > 0, a direction out of
  * range, q outside [0, 1] or not finite, a link given twice), MLBM_E_MESH
  * (an id that is not a fluid leaf, or a link whose neighbour is not

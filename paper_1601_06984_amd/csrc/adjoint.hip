@@ -101,6 +101,12 @@ size_t layout_adjoint(const SimState& s, const mlbm_plan& P, char* base, AdjStat
     char* cp = take(lp.csr_ptr.size() * 4);
     char* cn = take(lp.csr_ent.size() * 4);
     char* T = take((size_t)group_slots(d) * lp.n_groups * st * cb);
+    char* we = take(lp.wadj_ent.size() * 4);
+    char* wp = take(lp.wadj_ptr.size() * 4);
+    char* ws = take(lp.wadj_src.size() * 4);
+    char* wc = take(lp.wadj_coef.size() * 8);
+    char* wd = take(lp.wadj_seed.size() * 8);
+    char* wt = take((size_t)lp.n_wadj() * cb);
     if (A) {
       A->lam[0] = l0;
       A->lam[1] = l1;
@@ -115,6 +121,13 @@ size_t layout_adjoint(const SimState& s, const mlbm_plan& P, char* base, AdjStat
       A->csr_ptr = (int32_t*)cp;
       A->csr_ent = (int32_t*)cn;
       A->T = T;
+      A->n_wadj = lp.n_wadj();
+      A->wadj_ent = (int32_t*)we;
+      A->wadj_ptr = (int32_t*)wp;
+      A->wadj_src = (int32_t*)ws;
+      A->wadj_coef = (double*)wc;
+      A->wadj_seed = (double*)wd;
+      A->wadj_tmp = wt;
     }
   }
   const int64_t rec = std::max(os.off, oi.off);
@@ -311,6 +324,17 @@ struct Adj {
         hipLaunchKernelGGL((k_adj_copy_add<Lat::Q, C>), dim3((unsigned)blocks(A.n_copy, 256)),
                            dim3(256), 0, s.stream, A.copy_el, A.n_copy, s.lv[jb.k].n,
                            (const C*)A.copy_tmp, jb.lold);
+      // the stream-collide consumed the state after the curved-wall
+      // pre-pass: carry its adjoint back through the pre-pass
+      if (A.n_wadj) {
+        hipLaunchKernelGGL((k_adj_wall_gather<C>), dim3((unsigned)blocks(A.n_wadj, 256)),
+                           dim3(256), 0, s.stream, (const int4*)A.wadj_ent, A.wadj_ptr,
+                           (const int2*)A.wadj_src, A.wadj_coef, A.n_wadj, s.lv[jb.k].n,
+                           (const C*)jb.lold, (C*)A.wadj_tmp);
+        hipLaunchKernelGGL((k_adj_wall_store<C>), dim3((unsigned)blocks(A.n_wadj, 256)),
+                           dim3(256), 0, s.stream, (const int4*)A.wadj_ent, A.n_wadj,
+                           s.lv[jb.k].n, (const C*)A.wadj_tmp, jb.lold);
+      }
     }
   }
 
@@ -385,6 +409,10 @@ struct Adj {
         if (L.n_bounce)
           hipLaunchKernelGGL((k_seed_drag<Lat, C>), dim3((unsigned)blocks(L.n_bounce, 256)), dim3(256),
                              0, s.stream, L.bounce, L.n_bounce, L.n, scale, lam);
+        if (A.n_wadj)
+          hipLaunchKernelGGL((k_seed_wall_drag<C>), dim3((unsigned)blocks(A.n_wadj, 256)),
+                             dim3(256), 0, s.stream, (const int4*)A.wadj_ent, A.wadj_ptr,
+                             A.wadj_seed, A.n_wadj, L.n, scale, lam);
       }
       const int64_t ncap = L.n_cap * cap_stride(s.q);
       if (ncap)
@@ -489,13 +517,6 @@ int32_t hip_check(hipError_t e, const char* what) {
 
 using namespace mlbm;
 
-namespace {
-bool has_wall_links(const SimState& s) {
-  for (const DevLevel& L : s.lv)
-    if (L.n_wall) return true;
-  return false;
-}
-}  // namespace
 
 extern "C" {
 
@@ -503,8 +524,6 @@ int32_t mlbm_adjoint_workspace_bytes(const mlbm_sim* sim, const mlbm_plan* plan,
   if (!sim || !plan || !bytes) return fail(MLBM_E_ARG, "NULL argument");
   const SimState& s = sim->s;
   if (!plan_matches(s, *plan)) return fail(MLBM_E_ARG, "plan does not belong to this simulation");
-  if (has_wall_links(s))
-    return fail(MLBM_E_STATE, "the adjoint does not cover links with a wall fraction");
   OpBuilder os, oi;
   step_ops(s, 0, 0, os);
   init_ops(s, oi);
@@ -516,8 +535,6 @@ int32_t mlbm_adjoint_attach(mlbm_sim* sim, const mlbm_plan* plan, void* workspac
   if (!sim || !plan || !workspace) return fail(MLBM_E_ARG, "NULL argument");
   SimState& s = sim->s;
   if (!plan_matches(s, *plan)) return fail(MLBM_E_ARG, "plan does not belong to this simulation");
-  if (has_wall_links(s))
-    return fail(MLBM_E_STATE, "the adjoint does not cover links with a wall fraction");
   if (((uintptr_t)workspace) & 255) return fail(MLBM_E_ARG, "workspace must be 256-byte aligned");
   OpBuilder os, oi;
   step_ops(s, 0, 0, os);
@@ -543,6 +560,11 @@ int32_t mlbm_adjoint_attach(mlbm_sim* sim, const mlbm_plan* plan, void* workspac
     up(A.copy_el, lp.copy_elems.data(), lp.copy_elems.size() * 4);
     up(A.csr_ptr, lp.csr_ptr.data(), lp.csr_ptr.size() * 4);
     up(A.csr_ent, lp.csr_ent.data(), lp.csr_ent.size() * 4);
+    up(A.wadj_ent, lp.wadj_ent.data(), lp.wadj_ent.size() * 4);
+    up(A.wadj_ptr, lp.wadj_ptr.data(), lp.wadj_ptr.size() * 4);
+    up(A.wadj_src, lp.wadj_src.data(), lp.wadj_src.size() * 4);
+    up(A.wadj_coef, lp.wadj_coef.data(), lp.wadj_coef.size() * 8);
+    up(A.wadj_seed, lp.wadj_seed.data(), lp.wadj_seed.size() * 8);
     A.cur = 0;
   }
   up(a.ops_step, os.ops.data(), os.ops.size() * sizeof(AdjOp));
@@ -580,12 +602,20 @@ int32_t mlbm_adjoint_step(mlbm_sim* sim, const void* dev_ckpt, size_t bytes) {
     if (e != hipSuccess) return fail(MLBM_E_HIP, "adjoint step: %s", hipGetErrorString(e));
   }
   // the checkpoint's per-level arrays are read in place as substep 0 of
-  // the tape (nothing writes substep 0)
+  // the tape; a level with curved walls gets a copy, since the wall
+  // pre-pass writes into the state its stream-collide consumes
   const char* p = (const char*)dev_ckpt;
   size_t off = 256;
   for (size_t k = 0; k < s.lv.size(); ++k) {
-    s.adj.lv[k].X0 = p + off;
-    off += al((size_t)s.q * s.lv[k].n * sbytes(s.precision));
+    const size_t nb = (size_t)s.q * s.lv[k].n * sbytes(s.precision);
+    if (s.lv[k].n_wall) {
+      const hipError_t e = hipMemcpyAsync(s.adj.lv[k].X[0], p + off, nb,
+                                          hipMemcpyDeviceToDevice, s.stream);
+      if (e != hipSuccess) return fail(MLBM_E_HIP, "adjoint step: %s", hipGetErrorString(e));
+    } else {
+      s.adj.lv[k].X0 = p + off;
+    }
+    off += al(nb);
   }
   MLBM_ADJ_DISPATCH(s, J::step(s));
   for (auto& A : s.adj.lv) A.X0 = nullptr;

@@ -167,6 +167,56 @@ __global__ __launch_bounds__(256) void k_seed_drag(const int32_t* __restrict__ b
   lam[(int64_t)i * n + x] = (C)(2.0 * Lat::c(i, 0) * scale);
 }
 
+// Transpose of the curved-wall pre-pass (k_wall_prepass), in gather form:
+// every entry e the pre-pass reads or writes gets [e not written] lam[e] +
+// sum over its terms of coefficient * lam[written entry of the term's link],
+// formed for all entries before any is stored (two launches), so the sums
+// are fixed-order and free of races.
+template <class C>
+__global__ __launch_bounds__(256) void k_adj_wall_gather(
+    const int4* __restrict__ ent, const int32_t* __restrict__ ptr, const int2* __restrict__ src,
+    const double* __restrict__ coef, int64_t n_ent, int64_t n, const C* __restrict__ lam,
+    C* __restrict__ tmp) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_ent) return;
+  const int4 r = ent[e];
+  C acc = r.z ? lam[(int64_t)r.x * n + r.y] : C(0);
+  for (int32_t k = ptr[e]; k < ptr[e + 1]; ++k) {
+    const int2 w = src[k];
+    acc += (C)coef[k] * lam[(int64_t)w.x * n + w.y];
+  }
+  tmp[e] = acc;
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void k_adj_wall_store(const int4* __restrict__ ent,
+                                                        int64_t n_ent, int64_t n,
+                                                        const C* __restrict__ tmp,
+                                                        C* __restrict__ lam) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_ent) return;
+  const int4 r = ent[e];
+  lam[(int64_t)r.x * n + r.y] = tmp[e];
+}
+
+// Drag along x with curved walls: the returning value of a link is the
+// interpolated one, so d/dg* of c_ox (g*_o(x) + value) adds, over the
+// entries the value reads, c_ox (coefficient - [own entry]) to the halfway
+// seed 2 c_ox (k_seed_drag).
+template <class C>
+__global__ __launch_bounds__(256) void k_seed_wall_drag(const int4* __restrict__ ent,
+                                                        const int32_t* __restrict__ ptr,
+                                                        const double* __restrict__ seed,
+                                                        int64_t n_ent, int64_t n, double scale,
+                                                        C* __restrict__ lam) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_ent) return;
+  const int4 r = ent[e];
+  double acc = 0;
+  for (int32_t k = ptr[e]; k < ptr[e + 1]; ++k) acc += seed[k];
+  lam[(int64_t)r.x * n + r.y] += (C)(acc * scale);
+}
+
 // ------------------------------------------------- stream-collide reverse --
 // Gathers the tape state, forms mu = (d g*/d g)^T lam* [+ (d rec/d g)^T
 // lam_rec] in streamed passes over the directions (no per-direction

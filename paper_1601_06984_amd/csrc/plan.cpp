@@ -1205,12 +1205,54 @@ int32_t mlbm_plan_set_walls(mlbm_plan* plan, const uint64_t* ids, const int32_t*
           o.wall_dev_q.push_back(v[e].q);
         }
       }
+      // transpose of the pre-pass: link t writes W = (o, x) = a W + b (o, x2)
+      // + c (j, x) with (a, b, c) = (2q, 1 - 2q, 0) for q < 1/2 (x2 an
+      // element; else (1, 0, 0)) and (1/(2q), 0, 1 - 1/(2q)) for q >= 1/2
+      struct Term { int64_t key; int32_t sd, se; double coef, seed; bool own; };
+      std::vector<Term> terms;
+      const int64_t nn = plan->lv[k].n;
+      for (const Link& l : v) {
+        const int o = stencil_opp(plan->stencil, l.j);
+        const double cox = stencil_c(plan->stencil, o, 0);
+        double a = 1, b = 0, c = 0;
+        if (l.q < 0.5) {
+          if (l.x2 >= 0) { a = 2 * l.q; b = 1 - 2 * l.q; }
+        } else {
+          a = 1 / (2 * l.q);
+          c = 1 - a;
+        }
+        const int64_t w = (int64_t)o * nn + l.x;
+        terms.push_back({w, o, (int32_t)l.x, a, cox * (a - 1), true});
+        if (b != 0) terms.push_back({(int64_t)o * nn + l.x2, o, (int32_t)l.x, b, cox * b, false});
+        if (c != 0) terms.push_back({(int64_t)l.j * nn + l.x, o, (int32_t)l.x, c, cox * c, false});
+      }
+      std::stable_sort(terms.begin(), terms.end(),
+                       [](const Term& p, const Term& q2) { return p.key < q2.key; });
+      for (size_t e = 0; e < terms.size();) {
+        size_t f = e;
+        bool own = false;
+        while (f < terms.size() && terms[f].key == terms[e].key) own |= terms[f++].own;
+        o.wadj_ent.insert(o.wadj_ent.end(), {(int32_t)(terms[e].key / nn),
+                                             (int32_t)(terms[e].key % nn), own ? 0 : 1, 0});
+        o.wadj_ptr.push_back((int32_t)o.wadj_coef.size());
+        for (; e < f; ++e) {
+          o.wadj_src.insert(o.wadj_src.end(), {terms[e].sd, terms[e].se});
+          o.wadj_coef.push_back(terms[e].coef);
+          o.wadj_seed.push_back(terms[e].seed);
+        }
+      }
+      if (!terms.empty()) o.wadj_ptr.push_back((int32_t)o.wadj_coef.size());
     }
     for (int k = 0; k < nl; ++k) {
       plan->lv[k].wall.swap(next[k].wall);
       plan->lv[k].wall_q.swap(next[k].wall_q);
       plan->lv[k].wall_dev.swap(next[k].wall_dev);
       plan->lv[k].wall_dev_q.swap(next[k].wall_dev_q);
+      plan->lv[k].wadj_ent.swap(next[k].wadj_ent);
+      plan->lv[k].wadj_ptr.swap(next[k].wadj_ptr);
+      plan->lv[k].wadj_src.swap(next[k].wadj_src);
+      plan->lv[k].wadj_coef.swap(next[k].wadj_coef);
+      plan->lv[k].wadj_seed.swap(next[k].wadj_seed);
     }
   } catch (const std::bad_alloc&) {
     return fail(MLBM_E_OOM, "host allocation failed while setting walls");

@@ -36,6 +36,13 @@ struct LevelPlan {
   std::vector<double> wall_q;
   std::vector<int32_t> wall_dev;
   std::vector<double> wall_dev_q;
+  // transpose of the wall pre-pass in gather form: the entries it reads or
+  // writes [n_ent][4] {direction, element, keep own value (not written), 0},
+  // per entry its terms [ptr[e], ptr[e+1]) with the written entry they come
+  // from [nnz][2] {direction, element}, the coefficient and the x-drag seed
+  // coefficient c_ox (coefficient - [the entry is the link's own])
+  std::vector<int32_t> wadj_ent, wadj_ptr, wadj_src;
+  std::vector<double> wadj_coef, wadj_seed;
 
   // The pull table as the device holds it, over the updated range in blocks
   // of NBR_BLOCK elements: per (block, direction) up to NBR_BASES base
@@ -70,6 +77,7 @@ struct LevelPlan {
   int64_t n_bounce() const { return (int64_t)bounce.size() / 2; }
   int64_t n_wall() const { return (int64_t)wall_q.size(); }
   int64_t n_wall_dev() const { return (int64_t)wall_dev_q.size(); }
+  int64_t n_wadj() const { return (int64_t)wadj_ptr.size() - (wadj_ptr.empty() ? 0 : 1); }
 };
 
 }  // namespace mlbm

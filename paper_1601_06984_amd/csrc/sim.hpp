@@ -91,6 +91,14 @@ struct AdjLevel {
   int32_t* csr_ptr = nullptr;
   int32_t* csr_ent = nullptr;
   void* T = nullptr;
+  // transpose of the curved-wall pre-pass (the plan's wadj_* tables)
+  int64_t n_wadj = 0;
+  int32_t* wadj_ent = nullptr;
+  int32_t* wadj_ptr = nullptr;
+  int32_t* wadj_src = nullptr;
+  double* wadj_coef = nullptr;
+  double* wadj_seed = nullptr;
+  void* wadj_tmp = nullptr;    // [n_wadj] compute type
 };
 
 struct AdjState {

@@ -32,9 +32,13 @@ def _device():
     import paper_1601_06984_amd  # noqa: F401
 
 
-def gpu_gradient(spec, precision, tau0, fields, steps, objective="ke", u_in=None):
+def gpu_gradient(spec, precision, tau0, fields, steps, objective="ke", u_in=None, walls=False):
     import paper_1601_06984_amd as M
-    sim = H.gpu_sim(spec, precision, tau0, fields, u_in=u_in)
+    plan = None
+    if walls:   # a function of the velocity set giving the wall links
+        plan = M.Plan.from_spec(spec)
+        plan.set_walls(*walls(M.lattice(spec.stencil)[0]))
+    sim = H.gpu_sim(spec, precision, tau0, fields, u_in=u_in, plan=plan)
     sim.adjoint_attach()
     ckpts = []
     for _ in range(steps):
@@ -54,14 +58,15 @@ def gpu_gradient(spec, precision, tau0, fields, steps, objective="ke", u_in=None
     return sim, J, [d.cpu().numpy() for d in du], dtau, duin
 
 
-def oracle_gradient(spec, tau0, fields, steps, objective="ke", u_in=None):
+def oracle_gradient(spec, tau0, fields, steps, objective="ke", u_in=None, walls=False):
     om = omesh.build(spec)
+    wl = walls(om.lattice.c) if walls else None
     rho, u, S = {}, {}, {}
     for L in range(om.level0, om.lmax + 1):
         pos = om.positions(L)[:om.lev(L).n_fluid]
         r, uu, SS = fields(pos)
         rho[L], u[L], S[L] = r, uu, SS * 2.0 ** -(L - om.level0)
-    J, gt, gu, gin = oadj.gradient(om, tau0, rho, u, S, steps, objective, u_in=u_in)
+    J, gt, gu, gin = oadj.gradient(om, tau0, rho, u, S, steps, objective, u_in=u_in, walls=wl)
     return om, J, gt, gu, gin
 
 
@@ -163,6 +168,50 @@ def test_gradients_with_boundaries(objective, steps, precision, tol, stencil):
     assert np.abs(duin - gino).max() <= tol * np.abs(gino).max()
     assert abs(dtau - gto) <= tol * abs(gto)
     assert _compare(sim, om, du, guo) < tol * 10
+
+
+@pytest.mark.parametrize("stencil", ["D3Q19", "D3Q27"])
+@pytest.mark.parametrize("objective,steps", [("ke", 3), ("drag_x", 6)])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-8), ("f32", 5e-4)])
+def test_gradients_with_curved_walls(objective, steps, precision, tol, stencil):
+    """The sphere's links with wall fractions (linear interpolated
+    bounce-back) in reverse: the transposed wall pre-pass and the drag seed
+    of the interpolated returning values, against the oracle's reverse pass."""
+    spec = _compact_sphere(stencil)
+    uin = np.array([0.04, 0.0, 0.0])
+    fields = lambda p: W.uniform_fields(len(p), 3, uin)
+    _say("sphere walls", objective, precision, stencil)
+    links = lambda c: W.sphere_wall_links(spec, c)
+    sim, J, du, dtau, duin = gpu_gradient(spec, precision, 0.6, fields, steps, objective,
+                                          u_in=uin, walls=links)
+    om, Jo, gto, guo, gino = oracle_gradient(spec, 0.6, fields, steps, objective, u_in=uin,
+                                             walls=links)
+    assert abs(J - Jo) <= 1e-5 * abs(Jo)
+    print("duin", duin, gino, "dtau", dtau, gto)
+    assert abs(gino[0]) > 1.0
+    assert np.abs(duin - gino).max() <= tol * np.abs(gino).max()
+    assert abs(dtau - gto) <= tol * abs(gto)
+    assert _compare(sim, om, du, guo) < tol * 10
+
+
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("q_low,q_high", [(0.7, 0.8), (0.3, 0.6)])
+@pytest.mark.parametrize("height", [3, 4])
+def test_gradients_with_walls_on_both_sides_of_a_row(stencil, q_low, q_high, height):
+    """One or two fluid rows between two walls: one link's value reads the
+    entry the opposite link's value replaces (one row), or two links' terms
+    meet in one entry of the other row (two rows); F64 gradient of the
+    kinetic energy against the oracle's reverse pass."""
+    spec = W.plane_channel_mesh(stencil, 5, 4, height)
+    d = spec.dim
+    links = lambda c: W.plane_wall_links(spec, c, q_low, q_high)
+    fields = lambda p: W.tgv_perturbed_fields(p, 4, 0.03)
+    _say("two rows between walls", stencil, q_low, q_high)
+    sim, J, du, dtau, _ = gpu_gradient(spec, "f64", 0.8, fields, 4, walls=links)
+    om, Jo, gto, guo, _ = oracle_gradient(spec, 0.8, fields, 4, walls=links)
+    assert abs(J - Jo) <= 1e-10 * abs(Jo)
+    assert _compare(sim, om, du, guo) < 1e-8
+    assert abs(dtau - gto) <= 1e-8 * abs(gto)
 
 
 def test_f64_adjoint_matches_central_differences_of_gpu_forward():

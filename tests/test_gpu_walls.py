@@ -141,16 +141,3 @@ def test_walls_across_graph_replays_and_grouped_launches():
         out.append([sim.get_pdf(k) for k in range(plan.n_levels)])
     for a, b in zip(*out):
         assert torch.equal(a, b)
-
-
-def test_adjoint_refuses_wall_fractions():
-    import paper_1601_06984_amd as M
-    spec = _sphere_small("D3Q19")
-    lw = W.sphere_wall_links(spec, M.lattice("D3Q19")[0])
-    plan = M.Plan.from_spec(spec)
-    plan.set_walls(*lw)
-    uin = np.array([0.04, 0.0, 0.0])
-    sim = H.gpu_sim(spec, "f32", 0.6, lambda pos: W.uniform_fields(len(pos), 3, uin),
-                    u_in=uin, plan=plan)
-    with pytest.raises(M.MLBMError):
-        sim.adjoint_attach()
