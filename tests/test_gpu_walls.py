@@ -44,7 +44,7 @@ def _both(spec, links_of):
 
 
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
-@pytest.mark.parametrize("q_low,q_high", [(0.2, 0.7), (0.9, 0.35)])
+@pytest.mark.parametrize("q_low,q_high", [(0.2, 0.7), (0.9, 0.35), (0.0, 1.0)])
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
 def test_channel_walls_match_oracle(stencil, q_low, q_high, precision):
     import paper_1601_06984_amd as M

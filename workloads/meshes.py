@@ -310,7 +310,9 @@ def sphere_wall_links(spec: MeshSpec, c: np.ndarray):
     fluid = (a * a).sum(1) >= r * r
     cells, a = cells[fluid], a[fluid]
     tid = encode_tree_ids(lmax, cells)
-    leaf = np.isin(tid, spec.leaf_ids)
+    ids = spec.leaf_ids
+    ids = ids[(ids >= tid.min()) & (ids <= tid.max())]   # cheap pre-filter for big meshes
+    leaf = np.isin(tid, ids)
     cells, a, tid = cells[leaf], a[leaf], tid[leaf]
     lat = np.asarray(c, dtype=np.float64)
     ids, dirs, qs = [], [], []
