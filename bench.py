@@ -41,16 +41,16 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
 # kernel sources they were measured on (KERNEL_SOURCES digest); with any
 # other source the bench reports traffic as null.
 PMC_TRAFFIC = {
-    "sources_sha256_16": "b625b4061cb8a86a",
+    "sources_sha256_16": "5b523578dd764e9a",
     "bytes_per_launch": {
-        "tgv64/f32/6": 47463638,
-        "tgv64/f32/7": 60062349,
-        "sphere3/f32/9": 2194898888,
-        "sphere3/f32/10": 814198967,
-        "sphere3/f32/11": 851910788,
-        "sphere3/f16s/9": 1109434330,
-        "sphere3/f16s/10": 470795858,
-        "sphere3/f16s/11": 455547842,
+        "tgv64/f32/6": 47456038,
+        "tgv64/f32/7": 60060091,
+        "sphere3/f32/9": 2195942052,
+        "sphere3/f32/10": 814369911,
+        "sphere3/f32/11": 852082092,
+        "sphere3/f16s/9": 1109229543,
+        "sphere3/f16s/10": 470871971,
+        "sphere3/f16s/11": 455362311,
     },
 }
 KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")

@@ -631,6 +631,53 @@ inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStr
     hipLaunchKernelGGL(kernel, grid, block, 0, st, static_cast<KArgs>(args)...);
 }
 
+// FP16-shift stores of one element's post-collision values that keep the
+// element's stored mass and momentum as close to the exact ones as the
+// format allows: the diagonal directions round to nearest; each axis pair
+// (+a, -a) takes the momentum rounding error along a accumulated so far,
+// half on each (antisymmetric, so their mass is unchanged); the rest
+// direction takes the accumulated mass error.  What remains is the
+// rounding of those last values, instead of the sum over all directions.
+// Directions are ordered rest, axis pairs 2a+1 / 2a+2, then diagonals.
+template <class Lat>
+__device__ __forceinline__ bool store_f16s_conserving(__half* __restrict__ dst, int64_t x,
+                                                      const LevelArgs<float, Lat::Q>& a,
+                                                      const float* g, float drho, float rho,
+                                                      const float* u, float uu) {
+  constexpr int D = Lat::D, Q = Lat::Q;
+  bool ok = true;
+  // stores round(v) in direction i; returns the decoded value
+  auto put = [&](int i, float v) -> float {
+    const float hs = v * a.scale;
+    const __half h = __float2half_rn(hs);
+    store_elem(dst + (int64_t)i * a.n, a.n, (uint32_t)x, h);
+    ok &= fabsf(hs) <= 65504.0f;
+    return __half2float(h) * a.inv_scale;
+  };
+  auto post = [&](int i) -> float {
+    return g[i] + a.omega * (geq_i<Lat, float>(i, drho, rho, u, uu) - g[i]);
+  };
+  float em = 0.0f, ej[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int i = 2 * D + 1; i < Q; ++i) {
+    const float v = post(i);
+    const float err = put(i, v) - v;
+    em += err;
+#pragma unroll
+    for (int b = 0; b < D; ++b) ej[b] += (float)Lat::c(i, b) * err;
+  }
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const float vp = post(2 * b + 1), vm = post(2 * b + 2);
+    const float ep = put(2 * b + 1, vp - 0.5f * ej[b]) - vp;
+    const float eq = put(2 * b + 2, vm + 0.5f * ej[b]) - vm;
+    em += ep + eq;
+  }
+  const float v0 = post(0);
+  put(0, v0 - em);
+  return ok;
+}
+
 // The stream-collide of work-group `blk` (blk*BS < x1) of a level whose
 // updated range is [0, x1): elements blk*BS .. blk*BS+BS-1.  `stage` is the
 // work-group's record staging area, `slots` its pull-table slot area; every
@@ -672,10 +719,15 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
   }
   if (!valid) return;
   bool ok = true;
+  if constexpr (P == MLBM_F16S) {
+    ok = store_f16s_conserving<Lat>(dst, x, a, g, drho, rho, u, uu);
+  } else {
 #pragma unroll
-  for (int i = 0; i < Lat::Q; ++i) {
-    const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
-    ok &= store_row<P>(dst + (int64_t)i * a.n, a.n, (uint32_t)x, gs, a.wr[Lat::wclass(i)], a.scale);
+    for (int i = 0; i < Lat::Q; ++i) {
+      const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
+      ok &= store_row<P>(dst + (int64_t)i * a.n, a.n, (uint32_t)x, gs, a.wr[Lat::wclass(i)],
+                         a.scale);
+    }
   }
   const bool finite = (rho == rho) && (rho - rho == C(0));
   if (!finite || !ok)
