@@ -43,7 +43,11 @@ enum { MLBM_D2Q9 = 0, MLBM_D3Q19 = 1, MLBM_D3Q27 = 2 };
 
 /* Storage precision of the pdfs.  F64: double, FP64 collision.  F32: float,
  * FP32 collision.  F16S: half holding s_L * (f_i - w_i rho0) with a
- * power-of-two scale s_L per level; collision in FP32. */
+ * power-of-two scale s_L per level; collision in FP32.  The stream-collide
+ * rounds an element's diagonal directions to nearest and lets the axis pairs
+ * and the rest direction absorb the accumulated momentum and mass rounding
+ * errors, so each element's stored mass and momentum are off by the
+ * rounding of those last values only. */
 enum { MLBM_F64 = 0, MLBM_F32 = 1, MLBM_F16S = 2 };
 
 /* Face kinds, faces ordered x-, x+, y-, y+, z-, z+.  A periodic face must
