@@ -133,3 +133,81 @@ def test_sphere_channel_full_size_sampled_coarse_updates(precision):
             dj = (cvec[:, a][:, None] * d).sum(0)
             assert (np.abs(dj) <= 2.0 ** -11 * (g[pa] + g[ma]) + 2.0 ** -20 * gsum
                     + slack.sum(0)).all()
+
+
+def _sphere_bench_spec():
+    return W.sphere_channel_mesh(24, 3, outlet="eq")
+
+
+@pytest.mark.timeout(600)
+def test_sphere_channel_full_size_curved_walls():
+    """The benchmark's sphere channel with the sphere's wall fractions, at
+    full size and in the launch configuration the bench times:
+    (1) every wall fraction 1/2 reproduces halfway bounce-back bit for bit
+        in FP16-shifted storage (the pre-pass then rewrites each link's
+        entry with its own value, which the codec keeps exactly);
+    (2) the momentum-exchange force of the GPU's state, recomputed on the
+        host in FP64 with the oracle's interpolated bounce-back for every
+        link, equals the GPU's reduction."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1601_06984_amd as M
+    from oracle.solver import OracleSim
+    print("[gpu-case] sphere channel D=24, 3 levels, curved walls, full size", flush=True)
+    sys.stdout.flush()
+    uin = 0.04
+    spec = _sphere_bench_spec()
+    tau_f = 0.5 + 3.0 * uin * 24 / 100.0
+    tau0 = 0.5 + (tau_f - 0.5) / 4.0
+    c_lib, _ = M.lattice("D3Q19")
+    ids, dirs, q = W.sphere_wall_links(spec, c_lib)
+    fields = lambda p: W.uniform_fields(len(p), 3, [uin, 0.0, 0.0])
+
+    # (1) q = 1/2 everywhere against no fractions, F16S, bitwise
+    states = []
+    for walls in (None, np.full(len(q), 0.5)):
+        plan = M.Plan.from_spec(spec)
+        if walls is not None:
+            plan.set_walls(ids, dirs, walls)
+        sim = H.gpu_sim(spec, "f16s", tau0, fields, u_in=[uin, 0.0, 0.0], plan=plan)
+        sim.step(3)
+        states.append([sim.get_pdf(k) for k in range(plan.n_levels)])
+        del sim
+    for a, b in zip(*states):
+        assert torch.equal(a, b)
+
+    # (2) force of the state with the real fractions, F32
+    plan = M.Plan.from_spec(spec)
+    plan.set_walls(ids, dirs, q)
+    sim = H.gpu_sim(spec, "f32", tau0, fields, u_in=[uin, 0.0, 0.0], plan=plan)
+    sim.step(20)
+    assert sim.status() == 0
+    F_gpu = sim.diagnostics(M.DIAG_FORCE).cpu().numpy()[:3]
+    k = plan.n_levels - 1
+    lat = olat.get("D3Q19")
+    perm = np.asarray(H.direction_perm("D3Q19", lat))   # library i -> oracle index
+    inv = np.argsort(perm)
+    fstar = torch.as_tensor(sim.get_pdf(k).cpu().numpy()[inv])   # oracle direction order
+    wt = plan.export(k, "wall")
+    wq = plan.export(k, "wall_q")
+    x = wt[:, 0].astype(np.int64)
+    j_lib = wt[:, 1]
+    i_or = np.array([perm[int(np.where((c_lib == -c_lib[j]).all(1))[0][0])] for j in j_lib],
+                    dtype=np.int64)
+    stub = type("Stub", (), {})()
+    stub.lat, stub.dtype = lat, torch.float64
+    stub.walls = {k: (x, i_or, wq, wt[:, 2].astype(np.int64))}
+    out = OracleSim.curved_walls(stub, k, fstar, torch.zeros_like(fstar))
+    ret = out[lat.opp[i_or], x].numpy()                 # returning values of the links
+    c = lat.c.astype(np.float64)
+    F = (c[i_or] * (fstar[i_or, x].numpy() + ret)[:, None]).sum(0)
+    # halfway links: the returning value is f*_i(x) itself
+    b = plan.export(k, "bounce")
+    on_wall = set(zip(x.tolist(), j_lib.tolist()))
+    keep = np.array([(int(e), int(j)) not in on_wall for e, j in zip(b[0], b[1])], bool)
+    bi = np.array([perm[int(np.where((c_lib == -c_lib[j]).all(1))[0][0])] for j in b[1][keep]],
+                  dtype=np.int64)
+    F = F + (2.0 * c[bi] * fstar[bi, b[0][keep].astype(np.int64)].numpy()[:, None]).sum(0)
+    print("force gpu", F_gpu, "host", F)
+    assert F[0] > 0
+    assert np.allclose(F_gpu, F, rtol=1e-9, atol=1e-11)
