@@ -167,13 +167,17 @@ def linear_weights(pos, target, dtype=torch.float64):
     return torch.linalg.solve(A.t(), b)
 
 
-def fill(f_src, pos, target, omega_s, omega_t, dt_ratio, lat):
+def fill(f_src, pos, target, omega_s, omega_t, dt_ratio, lat, u_scale=1.0,
+         drho_scale=1.0, rho0=1.0):
     """Steps 1-5 of Sec. 2.2 for a group of ghosts sharing one source
     geometry.
 
     f_src (4, q, n) pre-collision pdfs of the four sources of each ghost,
     pos (4, d) source coordinates in source-level units, target (d,),
-    dt_ratio = dt_target / dt_source.  Returns the ghost pdfs (q, n)."""
+    dt_ratio = dt_target / dt_source.  u_scale and drho_scale take the
+    interpolated velocity and density deviation rho - rho0 from source to
+    target lattice units (1 under acoustic scaling, where both are level
+    invariant).  Returns the ghost pdfs (q, n)."""
     d = lat.d
     rhos, us, Ss, fneqs = [], [], [], []
     for k in range(4):                                   # Step 1
@@ -191,6 +195,9 @@ def fill(f_src, pos, target, omega_s, omega_t, dt_ratio, lat):
     w = linear_weights(pos, target).to(f_src.dtype)
     rho_t = sum(w[k] * rhos[k] for k in range(4))
     fneq_t = sum(w[k] * fneqs[k] for k in range(4))
+    if u_scale != 1.0 or drho_scale != 1.0:              # units of the target
+        u_t = u_t * u_scale
+        rho_t = rho0 + (rho_t - rho0) * drho_scale
     feq_t = physics.equilibrium(rho_t, u_t.t(), lat)      # Step 3
     fneq_t = fneq_t * (omega_s / omega_t) * dt_ratio      # Step 4
     return feq_t + fneq_t                                 # Step 5

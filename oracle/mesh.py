@@ -15,9 +15,12 @@ Readings taken where the paper is silent:
 
 * GhostFromCoarser (level L > L0): every position on level L that is not
   fluid, not refined further and not solid, inside the domain, whose
-  L-infinity distance to a level-L fluid element is 1 (inner layer) or 2
-  (outer layer).  Two layers are what two fine steps per coarse step
-  consume (Sec. 2.2, last paragraph).  Its parent must be level-(L-1) fluid.
+  L-infinity distance to a level-L fluid element is at most m, the number
+  of layers: distances 1 .. m-1 form the inner part (updated on the first
+  fine step after a fill), distance m the outer layer.  m fine steps per
+  coarse step consume m layers (Sec. 2.2, last paragraph): m = 2 under
+  acoustic scaling (the default), m = 4 under diffusive scaling.  Its
+  parent must be level-(L-1) fluid.
 * GhostFromFiner (level L < Lmax): every refined level-L position within
   L-infinity distance 1 of a level-L fluid element.
 * GhostFromCoarser sources (coarse level): with the ghost's octant signs s,
@@ -169,8 +172,11 @@ def _isin(keys, sorted_set):
     return sorted_set[pos] == keys
 
 
-def build(spec) -> Mesh:
-    """Build all tables from a workloads.MeshSpec."""
+def build(spec, gfc_layers: int = 2) -> Mesh:
+    """Build all tables from a workloads.MeshSpec; gfc_layers GhostFromCoarser
+    layers (2: acoustic scaling, 4: diffusive scaling)."""
+    if gfc_layers < 2:
+        raise MeshError("at least two GhostFromCoarser layers")
     lat = lat_mod.get(spec.stencil)
     d = lat.d
     geo = _Geometry(d, spec.level0, spec.box_origin, spec.box_extent,
@@ -240,7 +246,8 @@ def build(spec) -> Mesh:
         inner, outer = [], []
         if L > L0:
             occupied = np.unique(np.concatenate([fluid[L], refined[L], solid[L]]))
-            for off in product((-2, -1, 0, 1, 2), repeat=d):
+            m = gfc_layers
+            for off in product(range(-m, m + 1), repeat=d):
                 if not any(off):
                     continue
                 dist = max(abs(o) for o in off)
@@ -248,7 +255,7 @@ def build(spec) -> Mesh:
                 ok = ~out.any(1)
                 k = geo.key(c[ok], L)
                 k = k[~_isin(k, occupied)]
-                (inner if dist == 1 else outer).append(k)
+                (inner if dist < m else outer).append(k)
         ik = np.unique(np.concatenate(inner)) if inner else np.zeros(0, np.int64)
         ok_ = np.unique(np.concatenate(outer)) if outer else np.zeros(0, np.int64)
         ok_ = ok_[~_isin(ok_, ik)]

@@ -14,6 +14,15 @@ temporal interpolation); reading taken for the order:
     advance(L): step(L); if L < Lmax: advance(L+1); advance(L+1);
                 fill GhostFromFiner(L); fill GhostFromCoarser(L+1)
 
+Diffusive scaling (the variant Sec. 2.2 closes with; ``scaling="diffusive"``,
+mesh built with four GhostFromCoarser layers): dt halves twice per level,
+so advance(L+1) runs four times per step of L; tau is the same on every
+level (nu dt/dx^2 is level invariant); the fills take the interpolated
+velocity from source to target lattice units by (dt_t/dt_s)/(dx_t/dx_s)
+and the density deviation by its square, and Step 4 rescales f^neq by
+omega_s/omega_t times dt_t/dt_s as under acoustic scaling.  Mass and
+kinetic energy are reported in level-L0 units.
+
 Initialisation (reading taken; the paper is silent about ghosts at t=0):
 fluid pdfs are f^eq(rho, u) + f^neq(S) from the given fields, then one
 synchronous fill of all GhostFromFiner and then all GhostFromCoarser.
@@ -45,14 +54,23 @@ from .mesh import BOUNCE, COPY, EQ, MISSING
 
 class OracleSim:
     def __init__(self, mesh, tau0, rho0: float = 1.0, u_in=None,
-                 poison: bool = True, dtype=torch.float64, walls=None):
+                 poison: bool = True, dtype=torch.float64, walls=None,
+                 scaling: str = "acoustic"):
         self.mesh = mesh
         self.lat = mesh.lattice
         self.dtype = dtype
         self.L0, self.Lmax = mesh.level0, mesh.lmax
         self.tau0 = tau0
-        self.omega = {L: 1.0 / physics.level_tau(tau0, L, self.L0)
-                      for L in range(self.L0, self.Lmax + 1)}
+        if scaling not in ("acoustic", "diffusive"):
+            raise ValueError(scaling)
+        # fine steps per coarse step: dt_(L+1) = dt_L / n_sub, dx_(L+1) = dx_L / 2
+        self.scaling = scaling
+        self.n_sub = 2 if scaling == "acoustic" else 4
+        if scaling == "acoustic":
+            self.omega = {L: 1.0 / physics.level_tau(tau0, L, self.L0)
+                          for L in range(self.L0, self.Lmax + 1)}
+        else:   # nu dt / dx^2 is the same on every level
+            self.omega = {L: 1.0 / tau0 for L in range(self.L0, self.Lmax + 1)}
         self.rho0 = rho0
         d = self.lat.d
         if u_in is None:
@@ -121,8 +139,10 @@ class OracleSim:
         fs = self.f[L + 1]
         src = torch.from_numpy(t.gff_src)
         f_src = torch.stack([fs[:, src[:, k]] for k in range(4)], 0)
+        r = self.n_sub / 2.0          # (dt_c / dt_f) / (dx_c / dx_f)
         vals = interp.fill(f_src, pos, target, self.omega[L + 1], self.omega[L],
-                           2.0, self.lat)
+                           float(self.n_sub), self.lat, u_scale=r, drho_scale=r * r,
+                           rho0=self.rho0)
         idx = torch.arange(t.gff_begin, t.n)
         self.f[L] = self.f[L].index_copy(1, idx, vals)
 
@@ -147,8 +167,10 @@ class OracleSim:
             target = tuple(0.25 * v for v in s)
             src = torch.from_numpy(t.gfc_src[m])
             f_src = torch.stack([fc[:, src[:, k]] for k in range(4)], 0)
+            r = 2.0 / self.n_sub      # (dt_f / dt_c) / (dx_f / dx_c)
             vals = interp.fill(f_src, pos, target, self.omega[L - 1],
-                               self.omega[L], 0.5, self.lat)
+                               self.omega[L], 1.0 / self.n_sub, self.lat, u_scale=r,
+                               drho_scale=r * r, rho0=self.rho0)
             out = out.index_copy(1, torch.from_numpy(t.gfc_begin + m), vals)
         self.f[L] = out
 
@@ -191,8 +213,8 @@ class OracleSim:
     def advance(self, L):
         self.stream_collide(L)
         if L < self.Lmax:
-            self.advance(L + 1)
-            self.advance(L + 1)
+            for _ in range(self.n_sub):
+                self.advance(L + 1)
             self.fill_gff(L)
             self.fill_gfc(L + 1)
 
@@ -214,19 +236,28 @@ class OracleSim:
     def volume(self, L):
         return 2.0 ** (-self.lat.d * (L - self.L0))
 
+    def unit_ratio(self, L):
+        """Level-L0 lattice velocity per level-L lattice velocity:
+        (dx_L / dt_L) / (dx_L0 / dt_L0) = (n_sub / 2)^(L - L0)."""
+        return (self.n_sub / 2.0) ** (L - self.L0)
+
     def mass(self):
+        """sum_L V_L sum_fluid rho, density deviations in level-L0 units."""
         tot = 0.0
         for L in range(self.L0, self.Lmax + 1):
             rho, _, _ = self.fluid_moments(L)
-            tot = tot + self.volume(L) * rho.sum()
+            r = self.unit_ratio(L)
+            tot = tot + self.volume(L) * (self.rho0 + (rho - self.rho0) * r * r).sum()
         return tot
 
     def kinetic_energy(self):
-        """E = 1/2 sum_L V_L sum_fluid rho |u|^2 (V_L in level0 cells)."""
+        """E = 1/2 sum_L V_L sum_fluid rho |u|^2 (V_L in level0 cells, u in
+        level-L0 lattice units)."""
         tot = 0.0
         for L in range(self.L0, self.Lmax + 1):
             rho, u, _ = self.fluid_moments(L)
-            tot = tot + self.volume(L) * 0.5 * (rho * (u * u).sum(0)).sum()
+            r = self.unit_ratio(L)
+            tot = tot + self.volume(L) * 0.5 * (rho * (u * u).sum(0)).sum() * r * r
         return tot
 
     def force(self):
@@ -235,6 +266,8 @@ class OracleSim:
         next to the solid and the directions i pointing into it.  Each level's
         sum is in its own lattice units; they are added in finest-level units
         (force scales with dx^(d-1) under acoustic scaling)."""
+        if self.scaling != "acoustic":
+            raise NotImplementedError("force under diffusive scaling")
         d = self.lat.d
         c = self.lat.c_t(self.dtype)
         total = torch.zeros(d, dtype=self.dtype)

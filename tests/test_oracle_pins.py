@@ -584,3 +584,115 @@ def test_fluid_at_rest_stays_at_rest_with_curved_walls():
         nf = m.lev(L).n_fluid
         assert (sim.f[L][:, :nf] - w).abs().max() < 1e-15
     assert sim.force().abs().max() < 1e-13
+
+
+# ------------------------------------- diffusive scaling (Sec. 2.2, end) ----
+# dt_(L+1) = dt_L / 4, dx_(L+1) = dx_L / 2: four fine steps per coarse step,
+# four GhostFromCoarser layers, the same tau on every level; lattice velocity
+# halves and density deviation quarters per level (u dt/dx, p dt^2/dx^2).
+_DIFF_MESHES = [lambda: W.refined_box_mesh("D2Q9", 5, 8, 24),
+                lambda: W.refined_box_mesh("D3Q19", 4, 4, 12)]
+
+
+@pytest.mark.parametrize("spec_fn", _DIFF_MESHES)
+def test_diffusive_uniform_flow_and_pressure_kept(spec_fn):
+    """A uniform flow at uniform pressure is a fixed point when each level
+    holds it in its own lattice units; the fills must convert velocity and
+    density deviation between levels for that to hold."""
+    m = mesh.build(spec_fn(), gfc_layers=4)
+    d = m.d
+    uc = np.array([0.03, -0.02, 0.01][:d])
+    drho = 0.004
+    sim = solver.OracleSim(m, 0.7, scaling="diffusive")
+    rho, u, S = {}, {}, {}
+    for L in range(m.level0, m.lmax + 1):
+        r = 2.0 ** (L - m.level0)
+        rho[L], u[L], S[L] = W.uniform_fields(m.lev(L).n_fluid, d, uc / r, 1.0 + drho / (r * r))
+    sim.init(rho, u, S)
+    sim.step(3)
+    for L in range(m.level0, m.lmax + 1):
+        r = 2.0 ** (L - m.level0)
+        feq = physics.equilibrium(torch.tensor([1.0 + drho / (r * r)], dtype=torch.float64),
+                                  torch.tensor(uc / r)[:, None], m.lattice)
+        assert torch.allclose(sim.f[L], feq.expand_as(sim.f[L]), atol=1e-15), L
+
+
+@pytest.mark.parametrize("spec_fn", _DIFF_MESHES)
+def test_diffusive_fill_exact_on_quadratic_field(spec_fn):
+    """The sync fill under diffusive scaling reproduces a quadratic velocity
+    field (linear strain) at every ghost of all four layers, each level in
+    its own units: u / 2^(L-L0), S / 4^(L-L0).  At rho = 1: Step 4 rescales
+    f^neq by omega and dt only, while f^neq also carries rho, whose lattice
+    deviation changes between levels under this scaling (the uniform-flow
+    pin covers the density conversion)."""
+    m = mesh.build(spec_fn(), gfc_layers=4)
+    d = m.d
+    u_fn, S_fn = _quad_field(d, 42)
+    sim = solver.OracleSim(m, 0.57, scaling="diffusive")
+    drho = 0.0
+    expect = {}
+    for L in range(m.level0, m.lmax + 1):
+        r = 2.0 ** (L - m.level0)
+        pos = m.positions(L)
+        uu = u_fn(pos / 16.0) * 0.5 / r
+        SS = S_fn(pos / 16.0) * 0.5 / 16.0 / (r * r)
+        expect[L] = _pdf(m.lattice, 1.0 + drho / (r * r), uu, SS, sim.omega[L])
+        t = m.lev(L)
+        sim.f[L] = expect[L].clone()
+        sim.f[L][:, t.n_fluid:] = float("nan")
+    sim.fill_all()
+    for L in range(m.level0, m.lmax + 1):
+        t = m.lev(L)
+        got = sim.f[L][:, t.n_fluid:]
+        assert not torch.isnan(got).any()
+        assert torch.allclose(got, expect[L][:, t.n_fluid:], rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("spec_fn", _DIFF_MESHES)
+def test_diffusive_four_layers_feed_four_fine_steps(spec_fn):
+    """NaN-poisoned run: with four layers, nothing invalid reaches a fluid
+    element over four fine steps per coarse step; with two layers it does."""
+    spec = spec_fn()
+    d = 2 if spec.stencil == "D2Q9" else 3
+    n0 = spec.box_extent[0]
+
+    def run(layers):
+        m = mesh.build(spec, gfc_layers=layers)
+        sim = solver.OracleSim(m, 0.7, scaling="diffusive")
+        rho, u, S = {}, {}, {}
+        for L in range(m.level0, m.lmax + 1):
+            r = 2.0 ** (L - m.level0)
+            pos = m.positions(L)[:m.lev(L).n_fluid]
+            rr, uu, SS = W.tgv_fields(pos, n0, 0.02)
+            rho[L], u[L], S[L] = 1.0 + (rr - 1.0) / (r * r), uu / r, SS / (r * r)
+        sim.init(rho, u, S)
+        sim.step(2)
+        return all(torch.isfinite(sim.f[L][:, :m.lev(L).n_fluid]).all()
+                   for L in range(m.level0, m.lmax + 1))
+    assert run(4)
+    assert not run(2)
+
+
+def test_diffusive_tgv_decays_at_the_physical_viscosity():
+    """Two-level Taylor-Green vortex under diffusive scaling, each level
+    initialised in its own units: the energy decays at the rate the single
+    viscosity nu = (tau - 1/2)/3 (coarse units) gives, |k|^2 = 2 (2 pi/32)^2,
+    to 0.2% (measured +0.014%; a fine level with the acoustic tau, or
+    velocities not converted, moves it by several percent)."""
+    spec = W.refined_box_mesh("D2Q9", 5, 8, 24)
+    m = mesh.build(spec, gfc_layers=4)
+    sim = solver.OracleSim(m, 0.8, scaling="diffusive")
+    rho, u, S = {}, {}, {}
+    for L in range(m.level0, m.lmax + 1):
+        r = 2.0 ** (L - m.level0)
+        pos = m.positions(L)[:m.lev(L).n_fluid]
+        rr, uu, SS = W.tgv_fields(pos, 32, 0.01)
+        rho[L], u[L], S[L] = 1.0 + (rr - 1.0) / (r * r), uu / r, SS / (r * r)
+    sim.init(rho, u, S)
+    sim.step(20)
+    e1 = float(sim.kinetic_energy())
+    sim.step(200)
+    e2 = float(sim.kinetic_energy())
+    rate = math.log(e1 / e2) / (2 * 200)
+    want = 2 * 0.1 * (2 * math.pi / 32) ** 2
+    assert abs(rate / want - 1) < 2e-3, rate / want
