@@ -192,6 +192,17 @@ int32_t mlbm_set_morton_policy(double level_min_fraction, int32_t block_min_dire
  * solid).  Host only. */
 int32_t mlbm_plan_set_walls(mlbm_plan* plan, const uint64_t* ids, const int32_t* dirs,
                             const double* q, int64_t n);
+/* GhostFromCoarser layers of plans created after the call (Sec. 2.2, last
+ * paragraph): 2 (default) for acoustic scaling, two fine steps per coarse
+ * step; 4 for diffusive scaling, four fine steps per coarse step.  Distances
+ * 1 .. layers-1 from fine fluid form the inner part (MLBM_INFO_N_GFC_INNER),
+ * distance `layers` the outer layer.  Process-wide; not to be called while
+ * another thread creates a plan.  MLBM_E_ARG for other values.  A plan with
+ * 4 layers can be analysed and exported; mlbm_sim_create refuses it
+ * (MLBM_E_STATE) until the diffusive schedule runs on the GPU. */
+int32_t mlbm_set_gfc_layers(int32_t layers);
+/* The GhostFromCoarser layer count the plan was built with. */
+int32_t mlbm_plan_gfc_layers(const mlbm_plan* plan, int32_t* layers);
 /* Number of levels (Lmax - L0 + 1) and L0. */
 int32_t mlbm_plan_levels(const mlbm_plan* plan, int32_t* n_levels,
                          int32_t* level0);

@@ -41,6 +41,8 @@ SIGNATURES = {
     "mlbm_plan_destroy": (None, [_p]),
     "mlbm_set_morton_policy": (_i32, [C.c_double, _i32]),
     "mlbm_plan_set_walls": (_i32, [_p, _pu64, _pi32, _pd, _i64]),
+    "mlbm_set_gfc_layers": (_i32, [_i32]),
+    "mlbm_plan_gfc_layers": (_i32, [_p, _pi32]),
     "mlbm_plan_levels": (_i32, [_p, _pi32, _pi32]),
     "mlbm_plan_level_info": (_i32, [_p, _i32, _pi64]),
     "mlbm_plan_export": (_i32, [_p, _i32, _i32, _p, _psz]),

@@ -12,6 +12,12 @@ _STENCILS = {"D2Q9": _lib.D2Q9, "D3Q19": _lib.D3Q19, "D3Q27": _lib.D3Q27}
 _PRECISIONS = {"f64": _lib.F64, "f32": _lib.F32, "f16s": _lib.F16S}
 
 
+def set_gfc_layers(layers: int = 2):
+    """GhostFromCoarser layers of plans created afterwards: 2 (acoustic
+    scaling) or 4 (diffusive scaling; such plans have no GPU schedule yet)."""
+    check(lib().mlbm_set_gfc_layers(int(layers)))
+
+
 def lattice(stencil: str):
     """(c (q, d) int, w (q,) float64) of the library's velocity set."""
     s = _STENCILS[stencil]
@@ -58,6 +64,9 @@ class Plan:
         l0 = C.c_int32()
         check(lib().mlbm_plan_levels(self._h, C.byref(n), C.byref(l0)))
         self.n_levels, self.level0 = n.value, l0.value
+        g = C.c_int32()
+        check(lib().mlbm_plan_gfc_layers(self._h, C.byref(g)))
+        self.gfc_layers = g.value
         self._read_info()
 
     def _read_info(self):

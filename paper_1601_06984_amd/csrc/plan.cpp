@@ -245,6 +245,7 @@ struct PhaseTimer {
 // Morton-direction policy for plans created from now on.
 double g_morton_level_min = NBR_LEVEL_MIN_MORTON;
 int g_morton_block_min = NBR_MIN_MORTON;
+int g_gfc_layers = 2;
 
 // Marks the (block, direction) pairs whose sources follow from Morton
 // arithmetic: every element of the block has Morton code x + kself, and
@@ -538,10 +539,12 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
   T.mark("refined");
   // ---- ghost classification -------------------------------------------
   // GhostFromFiner(L): refined cells within L-infinity distance 1 of level-L
-  // fluid.  The fluid cells they touch are the ring whose children are the
-  // only candidates for GhostFromCoarser(L+1): a level-(L+1) position within
-  // distance 2 of level-(L+1) fluid has its parent within distance 1 of a
-  // refined level-L cell.
+  // fluid.  The fluid cells within distance R = ceil(layers/2) of a refined
+  // cell are the ring whose children are the only candidates for
+  // GhostFromCoarser(L+1): a level-(L+1) position within distance `layers`
+  // of level-(L+1) fluid has its parent within distance R of a refined
+  // level-L cell.
+  const int layers = P.gfc_layers, ring_r = (layers + 1) / 2;
   for (int k = 0; k < nlev; ++k) {
     const int L = L0 + k;
     auto& w = W[k];
@@ -552,13 +555,13 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
     for (int64_t r = 0; r < nr; ++r) {
       const int64_t* x = &w.refined[r * d];
       bool touches = false;
-      for_offsets(d, 1, [&](const int64_t* o, int) {
+      for_offsets(d, ring_r, [&](const int64_t* o, int dist) {
         int64_t y[3];
         for (int a = 0; a < d; ++a) y[a] = x[a] + o[a];
         if (g.wrap(y, L)) return;
         const int32_t v = m.get(y);
         if (v >= 0) {
-          touches = true;
+          if (dist == 1) touches = true;
           if (!ring_mark[v]) {
             ring_mark[v] = 1;
             for (int a = 0; a < d; ++a) w.ring.push_back(y[a]);
@@ -582,16 +585,16 @@ void build_plan(mlbm_plan& P, const uint64_t* leaf_ids, int64_t n_leaves,
         int64_t y[3];
         for (int a = 0; a < d; ++a) y[a] = 2 * ring[r * d + a] + ((c >> a) & 1);
         if (m.get(y) != V_EMPTY) continue;
-        int best = 3;
-        for_offsets(d, 2, [&](const int64_t* o, int dist) {
+        int best = layers + 1;
+        for_offsets(d, layers, [&](const int64_t* o, int dist) {
           if (dist >= best) return;
           int64_t z[3];
           for (int a = 0; a < d; ++a) z[a] = y[a] + o[a];
           if (g.wrap(z, L)) return;
           if (m.get(z) >= 0) best = dist;
         });
-        if (best <= 2) {
-          m.set(y, best == 1 ? V_GFC_IN : V_GFC_OUT);
+        if (best <= layers) {
+          m.set(y, best < layers ? V_GFC_IN : V_GFC_OUT);
           for (int a = 0; a < d; ++a) w.gfc.push_back(y[a]);
         }
       }
@@ -1082,6 +1085,18 @@ int32_t mlbm_set_morton_policy(double level_min_fraction, int32_t block_min_dire
   return MLBM_OK;
 }
 
+int32_t mlbm_set_gfc_layers(int32_t layers) {
+  if (layers != 2 && layers != 4) return fail(MLBM_E_ARG, "GhostFromCoarser layers must be 2 or 4");
+  g_gfc_layers = layers;
+  return MLBM_OK;
+}
+
+int32_t mlbm_plan_gfc_layers(const mlbm_plan* plan, int32_t* layers) {
+  if (!plan || !layers) return fail(MLBM_E_ARG, "NULL argument");
+  *layers = plan->gfc_layers;
+  return MLBM_OK;
+}
+
 int32_t mlbm_plan_create(int32_t stencil, int32_t level0, const int32_t* box_origin,
                          const int32_t* box_extent, const int32_t* face_bc,
                          const uint64_t* leaf_ids, int64_t n_leaves,
@@ -1116,6 +1131,7 @@ int32_t mlbm_plan_create(int32_t stencil, int32_t level0, const int32_t* box_ori
       P->extent[a] = box_extent[a];
     }
     for (int f = 0; f < 2 * d; ++f) P->faces[f] = face_bc[f];
+    P->gfc_layers = g_gfc_layers;
     build_plan(*P, leaf_ids, n_leaves, solid_ids, n_solids);
   } catch (const MeshError& e) {
     return fail(MLBM_E_MESH, "%s", e.what());

@@ -84,6 +84,7 @@ struct LevelPlan {
 
 struct mlbm_plan {
   int stencil = 0, d = 0, q = 0, level0 = 0;
+  int gfc_layers = 2;   // GhostFromCoarser layers: 2 acoustic, 4 diffusive scaling
   int32_t origin[3] = {0, 0, 0}, extent[3] = {1, 1, 1};
   int32_t faces[6] = {0, 0, 0, 0, 0, 0};
   std::vector<mlbm::LevelPlan> lv;

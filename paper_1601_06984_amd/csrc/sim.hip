@@ -259,6 +259,9 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
   if (!(tau0 > 0.5)) return fail(MLBM_E_ARG, "tau0 must exceed 1/2");
   if (!(rho0 > 0.0)) return fail(MLBM_E_ARG, "rho0 must be positive");
   if (((uintptr_t)workspace) & 255) return fail(MLBM_E_ARG, "workspace must be 256-byte aligned");
+  if (plan->gfc_layers != 2)
+    return fail(MLBM_E_STATE, "plans with four GhostFromCoarser layers (diffusive scaling) "
+                              "have no GPU schedule yet");
   // the stream-collide addresses a pair of pdf rows (and a neighbour row)
   // through one buffer descriptor with 32-bit byte offsets
   const size_t pdf_bytes = precision == MLBM_F64 ? 8 : precision == MLBM_F32 ? 4 : 2;

@@ -63,8 +63,33 @@ def test_plan_tables_bit_exact(name):
     treeIDs.  Layout rule: [fluid | GFC inner | GFC outer | GFF] with the
     fluid part split into [not an interpolation source | source], each part
     ascending by treeID; the ghost parts coincide with the oracle's."""
-    spec = MESHES[name]()
-    om = omesh.build(spec)
+    _check_tables(MESHES[name](), 2)
+
+
+@pytest.mark.parametrize("spec_fn", [lambda: W.refined_box_mesh("D2Q9", 5, 8, 24),
+                                     lambda: W.refined_box_mesh("D3Q19", 4, 4, 12),
+                                     lambda: W.refined_box_mesh("D2Q9", 6, 12, 44,
+                                                                extra_levels=[(32, 56)])])
+def test_plan_tables_bit_exact_four_layers(spec_fn):
+    """Diffusive-scaling plans (four GhostFromCoarser layers; distances 1-3
+    inner, 4 outer) against the oracle's four-layer mesh, and simulations
+    refuse them until the GPU schedule exists."""
+    M.set_gfc_layers(4)
+    try:
+        plan = _check_tables(spec_fn(), 4)
+    finally:
+        M.set_gfc_layers(2)
+    assert plan.gfc_layers == 4
+    out = ctypes.c_void_p()
+    code = M.lib().mlbm_sim_create(plan.handle, _lib.F32, 0.8, 1.0, None, None, None,
+                                   ctypes.c_void_p(1 << 20), 1 << 20, ctypes.byref(out))
+    assert code == _lib.E_STATE and not out.value
+    with pytest.raises(M.MLBMError):
+        M.set_gfc_layers(3)
+
+
+def _check_tables(spec, layers):
+    om = omesh.build(spec, gfc_layers=layers)
     plan = M.Plan.from_spec(spec)
     assert plan.n_levels == len(om.levels) and plan.level0 == om.level0
     perm = _dir_perm(spec.stencil, om.lattice)
@@ -108,6 +133,7 @@ def test_plan_tables_bit_exact(name):
             xs = np.where(ot.nbr[perm[i], :ot.n_fluid] == omesh.BOUNCE)[0]
             ob.update((int(x), i) for x in xs)
         assert got == ob
+    return plan
 
 
 COMPRESS_MESHES = dict(MESHES)
