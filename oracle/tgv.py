@@ -49,16 +49,18 @@ def l2_error(sim_vals, ana_vals) -> float:
 
 
 def errors(sim, n0: int, u0: float, nu0: float):
-    """(eps_u, eps_Sxx) of an OracleSim at its current time; S is converted
-    to coarsest-level units (S_L * 2^(L-L0))."""
+    """(eps_u, eps_Sxx) of an OracleSim at its current time, in coarsest-level
+    units: u_L times (dx_L/dt_L)/(dx_L0/dt_L0) (1 under acoustic scaling,
+    2^(L-L0) under diffusive), S_L times dt_L0/dt_L (2^(L-L0) acoustic,
+    4^(L-L0) diffusive)."""
     us, ua, ss, sa = [], [], [], []
     for L in range(sim.L0, sim.Lmax + 1):
         t = sim.mesh.lev(L)
         pos = sim.mesh.positions(L)[:t.n_fluid]
         rho, u, S = sim.fluid_moments(L)
         u_a, _, sxx_a = analytic(pos, n0, u0, nu0, float(sim.time))
-        us.append(u.detach().numpy()[0])
+        us.append(u.detach().numpy()[0] * sim.unit_ratio(L))
         ua.append(u_a[:, 0])
-        ss.append(S.detach().numpy()[0, 0] * 2.0 ** (L - sim.L0))
+        ss.append(S.detach().numpy()[0, 0] * float(sim.n_sub) ** (L - sim.L0))
         sa.append(sxx_a)
     return l2_error(us, ua), l2_error(ss, sa)

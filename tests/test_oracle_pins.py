@@ -696,3 +696,33 @@ def test_diffusive_tgv_decays_at_the_physical_viscosity():
     rate = math.log(e1 / e2) / (2 * 200)
     want = 2 * 0.1 * (2 * math.pi / 32) ** 2
     assert abs(rate / want - 1) < 2e-3, rate / want
+
+
+def test_diffusive_tgv_second_order_convergence_half_refined():
+    """Sec. 4.1 convergence study as the paper runs it, under diffusive
+    scaling (left half level L, right half L+1, four fine steps per coarse
+    step, u0 ~ 1/N and tau fixed, errors at t_D in coarse units): velocity
+    and strain rate converge at second order."""
+    eu, es = [], []
+    for lev in (4, 5, 6):
+        n0 = 1 << lev
+        u0 = 0.02 * 8 / n0
+        m = mesh.build(W.half_refined_2d(lev), gfc_layers=4)
+        sim = solver.OracleSim(m, 0.8, scaling="diffusive")
+        rho, u, S = {}, {}, {}
+        for L in range(m.level0, m.lmax + 1):
+            r = 2.0 ** (L - m.level0)
+            pos = m.positions(L)[:m.lev(L).n_fluid]
+            rr, uu, SS = W.tgv_fields(pos, n0, u0)
+            rho[L], u[L], S[L] = 1.0 + (rr - 1.0) / (r * r), uu / r, SS / (r * r)
+        sim.init(rho, u, S)
+        nu0 = tgv.nu_from_tau(0.8)
+        sim.step(int(round(tgv.decay_time(n0, nu0))))
+        a, b = tgv.errors(sim, n0, u0, nu0)
+        eu.append(a)
+        es.append(b)
+    su = [math.log2(eu[i] / eu[i + 1]) for i in range(2)]
+    ss = [math.log2(es[i] / es[i + 1]) for i in range(2)]
+    print("diffusive slopes u", su, "S", ss, "errors", eu, es)
+    assert all(1.8 < s < 2.4 for s in su), su
+    assert all(1.8 < s < 2.4 for s in ss), ss
