@@ -586,6 +586,102 @@ def test_fluid_at_rest_stays_at_rest_with_curved_walls():
     assert sim.force().abs().max() < 1e-13
 
 
+# ------------------------------- momentum-exchange force (Sec. 2.3) --------
+def _channel_fields(pos, width, height, d):
+    """A smooth, non-symmetric state of a channel: density bump, shear along
+    the walls and flow towards them (every force component is non-zero)."""
+    x = 2 * math.pi * pos[:, 0] / width
+    z = math.pi * pos[:, d - 1] / height
+    rho = 1.0 + 0.01 * np.sin(x) * np.cos(z) + 0.004 * np.cos(2 * z)
+    u = np.zeros((len(pos), d))
+    u[:, 0] = 0.03 * np.sin(z) + 0.01 * np.cos(x)
+    u[:, d - 1] = 0.02 * np.sin(x) * np.sin(2 * z) + 0.005
+    if d == 3:
+        u[:, 1] = 0.01 * np.cos(x + z)
+    return rho, u, np.zeros((len(pos), d, d))
+
+
+def _fluid_momentum(sim):
+    L = sim.L0
+    nf = sim.mesh.lev(L).n_fluid
+    return sim.lat.c.astype(np.float64).T @ sim.f[L][:, :nf].numpy().sum(1)
+
+
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
+@pytest.mark.parametrize("walls", ["halfway", "q<1/2 and q>1/2", "random q"])
+def test_force_is_the_momentum_the_walls_remove(stencil, walls):
+    """Sec. 2.3 momentum exchange, pinned by momentum balance.  BGK conserves
+    each element's momentum and periodic streaming only moves it, so in a
+    periodic channel the fluid momentum changes over one step exactly by what
+    the wall links take out (c_i f*_i(x) leaving along i) and put back (the
+    returning f_opp(i)(x, t+1)): P(t+1) - P(t) = -F(t).  A dropped returning
+    term, a wrong factor, sign or direction, or an interpolation rule whose
+    value is not the one streamed, all break the balance."""
+    d = 2 if stencil == "D2Q9" else 3
+    width, h = (16, 12) if d == 2 else (6, 10)
+    spec = W.plane_channel_mesh(stencil, 5, width, h)
+    m = mesh.build(spec)
+    wl = None
+    if walls != "halfway":
+        ids, dirs, q = W.plane_wall_links(spec, m.lattice.c, 0.3, 0.8)
+        if walls == "random q":
+            q = np.random.default_rng(7).uniform(0.0, 1.0, len(q))
+        wl = (ids, dirs, q)
+    sim = solver.OracleSim(m, 0.7, walls=wl)
+    pos = m.positions(5)[:m.lev(5).n_fluid]
+    r, u, S = _channel_fields(pos, width, h, d)
+    sim.init({5: r}, {5: u}, {5: S})
+    for _ in range(6):
+        F = sim.force().numpy()
+        P0 = _fluid_momentum(sim)
+        sim.step(1)
+        P1 = _fluid_momentum(sim)
+        assert np.abs(F).min() > 1e-6          # every component is exercised
+        assert np.abs((P1 - P0) + F).max() < 1e-13, (P1 - P0, F)
+
+
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
+def test_force_level_scaling_closed_form(stencil):
+    """Sec. 2.3 force on a two-level channel, the lower wall on the coarse
+    level and the upper wall on the fine level (the fine band spans the
+    periodic directions, so no ghost touches a wall).  For an equilibrium
+    state with velocity u along the walls and density rho(y), halfway
+    bounce-back returns f*_i = f^eq_i, and summing 2 c_i f^eq_i over the
+    directions into a wall gives, per wall cell, -rho/3 (lower) or +rho/3
+    (upper) normal to the wall and rho u_x/3 along it, on every one of the
+    three lattices.  Each level's sum is in its own lattice units; a force
+    scales as dx^(d-1) when dx/dt is level invariant, so in finest-level
+    units a coarse wall cell counts 2^(d-1) times:
+        F_y = (sum_upper rho - 2^(d-1) sum_lower rho) / 3
+        F_x = u_x (sum_upper rho + 2^(d-1) sum_lower rho) / 3."""
+    d = 2 if stencil == "D2Q9" else 3
+    w, h, L0 = (8, 8, 3) if d == 2 else (4, 8, 3)
+    spec = W.two_level_channel_mesh(stencil, L0, w, h)
+    m = mesh.build(spec)
+    ux = 0.03
+    sim = solver.OracleSim(m, 0.7)
+    rho, u, S = {}, {}, {}
+    wall_rho = {}
+    for L in (L0, L0 + 1):
+        nf = m.lev(L).n_fluid
+        pos = m.positions(L)[:nf]
+        rho[L] = 1.0 + 0.02 * pos[:, 1] / h + 0.01 * np.sin(2 * math.pi * pos[:, 0] / w)
+        u[L] = np.zeros((nf, d))
+        u[L][:, 0] = ux
+        S[L] = np.zeros((nf, d, d))
+        dy = 0.5 / 2 ** (L - L0)                   # half a cell of level L
+        wall_rho[L] = (rho[L][pos[:, 1] < dy + 1e-9].sum(), rho[L][pos[:, 1] > h - dy - 1e-9].sum())
+    sim.init(rho, u, S)
+    lower = wall_rho[L0][0] * 2 ** (d - 1)
+    upper = wall_rho[L0 + 1][1]
+    assert wall_rho[L0][1] == 0 and wall_rho[L0 + 1][0] == 0   # one wall per level
+    want = np.zeros(d)
+    want[0] = ux * (upper + lower) / 3.0
+    want[1] = (upper - lower) / 3.0
+    got = sim.force().numpy()
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max(), (got, want)
+
+
 # ------------------------------------- diffusive scaling (Sec. 2.2, end) ----
 # dt_(L+1) = dt_L / 4, dx_(L+1) = dx_L / 2: four fine steps per coarse step,
 # four GhostFromCoarser layers, the same tau on every level; lattice velocity
@@ -699,10 +795,12 @@ def test_diffusive_tgv_decays_at_the_physical_viscosity():
 
 
 def test_diffusive_tgv_second_order_convergence_half_refined():
-    """Sec. 4.1 convergence study as the paper runs it, under diffusive
-    scaling (left half level L, right half L+1, four fine steps per coarse
-    step, u0 ~ 1/N and tau fixed, errors at t_D in coarse units): velocity
-    and strain rate converge at second order."""
+    """The mesh of the Sec. 4.1 convergence study (left half level L, right
+    half L+1), run under this project's diffusive-scaling variant between
+    levels (four fine steps per coarse step; Sec. 2.2 applies acoustic
+    scaling and names diffusive scaling only as a possible extension), with
+    u0 ~ 1/N and tau fixed and errors at t_D in coarse units: velocity and
+    strain rate converge at second order."""
     eu, es = [], []
     for lev in (4, 5, 6):
         n0 = 1 << lev

@@ -15,7 +15,8 @@ produce inputs; each consumer has its own decoder.
 """
 from .meshes import (MeshSpec, partition_example, refined_box_mesh,
                      half_refined_2d, sphere_channel_mesh, uniform_box_mesh,
-                     plane_channel_mesh, plane_wall_links, sphere_wall_links)
+                     plane_channel_mesh, plane_wall_links, sphere_wall_links,
+                     two_level_channel_mesh)
 from .fields import (tgv_fields, tgv_perturbed_fields, fourier_perturbation,
                      uniform_fields, shear_wave_fields)
 
@@ -24,5 +25,5 @@ __all__ = [
     "sphere_channel_mesh", "uniform_box_mesh", "tgv_fields",
     "tgv_perturbed_fields", "fourier_perturbation", "uniform_fields",
     "plane_channel_mesh", "plane_wall_links", "sphere_wall_links",
-    "shear_wave_fields",
+    "shear_wave_fields", "two_level_channel_mesh",
 ]

@@ -270,6 +270,21 @@ def plane_channel_mesh(stencil: str, level0: int, width: int, height: int) -> Me
                        meta={"height": height, "level": level0})
 
 
+def two_level_channel_mesh(stencil: str, level0: int, width: int, height: int) -> MeshSpec:
+    """Two-level channel: periodic along x (and z in 3D, ``width`` cells
+    each), wall faces (halfway bounce-back) at y = 0 and y = ``height``; the
+    upper half y >= height/2 is refined once across the whole periodic
+    extent, so the lower wall touches level0 and the upper wall level0+1,
+    and the level interface runs parallel to the walls."""
+    d = 2 if stencil == "D2Q9" else 3
+    ext = (width, height) + ((width,) if d == 3 else ())
+    faces = ("periodic", "periodic", "wall", "wall") + (("periodic",) * 2 if d == 3 else ())
+    lo = (0, height // 2) + ((0,) if d == 3 else ())
+    hi = ext
+    return nested_mesh(f"channel2_{stencil}_{width}x{height}", stencil, level0, ext,
+                       [(lo, hi)], faces, meta={"height": height, "width": width})
+
+
 def plane_wall_links(spec: MeshSpec, c: np.ndarray, q_low: float, q_high: float):
     """Links of a ``plane_channel_mesh`` into its solid rows; the lower wall
     cuts every link at fraction q_low, the upper at q_high (planar walls at
