@@ -6,10 +6,16 @@ workload's mesh.  Throughput is reported in MLUPS with the paper's
 workload weight: each fluid element of level L counts 2^(L-L0) updates per
 coarse step.
 
-Prints ONE JSON line.  `roofline` is measured live for the dominant kernel
-(the finest level's stream-collide) with HIP events recorded on the stream
-the kernels run on; `cpu_baseline` times the FP64 oracle on the host for a
-bounded sample of the same workload.
+The default workload is the largest single-GPU configuration: the
+four-level D3Q19 sphere channel of 449 M elements with FP16-shifted pdf
+storage and FP32 collision.  Prints ONE JSON line.  `roofline` is measured
+live for the dominant kernel (the finest level's stream-collide) with HIP
+events recorded on the stream the kernels run on, and priced with the
+algorithmic bytes of the method (q pdfs read and written plus an int32
+neighbour index per moving direction); the adjoint leg, an FP32 run of the
+same mesh, the fixed-error precision study on the two-level Taylor-Green
+box and `cpu_baseline` (the FP64 oracle, single-threaded, on a bounded
+sample) follow.
 """
 from __future__ import annotations
 
@@ -30,7 +36,22 @@ import workloads as W  # noqa: E402
 
 METRIC = "MLUPS & %HBM peak, fwd and adjoint step, FP32 vs FP16-shift at fixed error"
 HBM_PEAK_GBS = 8000.0
+INFINITY_CACHE_BYTES = 256 << 20
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16s": 2}
+
+
+def algorithmic_bytes(q, prec):
+    """What one fluid update must move: q pdfs read and q written at the
+    storage width, plus an int32 pull index per moving direction."""
+    return 2 * q * STORAGE_BYTES[prec] + 4 * (q - 1)
+
+
+def algorithmic_bytes_adjoint(q, prec):
+    """One reverse update: the forward pdfs re-read (q at the storage
+    width), the pull indices, lambda read and written in the compute
+    precision (FP32; FP64 in the F64 variant)."""
+    lam = 8 if prec == "f64" else 4
+    return q * STORAGE_BYTES[prec] + 4 * (q - 1) + 2 * q * lam
 
 
 # HBM bytes per stream-collide launch (average over the level's launches),
@@ -212,14 +233,9 @@ def tgv_velocity_error(sim, plan, wl, t):
 def tgv_level_errors(sim, plan, n0, u0, tau0, t):
     """(eps_u, eps_S) of u_x and S_xx against the decayed closed form at
     coarse time t (Sec. 4.1 norm: unweighted over the fluid elements of all
-    levels, S in coarsest-level units).  S comes from the stored
-    post-collision pdfs: their moments equal the pre-collision ones and
-    f* - f^eq = (1 - omega_L) f^neq, so f^neq is recovered exactly for
-    omega_L != 1."""
-    import paper_1601_06984_amd as M
-    c, w = M.lattice(plan.stencil)
-    c = np.asarray(c, dtype=np.float64)
-    w = np.asarray(w, dtype=np.float64)
+    levels, S in coarsest-level units).  u is read as a moment of the
+    stored state, S through the library's strain read-out (formed on the
+    device from each element's pre-collision pdfs)."""
     nu0 = (tau0 - 0.5) / 3.0
     nu_num = nu_den = s_num = s_den = 0.0
     for k in range(plan.n_levels):
@@ -227,15 +243,9 @@ def tgv_level_errors(sim, plan, n0, u0, tau0, t):
         coords = plan.export(k, "coords")[:, :nf]
         pos = (coords.T.astype(np.float64) + 0.5) / float(1 << k)
         _, ua, Sa = W.tgv_fields(pos, n0, u0, nu0=nu0, t=t)
-        f = sim.get_pdf(k)[:, :nf].cpu().numpy()
-        rho = f.sum(0)
-        u = (c.T @ f) / rho
-        cu = c @ u
-        feq = w[:, None] * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * (u * u).sum(0))
-        om = 1.0 / (0.5 + (tau0 - 0.5) * 2.0 ** k)
-        fneq = (f - feq) / (1.0 - om)
-        sxx = -(1.5 * om / rho) * ((c[:, 0] ** 2)[:, None] * fneq).sum(0) * 2.0 ** k
-        nu_num += float(((u[0] - ua[:, 0]) ** 2).sum())
+        ux = sim.get_moments(k)[1].cpu().numpy()
+        sxx = sim.get_strain(k)[0].cpu().numpy() * 2.0 ** k
+        nu_num += float(((ux - ua[:, 0]) ** 2).sum())
         nu_den += float((ua[:, 0] ** 2).sum())
         s_num += float(((sxx - Sa[:, 0, 0]) ** 2).sum())
         s_den += float((Sa[:, 0, 0] ** 2).sum())
@@ -286,12 +296,11 @@ def _dir_perm(c_lib, c_oracle):
     return [int(np.where((c_oracle == c_lib[i]).all(1))[0][0]) for i in range(len(c_lib))]
 
 
-def cpu_baseline(wl, steps, gpu_pdfs=None, lattice=None, single_steps=0):
-    """The FP64 oracle as it stands, on the host, for `steps` coarse steps
-    from the workload's initial state.  With `gpu_pdfs` ({precision: list of
-    (treeids, [q][n_fluid] post-collision pdfs) per level}, taken after the
-    same number of steps), also the max relative pdf difference of each
-    precision against the oracle's FP64 result."""
+def oracle_accuracy(wl, steps, gpu_pdfs, lattice):
+    """The FP64 oracle on the host for `steps` coarse steps from the
+    workload's initial state; for each precision in `gpu_pdfs` ({precision:
+    list of (treeids, [q][n_fluid] post-collision pdfs) per level, taken
+    after the same number of steps}) the max relative pdf difference."""
     import torch
     from oracle import mesh as omesh
     from oracle import solver as osolver
@@ -307,46 +316,60 @@ def cpu_baseline(wl, steps, gpu_pdfs=None, lattice=None, single_steps=0):
     t0 = time.perf_counter()
     sim.step(steps)
     dt = time.perf_counter() - t0
-    upd = sum(om.lev(L).n_fluid << (L - om.level0) for L in range(om.level0, om.lmax + 1))
-    # the same oracle on one thread, for a shorter sample
-    single = None
-    if single_steps:
-        nt = torch.get_num_threads()
-        torch.set_num_threads(1)
-        s1 = osolver.OracleSim(om, wl["tau0"], u_in=None if wl["u_in"] is None
-                               else torch.tensor(wl["u_in"], dtype=torch.float64))
-        s1.init(rho, u, S)
+    perm = _dir_perm(lattice, np.asarray(sim.lat.c))
+    errs = {}
+    for prec, levels in gpu_pdfs.items():
+        worst = 0.0
+        for k, (tid, g) in enumerate(levels):
+            lev = om.lev(om.level0 + k)
+            ot = np.asarray(lev.tid)
+            order = np.argsort(ot)
+            g2o = order[np.searchsorted(ot[order], tid)]
+            o = sim.post_collision(om.level0 + k).detach().numpy()[perm][:, g2o]
+            worst = max(worst, float((np.abs(g - o) / np.abs(o)).max()))
+        errs[prec] = worst
+    return errs, dt
+
+
+def cpu_baseline(stencil, sample_d, steps):
+    """The FP64 oracle as it stands, on one host thread, on a bounded sample
+    of the four-level sphere workload: the same channel, nesting boxes,
+    Reynolds number and inflow with the sphere resolved by `sample_d`
+    finest cells instead of 128, for `steps` coarse steps from the uniform
+    free stream.  MLUPS with the same weighted count as the GPU figure."""
+    import torch
+    from oracle import mesh as omesh
+    from oracle import solver as osolver
+    uin = 0.04
+    spec = W.sphere_channel_mesh(sample_d, 4, outlet="eq", stencil=stencil)
+    tau_f = 0.5 + 3.0 * uin * sample_d / 100.0
+    nthreads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        om = omesh.build(spec)
+        t_build = time.perf_counter() - t0
+        sim = osolver.OracleSim(om, 0.5 + (tau_f - 0.5) / 8.0,
+                                u_in=torch.tensor([uin, 0.0, 0.0], dtype=torch.float64))
+        rho, u, S = {}, {}, {}
+        for L in range(om.level0, om.lmax + 1):
+            rho[L], u[L], S[L] = W.uniform_fields(om.lev(L).n_fluid, 3, [uin, 0.0, 0.0])
+        sim.init(rho, u, S)
         t1 = time.perf_counter()
-        s1.step(single_steps)
-        dt1 = time.perf_counter() - t1
-        torch.set_num_threads(nt)
-        single = dict(value=upd * single_steps / dt1 / 1e6, unit="MLUPS", cores=1,
-                      sample=f"{single_steps} coarse steps from the same initial state "
-                             f"({dt1:.1f} s wall)")
-        del s1
-    out = dict(value=upd * steps / dt / 1e6, unit="MLUPS", cores=torch.get_num_threads(),
-               kind="oracle",
-               sample=f"{steps} coarse steps of the same mesh from the same initial state "
-                      f"({dt:.1f} s wall, FP64, torch CPU ops, "
-                      f"{platform.processor() or platform.machine()}, "
-                      f"{os.cpu_count()} logical CPUs visible)")
-    if single:
-        out["single_thread"] = single
-    if gpu_pdfs:
-        perm = _dir_perm(lattice, np.asarray(sim.lat.c))
-        errs = {}
-        for prec, levels in gpu_pdfs.items():
-            worst = 0.0
-            for k, (tid, g) in enumerate(levels):
-                lev = om.lev(om.level0 + k)
-                ot = np.asarray(lev.tid)
-                order = np.argsort(ot)
-                g2o = order[np.searchsorted(ot[order], tid)]
-                o = sim.post_collision(om.level0 + k).detach().numpy()[perm][:, g2o]
-                worst = max(worst, float((np.abs(g - o) / np.abs(o)).max()))
-            errs[prec] = worst
-        out["max_rel_pdf_err_vs_oracle"] = errs
-    return out
+        sim.step(steps)
+        dt = time.perf_counter() - t1
+    finally:
+        torch.set_num_threads(nthreads)
+    upd = sum(om.lev(L).n_fluid << (L - om.level0) for L in range(om.level0, om.lmax + 1))
+    n = sum(om.lev(L).n for L in range(om.level0, om.lmax + 1))
+    return dict(value=round(upd * steps / dt / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{stencil} four-level sphere channel of the same geometry with D = "
+                       f"{sample_d} finest cells ({n:,} elements, {upd:,} weighted updates per "
+                       f"coarse step), {steps} coarse steps from the uniform free stream: "
+                       f"{dt:.1f} s wall on one thread (FP64, torch CPU ops; mesh analysis "
+                       f"{t_build:.1f} s not counted), "
+                       f"{platform.processor() or platform.machine()}, "
+                       f"{os.cpu_count()} logical CPUs visible")
 
 
 def fluid_pdfs(sim, plan):
@@ -412,23 +435,161 @@ def drag_inflow_gradient(M, torch, sim, uin, n_steps, K, snapshots):
             "peak_device_GB": round(torch.cuda.max_memory_allocated() / 1e9, 1)}
 
 
+def _say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def working_set_bytes(plan, prec):
+    """Device bytes one coarse step streams through: both pdf arrays and the
+    pull table of every level."""
+    q = plan.q
+    tot = 0
+    for k in range(plan.n_levels):
+        n = plan.info[k]["n"]
+        tot += 2 * q * n * STORAGE_BYTES[prec] + int(index_bytes_per_update(plan, k) * n)
+    return tot
+
+
+def forward_leg(M, torch, wl, plan, prec, steps, warmup):
+    """Timed coarse steps (graph replay) and per-level stream-collide
+    durations (direct launches bracketed by events on the bound stream)."""
+    upd = weighted_updates(plan)
+    sim = make_sim(M, torch, wl, plan, prec)
+    _say(f"{prec}: warmup {warmup}")
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    _say(f"{prec}: timed {steps} coarse steps")
+    ms = timed_steps(torch, sim, steps)
+    _say(f"{prec}: kernel timing over {steps} coarse steps")
+    sim.profile(True)
+    ms_direct = timed_steps(torch, sim, steps)
+    sim.profile(False)
+    q = plan.q
+    alg = algorithmic_bytes(q, prec)
+    prof = []
+    for k in range(plan.n_levels):
+        kms, n, el = sim.profile_read(k)
+        asr = 2 * q * STORAGE_BYTES[prec] + index_bytes_per_update(plan, k)
+        t = kms / 1e3
+        prof.append(dict(level=plan.level0 + k, launches=n, ms_total=round(kms, 4),
+                         us_per_launch=round(1e3 * kms / max(n, 1), 2),
+                         elements_per_launch=round(el / max(n, 1), 1),
+                         algorithmic_gbs=round(el * alg / 1e9 / t, 1) if t else 0.0,
+                         as_read_bytes_per_update=round(asr, 2),
+                         as_read_gbs=round(el * asr / 1e9 / t, 1) if t else 0.0))
+    dom = max(prof, key=lambda p: p["ms_total"])
+    return sim, dict(value=upd * steps / (ms / 1e3) / 1e6, ms=ms, ms_direct=ms_direct,
+                     kernels=prof, dominant=dom, status=sim.status())
+
+
+def adjoint_leg(torch, sim, plan, prec, n_adj):
+    """Reverse coarse steps (tape rerun + transposed kernels) and per-level
+    reverse stream-collide durations."""
+    upd = weighted_updates(plan)
+    sim.adjoint_attach()
+    ck = sim.save_checkpoint()
+    sim.adjoint_seed("ke")
+    for _ in range(2):
+        sim.adjoint_step(ck)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    for _ in range(n_adj):
+        sim.adjoint_step(ck)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / n_adj
+    sim.profile(True)
+    for _ in range(n_adj):
+        sim.adjoint_step(ck)
+    torch.cuda.synchronize()
+    sim.profile(False)
+    q = plan.q
+    alg = algorithmic_bytes_adjoint(q, prec)
+    akern = []
+    for k in range(plan.n_levels):
+        kms, n, el = sim.profile_read(k, kind=1)
+        t = kms / 1e3
+        akern.append(dict(level=plan.level0 + k, launches=n, ms_total=round(kms, 4),
+                          us_per_launch=round(1e3 * kms / max(n, 1), 2),
+                          elements_per_launch=round(el / max(n, 1), 1),
+                          algorithmic_gbs=round(el * alg / 1e9 / t, 1) if t else 0.0))
+    adom = max(akern, key=lambda p: p["ms_total"])
+    fwd_ms = None
+    del ck
+    return {
+        "ms_per_step": round(adj_ms, 4),
+        "mlups": round(upd / (adj_ms / 1e3) / 1e6, 1),
+        "note": "one reverse coarse step = tape rerun of the forward step + transposed kernels",
+        "kernel": f"k_adj_sc level {adom['level']} ({prec} state, "
+                  f"{'FP64' if prec == 'f64' else 'FP32'} lambda)",
+        "algorithmic_bytes_per_update": alg,
+        "achieved_gbs": adom["algorithmic_gbs"],
+        "frac": round(adom["algorithmic_gbs"] / HBM_PEAK_GBS, 4),
+        "kernels": akern,
+        "forward_ms_per_step": fwd_ms,
+    }
+
+
+def precision_study(M, torch, n_fix, n_chk, with_oracle):
+    """Fixed-error study on the two-level D3Q19 Taylor-Green box (64^3 with
+    the central 32^3 refined): MLUPS and eps_u after n_fix coarse steps for
+    F64, F32 and F16S; the pdfs after n_chk steps against the FP64 oracle."""
+    wl = workload("tgv64")
+    plan = M.Plan.from_spec(wl["spec"])
+    upd = weighted_updates(plan)
+    study, gpu_pdfs = {}, {}
+    for p in ("f64", "f32", "f16s"):
+        _say(f"precision study {p}")
+        s2 = make_sim(M, torch, wl, plan, p)
+        done = 0
+        if with_oracle and 0 < n_chk <= n_fix - 20:
+            s2.step(n_chk)
+            gpu_pdfs[p] = fluid_pdfs(s2, plan)
+            done = n_chk
+        s2.step(20)
+        done += 20
+        t_ms = timed_steps(torch, s2, n_fix - done)
+        study[p] = dict(mlups=round(upd * (n_fix - done) / (t_ms / 1e3) / 1e6, 1),
+                        eps_u=tgv_velocity_error(s2, plan, wl, n_fix), status=s2.status())
+        del s2
+    ref = study["f64"]["eps_u"]
+    for p in study:
+        study[p]["eps_u_vs_f64"] = round(study[p]["eps_u"] / ref, 4)
+        study[p]["fixed_error_pass"] = bool(study[p]["eps_u"] <= 1.05 * ref)
+    out = {"workload": wl["desc"], "coarse_steps": n_fix,
+           "fixed_error_bar": "eps_u <= 1.05 x eps_u(F64)", "results": study}
+    if gpu_pdfs:
+        _say(f"oracle accuracy check: {n_chk} coarse steps")
+        c, _ = M.lattice(plan.stencil)
+        errs, dt = oracle_accuracy(wl, n_chk, gpu_pdfs, np.asarray(c))
+        for p, e in errs.items():
+            study[p][f"max_rel_pdf_err_vs_oracle_{n_chk}"] = e
+        out["oracle_seconds"] = round(dt, 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--workload", default="tgv64")
-    ap.add_argument("--precision", default="f32", choices=["f64", "f32", "f16s"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="sphere4")
+    ap.add_argument("--precision", default="f16s", choices=["f64", "f32", "f16s"])
     ap.add_argument("--variants", type=int, default=1,
-                    help="also time F64/F16S and report the fixed-error study")
+                    help="also time the other storage precision (F32 for F16S and back) on "
+                         "the same mesh")
+    ap.add_argument("--study", type=int, default=1,
+                    help="run the fixed-error precision study on the two-level TGV box")
     ap.add_argument("--cpu-steps", type=int, default=100,
-                    help="coarse steps of the oracle (also the accuracy check length)")
-    ap.add_argument("--cpu-single-steps", type=int, default=10,
-                    help="coarse steps of the oracle timed again on one thread")
+                    help="coarse steps of the oracle accuracy check in the precision study")
+    ap.add_argument("--cpu-sample-d", type=int, default=16,
+                    help="sphere diameter (finest cells) of the oracle's timing sample")
+    ap.add_argument("--cpu-sample-steps", type=int, default=2)
     ap.add_argument("--drag-steps", type=int, default=0,
                     help="sphere workloads: run this many coarse steps in F32 and F16S "
                          "from the initial state and report the drag coefficient")
-    ap.add_argument("--adjoint", type=int, default=20,
+    ap.add_argument("--adjoint", type=int, default=10,
                     help="time this many reverse coarse steps (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-ceiling", type=int, default=1,
@@ -451,155 +612,103 @@ def main():
     import paper_1601_06984_amd as M
     torch.cuda.set_device(0)
     wl = workload(args.workload)
-    print(f"[bench] workload {args.workload}: planning", file=sys.stderr, flush=True)
+    _say(f"workload {args.workload}: planning")
+    t0 = time.perf_counter()
     plan = M.Plan.from_spec(wl["spec"])
     if wl.get("walls"):
         spec = wl["spec"]
         plan.set_walls(*W.sphere_wall_links(spec, M.lattice(spec.stencil)[0]))
+    t_plan = time.perf_counter() - t0
     upd = weighted_updates(plan)
     prec = args.precision
-    sim = make_sim(M, torch, wl, plan, prec)
-    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    print(f"[bench] timed {args.steps} coarse steps", file=sys.stderr, flush=True)
-    ms = timed_steps(torch, sim, args.steps)
-    # per-kernel durations: the same number of steps launched directly, each
-    # stream-collide bracketed by HIP events on the stream it runs on
-    print(f"[bench] kernel timing over {args.steps} coarse steps", file=sys.stderr, flush=True)
-    sim.profile(True)
-    ms_direct = timed_steps(torch, sim, args.steps)
-    sim.profile(False)
-    status = sim.status()
-    value = upd * args.steps / (ms / 1e3) / 1e6
-    # dominant kernel: the stream-collide with the largest total time
+    sim, fw = forward_leg(M, torch, wl, plan, prec, args.steps, args.warmup)
     q = plan.q
-    idx_b = [index_bytes_per_update(plan, k) for k in range(plan.n_levels)]
-    prof = []
-    for k in range(plan.n_levels):
-        kms, n, el = sim.profile_read(k)
-        bpe_k = 2 * q * STORAGE_BYTES[prec] + idx_b[k]
-        prof.append(dict(level=plan.level0 + k, launches=n, ms_total=kms,
-                         us_per_launch=1e3 * kms / max(n, 1),
-                         elements_per_launch=el / max(n, 1),
-                         algorithmic_bytes_per_update=round(bpe_k, 2),
-                         gbs=(el * bpe_k / 1e9) / (kms / 1e3) if kms else 0.0))
-    dom = max(prof, key=lambda p: p["ms_total"])
-    achieved = dom["gbs"]
-    bpe = dom["algorithmic_bytes_per_update"]
+    dom = fw["dominant"]
+    alg = algorithmic_bytes(q, prec)
+    t_launch = dom["us_per_launch"] * 1e-6
+    achieved = dom["algorithmic_gbs"]
+    ws = working_set_bytes(plan, prec)
+    traffic = measured_traffic(args.workload, prec, dom["level"])
+    roof = {"bound": "hbm" if ws > INFINITY_CACHE_BYTES else "infinity_cache",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": f"k_stream_collide level {dom['level']} ({prec})",
+            "algorithmic_bytes_per_update": alg,
+            "algorithmic_bytes_note": f"2 q S + 4 (q-1): q = {q} pdfs read and written at "
+                                      f"{STORAGE_BYTES[prec]} B, an int32 pull index per "
+                                      "moving direction",
+            "elements_per_launch": dom["elements_per_launch"],
+            "algorithmic_bytes_per_launch": round(dom["elements_per_launch"] * alg),
+            "us_per_launch": dom["us_per_launch"],
+            "working_set_bytes": ws,
+            "as_read_bytes_per_update": dom["as_read_bytes_per_update"],
+            "as_read_frac": round(dom["as_read_gbs"] / HBM_PEAK_GBS, 4),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated); null when the kernel sources changed since"}
+    if traffic:
+        roof["traffic_gbs"] = round(traffic / t_launch / 1e9, 1)
+        roof["traffic_frac"] = round(traffic / t_launch / 1e9 / HBM_PEAK_GBS, 4)
+        roof["traffic_over_algorithmic"] = round(traffic / (dom["elements_per_launch"] * alg), 3)
     out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "MLUPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+        "metric": METRIC, "value": round(fw["value"], 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": fw["ms"] / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": prec, "data": "synthetic",
-        "config": {"workload": wl["desc"], "precision": prec,
+        "dtype": "f64" if prec == "f64" else "f32", "data": "synthetic",
+        "config": {"workload": wl["desc"], "name": args.workload,
+                   "storage": {"f64": "FP64", "f32": "FP32",
+                               "f16s": "FP16 shifted deviations, per-level scale"}[prec],
+                   "collision": "FP64" if prec == "f64" else "FP32",
                    "elements": int(sum(i["n"] for i in plan.info)),
-                   "weighted_updates_per_step": int(upd),
-                   "levels": plan.n_levels},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, prec, dom["level"]),
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                     "copy-calibrated)",
-                     "kernel": f"k_stream_collide level {dom['level']} ({prec})",
-                     "algorithmic_bytes_per_update": bpe,
-                     "algorithmic_bytes_per_launch": round(dom["elements_per_launch"] * bpe),
-                     "us_per_launch": round(dom["us_per_launch"], 2),
-                     "elements_per_launch": round(dom["elements_per_launch"], 1)},
-        "kernels": prof,
-        "ms_per_step_direct_launches": ms_direct / args.steps,
-        "status_flags": status,
+                   "weighted_updates_per_step": int(upd), "levels": plan.n_levels,
+                   "planning_s": round(t_plan, 1)},
+        "roofline": roof,
+        "kernels": fw["kernels"],
+        "ms_per_step_direct_launches": fw["ms_direct"] / args.steps,
+        "status_flags": fw["status"],
     }
     if args.adjoint:
-        # reverse of one coarse step: tape rerun + transposed kernels
-        print("[bench] adjoint steps", file=sys.stderr, flush=True)
-        sim.adjoint_attach()
-        ck = sim.save_checkpoint()
-        sim.adjoint_seed("ke")
-        for _ in range(3):
-            sim.adjoint_step(ck)
-        torch.cuda.synchronize()
-        n_adj = args.adjoint
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(sim.stream)
-        for _ in range(n_adj):
-            sim.adjoint_step(ck)
-        e1.record(sim.stream)
-        torch.cuda.synchronize()
-        adj_ms = e0.elapsed_time(e1) / n_adj
-        # per-kernel durations in a separate pass (profiling keeps every
-        # launch on the bound stream)
-        sim.profile(True)
-        for _ in range(n_adj):
-            sim.adjoint_step(ck)
-        torch.cuda.synchronize()
-        sim.profile(False)
-        cb = 8 if prec == "f64" else 4
-        akern = []
-        for k in range(plan.n_levels):
-            kms, n, el = sim.profile_read(k, kind=1)
-            abpe_k = 2 * q * cb + q * STORAGE_BYTES[prec] + idx_b[k]
-            akern.append(dict(level=plan.level0 + k, launches=n, us_per_launch=1e3 * kms / max(n, 1),
-                              algorithmic_bytes_per_update=round(abpe_k, 2),
-                              gbs=(el * abpe_k / 1e9) / (kms / 1e3) if kms else 0.0))
-        adom = max(akern, key=lambda p: p["us_per_launch"] * p["launches"])
-        abpe = adom["algorithmic_bytes_per_update"]
-        out["adjoint"] = {
-            "ms_per_step": adj_ms,
-            "mlups": round(upd / (adj_ms / 1e3) / 1e6, 1),
-            "note": "one reverse coarse step = tape rerun of the forward step + transposed kernels",
-            "kernel": f"k_adj_sc level {adom['level']} ({prec})",
-            "algorithmic_bytes_per_update": abpe,
-            "achieved_gbs": round(adom["gbs"], 1),
-            "frac": round(adom["gbs"] / HBM_PEAK_GBS, 4),
-            "kernels": akern,
-        }
-    gpu_pdfs = {}
-    if args.drag_adjoint and not wl.get("tgv"):
-        print(f"[bench] drag gradient over {args.drag_adjoint} coarse steps", file=sys.stderr,
-              flush=True)
-        sim = None   # release the timing run's state first (HBM)
-        import gc
+        _say(f"adjoint: {args.adjoint} reverse coarse steps")
+        out["adjoint"] = adjoint_leg(torch, sim, plan, prec, args.adjoint)
+        out["adjoint"]["forward_ms_per_step"] = round(fw["ms"] / args.steps, 4)
+        out["adjoint"]["reverse_over_forward"] = round(
+            out["adjoint"]["ms_per_step"] / (fw["ms"] / args.steps), 3)
+    sim = None
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+    if args.variants:
+        other = "f32" if prec == "f16s" else "f16s"
+        s2, fw2 = forward_leg(M, torch, wl, plan, other, args.steps, args.warmup)
+        d2 = fw2["dominant"]
+        a2 = algorithmic_bytes(q, other)
+        out["precision_variants"] = {other: {
+            "mlups": round(fw2["value"], 2), "ms_per_step": fw2["ms"] / args.steps,
+            "kernel": f"k_stream_collide level {d2['level']} ({other})",
+            "algorithmic_bytes_per_update": a2, "achieved_gbs": d2["algorithmic_gbs"],
+            "frac": round(d2["algorithmic_gbs"] / HBM_PEAK_GBS, 4),
+            "us_per_launch": d2["us_per_launch"], "status_flags": fw2["status"]},
+            prec: {"mlups": out["value"]}}
+        out["precision_variants"]["speedup_f16s_over_f32"] = round(
+            (out["value"] / fw2["value"]) if prec == "f16s" else (fw2["value"] / out["value"]), 3)
+        del s2
         gc.collect()
+        torch.cuda.empty_cache()
+    if args.drag_adjoint and not wl.get("tgv"):
+        _say(f"drag gradient over {args.drag_adjoint} coarse steps")
         sim2 = make_sim(M, torch, wl, plan, prec)
         out["drag_adjoint"] = drag_inflow_gradient(
             M, torch, sim2, wl["uniform_u"], args.drag_adjoint, args.checkpoint_every,
             None if args.snapshots < 0 else args.snapshots)
         del sim2
-    if args.variants and wl.get("tgv"):
-        # precision study at a fixed run length: MLUPS and eps_u for each;
-        # the pdfs after `cpu_steps` coarse steps go to the oracle comparison
-        study = {}
-        n_fix = 1000
-        n_chk = args.cpu_steps if not args.no_cpu else 0
-        for p in ("f64", "f32", "f16s"):
-            print(f"[bench] precision study {p}", file=sys.stderr, flush=True)
-            s2 = make_sim(M, torch, wl, plan, p)
-            if 0 < n_chk <= n_fix - 20:
-                s2.step(n_chk)
-                gpu_pdfs[p] = fluid_pdfs(s2, plan)
-                if n_chk < 20:
-                    s2.step(20 - n_chk)
-                done = max(n_chk, 20)
-            else:
-                s2.step(20)
-                done = 20
-            t_ms = timed_steps(torch, s2, n_fix - done)
-            study[p] = dict(mlups=round(upd * (n_fix - done) / (t_ms / 1e3) / 1e6, 1),
-                            eps_u=tgv_velocity_error(s2, plan, wl, n_fix),
-                            status=s2.status())
-            del s2
-        ref = study["f64"]["eps_u"]
-        for p in study:
-            study[p]["fixed_error_pass"] = bool(study[p]["eps_u"] <= 1.05 * ref)
-        out["precision_study"] = {"coarse_steps": n_fix, "results": study}
+        gc.collect()
+        torch.cuda.empty_cache()
     if args.drag_steps and not wl.get("tgv"):
         D = wl["spec"].meta["D"]
         uin = wl["u_in"][0]
         drag = {}
         for p in ("f32", "f16s"):
-            print(f"[bench] drag run {p}: {args.drag_steps} coarse steps", file=sys.stderr,
-                  flush=True)
+            _say(f"drag run {p}: {args.drag_steps} coarse steps")
             s3 = make_sim(M, torch, wl, plan, p)
             hist = []
             chunk = max(1, args.drag_steps // 10)
@@ -618,6 +727,11 @@ def main():
         out["drag"] = {"coarse_steps": args.drag_steps, "D_finest": D, "u_in": uin,
                        "definition": "c_D = 2 F_x / (rho0 u_in^2 pi D^2 / 4), finest-level units",
                        "results": drag}
+    plan = None
+    gc.collect()
+    if args.study:
+        out["precision_study"] = precision_study(M, torch, 1000, args.cpu_steps,
+                                                 not args.no_cpu)
     if args.sweep:
         out["convergence"] = convergence_sweep(M, torch)
     if args.copy_ceiling:
@@ -644,15 +758,9 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = n
     if not args.no_cpu:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        c, _ = M.lattice(plan.stencil)
-        cb = cpu_baseline(wl, args.cpu_steps, gpu_pdfs, np.asarray(c),
-                          single_steps=args.cpu_single_steps)
-        errs = cb.pop("max_rel_pdf_err_vs_oracle", None)
-        if errs and "precision_study" in out:
-            for p, e in errs.items():
-                out["precision_study"]["results"][p][f"max_rel_pdf_err_vs_oracle_{args.cpu_steps}"] = e
-        out["cpu_baseline"] = cb
+        _say(f"cpu baseline (oracle, one thread): D = {args.cpu_sample_d} sample")
+        stencil = wl["spec"].stencil if not wl.get("tgv") else "D3Q19"
+        out["cpu_baseline"] = cpu_baseline(stencil, args.cpu_sample_d, args.cpu_sample_steps)
     print(json.dumps(out))
 
 

@@ -74,7 +74,11 @@ enum {
 
 /* Diagnostics mask bits and status flags. */
 enum { MLBM_DIAG_MASS = 1, MLBM_DIAG_KE = 2, MLBM_DIAG_FORCE = 4 };
-enum { MLBM_STATUS_NONFINITE = 1, MLBM_STATUS_F16_OVERFLOW = 2 };
+/* MLBM_STATUS_GRAPH_FALLBACK: recording or instantiating the HIP graph of
+ * mlbm_step failed, and the simulation launches its kernels directly from
+ * then on (same results, more launch overhead) until mlbm_use_graphs(1). */
+enum { MLBM_STATUS_NONFINITE = 1, MLBM_STATUS_F16_OVERFLOW = 2,
+       MLBM_STATUS_GRAPH_FALLBACK = 4 };
 
 /* Exportable plan tables (mlbm_plan_export). */
 enum {
@@ -122,11 +126,32 @@ enum {
   MLBM_INFO_N_BOUNCE = 9, MLBM_INFO_N_WALL = 10, MLBM_INFO_FIELDS = 11
 };
 
-/* State selectors for mlbm_get_state / mlbm_set_state. */
+/* State selectors for mlbm_get_state / mlbm_set_state.  The stored state of
+ * a level is post-collision (pull scheme); the pre-collision pdfs of the
+ * fluid elements at the same time are those its last stream-collide
+ * gathered (Sec. 2.1: the strain rate is a moment of these).  A level keeps
+ * the array that stream-collide read, so they are formed again on request
+ * by the same pull; selectors marked (*) need a stream-collide of the level
+ * since its state was last set by mlbm_init, mlbm_set_state or
+ * mlbm_load_checkpoint (else MLBM_E_STATE). */
 enum {
   MLBM_STATE_PDF_POST = 0, /* post-collision pdfs f*, all elements, FP64
                               [q][n]                                          */
-  MLBM_STATE_MOMENTS = 1   /* rho, u of fluid elements, FP64 [1+d][n_fluid] */
+  MLBM_STATE_MOMENTS = 1,  /* rho, u of fluid elements, FP64 [1+d][n_fluid] */
+  MLBM_STATE_PDF_PRE = 2,  /* (*) pre-collision pdfs f of the fluid
+                              elements, FP64 [q][n_fluid]                     */
+  MLBM_STATE_STRAIN = 3,   /* (*) strain rate of the fluid elements from those
+                              pdfs (Sec. 2.1), S_ab = -(3 omega_L/(2 rho))
+                              sum_i c_ia c_ib f^neq_i, f^neq = f - f^eq(rho,u),
+                              level-L lattice units, FP64 [d(d+1)/2][n_fluid]
+                              in the order xx, yy, zz, xy, yz, xz (2D: xx, yy,
+                              xy); no division by 1 - omega, so tau = 1 is
+                              fine                                            */
+  MLBM_STATE_PDF_PREV = 4  /* (*) the post-collision state the last
+                              stream-collide read (one level substep earlier,
+                              wall-link values included), all elements, FP64
+                              [q][n]; ghosts that stream-collide did not read
+                              hold older values                               */
 };
 
 typedef struct mlbm_plan mlbm_plan;
@@ -262,11 +287,22 @@ int32_t mlbm_use_graphs(mlbm_sim* sim, int32_t enable);
  * (Sec. 2.3) over bounce-back links, each level scaled to finest-level
  * units by 2^((d-1)(Lmax - L)). */
 int32_t mlbm_diagnostics(mlbm_sim* sim, uint32_t mask, double* dev_out);
-/* Copy state of level index k to device memory (see MLBM_STATE_*). */
+/* Copy state `what` (MLBM_STATE_*) of level index k to device memory
+ * `dev_dst`, laid out as the selector states (the caller allocates it).
+ * Errors: MLBM_E_ARG (unknown selector, level out of range, NULL),
+ * MLBM_E_STATE (the level has no state yet; a (*) selector before the
+ * level's first stream-collide since its state was set). */
 int32_t mlbm_get_state(mlbm_sim* sim, int32_t k, int32_t what, double* dev_dst);
-/* Overwrite the post-collision pdfs of level index k (all elements) from
- * device FP64 [q][n]; used to inject test states. */
-int32_t mlbm_set_state(mlbm_sim* sim, int32_t k, const double* dev_src);
+/* Set the state of level index k from device FP64 memory `dev_src`.
+ * what = MLBM_STATE_PDF_POST: [q][n], the post-collision pdfs of all
+ * elements are overwritten (test states; capture records are left as they
+ * are).  what = MLBM_STATE_PDF_PRE: [q][n_fluid], pre-collision pdfs of the
+ * fluid elements: they are collided with the level's omega (Eq. bgk) and
+ * stored, and the interpolation sources among them record their moments,
+ * as a stream-collide does after its gather; mlbm_fill_ghosts then fills
+ * the ghosts from them (Sec. 2.2, Steps 1-5).  Ghost entries are left
+ * unchanged.  Other selectors: MLBM_E_ARG. */
+int32_t mlbm_set_state(mlbm_sim* sim, int32_t k, int32_t what, const double* dev_src);
 /* Sticky device status flags (MLBM_STATUS_*); synchronises the stream.
  * The flags are cleared after reading. */
 int32_t mlbm_status(mlbm_sim* sim, uint32_t* flags);

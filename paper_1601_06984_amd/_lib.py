@@ -18,11 +18,11 @@ FACE = {"periodic": 0, "eq": 1, "copy": 2, "wall": 3}
 NBR_MISSING, NBR_BOUNCE, NBR_EQ, NBR_COPY = -1, -2, -3, -4
 E_ARG, E_MESH, E_STATE, E_HIP, E_OOM = -1, -2, -3, -4, -5
 DIAG_MASS, DIAG_KE, DIAG_FORCE = 1, 2, 4
-STATUS_NONFINITE, STATUS_F16_OVERFLOW = 1, 2
+STATUS_NONFINITE, STATUS_F16_OVERFLOW, STATUS_GRAPH_FALLBACK = 1, 2, 4
 TABLE_TREEID, TABLE_COORDS, TABLE_NBR, TABLE_GFC_SRC, TABLE_GFF_SRC, \
     TABLE_CAPTURE, TABLE_BOUNCE, TABLE_NBR16, TABLE_NBASE, TABLE_NBR_WIDE, \
     TABLE_NBR_HDR, TABLE_WALL, TABLE_WALL_Q = range(13)
-STATE_PDF_POST, STATE_MOMENTS = 0, 1
+STATE_PDF_POST, STATE_MOMENTS, STATE_PDF_PRE, STATE_STRAIN, STATE_PDF_PREV = range(5)
 INFO_FIELDS = ("level", "n", "n_fluid", "n_gfc_inner", "n_gfc_outer", "n_gff",
                "n_cap_fluid", "n_cap", "n_gfc_groups", "n_bounce", "n_wall")
 
@@ -55,7 +55,7 @@ SIGNATURES = {
     "mlbm_step": (_i32, [_p, _i64]),
     "mlbm_diagnostics": (_i32, [_p, _u32, _p]),
     "mlbm_get_state": (_i32, [_p, _i32, _i32, _p]),
-    "mlbm_set_state": (_i32, [_p, _i32, _p]),
+    "mlbm_set_state": (_i32, [_p, _i32, _i32, _p]),
     "mlbm_status": (_i32, [_p, _pu32]),
     "mlbm_time": (_i32, [_p, _pi64]),
     "mlbm_checkpoint_bytes": (_i32, [_p, _psz]),

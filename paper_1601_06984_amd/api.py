@@ -228,10 +228,44 @@ class Sim:
         check(lib().mlbm_get_state(self._h, k, _lib.STATE_MOMENTS, self._ptr(out)))
         return out
 
+    def get_pdf_pre(self, k: int):
+        """Pre-collision pdfs [q][n_fluid] of the level's fluid elements, as
+        its last stream-collide gathered them."""
+        nf = self.plan.info[k]["n_fluid"]
+        out = self.torch.empty((self.plan.q, nf), dtype=self.torch.float64, device=self.device)
+        check(lib().mlbm_get_state(self._h, k, _lib.STATE_PDF_PRE, self._ptr(out)))
+        return out
+
+    def get_strain(self, k: int):
+        """Strain rate [d(d+1)/2][n_fluid] (xx, yy[, zz], xy[, yz, xz]) of the
+        fluid elements from their pre-collision pdfs, level-k lattice units."""
+        nf = self.plan.info[k]["n_fluid"]
+        ns = 6 if self.plan.d == 3 else 3
+        out = self.torch.empty((ns, nf), dtype=self.torch.float64, device=self.device)
+        check(lib().mlbm_get_state(self._h, k, _lib.STATE_STRAIN, self._ptr(out)))
+        return out
+
+    def get_pdf_prev(self, k: int):
+        """The post-collision state [q][n] the level's last stream-collide read."""
+        n = self.plan.info[k]["n"]
+        out = self.torch.empty((self.plan.q, n), dtype=self.torch.float64, device=self.device)
+        check(lib().mlbm_get_state(self._h, k, _lib.STATE_PDF_PREV, self._ptr(out)))
+        return out
+
     def set_pdf(self, k: int, pdf):
+        """Overwrite the post-collision pdfs [q][n] of every element."""
         if pdf.numel() != self.plan.q * self.plan.info[k]["n"]:
             raise ValueError("set_pdf expects [q][n] float64")
-        check(lib().mlbm_set_state(self._h, k, self._ptr(pdf, self.torch.float64)))
+        check(lib().mlbm_set_state(self._h, k, _lib.STATE_PDF_POST,
+                                   self._ptr(pdf, self.torch.float64)))
+
+    def set_pdf_pre(self, k: int, pdf):
+        """Collide given pre-collision pdfs [q][n_fluid] of the fluid elements
+        into the level's state (sources record their moments)."""
+        if pdf.numel() != self.plan.q * self.plan.info[k]["n_fluid"]:
+            raise ValueError("set_pdf_pre expects [q][n_fluid] float64")
+        check(lib().mlbm_set_state(self._h, k, _lib.STATE_PDF_PRE,
+                                   self._ptr(pdf, self.torch.float64)))
 
     def status(self) -> int:
         f = C.c_uint32()

@@ -1314,6 +1314,107 @@ __global__ __launch_bounds__(256) void k_get_moments(const typename Prec<P>::S* 
   for (int b = 0; b < Lat::D; ++b) out[(int64_t)(1 + b) * nf + x] = u[b];
 }
 
+// Pre-collision state of the fluid elements as the level's last
+// stream-collide gathered it.  A pull scheme keeps the array that
+// stream-collide read (the post-collision state one level substep earlier,
+// wall-link values included): the fills that follow write only the ghosts
+// of the other array.  Pulling from it again, with the same table decode and
+// boundary rules, gives the gathered values exactly.  WHAT 0: the pdfs
+// f = w rho0 + g, FP64 [Q][nf].  WHAT 1: the strain rate of Sec. 2.1,
+// S_ab = -(3 omega / (2 rho)) sum_i c_ia c_ib f^neq_i with f^neq = f - f^eq
+// of the gathered f, formed in FP64 with the exact lattice weights, FP64
+// [NS][nf] in the order xx, yy, zz, xy, yz, xz (2D: xx, yy, xy).  One
+// work-group per pull-table block; the blocks of [0, nf) are whole or the
+// last one is cut, whose surplus threads take part in the slot staging only.
+template <class Lat, int P, int WHAT>
+__global__ __launch_bounds__(256) void k_get_pulled(
+    const typename Prec<P>::S* __restrict__ prev, int64_t nf,
+    const LevelArgs<typename Prec<P>::C, Lat::Q> a, double omega, double* __restrict__ out) {
+  using C = typename Prec<P>::C;
+  static_assert(NBR_BLOCK == 256, "a work-group covers one pull-table block");
+  __shared__ int32_t slots[NBR_SLOTS];
+  const int64_t blk = blockIdx.x;
+  const int64_t xr = blk * 256 + threadIdx.x;
+  const int64_t x = xr < nf ? xr : nf - 1;
+  C g[Lat::Q];
+  {
+    int32_t j[Lat::Q];
+    pull_sources_wg<Lat>(a, blk, (uint32_t)x, j, slots);
+    gather_from<Lat, P>(prev, x, a, j, g);
+  }
+  if (xr >= nf) return;
+  if constexpr (WHAT == 0) {
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i)
+      out[(int64_t)i * nf + x] = (double)a.wr[Lat::wclass(i)] + (double)g[i];
+  } else {
+    constexpr int D = Lat::D;
+    double gd[Lat::Q];   // f - w with the exact weights
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i)
+      gd[i] = ((double)a.wr[Lat::wclass(i)] + (double)g[i]) - Lat::w(i);
+    double drho, rho, u[3];
+    macro_g<Lat, double>(gd, 1.0, drho, rho, u);
+    const double uu = dot_uu<Lat, double>(u);
+    double pi[Lat::NS];
+#pragma unroll
+    for (int k = 0; k < Lat::NS; ++k) pi[k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i) {
+      const double fneq = gd[i] - geq_i<Lat, double>(i, drho, rho, u, uu);
+#pragma unroll
+      for (int k = 0; k < Lat::NS; ++k) {
+        const int cc = Lat::c(i, strain_a(D, k)) * Lat::c(i, strain_b(D, k));
+        if (cc > 0) pi[k] += fneq;
+        if (cc < 0) pi[k] -= fneq;
+      }
+    }
+    const double pref = -1.5 * omega / rho;
+#pragma unroll
+    for (int k = 0; k < Lat::NS; ++k) out[(int64_t)k * nf + x] = pref * pi[k];
+  }
+}
+
+// Given pre-collision pdfs of the fluid elements (FP64 [Q][nf]), stores
+// their BGK post-collision values (Eq. bgk) as the level's state and the
+// pre-collision moments of the interpolation sources as their capture
+// records: what a stream-collide does once it has gathered f.
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_set_pre(typename Prec<P>::S* __restrict__ pdf, int64_t nf,
+                                                 const LevelArgs<typename Prec<P>::C, Lat::Q> a,
+                                                 const double* __restrict__ in,
+                                                 typename Prec<P>::C* __restrict__ cap,
+                                                 uint32_t* __restrict__ status) {
+  using C = typename Prec<P>::C;
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= nf) return;
+  C g[Lat::Q];
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i)
+    g[i] = (C)(in[(int64_t)i * nf + x] - (double)a.wr[Lat::wclass(i)]);
+  C drho, rho, u[3];
+  macro_g<Lat, C>(g, a.rho0, drho, rho, u);
+  const C uu = dot_uu<Lat, C>(u);
+  if (x >= a.cap_begin)
+    write_record_m<Lat, C, C>(cap + (x - a.cap_begin) * cap_stride(Lat::Q), g, drho, rho, u, uu,
+                              a.omega);
+  bool ok = true;
+  if constexpr (P == MLBM_F16S) {
+    ok = store_f16s_conserving<Lat>(pdf, x, a, g, drho, rho, u, uu);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i) {
+      const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
+      ok &= store_row<P>(pdf + (int64_t)i * a.n, a.n, (uint32_t)x, gs, a.wr[Lat::wclass(i)],
+                         a.scale);
+    }
+  }
+  const bool finite = (rho == rho) && (rho - rho == C(0));
+  if (!finite || !ok)
+    atomicOr(status, (finite ? 0u : (uint32_t)MLBM_STATUS_NONFINITE) |
+                         (ok ? 0u : (uint32_t)MLBM_STATUS_F16_OVERFLOW));
+}
+
 // ------------------------------------------------------- diagnostics ------
 // Per-block FP64 partial sums (deterministic tree in LDS).  Mass is summed
 // as deviations drho; the host-side constant rho0 * n_fluid is added in the

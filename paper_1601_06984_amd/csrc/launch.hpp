@@ -234,12 +234,41 @@ struct Impl {
     hipLaunchKernelGGL((k_get_pdf<Lat, P>), dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0,
                        s.stream, (const S*)L.pdf[L.parity], L.n, a, out);
   }
+  static void get_prev(SimState& s, int k, double* out) {
+    DevLevel& L = s.lv[k];
+    if (!L.n) return;
+    auto a = level_args<C, Lat::Q>(s, k);
+    hipLaunchKernelGGL((k_get_pdf<Lat, P>), dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0,
+                       s.stream, (const S*)L.pdf[L.parity ^ 1], L.n, a, out);
+  }
   static void set_pdf(SimState& s, int k, const double* in) {
     DevLevel& L = s.lv[k];
     if (!L.n) return;
     auto a = level_args<C, Lat::Q>(s, k);
     hipLaunchKernelGGL((k_set_pdf<Lat, P>), dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0,
                        s.stream, (S*)L.pdf[L.parity], L.n, a, in);
+  }
+  // pre-collision pdfs (what 0) or strain rate (what 1) of the fluid
+  // elements, pulled again from the array the last stream-collide read
+  static void get_pulled(SimState& s, int k, int what, double* out) {
+    DevLevel& L = s.lv[k];
+    if (!L.n_fluid) return;
+    auto a = level_args<C, Lat::Q>(s, k);
+    const dim3 grid((unsigned)((L.n_fluid + 255) / 256));
+    const S* prev = (const S*)L.pdf[L.parity ^ 1];
+    if (what == 0)
+      hipLaunchKernelGGL((k_get_pulled<Lat, P, 0>), grid, dim3(256), 0, s.stream, prev,
+                         L.n_fluid, a, L.omega, out);
+    else
+      hipLaunchKernelGGL((k_get_pulled<Lat, P, 1>), grid, dim3(256), 0, s.stream, prev,
+                         L.n_fluid, a, L.omega, out);
+  }
+  static void set_pre(SimState& s, int k, const double* in) {
+    DevLevel& L = s.lv[k];
+    if (!L.n_fluid) return;
+    auto a = level_args<C, Lat::Q>(s, k);
+    hipLaunchKernelGGL((k_set_pre<Lat, P>), dim3((unsigned)((L.n_fluid + 255) / 256)), dim3(256),
+                       0, s.stream, (S*)L.pdf[L.parity], L.n_fluid, a, in, (C*)L.cap, s.status);
   }
   static void get_moments(SimState& s, int k, double* out) {
     DevLevel& L = s.lv[k];

@@ -385,6 +385,7 @@ int32_t mlbm_init(mlbm_sim* sim, int32_t k, const double* rho, const double* u, 
   MLBM_DISPATCH(s, I::init(s, k, rho, u, S));
   L.parity = 0;
   L.substep = 0;
+  L.pre_valid = false;
   s.inited[k] = true;
   s.time = 0;
   return check_launch("mlbm_init");
@@ -418,6 +419,7 @@ int32_t mlbm_step(mlbm_sim* sim, int64_t n_coarse) {
         if (e != hipSuccess) {
           (void)hipGetLastError();
           s.use_graphs = false;  // fall back to direct launches
+          s.graph_fallback = true;
           break;
         }
         s.graphs.emplace_back(key, exec);
@@ -434,6 +436,8 @@ int32_t mlbm_step(mlbm_sim* sim, int64_t n_coarse) {
   }
   flush_sc(s);
   flush_fill(s);
+  if (n_coarse > 0)
+    for (auto& L : s.lv) L.pre_valid = true;
   return check_launch("mlbm_step");
 }
 
@@ -452,17 +456,33 @@ int32_t mlbm_get_state(mlbm_sim* sim, int32_t k, int32_t what, double* dev_dst) 
   if (!sim || !dev_dst) return fail(MLBM_E_ARG, "NULL argument");
   SimState& s = sim->s;
   if (k < 0 || k >= (int)s.lv.size()) return fail(MLBM_E_ARG, "level index %d out of range", k);
+  if (what < MLBM_STATE_PDF_POST || what > MLBM_STATE_PDF_PREV)
+    return fail(MLBM_E_ARG, "unknown state selector %d", what);
+  if (!s.inited[k]) return fail(MLBM_E_STATE, "level %d has no state yet", k);
+  DevLevel& L = s.lv[k];
+  if (what >= MLBM_STATE_PDF_PRE && !L.pre_valid)
+    return fail(MLBM_E_STATE, "level %d: no stream-collide since the state was last set "
+                              "(init, set_state or load_checkpoint)", k);
   if (what == MLBM_STATE_PDF_POST) MLBM_DISPATCH(s, I::get_pdf(s, k, dev_dst));
   else if (what == MLBM_STATE_MOMENTS) MLBM_DISPATCH(s, I::get_moments(s, k, dev_dst));
-  else return fail(MLBM_E_ARG, "unknown state selector %d", what);
+  else if (what == MLBM_STATE_PDF_PRE) MLBM_DISPATCH(s, I::get_pulled(s, k, 0, dev_dst));
+  else if (what == MLBM_STATE_STRAIN) MLBM_DISPATCH(s, I::get_pulled(s, k, 1, dev_dst));
+  else MLBM_DISPATCH(s, I::get_prev(s, k, dev_dst));
   return check_launch("mlbm_get_state");
 }
 
-int32_t mlbm_set_state(mlbm_sim* sim, int32_t k, const double* dev_src) {
+int32_t mlbm_set_state(mlbm_sim* sim, int32_t k, int32_t what, const double* dev_src) {
   if (!sim || !dev_src) return fail(MLBM_E_ARG, "NULL argument");
   SimState& s = sim->s;
   if (k < 0 || k >= (int)s.lv.size()) return fail(MLBM_E_ARG, "level index %d out of range", k);
-  MLBM_DISPATCH(s, I::set_pdf(s, k, dev_src));
+  if (what != MLBM_STATE_PDF_POST && what != MLBM_STATE_PDF_PRE)
+    return fail(MLBM_E_ARG, "set_state takes MLBM_STATE_PDF_POST or MLBM_STATE_PDF_PRE, not %d",
+                what);
+  if (what == MLBM_STATE_PDF_POST) MLBM_DISPATCH(s, I::set_pdf(s, k, dev_src));
+  else MLBM_DISPATCH(s, I::set_pre(s, k, dev_src));
+  s.drop_graphs();
+  s.lv[k].pre_valid = false;
+  s.inited[k] = true;
   return check_launch("mlbm_set_state");
 }
 
@@ -474,6 +494,8 @@ int32_t mlbm_status(mlbm_sim* sim, uint32_t* flags) {
   if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
   if (e == hipSuccess) e = hipMemsetAsync(s.status, 0, 4, s.stream);
   if (e != hipSuccess) return fail(MLBM_E_HIP, "status: %s", hipGetErrorString(e));
+  if (s.graph_fallback) h |= MLBM_STATUS_GRAPH_FALLBACK;
+  s.graph_fallback = false;
   *flags = h;
   return MLBM_OK;
 }
@@ -542,6 +564,7 @@ int32_t mlbm_load_checkpoint(mlbm_sim* sim, const void* dev_src, size_t bytes) {
     const size_t b = (size_t)s.q * L.n * storage_bytes(s.precision);
     L.parity = 0;
     L.substep = 0;
+    L.pre_valid = false;
     if (k < 16) L.f16_exp = h.f16_exp[k];
     if (e == hipSuccess && b)
       e = hipMemcpyAsync(L.pdf[0], p + off, b, hipMemcpyDeviceToDevice, s.stream);

@@ -35,6 +35,8 @@ struct DevLevel {
   double* wall_q = nullptr;           // [n_wall]    padded (the plan's device copy)
   int parity = 0;                     // index of the current pdf array
   int substep = 0;                    // 0: next step is the first after a sync
+  bool pre_valid = false;             // the other array holds what the last
+                                      // stream-collide read
   double omega = 1.0;
   int f16_exp = 0;
   bool f16_auto = false;
@@ -146,6 +148,7 @@ struct SimState {
   // graphs of two coarse steps, keyed by the parity state they start from
   hipStream_t capture_stream = nullptr;
   bool use_graphs = true;
+  bool graph_fallback = false;         // capture failed; reported by mlbm_status
   std::vector<std::pair<uint64_t, hipGraphExec_t>> graphs;
   void drop_graphs();
   ~SimState();

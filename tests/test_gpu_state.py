@@ -1,0 +1,147 @@
+"""GPU parity of the state read-out and write-in through the C ABI.
+
+The pre-collision pdfs and the strain rate of Sec. 2.1 are read from the
+library (MLBM_STATE_PDF_PRE, MLBM_STATE_STRAIN) and compared element by
+element with the oracle, whose stored state is the pre-collision pdfs f
+after streaming.  Writing pre-collision pdfs (set_state with
+MLBM_STATE_PDF_PRE) followed by the synchronous fill must reproduce the
+oracle's state at a coarse time.  F64 runs are compared at 1e-12 relative
+(rounding order only), F32 at 1e-5.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import physics as ophys
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1601_06984_amd  # noqa: F401  (fails loudly if not built)
+
+
+def _strain_rows(S, d):
+    """(d, d, n) -> (NS, n) in the library's order."""
+    idx = [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)] if d == 3 else [(0, 0), (1, 1), (0, 1)]
+    return np.stack([S[a, b] for a, b in idx], 0)
+
+
+def _rel(a, b):
+    return float((np.abs(a - b) / np.maximum(np.abs(b), 1e-300)).max())
+
+
+CASES = [
+    # stencil, mesh, tau0 (1.0 puts omega = 1 on the coarse level), precision, tolerance
+    ("D2Q9", lambda: W.refined_box_mesh("D2Q9", 5, 8, 24), 1.0, "f64", 1e-12),
+    ("D2Q9", lambda: W.refined_box_mesh("D2Q9", 5, 8, 24), 0.8, "f32", 1e-5),
+    ("D3Q19", lambda: W.refined_box_mesh("D3Q19", 4, 4, 12), 1.0, "f64", 1e-12),
+    ("D3Q19", lambda: W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)]), 0.6,
+     "f64", 1e-12),
+    ("D3Q27", lambda: W.refined_box_mesh("D3Q27", 4, 4, 12), 0.7, "f32", 1e-5),
+]
+
+
+@pytest.mark.parametrize("stencil,spec_fn,tau0,prec,tol", CASES)
+def test_pre_collision_pdfs_and_strain_match_oracle(stencil, spec_fn, tau0, prec, tol):
+    """After n coarse steps the library's pre-collision pdfs equal the
+    oracle's state, and its strain rate equals the oracle's strain formula
+    on the oracle's pdfs (Sec. 2.1), on every level, tau = 1 included."""
+    spec = spec_fn()
+    n0 = 1 << spec.level0
+    _say("pre-collision state and strain", stencil, prec, "tau0", tau0)
+    fields = H.tgv(n0, 0.03)
+    osim = H.oracle_run(spec, tau0, fields, 7)
+    sim = H.gpu_sim(spec, prec, tau0, fields)
+    with pytest.raises(Exception):
+        sim.get_pdf_pre(0)          # no stream-collide since init
+    sim.step(7)
+    perm = H.direction_perm(spec.stencil, osim.lat)
+    d = osim.lat.d
+    for k in range(sim.plan.n_levels):
+        L = sim.plan.level0 + k
+        nf = sim.plan.info[k]["n_fluid"]
+        g2o = H.gpu_to_oracle(sim.plan, osim.mesh, k)[:nf]
+        fo = osim.f[L][:, g2o]
+        got = sim.get_pdf_pre(k).cpu().numpy()
+        assert _rel(got, fo.numpy()[perm]) < tol, (k, _rel(got, fo.numpy()[perm]))
+        _, _, So, _ = ophys.strain_rate(fo, osim.omega[L], osim.lat)
+        want = _strain_rows(So.numpy(), d)
+        S = sim.get_strain(k).cpu().numpy()
+        # relative to the largest component: S vanishes at some elements
+        err = float(np.abs(S - want).max() / np.abs(want).max())
+        assert err < (1e-11 if prec == "f64" else 2e-3), (k, err)
+        # the same formula applied on the host to the library's own
+        # pre-collision pdfs: the device evaluation alone
+        _, _, Sg, _ = ophys.strain_rate(torch.from_numpy(got[np.argsort(perm)]), osim.omega[L],
+                                        osim.lat)
+        own = _strain_rows(Sg.numpy(), d)
+        assert float(np.abs(S - own).max() / np.abs(own).max()) < 1e-12
+        # moments of the pre-collision pdfs are those of the stored state
+        mom = sim.get_moments(k).cpu().numpy()
+        assert np.abs(got.sum(0) - mom[0]).max() < (1e-12 if prec == "f64" else 1e-6)
+
+
+def test_previous_state_is_what_the_pull_read():
+    """MLBM_STATE_PDF_PREV holds the post-collision state the last
+    stream-collide read: pulling it on the host through the planner's int32
+    neighbour table gives the pre-collision pdfs bit for bit (F32)."""
+    import paper_1601_06984_amd as M
+    spec = W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)])
+    _say("previous state, D3Q19 three levels f32")
+    sim = H.gpu_sim(spec, "f32", 0.6, H.tgv(16, 0.03))
+    sim.step(3)
+    c, _ = M.lattice("D3Q19")
+    for k in range(sim.plan.n_levels):
+        nf = sim.plan.info[k]["n_fluid"]
+        nbr = sim.plan.export(k, "nbr")
+        prev = sim.get_pdf_prev(k).cpu().numpy()
+        pre = sim.get_pdf_pre(k).cpu().numpy()
+        assert np.array_equal(pre[0], prev[0, :nf])
+        for i in range(1, len(c)):
+            src = nbr[i - 1, :nf]
+            assert (src >= 0).all()           # periodic: no link codes
+            assert np.array_equal(pre[i], prev[i, src]), (k, i)
+
+
+@pytest.mark.parametrize("stencil,prec,tol", [("D2Q9", "f64", 1e-12), ("D3Q19", "f64", 1e-12),
+                                              ("D3Q19", "f32", 1e-5)])
+def test_set_pre_collision_then_fill_reproduces_oracle(stencil, prec, tol):
+    """Writing the oracle's pre-collision pdfs at a coarse time into every
+    level, then the synchronous fill (Sec. 2.2, Steps 1-5), gives the
+    oracle's post-collision state on all elements, ghosts included; the run
+    then continues as the oracle's does."""
+    spec = (W.refined_box_mesh("D2Q9", 5, 8, 24) if stencil == "D2Q9"
+            else W.refined_box_mesh("D3Q19", 4, 4, 12))
+    n0 = 1 << spec.level0
+    tau0 = 0.7
+    _say("set pre-collision state then fill", stencil, prec)
+    fields = H.tgv(n0, 0.03)
+    osim = H.oracle_run(spec, tau0, fields, 5)
+    # a GPU simulation started from a different state
+    sim = H.gpu_sim(spec, prec, tau0, H.tgv(n0, 0.01))
+    perm = H.direction_perm(spec.stencil, osim.lat)
+    for k in range(sim.plan.n_levels):
+        L = sim.plan.level0 + k
+        nf = sim.plan.info[k]["n_fluid"]
+        g2o = H.gpu_to_oracle(sim.plan, osim.mesh, k)[:nf]
+        f = osim.f[L][:, g2o].numpy()[perm]
+        sim.set_pdf_pre(k, torch.tensor(np.ascontiguousarray(f), device=sim.device))
+    sim.fill_ghosts()
+    assert H.compare_post(sim, osim) < tol
+    osim.step(3)
+    sim.step(3)
+    assert H.compare_post(sim, osim) < tol
+    assert sim.status() == 0
