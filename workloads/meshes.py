@@ -13,6 +13,7 @@ convergence study (Sec. 4.1), and the sphere in a channel of size
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
 from typing import Callable, Optional, Sequence
 
@@ -56,14 +57,29 @@ def _level_first_id(level: int, d: int) -> int:
     return ((1 << (d * level)) - 1) // ((1 << d) - 1)
 
 
+def _dilate(v: np.ndarray, d: int) -> np.ndarray:
+    """Spread the bits of v (< 2^21 in 3D, < 2^32 in 2D) d positions apart."""
+    v = v.astype(np.uint64)
+    if d == 3:
+        steps = ((32, 0x1F00000000FFFF), (16, 0x1F0000FF0000FF), (8, 0x100F00F00F00F00F),
+                 (4, 0x10C30C30C30C30C3), (2, 0x1249249249249249))
+        v &= np.uint64(0x1FFFFF)
+    else:
+        steps = ((16, 0x0000FFFF0000FFFF), (8, 0x00FF00FF00FF00FF), (4, 0x0F0F0F0F0F0F0F0F),
+                 (2, 0x3333333333333333), (1, 0x5555555555555555))
+        v &= np.uint64(0xFFFFFFFF)
+    for sh, mask in steps:
+        v = (v | (v << np.uint64(sh))) & np.uint64(mask)
+    return v
+
+
 def _interleave(coords: np.ndarray, level: int) -> np.ndarray:
-    """Morton code of integer coords (n, d); x bit lowest."""
+    """Morton code of integer coords (n, d) below 2^level; x bit lowest."""
     n, d = coords.shape
+    assert level <= (21 if d == 3 else 32)
     out = np.zeros(n, dtype=np.uint64)
-    c = coords.astype(np.uint64)
-    for b in range(level):
-        for a in range(d):
-            out |= ((c[:, a] >> np.uint64(b)) & np.uint64(1)) << np.uint64(d * b + a)
+    for a in range(d):
+        out |= _dilate(coords[:, a], d) << np.uint64(a)
     return out
 
 
@@ -113,27 +129,35 @@ def nested_mesh(name: str, stencil: str, level0: int, extent: Sequence[int],
         regions.append((tuple(2 * v for v in lo), tuple(2 * v for v in hi)))
     # the refinement box of level k+1 is stored in level-(k+1) cells now
     lmax = level0 + len(boxes)
-    leaf_chunks, solid_chunks = [], []
-    for k, (lo, hi) in enumerate(regions):
+
+    def slab_ids(k, x0, x1):
+        lo, hi = regions[k]
         level = level0 + k
-        # enumerate the region in slabs along x to bound memory
-        for x0 in range(lo[0], hi[0], slab):
-            x1 = min(hi[0], x0 + slab)
-            cells = _box_cells((x0,) + tuple(lo[1:]), (x1,) + tuple(hi[1:]))
-            if k + 1 < len(regions):
-                flo, fhi = regions[k + 1]
-                # a cell is refined if it lies inside the next box
-                # (boxes are given on this level's grid, doubled above)
-                plo = tuple(v // 2 for v in flo)
-                phi = tuple(v // 2 for v in fhi)
-                cells = cells[~_inside(cells, plo, phi)]
-            if level == lmax and solid is not None:
-                s = solid(cells)
-                if s.any():
-                    solid_chunks.append(encode_tree_ids(level, cells[s]))
-                cells = cells[~s]
-            if len(cells):
-                leaf_chunks.append(encode_tree_ids(level, cells))
+        cells = _box_cells((x0,) + tuple(lo[1:]), (x1,) + tuple(hi[1:]))
+        if k + 1 < len(regions):
+            flo, fhi = regions[k + 1]
+            # a cell is refined if it lies inside the next box
+            # (boxes are given on this level's grid, doubled above)
+            plo = tuple(v // 2 for v in flo)
+            phi = tuple(v // 2 for v in fhi)
+            cells = cells[~_inside(cells, plo, phi)]
+        sol = None
+        if level == lmax and solid is not None:
+            s = solid(cells)
+            if s.any():
+                sol = encode_tree_ids(level, cells[s])
+            cells = cells[~s]
+        return (encode_tree_ids(level, cells) if len(cells) else None), sol
+
+    # each region is enumerated in slabs along x to bound memory; slabs are
+    # independent, so a thread pool works on them (numpy releases the GIL)
+    tasks = [(k, x0, min(hi[0], x0 + slab)) for k, (lo, hi) in enumerate(regions)
+             for x0 in range(lo[0], hi[0], slab)]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+        parts = list(ex.map(lambda t: slab_ids(*t), tasks))
+    leaf_chunks = [p[0] for p in parts if p[0] is not None]
+    solid_chunks = [p[1] for p in parts if p[1] is not None]
     leaves = np.concatenate(leaf_chunks) if leaf_chunks else np.zeros(0, np.uint64)
     solids = (np.concatenate(solid_chunks) if solid_chunks
               else np.zeros(0, np.uint64))
