@@ -287,6 +287,16 @@ int32_t mlbm_use_graphs(mlbm_sim* sim, int32_t enable);
  * (Sec. 2.3) over bounce-back links, each level scaled to finest-level
  * units by 2^((d-1)(Lmax - L)). */
 int32_t mlbm_diagnostics(mlbm_sim* sim, uint32_t mask, double* dev_out);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * reductions of mlbm_diagnostics, bit for bit, with the per-block partials
+ * in a static scratch array of the library (one per GPU, 320 KiB, held
+ * until the process ends) instead of the simulation's workspace.  At most
+ * 16 levels (MLBM_E_ARG otherwise).  All calls on one GPU share that array:
+ * calls that overlap on a GPU (different streams, or simulations on other
+ * host threads) race and give undefined results; calls ordered on one
+ * stream do not.  Allocates nothing. */
+int32_t mlbm_diagnostics_noalloc(mlbm_sim* sim, uint32_t mask, double* dev_out);
 /* Copy state `what` (MLBM_STATE_*) of level index k to device memory
  * `dev_dst`, laid out as the selector states (the caller allocates it).
  * Errors: MLBM_E_ARG (unknown selector, level out of range, NULL),

@@ -54,6 +54,7 @@ SIGNATURES = {
     "mlbm_fill_ghosts": (_i32, [_p]),
     "mlbm_step": (_i32, [_p, _i64]),
     "mlbm_diagnostics": (_i32, [_p, _u32, _p]),
+    "mlbm_diagnostics_noalloc": (_i32, [_p, _u32, _p]),
     "mlbm_get_state": (_i32, [_p, _i32, _i32, _p]),
     "mlbm_set_state": (_i32, [_p, _i32, _i32, _p]),
     "mlbm_status": (_i32, [_p, _pu32]),

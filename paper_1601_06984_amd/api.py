@@ -216,6 +216,15 @@ class Sim:
         check(lib().mlbm_diagnostics(self._h, mask, self._ptr(out, self.torch.float64)))
         return out
 
+    def diagnostics_noalloc(self, mask: int, out):
+        """As diagnostics, into the preallocated device tensor `out`, with
+        the library's static scratch (allocates nothing)."""
+        n = (1 if mask & 1 else 0) + (1 if mask & 2 else 0) + (self.plan.d if mask & 4 else 0)
+        if out.numel() < n:
+            raise ValueError("diagnostics output too small")
+        check(lib().mlbm_diagnostics_noalloc(self._h, mask, self._ptr(out, self.torch.float64)))
+        return out
+
     def get_pdf(self, k: int):
         n = self.plan.info[k]["n"]
         out = self.torch.empty((self.plan.q, n), dtype=self.torch.float64, device=self.device)

@@ -278,11 +278,14 @@ struct Impl {
                        dim3(256), 0, s.stream, (const S*)L.pdf[L.parity], L.n_fluid, a, out);
   }
   static void diag_partial(SimState& s, int k) {
+    diag_partial_to(s, k, s.partial + (int64_t)k * DIAG_BLOCKS * DIAG_VALS);
+  }
+  // level k's block partials into `partial` (DIAG_BLOCKS * DIAG_VALS doubles)
+  static void diag_partial_to(SimState& s, int k, double* partial) {
     DevLevel& L = s.lv[k];
     auto a = level_args<C, Lat::Q>(s, k);
     hipLaunchKernelGGL((k_diag_partial<Lat, P>), dim3(DIAG_BLOCKS), dim3(256), 0, s.stream,
-                       (const S*)L.pdf[L.parity], L.n_fluid, L.bounce, L.n_bounce, a,
-                       s.partial + (int64_t)k * DIAG_BLOCKS * DIAG_VALS);
+                       (const S*)L.pdf[L.parity], L.n_fluid, L.bounce, L.n_bounce, a, partial);
   }
 };
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -15,7 +16,39 @@
 
 namespace mlbm {
 
+// Scratch of mlbm_diagnostics_noalloc: the per-block FP64 partials of the
+// diagnostics reductions for up to DIAG_STATIC_LEVELS levels, in a
+// file-scope device array (one copy per GPU, held until the process ends).
+// Host code never passes the array's name to a kernel: it is a host-side
+// stand-in there.  Its device address on each GPU comes from
+// hipGetSymbolAddress, taken once per device (scratch_on_device).
+constexpr int DIAG_STATIC_LEVELS = 16;
+constexpr size_t DIAG_STATIC_DOUBLES = (size_t)DIAG_STATIC_LEVELS * DIAG_BLOCKS * DIAG_VALS;
+static __device__ __align__(256) double scratch[DIAG_STATIC_DOUBLES];
+
 namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device` (which must be current); looked up
+// on the first call per device.  Returns nullptr and sets *err on failure.
+double* scratch_on_device(int device, hipError_t* err) {
+  *err = hipSuccess;
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_ptr[device]) {
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    scratch_ptr[device] = (double*)p;
+  }
+  return scratch_ptr[device];
+}
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -273,9 +306,18 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
   const size_t need = layout_workspace(*plan, precision, nullptr, nullptr);
   if (workspace_bytes < need)
     return fail(MLBM_E_ARG, "workspace too small: need %zu bytes, got %zu", need, workspace_bytes);
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return fail(MLBM_E_HIP, "no current HIP device");
+  {
+    // the no-allocation diagnostics' scratch: its address on this device
+    hipError_t se = hipSuccess;
+    if (!scratch_on_device(device, &se))
+      return fail(MLBM_E_HIP, "scratch address on device %d: %s", device, hipGetErrorString(se));
+  }
   mlbm_sim* sim = new (std::nothrow) mlbm_sim();
   if (!sim) return fail(MLBM_E_OOM, "host allocation failed");
   SimState& s = sim->s;
+  s.device = device;
   s.stencil = plan->stencil;
   s.d = plan->d;
   s.q = plan->q;
@@ -450,6 +492,26 @@ int32_t mlbm_diagnostics(mlbm_sim* sim, uint32_t mask, double* dev_out) {
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s.stream, s.partial, (int)s.lv.size(),
                      (const DiagLevel*)s.diag_levels, mask, s.d, dev_out);
   return check_launch("mlbm_diagnostics");
+}
+
+int32_t mlbm_diagnostics_noalloc(mlbm_sim* sim, uint32_t mask, double* dev_out) {
+  if (!sim || !dev_out) return fail(MLBM_E_ARG, "NULL argument");
+  SimState& s = sim->s;
+  if (!s.filled) return fail(MLBM_E_STATE, "no state yet");
+  if (mask & ~7u) return fail(MLBM_E_ARG, "bad diagnostics mask");
+  if ((int)s.lv.size() > DIAG_STATIC_LEVELS)
+    return fail(MLBM_E_ARG, "%d levels: the static scratch holds the partials of at most %d",
+                (int)s.lv.size(), DIAG_STATIC_LEVELS);
+  hipError_t se = hipSuccess;
+  double* part = scratch_on_device(s.device, &se);
+  if (!part) return fail(MLBM_E_HIP, "scratch address: %s", hipGetErrorString(se));
+  // every partial the final pass reads is written by this call's first
+  // pass (a fixed grid of DIAG_BLOCKS work-groups per level): nothing to clear
+  for (int k = 0; k < (int)s.lv.size(); ++k)
+    MLBM_DISPATCH(s, I::diag_partial_to(s, k, part + (size_t)k * DIAG_BLOCKS * DIAG_VALS));
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s.stream, (const double*)part,
+                     (int)s.lv.size(), (const DiagLevel*)s.diag_levels, mask, s.d, dev_out);
+  return check_launch("mlbm_diagnostics_noalloc");
 }
 
 int32_t mlbm_get_state(mlbm_sim* sim, int32_t k, int32_t what, double* dev_dst) {

@@ -124,6 +124,7 @@ struct AdjState {
 
 struct SimState {
   int stencil = 0, d = 3, q = 19, precision = 0, level0 = 0;
+  int device = 0;                      // HIP device current at creation
   double tau0 = 1.0, rho0 = 1.0, u_in[3] = {0, 0, 0};
   double wr[27], geq[27];
   hipStream_t stream = nullptr;
