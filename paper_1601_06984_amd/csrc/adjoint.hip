@@ -262,7 +262,7 @@ struct Adj {
     f.lam_cap = (C*)s.adj.lv[jb.k].lam_cap;
     f.lam_old = jb.lold;
     f.part = s.adj.part + (jb.off + (tail ? jb.nb1 : 0)) * DPART;
-    total += nb;
+    total += (nb + 7) / 8 * 8;
   }
 
   // Launches reverse stream-collides of distinct levels together: zeroing

@@ -395,6 +395,10 @@ struct AdjScMulti {
   AdjScSeg<C, S, Q> seg[ADJ_MAX_SEG];
 };
 
+// Every segment starts at a multiple of 8 work-groups (on XCD 0), so its
+// work-groups map to logical blocks by the XCD-sliced order (xcd_block):
+// each XCD gathers from and scatters to one contiguous slice, whose lines
+// its own L2 holds; the few work-groups between segments exit.
 template <class Lat, int P, bool REC>
 __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc(
     const AdjScMulti<typename Prec<P>::C, typename Prec<P>::S, Lat::Q> m) {
@@ -403,8 +407,10 @@ __global__ __launch_bounds__(256, (P != MLBM_F64 && !REC) ? 4 : 1) void k_adj_sc
   int sg = 0;
   while (sg + 1 < m.nseg && (int64_t)blockIdx.x >= m.seg[sg + 1].first) ++sg;
   const auto& f = m.seg[sg];
-  adj_sc_body<Lat, P, REC>((int64_t)blockIdx.x - f.first, f.X, f.x0, f.x1, f.a, f.lam_new,
-                           f.lam_cap, f.lam_old, f.part, sm, slots);
+  const int64_t b = (int64_t)blockIdx.x - f.first;
+  if (b >= f.nb) return;
+  adj_sc_body<Lat, P, REC>(xcd_block(b, f.nb), f.X, f.x0, f.x1, f.a, f.lam_new, f.lam_cap,
+                           f.lam_old, f.part, sm, slots);
 }
 
 // COPY links, part 1 (before k_adj_sc consumes the record adjoints):
