@@ -221,10 +221,11 @@ int32_t mlbm_plan_set_walls(mlbm_plan* plan, const uint64_t* ids, const int32_t*
  * paragraph): 2 (default) for acoustic scaling, two fine steps per coarse
  * step; 4 for diffusive scaling, four fine steps per coarse step.  Distances
  * 1 .. layers-1 from fine fluid form the inner part (MLBM_INFO_N_GFC_INNER),
- * distance `layers` the outer layer.  Process-wide; not to be called while
- * another thread creates a plan.  MLBM_E_ARG for other values.  A plan with
- * 4 layers can be analysed and exported; mlbm_sim_create refuses it
- * (MLBM_E_STATE) until the diffusive schedule runs on the GPU. */
+ * distance `layers` the outer layer.  A simulation of a 4-layer plan runs
+ * the diffusive schedule (see mlbm_sim_create, mlbm_step); its adjoint and
+ * its force are not available (MLBM_E_STATE).  Process-wide; not to be
+ * called while another thread creates a plan.  MLBM_E_ARG for other
+ * values. */
 int32_t mlbm_set_gfc_layers(int32_t layers);
 /* The GhostFromCoarser layer count the plan was built with. */
 int32_t mlbm_plan_gfc_layers(const mlbm_plan* plan, int32_t* layers);
@@ -246,7 +247,10 @@ int32_t mlbm_sim_workspace_bytes(const mlbm_plan* plan, int32_t precision,
 /* Create a simulation bound to `hip_stream` (a hipStream_t, may be NULL for
  * the null stream) using the caller's device `workspace` (256-byte aligned,
  * at least mlbm_sim_workspace_bytes).  tau0 is the BGK relaxation time of
- * level L0; finer levels follow Eq. fneq_scale with m = 2.  rho0 is the
+ * level L0; finer levels follow Eq. fneq_scale with m = 2 (acoustic
+ * scaling), or all levels take tau0 for a plan with four GhostFromCoarser
+ * layers (diffusive scaling: dx halves and dt quarters per level, so
+ * nu dt / dx^2 is level invariant).  rho0 is the
  * reference density (shift of F16S storage and density of EQ faces),
  * u_in (d doubles, host, may be NULL = 0) the EQ-face velocity.  f16_exp
  * (n_levels ints, host) sets s_L = 2^f16_exp[k] for F16S; NULL picks it at
@@ -272,8 +276,11 @@ int32_t mlbm_init(mlbm_sim* sim, int32_t k, const double* rho, const double* u,
  * synchronous time. */
 int32_t mlbm_fill_ghosts(mlbm_sim* sim);
 /* Advance n coarse steps with the recursive schedule: advance(L) = one
- * stream-collide of L; if L < Lmax: advance(L+1) twice, fill
- * GhostFromFiner(L), fill GhostFromCoarser(L+1).  Asynchronous.  Pairs of
+ * stream-collide of L; if L < Lmax: advance(L+1) twice (four times under
+ * diffusive scaling), fill GhostFromFiner(L), fill GhostFromCoarser(L+1).
+ * Under diffusive scaling the fills also take velocity and density
+ * deviation between the levels' lattice units (factor 2 and 4 per level,
+ * fine to coarse).  Asynchronous.  Pairs of
  * coarse steps are replayed from an instantiated HIP graph (recorded once
  * per parity state on an internal stream, launched on the bound stream);
  * the results are identical to direct launches. */
@@ -283,9 +290,12 @@ int32_t mlbm_use_graphs(mlbm_sim* sim, int32_t enable);
 /* FP64 reductions written to device memory `dev_out` (deterministic, no
  * atomics): for each bit set in `mask` in the order MASS (1 value),
  * KE (1), FORCE (d).  MASS = sum_L V_L sum_fluid rho; KE = 1/2 sum_L V_L
- * sum_fluid rho |u|^2 with V_L = 2^(-d (L - L0)); FORCE = momentum exchange
- * (Sec. 2.3) over bounce-back links, each level scaled to finest-level
- * units by 2^((d-1)(Lmax - L)). */
+ * sum_fluid rho |u|^2 with V_L = 2^(-d (L - L0)), density deviation and
+ * velocity in level-L0 lattice units (under diffusive scaling a level-L
+ * value is taken to L0 units by 2^(L-L0), squared for the density
+ * deviation); FORCE = momentum exchange (Sec. 2.3) over bounce-back links,
+ * each level scaled to finest-level units by 2^((d-1)(Lmax - L)), acoustic
+ * scaling only (MLBM_E_STATE otherwise). */
 int32_t mlbm_diagnostics(mlbm_sim* sim, uint32_t mask, double* dev_out);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the

@@ -522,6 +522,9 @@ extern "C" {
 
 int32_t mlbm_adjoint_workspace_bytes(const mlbm_sim* sim, const mlbm_plan* plan, size_t* bytes) {
   if (!sim || !plan || !bytes) return fail(MLBM_E_ARG, "NULL argument");
+  if (sim->s.n_sub != 2)
+    return fail(MLBM_E_STATE, "the adjoint covers acoustic scaling (two fine steps per coarse "
+                              "step) only");
   const SimState& s = sim->s;
   if (!plan_matches(s, *plan)) return fail(MLBM_E_ARG, "plan does not belong to this simulation");
   OpBuilder os, oi;
@@ -535,6 +538,9 @@ int32_t mlbm_adjoint_attach(mlbm_sim* sim, const mlbm_plan* plan, void* workspac
   if (!sim || !plan || !workspace) return fail(MLBM_E_ARG, "NULL argument");
   SimState& s = sim->s;
   if (!plan_matches(s, *plan)) return fail(MLBM_E_ARG, "plan does not belong to this simulation");
+  if (s.n_sub != 2)
+    return fail(MLBM_E_STATE, "the adjoint covers acoustic scaling (two fine steps per coarse "
+                              "step) only");
   if (((uintptr_t)workspace) & 255) return fail(MLBM_E_ARG, "workspace must be 256-byte aligned");
   OpBuilder os, oi;
   step_ops(s, 0, 0, os);

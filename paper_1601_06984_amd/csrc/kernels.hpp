@@ -851,9 +851,11 @@ __device__ __forceinline__ bool emit_ghost(typename Prec<P>::S* __restrict__ pdf
 // u = mean(u_k) - 1/4 (a_xx + a_yy + a_zz) per component.
 // gff_values gives the ghost's pre-collision drho, u and g^neq (rescaled to
 // the coarse level) from the capture slots s[4] of its four fine sources.
+// Velocity and density deviation are taken to coarse lattice units by
+// `us` and `rs` (1 under acoustic scaling, where both are level invariant).
 template <class Lat, class C>
 __device__ __forceinline__ void gff_values(const int32_t* s, const C* __restrict__ cap_fine,
-                                           C fneq_scale, C& drho, C* u, C* fneq) {
+                                           C fneq_scale, C us, C rs, C& drho, C* u, C* fneq) {
   constexpr int D = Lat::D;
   RecV<Lat, C> r[4];
 #pragma unroll
@@ -895,6 +897,9 @@ __device__ __forceinline__ void gff_values(const int32_t* s, const C* __restrict
     u[0] -= C(0.25) * (axx + ayy);
     u[1] -= C(0.25) * (bxx + byy);
   }
+  drho *= rs;
+#pragma unroll
+  for (int b = 0; b < D; ++b) u[b] *= us;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
     fneq[i] = C(0.25) * (r[0].fneq(i) + r[1].fneq(i) + r[2].fneq(i) + r[3].fneq(i)) * fneq_scale;
@@ -943,13 +948,13 @@ __device__ __forceinline__ void gff_ghost(
     const int32_t* __restrict__ slots, const typename Prec<P>::C* __restrict__ cap_fine,
     typename Prec<P>::C* __restrict__ cap_coarse, int64_t cap_gff_begin,
     const LevelArgs<typename Prec<P>::C, Lat::Q>& a, typename Prec<P>::C fneq_scale,
-    uint32_t* __restrict__ status) {
+    typename Prec<P>::C us, typename Prec<P>::C rs, uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   C drho, u[3], fneq[Lat::Q];
   int32_t s[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) s[k] = slots[k * n_gff + j];
-  gff_values<Lat, C>(s, cap_fine, fneq_scale, drho, u, fneq);
+  gff_values<Lat, C>(s, cap_fine, fneq_scale, us, rs, drho, u, fneq);
   const bool ok = emit_ghost<Lat, P>(pdf, gff_begin + j, a, drho, u, fneq);
   // pre-collision record of the ghost: it is a GhostFromCoarser source
   RecordWriter<C> w{cap_coarse + (cap_gff_begin + j) * cap_stride(Lat::Q), {}};
@@ -963,11 +968,11 @@ __global__ __launch_bounds__(64) void k_fill_gff(
     const int32_t* __restrict__ slots, const typename Prec<P>::C* __restrict__ cap_fine,
     typename Prec<P>::C* __restrict__ cap_coarse, int64_t cap_gff_begin,
     const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C fneq_scale,
-    uint32_t* __restrict__ status) {
+    typename Prec<P>::C us, typename Prec<P>::C rs, uint32_t* __restrict__ status) {
   const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (j >= n_gff) return;
   gff_ghost<Lat, P>(j, pdf, gff_begin, n_gff, slots, cap_fine, cap_coarse, cap_gff_begin, a,
-                    fneq_scale, status);
+                    fneq_scale, us, rs, status);
 }
 
 // GhostFromCoarser (Sec. 2.2) of fine level, both layers.  One work-group
@@ -987,6 +992,7 @@ struct GffOnTheFly {
   const int4* tab = nullptr;
   const C* cap_fine = nullptr;
   C fneq_scale = 0, omega = 0, rho0 = 0;
+  C us = 1, rs = 1;   // fine -> coarse velocity and density-deviation units
 };
 
 template <int Q> constexpr int gfc_lds_stride() { return cap_used(Q) | 1; }  // odd: no conflicts
@@ -998,6 +1004,7 @@ __device__ __forceinline__ void gfc_groups(
     int64_t n_groups, const int32_t* __restrict__ grp_src, const int32_t* __restrict__ grp_child,
     const typename Prec<P>::C* __restrict__ cap_coarse,
     const LevelArgs<typename Prec<P>::C, Lat::Q>& a, typename Prec<P>::C fneq_scale,
+    typename Prec<P>::C us, typename Prec<P>::C rs,
     const GffOnTheFly<typename Prec<P>::C>& fly, uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D;
@@ -1023,7 +1030,7 @@ __device__ __forceinline__ void gfc_groups(
     if (slot <= -2) {
       C drho, u[3], fneq[Lat::Q];
       const int32_t fs[4] = {-2 - t.x, t.y, t.z, t.w};
-      gff_values<Lat, C>(fs, fly.cap_fine, fly.fneq_scale, drho, u, fneq);
+      gff_values<Lat, C>(fs, fly.cap_fine, fly.fneq_scale, fly.us, fly.rs, drho, u, fneq);
       RowWriter<C> w{dst};
       ghost_record<Lat, C>(w, drho, u, fneq, fly.omega, fly.rho0);
     } else if (slot >= 0) {
@@ -1094,6 +1101,10 @@ __device__ __forceinline__ void gfc_groups(
     for (int i = 0; i < Lat::Q; ++i)
       fneq[i] = (w9 * R0.fneq(i) + w3 * (Rx.fneq(i) + Ry.fneq(i)) + w1 * Rxy.fneq(i)) * fneq_scale;
   }
+  // to fine lattice units (1 under acoustic scaling)
+  drho *= rs;
+#pragma unroll
+  for (int b = 0; b < D; ++b) u[b] *= us;
   if (!emit_ghost<Lat, P>(pdf, target, a, drho, u, fneq))
     atomicOr(status, (uint32_t)MLBM_STATUS_F16_OVERFLOW);
 }
@@ -1104,12 +1115,12 @@ __global__ __launch_bounds__(64) void k_fill_gfc(
     const int32_t* __restrict__ grp_src, const int32_t* __restrict__ grp_child,
     const typename Prec<P>::C* __restrict__ cap_coarse,
     const LevelArgs<typename Prec<P>::C, Lat::Q> a, typename Prec<P>::C fneq_scale,
-    uint32_t* __restrict__ status) {
+    typename Prec<P>::C us, typename Prec<P>::C rs, uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
   constexpr int D = Lat::D;
   __shared__ C sh[gfc_groups_per_block<D>() * group_slots(D) * gfc_lds_stride<Lat::Q>()];
   gfc_groups<Lat, P>(blockIdx.x, sh, pdf, n_groups, grp_src, grp_child, cap_coarse, a, fneq_scale,
-                     GffOnTheFly<C>{}, status);
+                     us, rs, GffOnTheFly<C>{}, status);
 }
 
 // The fills of one synchronisation of levels (k, k+1), for one or several
@@ -1133,14 +1144,14 @@ struct FillSeg {
   C* cap_coarse;
   int64_t cap_gff_begin;
   LevelArgs<C, Q> ac;
-  C scale_gff;
+  C scale_gff, us_gff, rs_gff;   // g^neq rescale, velocity and density units
   S* pdf_f;
   int64_t n_groups;
   const int32_t* grp_src;
   const int4* grp_tab;
   const int32_t* grp_child;
   LevelArgs<C, Q> af;
-  C scale_gfc;
+  C scale_gfc, us_gfc, rs_gfc;
 };
 template <class C, class S, int Q>
 struct FillMulti {
@@ -1164,7 +1175,7 @@ __global__ __launch_bounds__(64) void k_fill_sync(
     const int64_t j = b * 64 + threadIdx.x;
     if (j < f.n_gff)
       gff_ghost<Lat, P>(j, f.pdf_c, f.gff_begin, f.n_gff, f.gff_slot, f.cap_fine, f.cap_coarse,
-                        f.cap_gff_begin, f.ac, f.scale_gff, status);
+                        f.cap_gff_begin, f.ac, f.scale_gff, f.us_gff, f.rs_gff, status);
     return;
   }
   GffOnTheFly<C> fly;
@@ -1173,8 +1184,10 @@ __global__ __launch_bounds__(64) void k_fill_sync(
   fly.fneq_scale = f.scale_gff;
   fly.omega = f.ac.omega;
   fly.rho0 = f.ac.rho0;
+  fly.us = f.us_gff;
+  fly.rs = f.rs_gff;
   gfc_groups<Lat, P>(b - f.nb_gff, sh, f.pdf_f, f.n_groups, f.grp_src, f.grp_child,
-                     (const C*)f.cap_coarse, f.af, f.scale_gfc, fly, status);
+                     (const C*)f.cap_coarse, f.af, f.scale_gfc, f.us_gfc, f.rs_gfc, fly, status);
 }
 
 // -------------------------------------------------------------- init ------
@@ -1234,6 +1247,21 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho_in,
     const double gs = g[i] + omega * (geq_i<Lat, double>(i, drho, rho, u, uu) - g[i]);
     store_g<P>(pdf, (int64_t)i * a.n + x, (typename Prec<P>::C)gs, a.wr[Lat::wclass(i)], a.scale);
   }
+}
+
+// Ghost entries [nf, n) of a pdf array set to the rest state w_i rho0 (a
+// zero deviation).  Stream-collides that update inner ghost layers beyond
+// what the fluid reads (diffusive scaling) may read ghost entries of the
+// array that no fill writes; they then hold finite values.
+template <class Lat, int P>
+__global__ __launch_bounds__(256) void k_rest_ghosts(typename Prec<P>::S* __restrict__ pdf,
+                                                     int64_t nf, int64_t n,
+                                                     const LevelArgs<typename Prec<P>::C, Lat::Q> a) {
+  const int64_t x = nf + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= n) return;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i)
+    store_g<P>(pdf, (int64_t)i * a.n + x, typename Prec<P>::C(0), a.wr[Lat::wclass(i)], a.scale);
 }
 
 template <class Lat, int P>
@@ -1497,6 +1525,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(
 
 struct DiagLevel {
   double vol, force_scale, rho0_nf;
+  double unit2;   // (level-L0 velocity per level-L velocity)^2
 };
 
 // Final pass: one block; levels summed coarse to fine in fixed order.
@@ -1516,8 +1545,8 @@ static __global__ __launch_bounds__(256) void k_diag_final(const double* __restr
       block_sum(sm, s, &sm[0]);
       if (threadIdx.x == 0) {
         r = sm[0];
-        if (v == 0) tot[0] += lv[k].vol * (lv[k].rho0_nf + r);
-        else if (v == 1) tot[1] += lv[k].vol * r;
+        if (v == 0) tot[0] += lv[k].vol * (lv[k].rho0_nf + r * lv[k].unit2);
+        else if (v == 1) tot[1] += lv[k].vol * r * lv[k].unit2;
         else tot[v] += lv[k].force_scale * r;
       }
       __syncthreads();

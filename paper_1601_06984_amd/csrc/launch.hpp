@@ -40,6 +40,27 @@ inline LevelArgs<C, Q> level_args(const SimState& s, int k) {
   return a;
 }
 
+// Unit conversions of the fills between levels k and k+1 (Sec. 2.2, Step 4
+// and the velocity and density units): with n = n_sub fine steps per coarse
+// step, g^neq is rescaled by omega_s / omega_t times dt_t / dt_s, velocity
+// by (dt_t / dt_s) / (dx_t / dx_s) and the density deviation by its square.
+// Acoustic scaling (n = 2) leaves velocity and density as they are.
+struct FillUnits {
+  double fneq_gff, us_gff, rs_gff;   // fine -> coarse (GhostFromFiner)
+  double fneq_gfc, us_gfc, rs_gfc;   // coarse -> fine (GhostFromCoarser)
+};
+inline FillUnits fill_units(const SimState& s, int k) {
+  const double wc = s.lv[k].omega, wf = s.lv[k + 1].omega, n = s.n_sub;
+  FillUnits u;
+  u.fneq_gff = (wf / wc) * n;
+  u.us_gff = 0.5 * n;
+  u.rs_gff = u.us_gff * u.us_gff;
+  u.fneq_gfc = (wc / wf) / n;
+  u.us_gfc = 2.0 / n;
+  u.rs_gfc = u.us_gfc * u.us_gfc;
+  return u;
+}
+
 // ---- per (lattice, precision) launchers ------------------------------------
 template <class Lat, int P>
 struct Impl {
@@ -102,26 +123,25 @@ struct Impl {
   static void fill_gff_ptr(SimState& s, int k, void* pdf, const void* cap_fine, void* cap_coarse) {
     DevLevel& L = s.lv[k];
     if (!L.n_gff) return;
-    const DevLevel& F = s.lv[k + 1];
     auto a = level_args<C, Lat::Q>(s, k);
-    const C scale = (C)(2.0 * F.omega / L.omega);
+    const FillUnits fu = fill_units(s, k);
     const unsigned grid = (unsigned)((L.n_gff + 63) / 64);
     hipLaunchKernelGGL((k_fill_gff<Lat, P>), dim3(grid), dim3(64), 0, s.stream, (S*)pdf,
                        L.n_fluid + L.n_inner + L.n_outer, L.n_gff, L.gff_slot,
-                       (const C*)cap_fine, (C*)cap_coarse, L.n_cap_fluid, a, scale, s.status);
+                       (const C*)cap_fine, (C*)cap_coarse, L.n_cap_fluid, a, (C)fu.fneq_gff,
+                       (C)fu.us_gff, (C)fu.rs_gff, s.status);
   }
 
   static void fill_gfc_ptr(SimState& s, int k, void* pdf, const void* cap_coarse) {
     DevLevel& L = s.lv[k];
     if (!L.n_groups) return;
-    const DevLevel& Cl = s.lv[k - 1];
     auto a = level_args<C, Lat::Q>(s, k);
-    const C scale = (C)(Cl.omega / (2.0 * L.omega));
+    const FillUnits fu = fill_units(s, k - 1);
     constexpr int GPB = 64 / group_children(Lat::D);
     const unsigned grid = (unsigned)((L.n_groups + GPB - 1) / GPB);
     hipLaunchKernelGGL((k_fill_gfc<Lat, P>), dim3(grid), dim3(64), 0, s.stream, (S*)pdf,
-                       L.n_groups, L.grp_src, L.grp_child, (const C*)cap_coarse, a, scale,
-                       s.status);
+                       L.n_groups, L.grp_src, L.grp_child, (const C*)cap_coarse, a,
+                       (C)fu.fneq_gfc, (C)fu.us_gfc, (C)fu.rs_gfc, s.status);
   }
 
   // GhostFromFiner of level k and GhostFromCoarser of level k+1 in one
@@ -158,14 +178,19 @@ struct Impl {
       f.cap_coarse = (C*)jobs[j].cap_coarse;
       f.cap_gff_begin = L.n_cap_fluid;
       f.ac = level_args<C, Lat::Q>(s, k);
-      f.scale_gff = (C)(2.0 * F.omega / L.omega);
+      const FillUnits fu = fill_units(s, k);
+      f.scale_gff = (C)fu.fneq_gff;
+      f.us_gff = (C)fu.us_gff;
+      f.rs_gff = (C)fu.rs_gff;
       f.pdf_f = (S*)jobs[j].pdf_f;
       f.n_groups = F.n_groups;
       f.grp_src = F.grp_src;
       f.grp_tab = (const int4*)F.grp_tab;
       f.grp_child = F.grp_child;
       f.af = level_args<C, Lat::Q>(s, k + 1);
-      f.scale_gfc = (C)(L.omega / (2.0 * F.omega));
+      f.scale_gfc = (C)fu.fneq_gfc;
+      f.us_gfc = (C)fu.us_gfc;
+      f.rs_gfc = (C)fu.rs_gfc;
       total += f.nb;
     }
     if (!m.nseg) return;
@@ -215,6 +240,13 @@ struct Impl {
       const unsigned grid = (unsigned)((L.n_fluid + 255) / 256);
       hipLaunchKernelGGL((k_init<Lat, P>), dim3(grid), dim3(256), 0, s.stream, rho, u, S_,
                          L.n_fluid, (S*)pdf, a, s.rho0, L.omega);
+    }
+    if (L.n > L.n_fluid && pdf == L.pdf[L.parity]) {
+      // ghost entries of both arrays at rest until the first fill
+      const unsigned gg = (unsigned)((L.n - L.n_fluid + 255) / 256);
+      for (int b = 0; b < 2; ++b)
+        hipLaunchKernelGGL((k_rest_ghosts<Lat, P>), dim3(gg), dim3(256), 0, s.stream,
+                           (S*)L.pdf[b], L.n_fluid, L.n, a);
     }
     if (L.n_cap_fluid) {
       const unsigned gc = (unsigned)((L.n_cap_fluid + 255) / 256);

@@ -161,10 +161,22 @@ void flush_fill(SimState& s) {
   s.pending_fill.clear();
 }
 
+// Active set of a stream-collide of level k > 0: fluid, plus the inner
+// GhostFromCoarser layers on every step after a sync but the last of the
+// parent's step.  With n_sub = 2 (one inner layer) that is the first step.
+// With n_sub = 4 the inner layers are at distances 1-3 from fluid: the fluid
+// reads layer 1 at each step, which needs layer 2 one step and layer 3 two
+// steps earlier, and layer 3 reads the outer layer filled at the sync.  The
+// whole inner part is updated on the first three steps; values of the deeper
+// layers past what the fluid needs are never read by it.
+static int64_t active_count(const SimState& s, const DevLevel& L, int k) {
+  const bool inner = (k > 0) && (L.substep < s.n_sub - 1);
+  return L.n_fluid + (inner ? L.n_inner : 0);
+}
+
 void sc_level(SimState& s, int k) {
   DevLevel& L = s.lv[k];
-  const bool first = (k > 0) && (L.substep == 0);
-  const int64_t n_act = L.n_fluid + (first ? L.n_inner : 0);
+  const int64_t n_act = active_count(s, L, k);
   flush_fill(s);   // a stream-collide reads the ghosts the fills write
   if (!s.prof.on) {
     // consecutive stream-collides of different levels share a launch; a
@@ -177,7 +189,7 @@ void sc_level(SimState& s, int k) {
     if ((int)s.pending.size() == SC_MAX_SEG) flush_sc(s);
     s.pending.push_back(ScJob{k, n_act, L.pdf[L.parity], L.pdf[L.parity ^ 1], L.cap});
     L.parity ^= 1;
-    if (k > 0) L.substep ^= 1;
+    if (k > 0) L.substep = (L.substep + 1) % s.n_sub;
     return;
   }
   flush_sc(s);
@@ -194,7 +206,7 @@ void sc_level(SimState& s, int k) {
   s.launch_ev[0] = s.launch_ev[1] = nullptr;
   if (s.prof.on && e0 && e1) s.prof.rec.push_back({0, k, n_act, e0, e1});
   L.parity ^= 1;
-  if (k > 0) L.substep ^= 1;
+  if (k > 0) L.substep = (L.substep + 1) % s.n_sub;
 }
 
 void fill_gff(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_gff(s, k)); }
@@ -220,22 +232,22 @@ void fill_gfc(SimState& s, int k) { MLBM_DISPATCH(s, I::fill_gfc(s, k)); }
 void advance(SimState& s, int k) {
   sc_level(s, k);
   if (k + 1 < (int)s.lv.size()) {
-    advance(s, k + 1);
-    advance(s, k + 1);
+    for (int t = 0; t < s.n_sub; ++t) advance(s, k + 1);
     fill_sync(s, k);   // GhostFromFiner(k) and GhostFromCoarser(k+1)
   }
 }
 
 static uint64_t parity_key(const SimState& s) {
   uint64_t key = 0;
-  for (size_t k = 0; k < s.lv.size() && k < 32; ++k)
-    key |= (uint64_t)(s.lv[k].parity & 1) << (2 * k) | (uint64_t)(s.lv[k].substep & 1) << (2 * k + 1);
+  for (size_t k = 0; k < s.lv.size() && k < 21; ++k)
+    key |= (uint64_t)(s.lv[k].parity & 1) << (3 * k) | (uint64_t)(s.lv[k].substep & 3) << (3 * k + 1);
   return key;
 }
 
 // Records two coarse steps into a graph on the capture stream.  Every level
-// takes an even number of stream-collides in two coarse steps, so the
-// parity state after the graph equals the state it was captured from.
+// takes an even number of stream-collides in two coarse steps, a multiple of
+// n_sub below the coarsest, so the parity and substep state after the graph
+// equals the state it was captured from.
 static hipError_t two_step_graph(SimState& s, hipGraphExec_t* exec) {
   hipError_t e = hipSuccess;
   if (!s.capture_stream) e = hipStreamCreateWithFlags(&s.capture_stream, hipStreamNonBlocking);
@@ -292,9 +304,6 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
   if (!(tau0 > 0.5)) return fail(MLBM_E_ARG, "tau0 must exceed 1/2");
   if (!(rho0 > 0.0)) return fail(MLBM_E_ARG, "rho0 must be positive");
   if (((uintptr_t)workspace) & 255) return fail(MLBM_E_ARG, "workspace must be 256-byte aligned");
-  if (plan->gfc_layers != 2)
-    return fail(MLBM_E_STATE, "plans with four GhostFromCoarser layers (diffusive scaling) "
-                              "have no GPU schedule yet");
   // the stream-collide addresses a pair of pdf rows (and a neighbour row)
   // through one buffer descriptor with 32-bit byte offsets
   const size_t pdf_bytes = precision == MLBM_F64 ? 8 : precision == MLBM_F32 ? 4 : 2;
@@ -318,6 +327,7 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
   if (!sim) return fail(MLBM_E_OOM, "host allocation failed");
   SimState& s = sim->s;
   s.device = device;
+  s.n_sub = plan->gfc_layers == 4 ? 4 : 2;   // four layers: diffusive scaling
   s.stencil = plan->stencil;
   s.d = plan->d;
   s.q = plan->q;
@@ -346,7 +356,9 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
     L.n_bounce = lp.n_bounce();
     L.n_wall = lp.n_wall_dev();
     L.morton = lp.morton;
-    const double tau = 0.5 + std::ldexp(tau0 - 0.5, lp.level - plan->level0);
+    // acoustic scaling: Eq. fneq_scale per level jump (tau_L - 1/2 doubles);
+    // diffusive scaling: nu dt / dx^2 is level invariant, one tau everywhere
+    const double tau = s.n_sub == 4 ? tau0 : 0.5 + std::ldexp(tau0 - 0.5, lp.level - plan->level0);
     L.omega = 1.0 / tau;
     L.f16_exp = f16_exp ? f16_exp[k] : 0;
     L.f16_auto = (f16_exp == nullptr) && precision == MLBM_F16S;
@@ -388,6 +400,9 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
     dl[k].vol = std::ldexp(1.0, -s.d * (L - plan->level0));
     dl[k].force_scale = std::ldexp(1.0, (s.d - 1) * (plan->level0 + plan->nlev() - 1 - L));
     dl[k].rho0_nf = rho0 * (double)plan->lv[k].n_fluid;
+    // level-L0 units of velocity and density deviation: u dt/dx and
+    // (rho - rho0) dt^2/dx^2 grow by n_sub/2 and its square per level
+    dl[k].unit2 = std::pow(0.5 * s.n_sub, 2.0 * (L - plan->level0));
   }
   up(s.diag_levels, dl.data(), dl.size() * sizeof(DiagLevel));
   std::vector<double> geq_d(s.geq, s.geq + s.q);
@@ -488,6 +503,8 @@ int32_t mlbm_diagnostics(mlbm_sim* sim, uint32_t mask, double* dev_out) {
   SimState& s = sim->s;
   if (!s.filled) return fail(MLBM_E_STATE, "no state yet");
   if (mask & ~7u) return fail(MLBM_E_ARG, "bad diagnostics mask");
+  if ((mask & MLBM_DIAG_FORCE) && s.n_sub != 2)
+    return fail(MLBM_E_STATE, "the force is defined for acoustic scaling only");
   for (int k = 0; k < (int)s.lv.size(); ++k) MLBM_DISPATCH(s, I::diag_partial(s, k));
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s.stream, s.partial, (int)s.lv.size(),
                      (const DiagLevel*)s.diag_levels, mask, s.d, dev_out);
@@ -499,6 +516,8 @@ int32_t mlbm_diagnostics_noalloc(mlbm_sim* sim, uint32_t mask, double* dev_out) 
   SimState& s = sim->s;
   if (!s.filled) return fail(MLBM_E_STATE, "no state yet");
   if (mask & ~7u) return fail(MLBM_E_ARG, "bad diagnostics mask");
+  if ((mask & MLBM_DIAG_FORCE) && s.n_sub != 2)
+    return fail(MLBM_E_STATE, "the force is defined for acoustic scaling only");
   if ((int)s.lv.size() > DIAG_STATIC_LEVELS)
     return fail(MLBM_E_ARG, "%d levels: the static scratch holds the partials of at most %d",
                 (int)s.lv.size(), DIAG_STATIC_LEVELS);
@@ -690,9 +709,9 @@ int32_t mlbm_launches_per_step(const mlbm_sim* sim, int64_t* launches) {
   if (!sim || !launches) return fail(MLBM_E_ARG, "NULL argument");
   const SimState& s = sim->s;
   int64_t total = 0;
-  for (size_t k = 0; k < s.lv.size(); ++k) {
+  int64_t reps = 1;
+  for (size_t k = 0; k < s.lv.size(); ++k, reps *= s.n_sub) {
     const auto& L = s.lv[k];
-    const int64_t reps = (int64_t)1 << k;
     total += reps;
     if (k + 1 < s.lv.size()) total += reps * ((L.n_gff || s.lv[k + 1].n_groups) ? 1 : 0);
   }

@@ -34,7 +34,7 @@ struct DevLevel {
   int32_t* wall = nullptr;            // [n_wall][4] links with a wall fraction,
   double* wall_q = nullptr;           // [n_wall]    padded (the plan's device copy)
   int parity = 0;                     // index of the current pdf array
-  int substep = 0;                    // 0: next step is the first after a sync
+  int substep = 0;                    // steps since the last sync (0: the first after one)
   bool pre_valid = false;             // the other array holds what the last
                                       // stream-collide read
   double omega = 1.0;
@@ -125,6 +125,8 @@ struct AdjState {
 struct SimState {
   int stencil = 0, d = 3, q = 19, precision = 0, level0 = 0;
   int device = 0;                      // HIP device current at creation
+  int n_sub = 2;                       // steps of level L+1 per step of L: 2 acoustic,
+                                       // 4 diffusive scaling (Sec. 2.2)
   double tau0 = 1.0, rho0 = 1.0, u_in[3] = {0, 0, 0};
   double wr[27], geq[27];
   hipStream_t stream = nullptr;

@@ -72,18 +72,14 @@ def test_plan_tables_bit_exact(name):
                                                                 extra_levels=[(32, 56)])])
 def test_plan_tables_bit_exact_four_layers(spec_fn):
     """Diffusive-scaling plans (four GhostFromCoarser layers; distances 1-3
-    inner, 4 outer) against the oracle's four-layer mesh, and simulations
-    refuse them until the GPU schedule exists."""
+    inner, 4 outer) against the oracle's four-layer mesh; layer counts
+    other than 2 and 4 are refused."""
     M.set_gfc_layers(4)
     try:
         plan = _check_tables(spec_fn(), 4)
     finally:
         M.set_gfc_layers(2)
     assert plan.gfc_layers == 4
-    out = ctypes.c_void_p()
-    code = M.lib().mlbm_sim_create(plan.handle, _lib.F32, 0.8, 1.0, None, None, None,
-                                   ctypes.c_void_p(1 << 20), 1 << 20, ctypes.byref(out))
-    assert code == _lib.E_STATE and not out.value
     with pytest.raises(M.MLBMError):
         M.set_gfc_layers(3)
 
