@@ -1,7 +1,9 @@
 """ctypes declarations of the C ABI in include/mlbm.h.
 
 Loading fails loudly if the in-tree library has not been built; there is no
-fallback implementation.
+fallback implementation.  The environment variable MLBM_LIBRARY may name
+another build of the same library (the tests use a build whose host code is
+compiled with AddressSanitizer and UndefinedBehaviorSanitizer).
 """
 from __future__ import annotations
 
@@ -9,7 +11,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "lib", "libmlbm.so")
+LIB_PATH = os.environ.get("MLBM_LIBRARY") or os.path.join(HERE, "lib", "libmlbm.so")
 
 # enums mirrored from include/mlbm.h
 D2Q9, D3Q19, D3Q27 = 0, 1, 2

@@ -57,5 +57,42 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized_host(out_dir: str) -> str:
+    """A variant of the library whose host plan builder is compiled with
+    AddressSanitizer and UndefinedBehaviorSanitizer (g++; the device code and
+    the HIP host objects are the normal build's, so build() must have run).
+    Returns the path of the shared library; load it with the sanitizer
+    runtime preloaded (see sanitizer_env)."""
+    objs = [os.path.join(BUILD, src + ".o") for src in HIP_SOURCES]
+    missing = [o for o in objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError("build() first: missing " + ", ".join(missing))
+    os.makedirs(out_dir, exist_ok=True)
+    plan_o = os.path.join(out_dir, "plan_sanitized.o")
+    lib = os.path.join(out_dir, "libmlbm_sanitized.so")
+    flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined", "-std=c++17", "-fPIC", "-pthread"]
+    _run(["g++"] + flags + ["-c", "plan.cpp", "-o", plan_o])
+    _run(["g++", "-shared", "-fsanitize=address,undefined", "-pthread", plan_o] + objs +
+         ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", lib])
+    return lib
+
+
+def sanitizer_env(lib: str, log_dir: str) -> dict:
+    """Environment for a process that loads the sanitized library: the ASan
+    runtime first, then libstdc++ (so that ASan finds the C++ exception
+    runtime a Python process loads late), reports written under log_dir."""
+    def rt(name):
+        return subprocess.run(["g++", "-print-file-name=" + name], capture_output=True,
+                              text=True, check=True).stdout.strip()
+    env = dict(os.environ)
+    env["MLBM_LIBRARY"] = lib
+    env["LD_PRELOAD"] = rt("libasan.so") + " " + rt("libstdc++.so")
+    env["ASAN_OPTIONS"] = "detect_leaks=0:log_path=" + os.path.join(log_dir, "asan")
+    env["UBSAN_OPTIONS"] = ("halt_on_error=1:print_stacktrace=1:log_path=" +
+                            os.path.join(log_dir, "ubsan"))
+    return env
+
+
 if __name__ == "__main__":
     build(verbose=True)
