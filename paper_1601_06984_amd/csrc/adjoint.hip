@@ -84,15 +84,15 @@ size_t layout_adjoint(const SimState& s, const mlbm_plan& P, char* base, AdjStat
     AdjLevel* A = a ? &a->lv[k] : nullptr;
     const int sub = 1 << k;
     for (int j = 0; j <= sub; ++j) {
-      char* p = take((size_t)q * lp.n * sb);
+      char* p = take((size_t)q * row_stride(lp.n) * sb);
       if (A) A->X[j] = p;
     }
     for (int j = 0; j < sub; ++j) {
       char* p = take((size_t)lp.n_cap() * st * cb);
       if (A) A->cap[j] = p;
     }
-    char* l0 = take((size_t)q * lp.n * cb);
-    char* l1 = take((size_t)q * lp.n * cb);
+    char* l0 = take((size_t)q * row_stride(lp.n) * cb);
+    char* l1 = take((size_t)q * row_stride(lp.n) * cb);
     char* lc = take((size_t)lp.n_cap() * st * cb);
     char* u0 = take(lp.unassigned[0].size() * 4);
     char* u1 = take(lp.unassigned[1].size() * 4);
@@ -214,7 +214,7 @@ struct Adj {
     const int64_t nb = blocks(L.n_groups, 64 / group_children(Lat::D));
     hipLaunchKernelGGL((k_adj_gfc<Lat, P>), dim3((unsigned)nb), dim3(64), 0, s.stream,
                        L.n_groups, (const int32_t*)L.grp_src, (const int32_t*)L.grp_child,
-                       (const C*)cap_coarse, lam, L.n, (C*)A.T, (C)L.omega, (C)Cl.omega,
+                       (const C*)cap_coarse, lam, L.ld, (C*)A.T, (C)L.omega, (C)Cl.omega,
                        (C)s.rho0, s.adj.part + off * DPART);
     off += nb;
     constexpr int W = cap_used(Lat::Q);
@@ -231,7 +231,7 @@ struct Adj {
     const int64_t nb = blocks(L.n_gff, 64);
     hipLaunchKernelGGL((k_adj_gff<Lat, P>), dim3((unsigned)nb), dim3(64), 0, s.stream,
                        L.n_fluid + L.n_inner + L.n_outer, L.n_gff, L.gff_slot, (const C*)cap_fine,
-                       (const C*)lam, L.n, (C*)s.adj.lv[k].lam_cap, L.n_cap_fluid,
+                       (const C*)lam, L.ld, (C*)s.adj.lv[k].lam_cap, L.n_cap_fluid,
                        (C*)s.adj.lv[k + 1].lam_cap, (C)L.omega, (C)F.omega, (C)s.rho0,
                        s.adj.part + off * DPART);
     off += nb;
@@ -278,10 +278,11 @@ struct Adj {
       DevLevel& L = s.lv[jb.k];
       AdjLevel& A = s.adj.lv[jb.k];
       // entries no pull assigns: the ghost rows and the listed fluid entries
-      const int64_t nz = (L.n - L.n_fluid) * Lat::Q + A.n_unas[jb.v];
+      // ghost rows [n_fluid, ld) (padding included) and the listed entries
+      const int64_t nz = (L.ld - L.n_fluid) * Lat::Q + A.n_unas[jb.v];
       if (nz)
         hipLaunchKernelGGL((k_zero_unassigned<C>), dim3((unsigned)blocks(nz, 256)), dim3(256), 0,
-                           s.stream, jb.lold, L.n, L.n_fluid, Lat::Q, A.unas[jb.v], A.n_unas[jb.v]);
+                           s.stream, jb.lold, L.ld, L.n_fluid, Lat::Q, A.unas[jb.v], A.n_unas[jb.v]);
       if (A.n_copy)
         hipLaunchKernelGGL((k_adj_copy_pre<Lat, P>), dim3((unsigned)blocks(A.n_copy, 256)), dim3(256),
                            0, s.stream, (const S*)jb.X, A.copy_el, A.n_copy, jb.n_act,
@@ -322,18 +323,18 @@ struct Adj {
       AdjLevel& A = s.adj.lv[jb.k];
       if (A.n_copy)
         hipLaunchKernelGGL((k_adj_copy_add<Lat::Q, C>), dim3((unsigned)blocks(A.n_copy, 256)),
-                           dim3(256), 0, s.stream, A.copy_el, A.n_copy, s.lv[jb.k].n,
+                           dim3(256), 0, s.stream, A.copy_el, A.n_copy, s.lv[jb.k].ld,
                            (const C*)A.copy_tmp, jb.lold);
       // the stream-collide consumed the state after the curved-wall
       // pre-pass: carry its adjoint back through the pre-pass
       if (A.n_wadj) {
         hipLaunchKernelGGL((k_adj_wall_gather<C>), dim3((unsigned)blocks(A.n_wadj, 256)),
                            dim3(256), 0, s.stream, (const int4*)A.wadj_ent, A.wadj_ptr,
-                           (const int2*)A.wadj_src, A.wadj_coef, A.n_wadj, s.lv[jb.k].n,
+                           (const int2*)A.wadj_src, A.wadj_coef, A.n_wadj, s.lv[jb.k].ld,
                            (const C*)jb.lold, (C*)A.wadj_tmp);
         hipLaunchKernelGGL((k_adj_wall_store<C>), dim3((unsigned)blocks(A.n_wadj, 256)),
                            dim3(256), 0, s.stream, (const int4*)A.wadj_ent, A.n_wadj,
-                           s.lv[jb.k].n, (const C*)A.wadj_tmp, jb.lold);
+                           s.lv[jb.k].ld, (const C*)A.wadj_tmp, jb.lold);
       }
     }
   }
@@ -403,16 +404,16 @@ struct Adj {
         hipLaunchKernelGGL((k_seed_ke<Lat, P>), dim3((unsigned)blocks(L.n, 256)), dim3(256), 0,
                            s.stream, (const S*)L.pdf[L.parity], a, vol, lam);
       } else {
-        hipLaunchKernelGGL((k_fill_value<C>), dim3((unsigned)blocks(L.n * Lat::Q, 256)), dim3(256), 0,
-                           s.stream, lam, L.n * Lat::Q, C(0));
+        hipLaunchKernelGGL((k_fill_value<C>), dim3((unsigned)blocks(L.ld * Lat::Q, 256)), dim3(256), 0,
+                           s.stream, lam, L.ld * Lat::Q, C(0));
         const double scale = std::ldexp(1.0, (s.d - 1) * ((int)s.lv.size() - 1 - (int)k));
         if (L.n_bounce)
           hipLaunchKernelGGL((k_seed_drag<Lat, C>), dim3((unsigned)blocks(L.n_bounce, 256)), dim3(256),
-                             0, s.stream, L.bounce, L.n_bounce, L.n, scale, lam);
+                             0, s.stream, L.bounce, L.n_bounce, L.ld, scale, lam);
         if (A.n_wadj)
           hipLaunchKernelGGL((k_seed_wall_drag<C>), dim3((unsigned)blocks(A.n_wadj, 256)),
                              dim3(256), 0, s.stream, (const int4*)A.wadj_ent, A.wadj_ptr,
-                             A.wadj_seed, A.n_wadj, L.n, scale, lam);
+                             A.wadj_seed, A.n_wadj, L.ld, scale, lam);
       }
       const int64_t ncap = L.n_cap * cap_stride(s.q);
       if (ncap)
@@ -479,7 +480,7 @@ struct Adj {
     DevLevel& L = s.lv[k];
     AdjLevel& A = s.adj.lv[k];
     hipLaunchKernelGGL((k_to_double<C>), dim3((unsigned)blocks(L.n * Lat::Q, 256)), dim3(256), 0,
-                       s.stream, (const C*)A.lam[A.cur], L.n * Lat::Q, out);
+                       s.stream, (const C*)A.lam[A.cur], L.n, L.ld, L.n * Lat::Q, out);
   }
 };
 
@@ -613,7 +614,7 @@ int32_t mlbm_adjoint_step(mlbm_sim* sim, const void* dev_ckpt, size_t bytes) {
   const char* p = (const char*)dev_ckpt;
   size_t off = 256;
   for (size_t k = 0; k < s.lv.size(); ++k) {
-    const size_t nb = (size_t)s.q * s.lv[k].n * sbytes(s.precision);
+    const size_t nb = (size_t)s.q * s.lv[k].ld * sbytes(s.precision);
     if (s.lv[k].n_wall) {
       const hipError_t e = hipMemcpyAsync(s.adj.lv[k].X[0], p + off, nb,
                                           hipMemcpyDeviceToDevice, s.stream);

@@ -899,11 +899,13 @@ __global__ __launch_bounds__(256) void k_adj_init(
   block_sums(sm, acc, DPART, part + (int64_t)blockIdx.x * DPART);
 }
 
+// [q][ld] in the compute type -> [q][n] FP64 (total = q n entries)
 template <class C>
 __global__ __launch_bounds__(256) void k_to_double(const C* __restrict__ in, int64_t n,
+                                                   int64_t ld, int64_t total,
                                                    double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t < n) out[t] = (double)in[t];
+  if (t < total) out[t] = (double)in[(t / n) * ld + t % n];
 }
 
 // Deterministic reduction of all partial records, op by op in a fixed order.

@@ -126,7 +126,7 @@ __device__ __forceinline__ bool store_row(typename Prec<P>::S* __restrict__ row,
 // Per-level parameters passed by value.
 template <class C, int Q>
 struct LevelArgs {
-  int64_t n;          // elements (row stride of the pdf arrays)
+  int64_t n;          // row stride of the [q][n] pdf arrays (the level's padded stride)
   // pull table, device form (see the plan's NBR16 table): 16-bit codes
   // [q-1][ld16], bases [blocks][q-1][NBR_BASES], wide rows [q-1][ldw]
   const uint16_t* nbr16;
@@ -639,8 +639,10 @@ inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStr
 // direction takes the accumulated mass error.  What remains is the
 // rounding of those last values, instead of the sum over all directions.
 // Directions are ordered rest, axis pairs 2a+1 / 2a+2, then diagonals.
-template <class Lat>
-__device__ __forceinline__ bool store_f16s_conserving(__half* __restrict__ dst, int64_t x,
+// `sink(i, h)` receives the half of direction i (a store to the pdf array,
+// or to the work-group's store tile).
+template <class Lat, class Sink>
+__device__ __forceinline__ bool store_f16s_conserving(Sink&& sink,
                                                       const LevelArgs<float, Lat::Q>& a,
                                                       const float* g, float drho, float rho,
                                                       const float* u, float uu) {
@@ -650,7 +652,7 @@ __device__ __forceinline__ bool store_f16s_conserving(__half* __restrict__ dst, 
   auto put = [&](int i, float v) -> float {
     const float hs = v * a.scale;
     const __half h = __float2half_rn(hs);
-    store_elem(dst + (int64_t)i * a.n, a.n, (uint32_t)x, h);
+    sink(i, h);
     ok &= fabsf(hs) <= 65504.0f;
     return __half2float(h) * a.inv_scale;
   };
@@ -717,16 +719,51 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
              m, lane, {}};
     record_values<Lat, C>(w, g, drho, rho, u, uu, a.omega);
   }
-  if (!valid) return;
+  using S = typename Prec<P>::S;
   bool ok = true;
-  if constexpr (P == MLBM_F16S) {
-    ok = store_f16s_conserving<Lat>(dst, x, a, g, drho, rho, u, uu);
-  } else {
+  // Stores.  A whole work-group (all but the last of the range) puts its
+  // post-collision values into an LDS tile [Q][BS] and writes each row's BS
+  // consecutive values with aligned 16-byte stores: rows start on 128-byte
+  // lines (padded row stride) and blk * BS is a multiple of 8, so the
+  // vector memory instructions for the stores drop from Q per wave to about
+  // Q * BS * sizeof(S) / (16 * BS) per thread.  The record stager's LDS is
+  // the tile once every wave has finished its records.
+  if (P != MLBM_F64 && (blk + 1) * BS <= x1) {
+    __syncthreads();
+    S* __restrict__ tile = reinterpret_cast<S*>(stage);
+    const int t = threadIdx.x;
+    if constexpr (P == MLBM_F16S) {
+      ok = store_f16s_conserving<Lat>([&](int i, __half h) { tile[i * BS + t] = h; }, a, g,
+                                      drho, rho, u, uu);
+    } else {
 #pragma unroll
-    for (int i = 0; i < Lat::Q; ++i) {
-      const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
-      ok &= store_row<P>(dst + (int64_t)i * a.n, a.n, (uint32_t)x, gs, a.wr[Lat::wclass(i)],
-                         a.scale);
+      for (int i = 0; i < Lat::Q; ++i) {
+        const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
+        tile[i * BS + t] = (S)(a.wr[Lat::wclass(i)] + gs);
+      }
+    }
+    __syncthreads();
+    typedef int VT __attribute__((ext_vector_type(4)));
+    constexpr int PER = 16 / (int)sizeof(S);          // values per 16-byte chunk
+    constexpr int CPR = BS / PER;                     // chunks per row
+    const VT* __restrict__ tv = reinterpret_cast<const VT*>(tile);
+    for (int c = t; c < Lat::Q * CPR; c += BS) {
+      const int i = c / CPR, k = c % CPR;
+      *reinterpret_cast<VT*>(dst + (int64_t)i * a.n + blk * BS + k * PER) = tv[c];
+    }
+  } else {
+    if (!valid) return;
+    if constexpr (P == MLBM_F16S) {
+      ok = store_f16s_conserving<Lat>(
+          [&](int i, __half h) { store_elem(dst + (int64_t)i * a.n, a.n, (uint32_t)x, h); }, a, g,
+          drho, rho, u, uu);
+    } else {
+#pragma unroll
+      for (int i = 0; i < Lat::Q; ++i) {
+        const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
+        ok &= store_row<P>(dst + (int64_t)i * a.n, a.n, (uint32_t)x, gs, a.wr[Lat::wclass(i)],
+                           a.scale);
+      }
     }
   }
   const bool finite = (rho == rho) && (rho - rho == C(0));
@@ -739,6 +776,16 @@ template <class C, int Q>
 constexpr int sc_stage_values(int bs) {
   return (bs / 64) * WaveRecordStager<C, cap_stride(Q)>::LDS_PER_WAVE;
 }
+// LDS of a stream-collide work-group, in compute values: the record stager,
+// which is also the store tile of Q * bs stored values (not for FP64)
+template <int P, int Q>
+constexpr int sc_lds_values(int bs) {
+  using C = typename Prec<P>::C;
+  using S = typename Prec<P>::S;
+  constexpr int tile = P == MLBM_F64 ? 0 : (int)((Q * 256 * sizeof(S) + sizeof(C) - 1) / sizeof(C));
+  const int stage = sc_stage_values<C, Q>(bs);
+  return stage > tile * bs / 256 ? stage : tile * bs / 256;
+}
 
 // One level's stream-collide over [0, x1); the block map balances the plain
 // range and the tail (capture sources, inner ghosts) over the XCDs.
@@ -748,7 +795,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(
     int64_t x1, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
     typename Prec<P>::C* __restrict__ cap, uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
-  __shared__ C stage[sc_stage_values<C, Lat::Q>(BS)];
+  __shared__ __align__(16) C stage[sc_lds_values<P, Lat::Q>(BS)];
   __shared__ int32_t slots[NBR_SLOTS];
   const int64_t blk = xcd_block2(blockIdx.x, gridDim.x, a.cap_begin / BS);
   sc_body<Lat, P, BS>(blk, x1, src, dst, a, cap, status, stage, slots);
@@ -778,7 +825,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide_multi(
     const ScMulti<typename Prec<P>::C, typename Prec<P>::S, Lat::Q> m,
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
-  __shared__ C stage[sc_stage_values<C, Lat::Q>(BS)];
+  __shared__ __align__(16) C stage[sc_lds_values<P, Lat::Q>(BS)];
   __shared__ int32_t slots[NBR_SLOTS];
   int sg = 0;
   while (sg + 1 < m.nseg && (int64_t)blockIdx.x >= m.first[sg + 1]) ++sg;
@@ -1302,6 +1349,7 @@ __global__ __launch_bounds__(256) void k_init_maxdev(const double* __restrict__ 
 }
 
 // --------------------------------------------------------- state I/O ------
+// pdf rows have stride a.n (the padded row stride), out rows stride n
 template <class Lat, int P>
 __global__ __launch_bounds__(256) void k_get_pdf(const typename Prec<P>::S* __restrict__ pdf,
                                                  int64_t n, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
@@ -1310,7 +1358,7 @@ __global__ __launch_bounds__(256) void k_get_pdf(const typename Prec<P>::S* __re
   if (x >= n) return;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
-    out[(int64_t)i * n + x] = (double)a.wr[Lat::wclass(i)] + (double)load_g<P>(pdf, (int64_t)i * n + x, a.wr[Lat::wclass(i)], a.inv_scale);
+    out[(int64_t)i * n + x] = (double)a.wr[Lat::wclass(i)] + (double)load_g<P>(pdf, (int64_t)i * a.n + x, a.wr[Lat::wclass(i)], a.inv_scale);
 }
 
 template <class Lat, int P>
@@ -1321,7 +1369,7 @@ __global__ __launch_bounds__(256) void k_set_pdf(typename Prec<P>::S* __restrict
   if (x >= n) return;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
-    store_g<P>(pdf, (int64_t)i * n + x, (typename Prec<P>::C)(in[(int64_t)i * n + x] - (double)a.wr[Lat::wclass(i)]),
+    store_g<P>(pdf, (int64_t)i * a.n + x, (typename Prec<P>::C)(in[(int64_t)i * n + x] - (double)a.wr[Lat::wclass(i)]),
                a.wr[Lat::wclass(i)], a.scale);
 }
 
@@ -1428,7 +1476,9 @@ __global__ __launch_bounds__(256) void k_set_pre(typename Prec<P>::S* __restrict
                               a.omega);
   bool ok = true;
   if constexpr (P == MLBM_F16S) {
-    ok = store_f16s_conserving<Lat>(pdf, x, a, g, drho, rho, u, uu);
+    ok = store_f16s_conserving<Lat>(
+        [&](int i, __half h) { store_elem(pdf + (int64_t)i * a.n, a.n, (uint32_t)x, h); }, a, g,
+        drho, rho, u, uu);
   } else {
 #pragma unroll
     for (int i = 0; i < Lat::Q; ++i) {

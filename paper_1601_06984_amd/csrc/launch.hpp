@@ -16,7 +16,7 @@ template <class C, int Q>
 inline LevelArgs<C, Q> level_args(const SimState& s, int k) {
   const DevLevel& L = s.lv[k];
   LevelArgs<C, Q> a;
-  a.n = L.n;
+  a.n = L.ld;   // row stride of the pdf arrays
   a.nbr16 = L.nbr16;
   a.nbase = L.nbase;
   a.nbr_wide = L.nbr_wide;

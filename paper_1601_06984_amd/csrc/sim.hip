@@ -73,8 +73,9 @@ size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState*
   for (int k = 0; k < P.nlev(); ++k) {
     const auto& lp = P.lv[k];
     DevLevel* L = s ? &s->lv[k] : nullptr;
-    char* p0 = take((size_t)q * lp.n * sb);
-    char* p1 = take((size_t)q * lp.n * sb);
+    const int64_t ld = row_stride(lp.n);
+    char* p0 = take((size_t)q * ld * sb);
+    char* p1 = take((size_t)q * ld * sb);
     char* n16 = take(lp.nbr16.size() * 2);
     char* nbs = take(lp.nbase.size() * 4);
     char* nwd = take(lp.nbr_wide.size() * 2);
@@ -308,7 +309,7 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
   // through one buffer descriptor with 32-bit byte offsets
   const size_t pdf_bytes = precision == MLBM_F64 ? 8 : precision == MLBM_F32 ? 4 : 2;
   for (const auto& lp : plan->lv)
-    if ((uint64_t)lp.n * pdf_bytes * 2 >= (1ull << 32) || (uint64_t)lp.n * 4 >= (1ull << 32))
+    if ((uint64_t)row_stride(lp.n) * pdf_bytes * 2 >= (1ull << 32) || (uint64_t)lp.n * 4 >= (1ull << 32))
       return fail(MLBM_E_ARG,
                   "level %d has %lld elements: two pdf rows must stay below 4 GiB",
                   lp.level, (long long)lp.n);
@@ -345,6 +346,7 @@ int32_t mlbm_sim_create(const mlbm_plan* plan, int32_t precision, double tau0, d
     DevLevel& L = s.lv[k];
     L.level = lp.level;
     L.n = lp.n;
+    L.ld = row_stride(lp.n);
     L.n_fluid = lp.n_fluid;
     L.n_inner = lp.n_inner;
     L.n_outer = lp.n_outer;
@@ -591,7 +593,7 @@ int32_t mlbm_checkpoint_bytes(const mlbm_sim* sim, size_t* bytes) {
   if (!sim || !bytes) return fail(MLBM_E_ARG, "NULL argument");
   const SimState& s = sim->s;
   size_t b = 256;
-  for (const auto& L : s.lv) b += align_up((size_t)s.q * L.n * storage_bytes(s.precision));
+  for (const auto& L : s.lv) b += align_up((size_t)s.q * L.ld * storage_bytes(s.precision));
   *bytes = b;
   return MLBM_OK;
 }
@@ -613,7 +615,7 @@ int32_t mlbm_save_checkpoint(mlbm_sim* sim, void* dev_dst, size_t bytes) {
   hipError_t e = hipMemcpyAsync(p, &h, sizeof h, hipMemcpyHostToDevice, s.stream);
   size_t off = 256;
   for (auto& L : s.lv) {
-    const size_t b = (size_t)s.q * L.n * storage_bytes(s.precision);
+    const size_t b = (size_t)s.q * L.ld * storage_bytes(s.precision);
     if (e == hipSuccess && b)
       e = hipMemcpyAsync(p + off, L.pdf[L.parity], b, hipMemcpyDeviceToDevice, s.stream);
     off += align_up(b);
@@ -642,7 +644,7 @@ int32_t mlbm_load_checkpoint(mlbm_sim* sim, const void* dev_src, size_t bytes) {
   s.drop_graphs();
   for (size_t k = 0; k < s.lv.size(); ++k) {
     DevLevel& L = s.lv[k];
-    const size_t b = (size_t)s.q * L.n * storage_bytes(s.precision);
+    const size_t b = (size_t)s.q * L.ld * storage_bytes(s.precision);
     L.parity = 0;
     L.substep = 0;
     L.pre_valid = false;

@@ -16,6 +16,7 @@ namespace mlbm {
 struct DevLevel {
   int level = 0;
   int64_t n = 0, n_fluid = 0, n_inner = 0, n_outer = 0, n_gff = 0, n_act_max = 0;
+  int64_t ld = 0;                     // row stride of the [q][ld] pdf-like arrays
   int64_t n_cap_fluid = 0, n_cap = 0, n_groups = 0, n_bounce = 0, n_wall = 0;
   void* pdf[2] = {nullptr, nullptr};  // storage arrays [q][n]
   uint16_t* nbr16 = nullptr;          // pull table, device form: [q-1][ld16]
@@ -165,6 +166,12 @@ struct CheckpointHeader {
 };
 
 size_t layout_workspace(const mlbm_plan& P, int precision, char* base, SimState* s);
+
+// Row stride of a level's [q][ld] arrays (pdfs, lambda, tape): the element
+// count rounded up to 64, so that every row starts on a 128-byte line and a
+// work-group's 256 consecutive elements of a row can be written with
+// aligned 16-byte stores.  Entries [n, ld) of a row are never read.
+inline int64_t row_stride(int64_t n) { return (n + 63) & ~(int64_t)63; }
 hipEvent_t prof_event(SimState& s);
 
 }  // namespace mlbm
