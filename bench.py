@@ -54,24 +54,21 @@ def algorithmic_bytes_adjoint(q, prec):
     return q * STORAGE_BYTES[prec] + 4 * (q - 1) + 2 * q * lam
 
 
-# HBM bytes per stream-collide launch (average over the level's launches),
+# HBM bytes per stream-collide launch (average over the level's launches,
+# which alternate between the fluid range and fluid plus the inner ghosts),
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of this bench
-# on MI355X, each scaled by what the counter reads for a plain 1 GiB device
-# copy (fetch x 2.0, write x 1.0).  Summaries and commands:
-# profiles/stream_collide_<workload>_f32.md.  The figures belong to the
+# on MI355X, each scaled by what the counter reads for a plain 1536 MiB
+# device copy (fetch x 2.0, write x 1.0).  Summary and commands:
+# profiles/stream_collide_sphere4_f16s.md.  The figures belong to the
 # kernel sources they were measured on (KERNEL_SOURCES digest); with any
 # other source the bench reports traffic as null.
 PMC_TRAFFIC = {
-    "sources_sha256_16": "5b523578dd764e9a",
+    "sources_sha256_16": "d3d42d4b5634769c",
     "bytes_per_launch": {
-        "tgv64/f32/6": 47456038,
-        "tgv64/f32/7": 60060091,
-        "sphere3/f32/9": 2195942052,
-        "sphere3/f32/10": 814369911,
-        "sphere3/f32/11": 852082092,
-        "sphere3/f16s/9": 1109229543,
-        "sphere3/f16s/10": 470871971,
-        "sphere3/f16s/11": 455362311,
+        "sphere4/f16s/10": 19721792512,
+        "sphere4/f16s/11": 7158816256,
+        "sphere4/f16s/12": 7158816256,
+        "sphere4/f16s/13": 7656523264,
     },
 }
 KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")
@@ -617,7 +614,7 @@ def main():
                     help="coarse steps of the oracle accuracy check in the precision study")
     ap.add_argument("--cpu-sample-d", type=int, default=16,
                     help="sphere diameter (finest cells) of the oracle's timing sample")
-    ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--drag-steps", type=int, default=0,
                     help="sphere workloads: run this many coarse steps in F32 and F16S "
                          "from the initial state and report the drag coefficient")
@@ -679,6 +676,8 @@ def main():
         roof["traffic_gbs"] = round(traffic / t_launch / 1e9, 1)
         roof["traffic_frac"] = round(traffic / t_launch / 1e9 / HBM_PEAK_GBS, 4)
         roof["traffic_over_algorithmic"] = round(traffic / (dom["elements_per_launch"] * alg), 3)
+        roof["traffic_over_as_read"] = round(
+            traffic / (dom["elements_per_launch"] * dom["as_read_bytes_per_update"]), 3)
     out = {
         "metric": METRIC, "value": round(fw["value"], 2), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": fw["ms"] / args.steps,
