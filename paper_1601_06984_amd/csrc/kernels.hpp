@@ -311,11 +311,20 @@ __device__ __forceinline__ void pull_sources_wg_mode(const LA& a, int64_t blk, u
   constexpr int Q = Lat::Q, NSL = (Q - 1) * NBR_BASES;
   static_assert(NSL <= NBR_SLOTS && NSL <= 256, "slots fit the staging area");
   uint32_t c[Q];
-  if constexpr (MODE != 1) {
+  if constexpr (MODE == 0) {
 #pragma unroll
     for (int i = 1; i < Q; ++i)
-      c[i] = load_u16(a.nbr16 + (int64_t)(i - 1) * a.ld16, a.ld16,
-                      (MODE == 2 && ((regm >> i) & 1u)) ? NBR_NO_CODE : x);
+      c[i] = load_u16(a.nbr16 + (int64_t)(i - 1) * a.ld16, a.ld16, x);
+  } else if constexpr (MODE == 2) {
+    // regm is uniform over the work-group: each code load sits behind a
+    // scalar branch, so the Morton directions issue no memory instruction;
+    // nothing inside the branches uses a loaded value, so the loads of all
+    // code directions are still in flight together
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      c[i] = 0u;
+      if (!((regm >> i) & 1u)) c[i] = load_u16(a.nbr16 + (int64_t)(i - 1) * a.ld16, a.ld16, x);
+    }
   }
   if (threadIdx.x < NSL) sl[threadIdx.x] = a.nbase[blk * NSL + threadIdx.x];
   __syncthreads();
