@@ -6,7 +6,9 @@ element with the oracle, whose stored state is the pre-collision pdfs f
 after streaming.  Writing pre-collision pdfs (set_state with
 MLBM_STATE_PDF_PRE) followed by the synchronous fill must reproduce the
 oracle's state at a coarse time.  F64 runs are compared at 1e-12 relative
-(rounding order only), F32 at 1e-5.
+(rounding order only), F32 at 1e-5, FP16-shift at 2e-3 (its storage
+rounding; the strain rate, a difference of nearly equal pdfs, at 2e-2 of
+its largest component).
 """
 import sys
 
@@ -51,6 +53,8 @@ CASES = [
     ("D3Q19", lambda: W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)]), 0.6,
      "f64", 1e-12),
     ("D3Q27", lambda: W.refined_box_mesh("D3Q27", 4, 4, 12), 0.7, "f32", 1e-5),
+    ("D3Q19", lambda: W.refined_box_mesh("D3Q19", 4, 2, 14, extra_levels=[(10, 18)]), 0.7,
+     "f16s", 2e-3),
 ]
 
 
@@ -82,7 +86,7 @@ def test_pre_collision_pdfs_and_strain_match_oracle(stencil, spec_fn, tau0, prec
         S = sim.get_strain(k).cpu().numpy()
         # relative to the largest component: S vanishes at some elements
         err = float(np.abs(S - want).max() / np.abs(want).max())
-        assert err < (1e-11 if prec == "f64" else 2e-3), (k, err)
+        assert err < {"f64": 1e-11, "f32": 2e-3, "f16s": 2e-2}[prec], (k, err)
         # the same formula applied on the host to the library's own
         # pre-collision pdfs: the device evaluation alone
         _, _, Sg, _ = ophys.strain_rate(torch.from_numpy(got[np.argsort(perm)]), osim.omega[L],
@@ -91,7 +95,7 @@ def test_pre_collision_pdfs_and_strain_match_oracle(stencil, spec_fn, tau0, prec
         assert float(np.abs(S - own).max() / np.abs(own).max()) < 1e-12
         # moments of the pre-collision pdfs are those of the stored state
         mom = sim.get_moments(k).cpu().numpy()
-        assert np.abs(got.sum(0) - mom[0]).max() < (1e-12 if prec == "f64" else 1e-6)
+        assert np.abs(got.sum(0) - mom[0]).max() < {"f64": 1e-12, "f32": 1e-6, "f16s": 1e-5}[prec]
 
 
 def test_previous_state_is_what_the_pull_read():
@@ -117,7 +121,7 @@ def test_previous_state_is_what_the_pull_read():
 
 
 @pytest.mark.parametrize("stencil,prec,tol", [("D2Q9", "f64", 1e-12), ("D3Q19", "f64", 1e-12),
-                                              ("D3Q19", "f32", 1e-5)])
+                                              ("D3Q19", "f32", 1e-5), ("D3Q19", "f16s", 2e-3)])
 def test_set_pre_collision_then_fill_reproduces_oracle(stencil, prec, tol):
     """Writing the oracle's pre-collision pdfs at a coarse time into every
     level, then the synchronous fill (Sec. 2.2, Steps 1-5), gives the
