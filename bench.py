@@ -433,6 +433,8 @@ def drag_inflow_gradient(M, torch, sim, uin, n_steps, K, snapshots):
     if getattr(sim, "adj_workspace", None) is None:
         sim.adjoint_attach()
     sim.adjoint_seed("drag_x")
+    if snapshots == "auto":
+        snapshots = AG.snapshot_budget(sim)
     for start in sorted(ck, reverse=True):
         print(f"[bench] reversing coarse steps {start}..{min(start + K, n_steps)}",
               file=sys.stderr, flush=True)
@@ -627,7 +629,8 @@ def main():
                     help="sphere workloads: dJ/du_in of the x drag over this many coarse steps")
     ap.add_argument("--checkpoint-every", type=int, default=50)
     ap.add_argument("--snapshots", type=int, default=-1,
-                    help="extra states kept while reversing a segment (-1: all)")
+                    help="extra states kept while reversing a segment "
+                         "(-1: as many as the free device memory holds)")
     ap.add_argument("--sweep", type=int, default=0,
                     help="also run the FP64 convergence sweep (bases 32/64/128 to t_D)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -729,7 +732,7 @@ def main():
         sim2 = make_sim(M, torch, wl, plan, prec)
         out["drag_adjoint"] = drag_inflow_gradient(
             M, torch, sim2, wl["uniform_u"], args.drag_adjoint, args.checkpoint_every,
-            None if args.snapshots < 0 else args.snapshots)
+            "auto" if args.snapshots < 0 else args.snapshots)
         del sim2
         gc.collect()
         torch.cuda.empty_cache()

@@ -29,7 +29,8 @@ class MultilevelLBMFunction(torch.autograd.Function):
 
     spec   dict: plan, precision, rho (list per level), S (list or None),
            n_steps, checkpoint_every, objective ('ke' | 'drag_x'),
-           max_snapshots (None: keep every step state of a segment)
+           max_snapshots (None: keep every step state of a segment;
+           "auto": as many as the free device memory holds)
     tau0   0-dim float64 tensor (coarsest-level relaxation time)
     u_in   (d,) float64 tensor (EQ-face velocity) or None
     u0     per-level (d, n_fluid) float64 device tensors (initial velocity)
@@ -88,12 +89,23 @@ class MultilevelLBMFunction(torch.autograd.Function):
         return (None, d_tau, d_uin, *grads)
 
 
+def snapshot_budget(sim, reserve=0.05):
+    """Number of extra step states the free device memory holds, keeping
+    `reserve` of the device's memory free."""
+    free, total = torch.cuda.mem_get_info(sim.device)
+    room = free - int(reserve * total)
+    return max(0, room // max(1, sim.checkpoint_bytes()))
+
+
 def reverse_steps(sim, start_ckpt, n, max_snapshots=None):
     """Reverse n coarse steps whose first starts from the state in
     `start_ckpt`; lambda holds the adjoint of the state after the n steps.
-    Keeps at most `max_snapshots` extra states alive (None: no limit)."""
+    Keeps at most `max_snapshots` extra states alive (None: no limit;
+    "auto": snapshot_budget at the start)."""
     if n <= 0:
         return
+    if max_snapshots == "auto":
+        max_snapshots = snapshot_budget(sim)
     if n == 1:
         sim.adjoint_step(start_ckpt)
         return

@@ -71,15 +71,16 @@ def test_checkpointed_gradient_equals_stepwise_adjoint_and_oracle():
 def test_bisection_checkpointing_matches_stored_states():
     """Reversing a segment by recursive bisection with few stored states
     recomputes the same forward states, so the gradient is bitwise the one
-    obtained by keeping every step state."""
+    obtained by keeping every step state; so does the budget taken from the
+    free device memory."""
     import paper_1601_06984_amd as M
     spec = W.refined_box_mesh("D3Q19", 4, 4, 12)
     fields = lambda p: W.tgv_perturbed_fields(p, 16, 0.03)
     plan = M.Plan.from_spec(spec)
     rho, u, S = _inputs(plan, fields, "cuda")
-    _say("autograd snapshots None/2/0, 11 steps, K=11 and K=4, f32")
+    _say("autograd snapshots None/2/0/auto, 11 steps, K=11 and K=4, f32")
     ref = _run(plan, "f32", rho, u, S, 0.56, 11, 11)
-    for K, snaps in ((11, 2), (11, 0), (4, 1)):
+    for K, snaps in ((11, 2), (11, 0), (4, 1), (11, "auto")):
         J, gu, gt, _ = _run(plan, "f32", rho, u, S, 0.56, 11, K, snapshots=snaps)
         assert J == ref[0] and gt == ref[2]
         for a, b in zip(gu, ref[1]):
