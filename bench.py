@@ -74,6 +74,29 @@ PMC_TRAFFIC = {
 KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "common.hpp")
 
 
+def calib_gather(torch, nbytes, m=1 << 22, reps=3):
+    """Three gathers of m 2-byte values at seeded uniform random positions of
+    a never-touched buffer of nbytes (torch.index_select, one kernel each,
+    each with its own positions), and the distinct 64- and 128-byte lines
+    each one touches, for reading FETCH_SIZE on partial-line requests."""
+    import numpy as np
+    n = nbytes // 2
+    buf = torch.empty(n, dtype=torch.float16, device="cuda")
+    rng = np.random.default_rng(1601)
+    runs = []
+    for _ in range(reps):
+        idx = np.sort(rng.integers(0, n, size=m))
+        runs.append({"values": m, "index_bytes": 8 * m, "out_bytes": 2 * m,
+                     "distinct_64B_lines": int(np.unique(idx >> 5).size),
+                     "distinct_128B_lines": int(np.unique(idx >> 6).size)})
+        it = torch.from_numpy(idx).to("cuda")
+        torch.index_select(buf, 0, it)
+        torch.cuda.synchronize()
+        del it
+    del buf
+    return {"buffer_bytes": nbytes, "runs": runs}
+
+
 def kernel_sources_digest():
     import hashlib
     h = hashlib.sha256()
@@ -635,6 +658,9 @@ def main():
                     help="also run the FP64 convergence sweep (bases 32/64/128 to t_D)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--calib-gather-mib", type=int, default=0,
+                    help="gather 2-byte values at random positions of a buffer of this size "
+                         "(counter calibration for partial-line reads)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -790,6 +816,8 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = n
+    if args.calib_gather_mib:
+        out["calib_gather"] = calib_gather(torch, args.calib_gather_mib << 20)
     if not args.no_cpu:
         _say(f"cpu baseline (oracle, one thread): D = {args.cpu_sample_d} sample")
         stencil = wl["spec"].stencil if not wl.get("tgv") else "D3Q19"
