@@ -585,11 +585,13 @@ def adjoint_leg(torch, sim, plan, prec, n_adj):
     }
 
 
-def precision_study(M, torch, n_fix, n_chk, with_oracle):
-    """Fixed-error study on the two-level D3Q19 Taylor-Green box (64^3 with
-    the central 32^3 refined): MLUPS and eps_u after n_fix coarse steps for
-    F64, F32 and F16S; the pdfs after n_chk steps against the FP64 oracle."""
-    wl = workload("tgv64")
+def precision_study(M, torch, n_fix, n_chk, with_oracle, name="tgv64"):
+    """Fixed-error study on a two-level D3Q19 Taylor-Green box (tgv64: 64^3
+    with the central 32^3 refined, cache resident; tgv128: 128^3 with the
+    central 64^3 refined, 0.9 GB, HBM bound): MLUPS and eps_u after n_fix
+    coarse steps for F64, F32 and F16S; with the oracle, the pdfs after
+    n_chk steps against the FP64 oracle."""
+    wl = workload(name)
     plan = M.Plan.from_spec(wl["spec"])
     upd = weighted_updates(plan)
     study, gpu_pdfs = {}, {}
@@ -605,7 +607,8 @@ def precision_study(M, torch, n_fix, n_chk, with_oracle):
         done += 20
         t_ms = timed_steps(torch, s2, n_fix - done)
         study[p] = dict(mlups=round(upd * (n_fix - done) / (t_ms / 1e3) / 1e6, 1),
-                        eps_u=tgv_velocity_error(s2, plan, wl, n_fix), status=s2.status())
+                        eps_u=tgv_velocity_error(s2, plan, wl, n_fix), status=s2.status(),
+                        working_set_bytes=working_set_bytes(plan, p))
         del s2
     ref = study["f64"]["eps_u"]
     for p in study:
@@ -791,6 +794,10 @@ def main():
     if args.study:
         out["precision_study"] = precision_study(M, torch, 1000, args.cpu_steps,
                                                  not args.no_cpu)
+        gc.collect()
+        torch.cuda.empty_cache()
+        # the same study where the working set exceeds the Infinity Cache
+        out["precision_study_hbm"] = precision_study(M, torch, 1000, 0, False, "tgv128")
     if args.sweep:
         out["convergence"] = convergence_sweep(M, torch)
     if args.copy_ceiling:
