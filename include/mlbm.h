@@ -41,8 +41,9 @@ extern "C" {
 /* ---- enumerations --------------------------------------------------- */
 enum { MLBM_D2Q9 = 0, MLBM_D3Q19 = 1, MLBM_D3Q27 = 2 };
 
-/* Storage precision of the pdfs.  F64: double, FP64 collision.  F32: float,
- * FP32 collision.  F16S: half holding s_L * (f_i - w_i rho0) with a
+/* Storage precision of the pdfs.  F64: double holding f_i, FP64 collision.
+ * F32: float holding the deviation f_i - w_i rho0; moments and equilibria
+ * in FP64, the relaxation in FP32.  F16S: half holding s_L * (f_i - w_i rho0) with a
  * power-of-two scale s_L per level; collision in FP32.  The stream-collide
  * rounds an element's diagonal directions to nearest and lets the axis pairs
  * and the rest direction absorb the accumulated momentum and mass rounding

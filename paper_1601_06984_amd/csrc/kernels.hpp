@@ -3,7 +3,7 @@
 // state conversion and FP64 diagnostics.
 //
 // All arithmetic works on deviations g_i = f_i - w_i rho0 (exact for the
-// F64/F32 stored values by Sterbenz' lemma, and the native form of F16S),
+// F64 stored values by Sterbenz' lemma; the stored form of F32 and F16S),
 // which keeps FP32 rounding relative to the small deviations instead of
 // to the O(1) pdfs.
 #pragma once
@@ -17,6 +17,10 @@
 namespace mlbm {
 
 // ---------------------------------------------------------------- storage --
+// Stored value of g_i = f_i - w_i rho0: F64 keeps f itself (its rounding is
+// far below anything the method resolves); F32 keeps the deviation g, whose
+// rounding is relative to O(u) values instead of to f ~ w_i; F16S keeps
+// fp16(s_L g).
 template <int P> struct Prec;
 template <> struct Prec<MLBM_F64> { using S = double; using C = double; };
 template <> struct Prec<MLBM_F32> { using S = float; using C = float; };
@@ -29,6 +33,10 @@ __device__ __forceinline__ typename Prec<P>::C load_g(const typename Prec<P>::S*
   if constexpr (P == MLBM_F16S) {
     (void)wr;
     return __half2float(p[idx]) * inv_scale;
+  } else if constexpr (P == MLBM_F32) {
+    (void)wr;
+    (void)inv_scale;
+    return p[idx];
   } else {
     (void)inv_scale;
     return (typename Prec<P>::C)p[idx] - wr;
@@ -44,6 +52,11 @@ __device__ __forceinline__ bool store_g(typename Prec<P>::S* __restrict__ p, int
     const float h = g * scale;
     p[idx] = __float2half_rn(h);
     return fabsf(h) <= 65504.0f;
+  } else if constexpr (P == MLBM_F32) {
+    (void)wr;
+    (void)scale;
+    p[idx] = g;
+    return true;
   } else {
     (void)scale;
     p[idx] = (typename Prec<P>::S)(wr + g);
@@ -100,6 +113,10 @@ __device__ __forceinline__ typename Prec<P>::C load_row(const typename Prec<P>::
   if constexpr (P == MLBM_F16S) {
     (void)wr;
     return __half2float(load_elem(row, len, e)) * inv_scale;
+  } else if constexpr (P == MLBM_F32) {
+    (void)wr;
+    (void)inv_scale;
+    return load_elem(row, len, e);
   } else {
     (void)inv_scale;
     return (typename Prec<P>::C)load_elem(row, len, e) - wr;
@@ -116,6 +133,11 @@ __device__ __forceinline__ bool store_row(typename Prec<P>::S* __restrict__ row,
     const float h = g * scale;
     store_elem(row, len, e, __float2half_rn(h));
     return fabsf(h) <= 65504.0f;
+  } else if constexpr (P == MLBM_F32) {
+    (void)wr;
+    (void)scale;
+    store_elem(row, len, e, (S)g);
+    return true;
   } else {
     (void)scale;
     store_elem(row, len, e, (S)(wr + g));
@@ -170,6 +192,29 @@ __device__ __forceinline__ void macro_g(const C* g, C rho0, C& drho, C& rho, C* 
   const C inv = C(1) / rho;
 #pragma unroll
   for (int a = 0; a < 3; ++a) u[a] = a < Lat::D ? j[a] * inv : C(0);
+}
+
+// macro_g of FP32 deviations accumulated in FP64
+template <class Lat>
+__device__ __forceinline__ void macro_g_wide(const float* g, double rho0, double& drho,
+                                             double& rho, double* u) {
+  double s = 0, j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    const double gi = g[i];
+    s += gi;
+#pragma unroll
+    for (int a = 0; a < Lat::D; ++a) {
+      const int ci = Lat::c(i, a);
+      if (ci > 0) j[a] += gi;
+      if (ci < 0) j[a] -= gi;
+    }
+  }
+  drho = s;
+  rho = rho0 + s;
+  const double inv = 1.0 / rho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = a < Lat::D ? j[a] * inv : 0.0;
 }
 
 template <class Lat, class C>
@@ -717,8 +762,28 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
     gather_from<Lat, P>(src, x, a, j, g);
   }
   C drho, rho, u[3];
-  macro_g<Lat, C>(g, a.rho0, drho, rho, u);
+  // F32: moments and equilibria in FP64, the relaxation in FP32.  With all
+  // of it in FP32 the rounding of the moment sums and equilibria dominated
+  // the FP32 variant's error on fine meshes near tau = 1/2 (unused in the
+  // other precisions; F16S is bound by its storage instead).
+  double drho_w = 0, rho_w = 0, u_w[3] = {0, 0, 0}, uu_w = 0;
+  if constexpr (P == MLBM_F32) {
+    macro_g_wide<Lat>(g, (double)a.rho0, drho_w, rho_w, u_w);
+    uu_w = dot_uu<Lat, double>(u_w);
+    drho = (C)drho_w;
+    rho = (C)rho_w;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u[b] = (C)u_w[b];
+  } else {
+    macro_g<Lat, C>(g, a.rho0, drho, rho, u);
+  }
   const C uu = dot_uu<Lat, C>(u);
+  auto post = [&](int i) -> C {
+    if constexpr (P == MLBM_F32)
+      return g[i] + a.omega * ((C)geq_i<Lat, double>(i, drho_w, rho_w, u_w, uu_w) - g[i]);
+    else
+      return g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
+  };
   // interpolation sources keep their pre-collision moments
   const bool is_src = valid && x >= a.cap_begin && x < a.n_fluid;
   const uint64_t m = __ballot(is_src);
@@ -746,10 +811,7 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
                                       drho, rho, u, uu);
     } else {
 #pragma unroll
-      for (int i = 0; i < Lat::Q; ++i) {
-        const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
-        tile[i * BS + t] = (S)(a.wr[Lat::wclass(i)] + gs);
-      }
+      for (int i = 0; i < Lat::Q; ++i) tile[i * BS + t] = (S)post(i);   // FP32: the deviation
     }
     __syncthreads();
     typedef int VT __attribute__((ext_vector_type(4)));
@@ -768,11 +830,9 @@ __device__ __forceinline__ void sc_body(int64_t blk, int64_t x1,
           drho, rho, u, uu);
     } else {
 #pragma unroll
-      for (int i = 0; i < Lat::Q; ++i) {
-        const C gs = g[i] + a.omega * (geq_i<Lat, C>(i, drho, rho, u, uu) - g[i]);
-        ok &= store_row<P>(dst + (int64_t)i * a.n, a.n, (uint32_t)x, gs, a.wr[Lat::wclass(i)],
-                           a.scale);
-      }
+      for (int i = 0; i < Lat::Q; ++i)
+        ok &= store_row<P>(dst + (int64_t)i * a.n, a.n, (uint32_t)x, post(i),
+                           a.wr[Lat::wclass(i)], a.scale);
     }
   }
   const bool finite = (rho == rho) && (rho - rho == C(0));
@@ -799,7 +859,7 @@ constexpr int sc_lds_values(int bs) {
 // One level's stream-collide over [0, x1); the block map balances the plain
 // range and the tail (capture sources, inner ghosts) over the XCDs.
 template <class Lat, int P, int BS>
-__global__ __launch_bounds__(BS) void k_stream_collide(
+__global__ __launch_bounds__(BS, (P == MLBM_F32 && Lat::Q == 19) ? 6 : 1) void k_stream_collide(
     const typename Prec<P>::S* __restrict__ src, typename Prec<P>::S* __restrict__ dst,
     int64_t x1, const LevelArgs<typename Prec<P>::C, Lat::Q> a,
     typename Prec<P>::C* __restrict__ cap, uint32_t* __restrict__ status) {
@@ -830,7 +890,7 @@ struct ScMulti {
 };
 
 template <class Lat, int P, int BS>
-__global__ __launch_bounds__(BS) void k_stream_collide_multi(
+__global__ __launch_bounds__(BS, (P == MLBM_F32 && Lat::Q == 19) ? 6 : 1) void k_stream_collide_multi(
     const ScMulti<typename Prec<P>::C, typename Prec<P>::S, Lat::Q> m,
     uint32_t* __restrict__ status) {
   using C = typename Prec<P>::C;
