@@ -1,5 +1,6 @@
 """Pins of the oracle's reverse pass against central finite differences of
-the forward oracle (independent of automatic differentiation)."""
+the forward oracle and against exact complex-step tangents of it (both
+independent of automatic differentiation)."""
 import numpy as np
 import pytest
 
@@ -97,3 +98,61 @@ def test_gradient_with_curved_walls(objective, steps):
     # the walls change the gradient
     _, _, _, g_in_h = adjoint.gradient(m, 0.6, rho, u, S, steps, objective=objective, u_in=uin)
     assert abs(g_in_h[0] - g_in[0]) > 1e-4 * abs(g_in[0])
+
+
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19"])
+def test_reverse_pass_equals_complex_step_tangents(stencil):
+    """Dot-product test with exact tangents: the forward oracle run in
+    complex128 with the input perturbed by i h d (h = 1e-30) gives
+    dJ/dx . d as Im J / h with no cancellation, so the reverse pass must
+    match it to rounding (1e-12), along a random initial-velocity
+    direction and along tau0."""
+    import torch
+    from oracle.solver import OracleSim
+    spec = (W.refined_box_mesh("D3Q19", 3, 2, 6) if stencil == "D3Q19"
+            else W.refined_box_mesh("D2Q9", 4, 4, 12))
+    m = mesh.build(spec)
+    n0 = spec.box_extent[0]
+    rho, u, S = _fields(m, n0, lambda p: W.tgv_perturbed_fields(p, n0, 0.03))
+    J, g_tau, g_u, _ = adjoint.gradient(m, 0.57, rho, u, S, 4)
+    rng = np.random.default_rng(7)
+    du = {L: rng.normal(size=u[L].shape) for L in u}
+    h = 1e-30
+
+    def tangent(tau, uu):
+        sim = OracleSim(m, torch.tensor(tau, dtype=torch.complex128), poison=False,
+                        dtype=torch.complex128)
+        sim.init(rho, uu, S)
+        sim.step(4)
+        Jc = sim.kinetic_energy()
+        assert abs(float(Jc.real) - J) <= 1e-14 * abs(J)
+        return float(Jc.imag) / h
+
+    ad = sum((g_u[L] * du[L]).sum() for L in u)
+    cs = tangent(0.57, {L: np.asarray(u[L]) + 1j * h * du[L] for L in u})
+    assert abs(cs - ad) <= 1e-12 * abs(ad), (cs, ad)
+    cs = tangent(0.57 + 1j * h, u)
+    assert abs(cs - g_tau) <= 1e-12 * abs(g_tau), (cs, g_tau)
+
+
+def test_inflow_gradient_equals_complex_step_tangent():
+    """The drag's derivative with respect to the free-stream velocity (EQ
+    faces and momentum exchange on the sphere) against its complex-step
+    tangent, to rounding."""
+    import torch
+    from oracle.solver import OracleSim
+    m = mesh.build(_compact_sphere())
+    uin = np.array([0.04, 0.0, 0.0])
+    rho, u, S = {}, {}, {}
+    for L in range(m.level0, m.lmax + 1):
+        rho[L], u[L], S[L] = W.uniform_fields(m.lev(L).n_fluid, 3, uin)
+    _, _, _, g_in = adjoint.gradient(m, 0.6, rho, u, S, 6, objective="drag_x", u_in=uin)
+    h = 1e-30
+    sim = OracleSim(m, torch.tensor(0.6, dtype=torch.complex128),
+                    u_in=torch.tensor(uin + 1j * h * np.array([1.0, 0.0, 0.0]),
+                                      dtype=torch.complex128),
+                    poison=False, dtype=torch.complex128)
+    sim.init(rho, u, S)
+    sim.step(6)
+    cs = float(sim.force()[0].imag) / h
+    assert abs(cs - g_in[0]) <= 1e-12 * abs(g_in[0]), (cs, g_in[0])
