@@ -189,7 +189,13 @@ struct Adj {
         break;
       }
     if ((int)q.size() == SC_MAX_SEG) tape_flush(s, q);
-    q.push_back(ScJob{k, L.n_fluid + (first ? L.n_inner : 0), X_of(A, j), A.X[j + 1], A.cap[j]});
+    // the last substep of the coarse step: its state X[2^k] is read by no
+    // transposed kernel (each reverse stream-collide gathers from the state
+    // it consumed; the fills' transposes read records), so only the
+    // interpolation sources, whose records the fills use, are updated
+    const bool last = j == (1 << k) - 1;
+    q.push_back(ScJob{k, L.n_fluid + (first ? L.n_inner : 0), X_of(A, j), A.X[j + 1], A.cap[j],
+                      last ? L.n_fluid - L.n_cap_fluid : 0});
     if (k + 1 < (int)s.lv.size()) {
       tape_advance(s, k + 1, 2 * j, q, qf);
       tape_advance(s, k + 1, 2 * j + 1, q, qf);

@@ -881,6 +881,7 @@ template <class C, class S, int Q>
 struct ScMulti {
   int nseg;
   int64_t first[SC_MAX_SEG];
+  int64_t b0[SC_MAX_SEG];     // first pull-table block of the segment
   int64_t nb[SC_MAX_SEG];
   int64_t n_act[SC_MAX_SEG];
   const S* src[SC_MAX_SEG];
@@ -901,7 +902,8 @@ __global__ __launch_bounds__(BS, (P == MLBM_F32 && Lat::Q == 19) ? 6 : 1) void k
   const int64_t b = (int64_t)blockIdx.x - m.first[sg];
   if (b >= m.nb[sg]) return;
   const LevelArgs<C, Lat::Q>& a = m.a[sg];
-  const int64_t blk = xcd_block2(b, m.nb[sg], a.cap_begin / BS);
+  const int64_t plain = a.cap_begin / BS - m.b0[sg];
+  const int64_t blk = m.b0[sg] + xcd_block2(b, m.nb[sg], plain > 0 ? plain : 0);
   sc_body<Lat, P, BS>(blk, m.n_act[sg], m.src[sg], m.dst[sg], a, m.cap[sg], status, stage,
                       slots);
 }

@@ -94,7 +94,7 @@ struct Impl {
 
   // stream-collides of distinct levels (jobs) in one launch
   static void stream_collide_multi(SimState& s, const ScJob* jobs, int n) {
-    if (n == 1) {
+    if (n == 1 && jobs[0].x0 == 0) {
       stream_collide_ptr(s, jobs[0].k, jobs[0].n_act, jobs[0].src, jobs[0].dst, jobs[0].cap);
       return;
     }
@@ -104,8 +104,10 @@ struct Impl {
     for (int j = 0; j < n; ++j) {
       if (jobs[j].n_act <= 0) continue;
       const int sg = m.nseg++;
-      const int64_t nb = (jobs[j].n_act + BS - 1) / BS;
+      const int64_t b0 = std::min(jobs[j].x0, jobs[j].n_act - 1) / BS;
+      const int64_t nb = (jobs[j].n_act + BS - 1) / BS - b0;
       m.first[sg] = total;
+      m.b0[sg] = b0;
       m.nb[sg] = nb;
       m.n_act[sg] = jobs[j].n_act;
       m.src[sg] = (const S*)jobs[j].src;

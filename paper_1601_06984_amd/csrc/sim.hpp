@@ -68,6 +68,8 @@ struct ScJob {
   const void* src;
   void* dst;
   void* cap;
+  int64_t x0 = 0;   // elements below the block of x0 are skipped (their
+                    // results are not needed; see the adjoint's tape)
 };
 // A fill of levels (k, k+1) waiting likewise (see mlbm::flush_fill).
 struct FillJob {
