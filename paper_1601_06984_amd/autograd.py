@@ -140,8 +140,10 @@ def reverse_steps(sim, start_ckpt, n, max_snapshots=None):
 
 
 def objective(plan, rho, u0, tau0, n_steps, *, S=None, u_in=None, precision="f32",
-              checkpoint_every=None, objective="ke", max_snapshots=None):
-    """Differentiable objective J(u0, tau0[, u_in]) of a multilevel run."""
+              checkpoint_every=None, objective="ke", max_snapshots="auto"):
+    """Differentiable objective J(u0, tau0[, u_in]) of a multilevel run.
+    max_snapshots: extra step states kept while reversing a segment ("auto":
+    as many as the free device memory holds; None: all of them)."""
     spec = dict(plan=plan, precision=precision, rho=rho, S=S, n_steps=n_steps,
                 checkpoint_every=checkpoint_every or n_steps, objective=objective,
                 max_snapshots=max_snapshots)
