@@ -50,7 +50,9 @@ def test_config2_d3q19_f32_100_steps(base, lo, hi, morton):
     """D3Q19 TGV with the central cube refined, u0 = 0.02, Re = 100
     (tau0 = 0.5 + 3 u0 N/(2 pi Re)), FP32 storage and collision: max
     relative pdf error <= 1e-5 after 100 coarse steps (64^3 is the full
-    configuration)."""
+    configuration).  With its moments and equilibria in FP64 the FP32
+    variant stays within 5e-7 (measured 6e-8, a few FP32 roundings of the
+    stored deviations)."""
     n0 = 1 << base
     tau0 = 0.5 + 3 * 0.02 * n0 / (2 * np.pi * 100)
     spec = W.refined_box_mesh("D3Q19", base, lo, hi)
@@ -61,6 +63,7 @@ def test_config2_d3q19_f32_100_steps(base, lo, hi, morton):
     err = H.compare_post(sim, osim)
     print("max rel pdf err", err)
     assert err < 1e-5
+    assert err < 5e-7
     assert sim.status() == 0
 
 
